@@ -1,0 +1,96 @@
+"""Pins of the oracle's saddle-point assembly (Secs. 3.1-3.3, App. A).
+
+The Kronecker assembly is compared with direct 3D quadrature of the weak
+form (which fixes the nu scaling of each block), and with invariants:
+symmetry, definiteness, the pressure null space, the divergence identity
+B^T u = M_q D u and the Kronecker-product identities of App. A.1-A.2.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sps
+
+from oracle.assemble import KronSystem, assemble_quadrature, kron3
+from oracle.matrices1d import difference_matrix
+
+
+@pytest.mark.parametrize("E,p,nu", [(1, 2, 1.0), (2, 2, 2.0), (2, 3, 0.5), (3, 2, 1.0)])
+def test_kronecker_equals_quadrature(E, p, nu):
+    S = KronSystem(E, p, nu)
+    A, B, F = assemble_quadrature(E, p, nu, U=1.3)
+    assert np.abs(S.A.toarray() - A).max() <= 1e-13 * np.abs(A).max()
+    assert np.abs(S.B.toarray() - B).max() <= 1e-13 * np.abs(B).max()
+    Fk = S.lid_rhs(1.3)[:S.nV]
+    assert np.abs(Fk - F).max() <= 1e-13 * np.abs(F).max()
+
+
+def test_body_force_rhs_equals_quadrature():
+    modes = [[(0.7, (1, 2, 1)), (-0.2, (3, 1, 2))], [(0.4, (2, 2, 1))], [(1.1, (1, 1, 3))]]
+    E, p = 2, 3
+    S = KronSystem(E, p, 1.0)
+    _, _, F0 = assemble_quadrature(E, p, 1.0, U=0.0)
+    _, _, F1 = assemble_quadrature(E, p, 1.0, U=0.0, modes=modes)
+    Fb = S.body_force_rhs(modes)[:S.nV]
+    assert np.abs(Fb - (F1 - F0)).max() <= 1e-12 * np.abs(Fb).max()
+
+
+@pytest.mark.parametrize("E,p", [(2, 2), (3, 3), (2, 4)])
+def test_symmetry_and_definiteness(E, p):
+    S = KronSystem(E, p, 1.0)
+    K = S.K.toarray()
+    assert np.abs(K - K.T).max() <= 1e-14 * np.abs(K).max()
+    assert np.linalg.eigvalsh(S.A.toarray()).min() > 0
+    ev = np.linalg.eigvalsh(K)
+    # saddle point: n_V positive, n_Q - 1 negative, one zero (constant pressure)
+    tol = 1e-10 * np.abs(ev).max()
+    assert (ev > tol).sum() == S.nV
+    assert (ev < -tol).sum() == S.nQ - 1
+
+
+@pytest.mark.parametrize("E,p", [(2, 2), (5, 3), (4, 4)])
+def test_constant_pressure_is_in_null_space_of_B(E, p):
+    """B q_c = 0 for the constant pressure: int div v = int v.n = 0."""
+    S = KronSystem(E, p, 1.0)
+    g = S.m.sp.m_integrals        # 1 = sum_i (int N_{i,p-1}) M_i
+    qc = np.kron(g, np.kron(g, g))
+    assert np.abs(S.B @ qc).max() <= 1e-13 * np.abs(S.B).max() * np.abs(qc).max()
+
+
+@pytest.mark.parametrize("E,p", [(3, 2), (4, 3)])
+def test_divergence_identity(E, p):
+    """B^T u = M_q D u with D the coefficient-wise difference (App. B.1)."""
+    S = KronSystem(E, p, 1.0)
+    n = S.m.n
+    Dh = difference_matrix(n)[:, 1:-1]     # boundary columns removed
+    nM = n - 1
+    I = np.eye(nM)
+    D = sps.hstack([kron3(I, I, Dh), kron3(I, Dh, I), kron3(Dh, I, I)])
+    u = np.random.default_rng(3).standard_normal(S.nV)
+    assert np.allclose(S.B.T @ u, S.Mq @ (D @ u), atol=1e-12 * np.abs(S.B.T @ u).max())
+
+
+def test_kronecker_identities():
+    """App. A.1 properties and the tensor-contraction form of App. A.2."""
+    rng = np.random.default_rng(5)
+    A, B, C, Dm = (rng.standard_normal((3, 3)), rng.standard_normal((4, 4)),
+                   rng.standard_normal((3, 2)), rng.standard_normal((4, 5)))
+    assert np.allclose(np.kron(A, B) @ np.kron(C, Dm), np.kron(A @ C, B @ Dm))
+    assert np.allclose(np.linalg.inv(np.kron(A, B)), np.kron(np.linalg.inv(A), np.linalg.inv(B)))
+    assert np.allclose(np.kron(A, B).T, np.kron(A.T, B.T))
+    assert np.allclose(np.kron(np.kron(A, B), C), np.kron(A, np.kron(B, C)))
+    # vec ordering: direction 1 fastest
+    D1, D2, D3 = rng.standard_normal((2, 3)), rng.standard_normal((4, 5)), rng.standard_normal((3, 2))
+    X = rng.standard_normal((3, 5, 2))            # X[i1, i2, i3]
+    vecX = X.reshape(-1, order="F")
+    Y = np.einsum("ai,bj,ck,ijk->abc", D1, D2, D3, X)
+    assert np.allclose(kron3(D3, D2, D1) @ vecX, Y.reshape(-1, order="F"))
+
+
+def test_sizes_match_the_complex():
+    """dim V_h = 3 (E+p-2)(E+p-1)^2, dim Q_h = (E+p-1)^3 (App. B.2)."""
+    for E, p in [(8, 2), (32, 3)]:
+        S = KronSystem(E, p, 1.0) if E == 8 else None
+        nN, nM = E + p - 2, E + p - 1
+        if S is not None:
+            assert S.nV == 3 * nN * nM * nM and S.nQ == nM ** 3
+    assert 3 * 8 * 81 + 729 == 2673
+    assert 3 * 33 * 34 ** 2 + 34 ** 3 == 153748

@@ -1,0 +1,217 @@
+"""Pins of the oracle's preconditioners (Secs. 2, 4, 5.2, App. A.4).
+
+* fast diagonalization (App. A.4) written with numpy's eigh reproduces the
+  dense inverse of each diagonal block of A (the oracle's P_{V,0} uses LU);
+* trace(P_{V,0}^{-1} A) = n_V;
+* the spectrum at 2^3 elements, degree 4 (the paper's worked example);
+* Lemma Sk_posdef / Corollary cor:Skform: sigma(P_k^{-1} A) is the image
+  of sigma(P_0^{-1} A) under l_q(t) = 1 - (1 - t)^q, condition numbers
+  decrease, every P_k is SPD (Theorem positive definite);
+* the closed forms I - A P_{V,k}^{-1} = (I - A P_{V,0}^{-1})^{q^k} (and
+  the same for eq. Pcq2 and one step of eq. Pcq1), by dense brute force;
+* application counts and the cost ratios of Sec. 5.1.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.assemble import KronSystem
+from oracle.precond import BasePreconditioner, HyperPower, dense_hyperpower
+
+
+def _read_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    rows = {}
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        parts = line.split()
+        rows[parts[0]] = [float(v) for v in parts[1:]]
+    return rows
+
+
+def _dense_ops(S):
+    A = S.A.toarray()
+    o = S.offsets
+    Dv = np.zeros_like(A)
+    for c in range(3):
+        Dv[o[c]:o[c + 1], o[c]:o[c + 1]] = A[o[c]:o[c + 1], o[c]:o[c + 1]]
+    return A, Dv
+
+
+@pytest.mark.parametrize("E,p", [(2, 2), (3, 3)])
+def test_fast_diagonalization_equals_dense_inverse(E, p):
+    """App. A.4: (U3 (x) U2 (x) U1) diag(1/(l1+l2+l3)) (U3 (x) U2 (x) U1)^T
+    with U_k the M_k-orthonormal generalised eigenvectors of (A_k, M_k)."""
+    nu = 0.7
+    S = KronSystem(E, p, nu)
+    m = S.m
+
+    def geig(A, M):
+        lam, U = sla.eigh(A, M)
+        return lam, U
+
+    lK, UK = geig(m.K_int, m.M_int)
+    lT, UT = geig(m.Tc, m.Mc)
+    fams = [((lK, UK), (lT, UT), (lT, UT)),    # component 1: K in dir 1
+            ((lT, UT), (lK, UK), (lT, UT)),
+            ((lT, UT), (lT, UT), (lK, UK))]
+    A, _ = _dense_ops(S)
+    o = S.offsets
+    for c in range(3):
+        (l1, U1), (l2, U2), (l3, U3) = fams[c]
+        U = np.kron(U3, np.kron(U2, U1))
+        lam = (l3[:, None, None] + l2[None, :, None] + l1[None, None, :]).reshape(-1)
+        Pinv = U @ np.diag(1.0 / (2 * nu * lam)) @ U.T
+        blk = A[o[c]:o[c + 1], o[c]:o[c + 1]]
+        assert np.abs(Pinv @ blk - np.eye(blk.shape[0])).max() < 1e-10
+
+
+def test_trace_of_preconditioned_A():
+    S = KronSystem(3, 2, 1.0)
+    A, Dv = _dense_ops(S)
+    assert abs(np.trace(np.linalg.solve(Dv, A)) - S.nV) < 1e-9 * S.nV
+
+
+def test_spectrum_worked_example():
+    """2^3 elements, degree 4: sigma(P_{V,0}^{-1} A) within 0.02 of [0.71, 1.41]."""
+    g = _read_golden("spectrum_2cube_p4.txt")
+    S = KronSystem(2, 4, 1.0)
+    A, Dv = _dense_ops(S)
+    ev = sla.eigh(A, Dv, eigvals_only=True)
+    assert abs(ev.min() - g["lambda0_min"][0]) < 0.02
+    assert abs(ev.max() - g["lambda0_max"][0]) < 0.02
+    assert ev.min() > 0 and ev.max() < 2
+
+
+def test_lambda_min_sequence_from_the_paper():
+    """Corollary cor:Skform applied to [0.71, 1.41] gives the printed sequence."""
+    g = _read_golden("spectrum_2cube_p4.txt")
+    l = lambda t: 2 * t - t * t
+    lo, hi = g["lambda0_min"][0], g["lambda0_max"][0]
+    seq = [lo]
+    lo, hi = min(l(lo), l(hi)), max(l(lo), l(hi))
+    seq.append(lo)
+    for _ in range(2):
+        lo = l(lo)
+        seq.append(lo)
+    assert np.allclose(seq, g["lambda_min_k"], atol=6e-5)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_spectral_map_and_spd(q):
+    S = KronSystem(2, 3, 1.0)
+    A, Dv = _dense_ops(S)
+    X0 = np.linalg.inv(Dv)
+    Xs = dense_hyperpower(A, X0, q, 3)
+    ev0 = np.sort(np.linalg.eigvals(X0 @ A).real)
+    lq = lambda t: 1 - (1 - t) ** q
+    kappa = []
+    for k, X in enumerate(Xs):
+        evk = np.sort(np.linalg.eigvals(X @ A).real)
+        pred = np.sort(ev0.copy())
+        for _ in range(k):
+            pred = lq(pred)
+        assert np.allclose(evk, np.sort(pred), atol=1e-9)
+        Xs_sym = 0.5 * (X + X.T)
+        assert np.abs(X - X.T).max() < 1e-9 * np.abs(X).max()
+        assert np.linalg.eigvalsh(Xs_sym).min() > 0
+        kappa.append(evk.max() / evk.min())
+        if k > 0:
+            # (0, 1] for even q (Lemma Sk_posdef, q = 2); odd q keeps (0, 2)
+            top = 1 + 1e-12 if q % 2 == 0 else 2.0
+            assert evk.max() <= top and evk.min() > 0
+    assert all(kappa[i + 1] < kappa[i] for i in range(len(kappa) - 1))
+
+
+@pytest.mark.parametrize("q,k", [(2, 1), (2, 2), (3, 1), (3, 2)])
+def test_operator_recursion_matches_closed_forms(q, k):
+    """Literal recursion (operator form) vs dense closed forms (block-wise)."""
+    S = KronSystem(2, 2, 1.3)
+    A, Dv = _dense_ops(S)
+    B = S.B.toarray()
+    nV, nQ = S.nV, S.nQ
+    P0 = BasePreconditioner(S)
+    X0v = np.linalg.inv(Dv)
+    X0q = np.column_stack([P0.apply_Q0(e) for e in np.eye(nQ)])
+    # V block: I - A P_{V,k}^{-1} = (I - A P_{V,0}^{-1})^{q^k}
+    for variant in ("Pcq1", "Pcq2"):
+        H = HyperPower(S, q, k, variant=variant, base=P0)
+        Xv = np.column_stack([H.apply_V(k, e) for e in np.eye(nV)])
+        lhs = np.eye(nV) - A @ Xv
+        rhs = np.linalg.matrix_power(np.eye(nV) - A @ X0v, q ** k)
+        assert np.abs(lhs - rhs).max() < 1e-10
+        Xq = np.column_stack([H.apply_Q(k, e) for e in np.eye(nQ)])
+        if variant == "Pcq2":
+            St = B.T @ X0v @ B
+            rhs = np.linalg.matrix_power(np.eye(nQ) - St @ X0q, q ** k)
+            assert np.abs((np.eye(nQ) - St @ Xq) - rhs).max() < 1e-10
+        else:
+            # one step of eq. Pcq1: I - S_l P_k = (I - S_l P_{k-1})^q
+            Xprev = np.column_stack([H.apply_Q(k - 1, e) for e in np.eye(nQ)])
+            lv = H.l_of(k)
+            Xvl = np.column_stack([H.apply_V(lv, e) for e in np.eye(nV)])
+            St = B.T @ Xvl @ B
+            rhs = np.linalg.matrix_power(np.eye(nQ) - St @ Xprev, q)
+            assert np.abs((np.eye(nQ) - St @ Xq) - rhs).max() < 1e-10
+        assert np.abs(Xq - Xq.T).max() < 1e-10 * np.abs(Xq).max()
+        assert np.linalg.eigvalsh(0.5 * (Xq + Xq.T)).min() > -1e-12
+
+
+def test_schur_spectrum_in_unit_interval():
+    """sigma(P_{Q,0}^{-1} B^T A^{-1} B) in [0, 1] (a(v,v) >= 2 nu ||div v||^2)."""
+    S = KronSystem(3, 2, 0.8)
+    A = S.A.toarray()
+    B = S.B.toarray()
+    Sch = B.T @ np.linalg.solve(A, B)
+    P0 = BasePreconditioner(S)
+    X0q = np.column_stack([P0.apply_Q0(e) for e in np.eye(S.nQ)])
+    ev = np.sort(np.linalg.eigvals(X0q @ Sch).real)
+    assert ev[0] > -1e-12 and abs(ev[0]) < 1e-10      # constant pressure
+    assert ev[1] > 0.01 and ev[-1] <= 1 + 1e-12
+
+
+# Appendix of base-operator counts per application of P_k^{-1}
+COUNTS = {
+    # (q, k): (V: PV0, A), Pcq1 literal: (PQ0, Bpairs, PV0, A), Pcq2: (PV0, Bpairs)
+    (2, 0): ((1, 0), (1, 0, 0, 0), (0, 0)),
+    (2, 1): ((2, 1), (2, 1, 1, 0), (1, 1)),
+    (2, 2): ((4, 3), (4, 3, 6, 3), (3, 3)),
+    (2, 3): ((8, 7), (8, 7, 20, 13), (7, 7)),
+    (3, 1): ((3, 2), (3, 2, 2, 0), (2, 2)),
+    (3, 2): ((9, 8), (9, 8, 24, 16), (8, 8)),
+}
+
+
+@pytest.mark.parametrize("qk", sorted(COUNTS))
+def test_application_counts(qk):
+    q, k = qk
+    S = KronSystem(1, 2, 1.0)
+    (v_p, v_a), (q_p, q_b, q_pv, q_a), (c2_pv, c2_b) = COUNTS[qk]
+    P0 = BasePreconditioner(S)
+    H = HyperPower(S, q, k, variant="Pcq1", base=P0)
+    H.apply_V(k, np.ones(S.nV))
+    assert (P0.counts["PV0"], P0.counts["A"]) == (v_p, v_a)
+    for key in P0.counts:
+        P0.counts[key] = 0
+    H.apply_Q(k, np.ones(S.nQ))
+    c = P0.counts
+    assert (c["PQ0"], c["B"], c["Bt"], c["PV0"], c["A"]) == (q_p, q_b, q_b, q_pv, q_a)
+    for key in P0.counts:
+        P0.counts[key] = 0
+    H2 = HyperPower(S, q, k, variant="Pcq2", base=P0)
+    H2.apply_Q(k, np.ones(S.nQ))
+    assert (c["PQ0"], c["PV0"], c["B"]) == (q ** k, c2_pv, c2_b)
+
+
+def test_cost_model_ratios():
+    g = _read_golden("cost_model.txt")
+    cP, cA = g["c_P_numer"][0], g["c_A_numer"][0]
+    C = lambda k: 2 ** k * cP + (2 ** k - 1) * cA
+    assert C(1) / C(0) == pytest.approx(g["ratio_k1"][0])
+    assert C(2) / C(0) == pytest.approx(g["ratio_k2"][0], abs=0.03)
+    t0, t1, t2 = g["timing_384"]
+    assert t1 / t0 == pytest.approx(C(1) / C(0), rel=0.01)
+    assert t2 / t0 == pytest.approx(C(2) / C(0), rel=0.01)
