@@ -1,0 +1,184 @@
+/*
+ * hyperpower.h -- C ABI of the MI355X hyper-power preconditioned Stokes solver.
+ *
+ * Method: M.L. Mika, M.F.P. ten Eikelder, D. Schillinger, R.R. Hiemstra,
+ * "Matrix-free polynomial preconditioning of saddle point systems using the
+ * hyper-power method" (arXiv 2311.06926).
+ *
+ * Problem (Sec. 3.2, eq. systemmatrix): find u_h in V_h, p_h in Q_h with
+ *
+ *      [ A  B ] [u]   [f]
+ *      [ B' 0 ] [p] = [0],
+ *
+ * the divergence-conforming tensor-product B-spline discretisation of the
+ * Stokes equations on [0,1]^3 with E uniform elements per direction,
+ * velocity degree p (component i has degree p in direction i and p-1 in the
+ * others, App. B.2), pressure degree p-1, strong v.n = 0 and Nitsche
+ * (weak) tangential conditions with alpha = c_pen * E (Sec. 3.1).
+ *
+ * VECTOR LAYOUT (all buffers): [u1 | u2 | u3 | p], each block a 3-tensor
+ * stored with direction 1 fastest (vec ordering of App. A.2).  With
+ * nN = E+p-2 and nM = E+p-1 the block shapes (n1, n2, n3) are
+ *      u1: (nN, nM, nM)   u2: (nM, nN, nM)   u3: (nM, nM, nN)   p: (nM, nM, nM)
+ * n_V = 3 nN nM^2, n_Q = nM^3, N = n_V + n_Q.  A batch of nrhs vectors is
+ * stored back to back (the right-hand-side index is the slowest mode,
+ * stride N).  Velocity-only buffers (apply_A/apply_B outputs) have stride
+ * n_V, pressure-only buffers stride n_Q.
+ *
+ * MEMORY: every vector argument is a DEVICE pointer (FP64) on the device
+ * that was current at hp_setup; the caller owns it.  The library owns only
+ * the context and its tables/workspace.  Inputs and outputs must not
+ * overlap unless stated.
+ *
+ * STREAMS: all work is enqueued on the stream given to hp_setup (0 = the
+ * null stream).  hp_apply_* are asynchronous; hp_solve and hp_grad return
+ * after the result is complete and fill their host-side info structs.
+ *
+ * ERRORS: functions return hp_status.  HP_EINVAL: a bad argument (nothing
+ * is written).  HP_EHIP: a HIP runtime error.  HP_ENOMEM: device
+ * allocation failed.  HP_ENOTSPD: a preconditioned inner product
+ * r' P^{-1} r <= 0 was met (the preconditioner is not positive definite,
+ * Sec. 2 Remark rmk:convergence_Pk), HP_EBREAKDOWN: Krylov breakdown,
+ * HP_ENOCONV: maxit reached (x holds the last iterate), HP_ENAN: a NaN/Inf
+ * appeared.  No C++ exception crosses this interface.
+ */
+#ifndef HYPERPOWER_H
+#define HYPERPOWER_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hp_ctx hp_ctx;
+
+typedef enum {
+    HP_OK = 0,
+    HP_EINVAL = -1,
+    HP_EHIP = -2,
+    HP_ENOMEM = -3,
+    HP_ENOTSPD = -4,
+    HP_EBREAKDOWN = -5,
+    HP_ENOCONV = -6,
+    HP_ENAN = -7
+} hp_status;
+
+/* Precision of the preconditioner (the Krylov method always runs in FP64). */
+enum { HP_PREC_FP64 = 0, HP_PREC_FP32 = 1, HP_PREC_BF16X3 = 2 };
+/* Krylov method. MINRES needs an exactly symmetric preconditioner (FP64). */
+enum { HP_MINRES = 0, HP_FGMRES = 1 };
+/* Schur-complement sequence of Sec. 4.1: eq. Pcq1 (with inner updates) or
+ * eq. Pcq2 (without). */
+enum { HP_SCHUR_PCQ1 = 1, HP_SCHUR_PCQ2 = 2 };
+/* Index l of P_{V,l} used by the k-th update of eq. Pcq1: LITERAL is the
+ * schedule of Sec. 4.1 option (5), l = 0 for k = 1 and l = k for k > 1;
+ * PREV uses l = k - 1. */
+enum { HP_L_LITERAL = 0, HP_L_PREV = 1 };
+
+typedef struct hp_opts {
+    double c_pen;       /* Nitsche penalty constant, alpha = c_pen / h (default 12.5) */
+    int schur_variant;  /* HP_SCHUR_PCQ1 (default) or HP_SCHUR_PCQ2 */
+    int l_schedule;     /* HP_L_LITERAL (default) or HP_L_PREV */
+    int precision;      /* HP_PREC_* for P_k (default FP64) */
+    int krylov;         /* HP_MINRES (default) or HP_FGMRES */
+    int restart;        /* FGMRES restart length m (default 50, <= 128) */
+    int maxit;          /* Krylov iteration limit (default 1000) */
+    int order;          /* hyper-power order q >= 2 used by hp_solve (default 2) */
+    int iters;          /* hyper-power updates k >= 0 used by hp_solve (default 1) */
+    int max_rhs;        /* largest batch accepted (workspace size, default 1) */
+    int check_every;    /* solve: host polls convergence every m iterations (default 6) */
+    int use_graph;      /* solve: replay blocks of iterations as HIP graphs (default 1) */
+} hp_opts;
+
+/* Per-solve report (host struct, filled by hp_solve / hp_grad). */
+typedef struct hp_solve_info {
+    int iterations;        /* max over the batch */
+    int converged;         /* 1 if every right-hand side met tol */
+    double relres;         /* max over the batch of the monitored relative residual */
+    double true_relres;    /* max over the batch of ||b - K x||_2 / ||b||_2 (FP64) */
+    double seconds;        /* wall time of the call */
+    int iters_per_rhs[64]; /* iteration count of each right-hand side (first 64) */
+} hp_solve_info;
+
+/* Fill *o with the defaults listed above. */
+void hp_default_opts(hp_opts* o);
+
+/* Build the univariate tables (App. B.3, Sec. 3.3), the generalised
+ * eigen-decompositions for fast diagonalisation (App. A.3-A.4) and the
+ * workspace.  elements >= 1, 2 <= degree <= 4, nu > 0.  opts may be NULL
+ * (defaults).  stream: a hipStream_t or NULL.  *out receives the context. */
+hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts,
+                   void* stream, hp_ctx** out);
+
+/* Change the viscosity (A, P_{V,0} scale with nu, P_{Q,0} with 1/nu,
+ * Sec. 4; the tables are nu-free). */
+hp_status hp_set_nu(hp_ctx* ctx, double nu);
+
+/* Block shapes dims[b][d] (b = u1,u2,u3,p; d = direction) and offsets
+ * (start of u1,u2,u3,p and N) of one vector.  Host arrays. */
+hp_status hp_sizes(const hp_ctx* ctx, int64_t dims[4][3], int64_t offsets[5]);
+
+/* y = K x for nrhs vectors (eq. systemmatrix): y_u = A u + B p, y_p = B' u. */
+hp_status hp_apply_K(hp_ctx* ctx, const double* x, double* y, int nrhs);
+
+/* y = A u (velocity only, stride n_V; Sec. 3.3). */
+hp_status hp_apply_A(hp_ctx* ctx, const double* u, double* y, int nrhs);
+
+/* y = B p (pressure in, stride n_Q; velocity out, stride n_V; Sec. 3.3). */
+hp_status hp_apply_B(hp_ctx* ctx, const double* p, double* y, int nrhs);
+
+/* y = B' u (velocity in, stride n_V; pressure out, stride n_Q). */
+hp_status hp_apply_Bt(hp_ctx* ctx, const double* u, double* y, int nrhs);
+
+/* y = P_0^{-1} x, the block-diagonal base preconditioner of Sec. 4
+ * (eq. blockdiagprecond): the three diagonal blocks of A inverted by fast
+ * diagonalisation (App. A.4) and P_{Q,0}^{-1} = 2 nu (M^^{-1})^{(x)3}. */
+hp_status hp_apply_P0(hp_ctx* ctx, const double* x, double* y, int nrhs);
+
+/* y = P_k^{-1} x, k = iters hyper-power updates of order q = order applied
+ * block-wise to P_0 (eqs. hyperpowersequence, Pcv, Pcq1/Pcq2 per
+ * opts.schur_variant and opts.l_schedule).  order >= 2, 0 <= iters <= 6. */
+hp_status hp_apply_hyperpower(hp_ctx* ctx, int order, int iters, const double* x,
+                              double* y, int nrhs);
+
+/* Solve K x = b to relative tolerance tol with x_0 = 0 (Sec. 5: MINRES to
+ * 1e-8), preconditioned by P_k (opts.order, opts.iters).  MINRES monitors
+ * ||r||_{P^{-1}} / ||b||_{P^{-1}}, FGMRES ||r||_2 / ||b||_2.  info may be
+ * NULL.  Returns HP_ENOCONV (x = last iterate) if maxit is reached. */
+hp_status hp_solve(hp_ctx* ctx, const double* b, double* x, int nrhs, double tol,
+                   hp_solve_info* info);
+
+/* Right-hand side of the lid-driven cavity (Sec. 5, Fig. liddrivencavity)
+ * with a separable body force: for each rhs r, lid speed lid[r] on x3 = 1
+ * (Nitsche data, Sec. 3.1), and for each velocity component c and mode m
+ * b_c += amp[(r*3 + c)*nmodes + m] * prod_d sin(pi k_d x_d) with
+ * k_d = waves[((r*3 + c)*nmodes + m)*3 + d].  Host arrays lid, amp, waves
+ * (amp/waves may be NULL when nmodes == 0); device output b (N x nrhs). */
+hp_status hp_build_rhs(hp_ctx* ctx, const double* lid, int nmodes, const double* amp,
+                       const int* waves, double* b, int nrhs);
+
+/* y = M_V u, the velocity mass matrix (block diagonal L2 Gram matrix of
+ * V_h), stride n_V; used by the loss gradient of the differentiable solve. */
+hp_status hp_apply_MV(hp_ctx* ctx, const double* u, double* y, int nrhs);
+
+/* Adjoint pieces of the differentiable solve with K x = [F_lid(nu) + M_V beta; 0]:
+ * given the forward solution x and the adjoint lambda (K lambda = [dL/du; 0]),
+ *   dL_dbeta = M_V lambda_u                          (device, stride n_V)
+ *   dL_dnu[r] = lambda_u' (F_lid/nu - A u / nu)       (host, one per rhs)
+ * F_lid is rebuilt from lid[r] (host).  K is symmetric, so lambda comes
+ * from hp_solve with the same preconditioner. */
+hp_status hp_grad(hp_ctx* ctx, const double* x, const double* lambda, const double* lid,
+                  double* dL_dbeta, double* dL_dnu, int nrhs);
+
+/* Release the context and its device memory. */
+void hp_destroy(hp_ctx* ctx);
+
+/* Static string for a status code. */
+const char* hp_status_string(hp_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HYPERPOWER_H */

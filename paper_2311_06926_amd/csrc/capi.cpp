@@ -1,0 +1,914 @@
+// C ABI of the solver (include/hyperpower.h) and the host-side orchestration
+// of the hyper-power preconditioner and the Krylov solvers.  Every numerical
+// step runs in the HIP kernels of ops.hip, fd.hip and krylov.hip; this file
+// only sequences them, holds the O(1)-per-iteration Krylov scalars and owns
+// device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <vector>
+
+#include "hp_internal.h"
+#include "vec.h"
+
+using namespace hp;
+
+namespace {
+
+constexpr int KMAX = 6;  // largest number of hyper-power updates
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return HP_EHIP;          \
+    } while (0)
+
+int pad16(int n) { return (n + 15) & ~15; }
+
+// ---- buffers -------------------------------------------------------------------
+struct Extra {
+    // hyper-power temporaries
+    double* hv = nullptr;  // 3 velocity vectors x max_rhs
+    double* hq = nullptr;  // 3 pressure vectors per level x (KMAX+1) x max_rhs
+    // Krylov vectors
+    double* kv = nullptr;
+    size_t kv_doubles = 0;
+    double* dcoef = nullptr;  // device coefficient staging
+    double* hcoef = nullptr;  // pinned host coefficients
+    size_t coef_doubles = 0;
+};
+
+Extra* extra_of(hp_ctx* c);
+
+struct CtxExtra {
+    hp_ctx ctx;
+    Extra ex;
+};
+
+Extra* extra_of(hp_ctx* c) { return &reinterpret_cast<CtxExtra*>(c)->ex; }
+
+Fields full_fields(hp_ctx* c, const double* base) {
+    Fields f{};
+    for (int b = 0; b < 4; ++b) {
+        f.f[b] = const_cast<double*>(base) + c->off[b];
+        f.stride[b] = c->N;
+    }
+    return f;
+}
+
+Fields vel_fields(hp_ctx* c, const double* base, long long stride) {
+    Fields f{};
+    for (int b = 0; b < 3; ++b) {
+        f.f[b] = const_cast<double*>(base) + c->off[b];
+        f.stride[b] = stride;
+    }
+    f.f[3] = nullptr;
+    f.stride[3] = 0;
+    return f;
+}
+
+Fields pres_fields(hp_ctx* c, const double* base, long long stride) {
+    Fields f{};
+    f.f[3] = const_cast<double*>(base);
+    f.stride[3] = stride;
+    return f;
+}
+
+// velocity / pressure views of full vectors
+Fields vel_of_full(hp_ctx* c, const double* base) { return vel_fields(c, base, c->N); }
+Fields pres_of_full(hp_ctx* c, const double* base) {
+    return pres_fields(c, base + c->off[3], c->N);
+}
+
+hp_status check_rhs(hp_ctx* c, int nrhs) {
+    if (!c || nrhs < 1 || nrhs > c->opts.max_rhs) return HP_EINVAL;
+    return HP_OK;
+}
+
+// device copy of strided block data: y_b = a x_b + b y_b for each rhs, per block
+hipError_t fields_axpby(hp_ctx* c, const Fields& x, const Fields& y, double a, double b,
+                        bool vel, bool pres, int nrhs) {
+    for (int blk = vel ? 0 : 3; blk < (pres ? 4 : 3); ++blk) {
+        long long n = c->dims[blk][0] * c->dims[blk][1] * c->dims[blk][2];
+        for (int r = 0; r < nrhs; ++r) {
+            hipError_t e = vec_axpby(c->stream, n, a, x.f[blk] + r * x.stride[blk], b,
+                                     y.f[blk] + r * y.stride[blk]);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+// ---- hyper-power preconditioner (Secs. 2, 4.1) ------------------------------------
+
+// y = P_{V,level}^{-1} x: q^level Richardson steps y <- y + P_{V,0}^{-1}(x - A y)
+// from y = 0, which equals the hyper-power recursion of eq. Pcv (its Neumann
+// form, eq. neumann).  x, y: velocity views; must not alias each other.
+hipError_t apply_PV(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
+                    int prec) {
+    Extra* ex = extra_of(c);
+    hipError_t e = launch_P0(c, x, y, true, false, false, prec, nrhs);
+    if (e != hipSuccess) return e;
+    long long steps = 1;
+    for (int i = 0; i < level; ++i) steps *= q;
+    Fields r = vel_fields(c, ex->hv, c->nV);  // hv slot 0
+    for (long long j = 1; j < steps; ++j) {
+        e = launch_operator(c, OP_A, y, r, -1.0, 1.0, &x, nrhs);  // r = x - A y
+        if (e != hipSuccess) return e;
+        e = launch_P0(c, r, y, true, false, true, prec, nrhs);  // y += P0^{-1} r
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// out = S~_l t = B^T P_{V,l}^{-1} B t  (pressure views)
+hipError_t apply_Stilde(hp_ctx* c, int q, int l, const Fields& t, const Fields& out, int nrhs,
+                        int prec) {
+    Extra* ex = extra_of(c);
+    const long long nV = c->nV;
+    Fields b1 = vel_fields(c, ex->hv + nV * c->opts.max_rhs, nV);       // slot 1
+    Fields b2 = vel_fields(c, ex->hv + 2 * nV * c->opts.max_rhs, nV);   // slot 2
+    hipError_t e = launch_operator(c, OP_B, t, b1, 1.0, 0.0, nullptr, nrhs);
+    if (e != hipSuccess) return e;
+    e = apply_PV(c, q, l, b1, b2, nrhs, prec);
+    if (e != hipSuccess) return e;
+    return launch_operator(c, OP_BT, b2, out, 1.0, 0.0, nullptr, nrhs);
+}
+
+int l_of(const hp_ctx* c, int k) {
+    if (c->opts.l_schedule == HP_L_LITERAL) return k == 1 ? 0 : k;
+    return k - 1;
+}
+
+Fields hq_slot(hp_ctx* c, int level, int slot) {
+    Extra* ex = extra_of(c);
+    const long long nQ = c->nQ, R = c->opts.max_rhs;
+    return pres_fields(c, ex->hq + ((long long)level * 3 + slot) * nQ * R, nQ);
+}
+
+// y = P^_{Q,level}^{-1} x by the literal recursion of eq. Pcq1:
+// X_k = X_{k-1} sum_{i<q} (I - S~_{l(k)} X_{k-1})^i.
+hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
+                     int prec) {
+    if (level == 0) return launch_P0(c, x, y, false, true, false, prec, nrhs);
+    Fields z = hq_slot(c, level, 0), s = hq_slot(c, level, 1), t = hq_slot(c, level, 2);
+    hipError_t e = fields_axpby(c, x, z, 1.0, 0.0, false, true, nrhs);
+    if (e != hipSuccess) return e;
+    e = fields_axpby(c, x, s, 1.0, 0.0, false, true, nrhs);
+    if (e != hipSuccess) return e;
+    const int lv = l_of(c, level);
+    for (int i = 1; i < q; ++i) {
+        e = apply_PQ1(c, q, level - 1, z, t, nrhs, prec);      // t = X_{k-1} z
+        if (e != hipSuccess) return e;
+        e = apply_Stilde(c, q, lv, t, t, nrhs, prec);          // t = S~ t (B reads t first)
+        if (e != hipSuccess) return e;
+        e = fields_axpby(c, t, z, -1.0, 1.0, false, true, nrhs);  // z -= t
+        if (e != hipSuccess) return e;
+        e = fields_axpby(c, z, s, 1.0, 1.0, false, true, nrhs);   // s += z
+        if (e != hipSuccess) return e;
+    }
+    return apply_PQ1(c, q, level - 1, s, y, nrhs, prec);
+}
+
+// y = P_{Q,level}^{-1} x for eq. Pcq2 (fixed S~_0): q^level Richardson steps.
+hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
+                     int prec) {
+    hipError_t e = launch_P0(c, x, y, false, true, false, prec, nrhs);
+    if (e != hipSuccess) return e;
+    long long steps = 1;
+    for (int i = 0; i < level; ++i) steps *= q;
+    Fields t = hq_slot(c, 0, 0);
+    for (long long j = 1; j < steps; ++j) {
+        e = apply_Stilde(c, q, 0, y, t, nrhs, prec);                 // t = S~_0 y
+        if (e != hipSuccess) return e;
+        e = fields_axpby(c, x, t, 1.0, -1.0, false, true, nrhs);    // t = x - t
+        if (e != hipSuccess) return e;
+        e = launch_P0(c, t, y, false, true, true, prec, nrhs);       // y += P_Q0^{-1} t
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs) {
+    const int prec = c->opts.precision;
+    hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+    if (e != hipSuccess) return e;
+    if (c->opts.schur_variant == HP_SCHUR_PCQ2)
+        return apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+    return apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+}
+
+// ---- device memory --------------------------------------------------------------------
+hp_status alloc_device(double** p, size_t doubles) {
+    if (hipMalloc(reinterpret_cast<void**>(p), std::max<size_t>(doubles, 1) * sizeof(double)) !=
+        hipSuccess)
+        return HP_ENOMEM;
+    return HP_OK;
+}
+
+hp_status ensure_krylov(hp_ctx* c, size_t doubles) {
+    Extra* ex = extra_of(c);
+    if (ex->kv_doubles >= doubles) return HP_OK;
+    if (ex->kv) (void)hipFree(ex->kv);
+    ex->kv = nullptr;
+    ex->kv_doubles = 0;
+    hp_status s = alloc_device(&ex->kv, doubles);
+    if (s != HP_OK) return s;
+    ex->kv_doubles = doubles;
+    return HP_OK;
+}
+
+hp_status stage_coef(hp_ctx* c, const std::vector<double>& v) {
+    Extra* ex = extra_of(c);
+    if (v.size() > ex->coef_doubles) return HP_EINVAL;
+    std::memcpy(ex->hcoef, v.data(), v.size() * sizeof(double));
+    if (hipMemcpyAsync(ex->dcoef, ex->hcoef, v.size() * sizeof(double), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess)
+        return HP_EHIP;
+    // the pinned staging buffer is reused: wait until the copy has been consumed
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return HP_EHIP;
+    return HP_OK;
+}
+
+// dots of nrhs pairs over full vectors -> host
+hp_status dots(hp_ctx* c, const double* x, const double* y, int nrhs, std::vector<double>& out) {
+    out.resize(nrhs);
+    if (vec_dots(c, c->N, c->N, x, y, nrhs, out.data()) != hipSuccess) return HP_EHIP;
+    return HP_OK;
+}
+
+// ---- MINRES (preconditioned; Lanczos in the P^{-1} inner product) ------------------
+hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp_solve_info* info) {
+    const long long N = c->N;
+    const long long V = N * nrhs;
+    if (ensure_krylov(c, 9 * N * (size_t)c->opts.max_rhs) != HP_OK) return HP_ENOMEM;
+    double* base = extra_of(c)->kv;
+    double* vo = base;
+    double* v = base + V;
+    double* vn = base + 2 * V;
+    double* z = base + 3 * V;
+    double* zn = base + 4 * V;
+    double* wo = base + 5 * V;
+    double* w = base + 6 * V;
+    double* wn = base + 7 * V;
+    double* Kz = base + 8 * V;
+    const int q = c->opts.order, k = c->opts.iters;
+    HIPCHK(vec_zero(c->stream, V, x));
+    HIPCHK(vec_zero(c->stream, V, vo));
+    HIPCHK(vec_zero(c->stream, V, wo));
+    HIPCHK(vec_zero(c->stream, V, w));
+    HIPCHK(vec_copy(c->stream, V, b, v));
+    HIPCHK(apply_Pk(c, q, k, v, z, nrhs));
+    std::vector<double> zv, dl;
+    if (dots(c, z, v, nrhs, zv) != HP_OK) return HP_EHIP;
+    std::vector<double> gamma(nrhs), gamma_old(nrhs, 1.0), beta0(nrhs), eta(nrhs), c0(nrhs, 1.0),
+        c1(nrhs, 1.0), s0(nrhs, 0.0), s1(nrhs, 0.0), rel(nrhs, 1.0);
+    std::vector<int> done(nrhs, 0), iters(nrhs, 0);
+    for (int r = 0; r < nrhs; ++r) {
+        if (!(zv[r] >= 0.0) || !std::isfinite(zv[r])) return zv[r] < 0 ? HP_ENOTSPD : HP_ENAN;
+        gamma[r] = std::sqrt(zv[r]);
+        beta0[r] = gamma[r];
+        eta[r] = gamma[r];
+        if (gamma[r] == 0.0) done[r] = 1, rel[r] = 0.0;
+    }
+    hp_status status = HP_OK;
+    int it = 0;
+    std::vector<double> cf(4 * nrhs);
+    auto all_done = [&]() {
+        for (int r = 0; r < nrhs; ++r)
+            if (!done[r]) return false;
+        return true;
+    };
+    while (!all_done() && it < c->opts.maxit) {
+        ++it;
+        HIPCHK(launch_operator(c, OP_K, full_fields(c, z), full_fields(c, Kz), 1.0, 0.0, nullptr,
+                               nrhs));
+        if (dots(c, Kz, z, nrhs, dl) != HP_OK) return HP_EHIP;
+        std::vector<double> delta(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            delta[r] = done[r] ? 0.0 : dl[r] / (gamma[r] * gamma[r]);
+            cf[3 * r + 0] = done[r] ? 0.0 : 1.0 / gamma[r];
+            cf[3 * r + 1] = done[r] ? 0.0 : -delta[r] / gamma[r];
+            cf[3 * r + 2] = done[r] ? 0.0 : -gamma[r] / gamma_old[r];
+        }
+        std::vector<double> cc(cf.begin(), cf.begin() + 3 * nrhs);
+        if (stage_coef(c, cc) != HP_OK) return HP_EHIP;
+        {
+            const double* xs[3] = {Kz, v, vo};
+            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 3, xs, extra_of(c)->dcoef, vn));
+        }
+        HIPCHK(apply_Pk(c, q, k, vn, zn, nrhs));
+        if (dots(c, zn, vn, nrhs, zv) != HP_OK) return HP_EHIP;
+        std::vector<double> wc(3 * nrhs), xc(2 * nrhs);
+        std::vector<double> gnew(nrhs), cn(nrhs), sn(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            if (done[r]) {
+                wc[3 * r] = wc[3 * r + 1] = wc[3 * r + 2] = 0.0;
+                xc[2 * r] = 1.0;
+                xc[2 * r + 1] = 0.0;
+                gnew[r] = gamma[r];
+                cn[r] = c1[r];
+                sn[r] = s1[r];
+                continue;
+            }
+            if (!std::isfinite(zv[r])) return HP_ENAN;
+            if (zv[r] < 0.0) { status = HP_ENOTSPD; zv[r] = 0.0; }
+            gnew[r] = std::sqrt(zv[r]);
+            double g = gamma[r];
+            double a0 = c1[r] * delta[r] - c0[r] * s1[r] * g;
+            double a1 = std::hypot(a0, gnew[r]);
+            double a2 = s1[r] * delta[r] + c0[r] * c1[r] * g;
+            double a3 = s0[r] * g;
+            if (a1 == 0.0) return HP_EBREAKDOWN;
+            cn[r] = a0 / a1;
+            sn[r] = gnew[r] / a1;
+            wc[3 * r + 0] = 1.0 / (g * a1);
+            wc[3 * r + 1] = -a3 / a1;
+            wc[3 * r + 2] = -a2 / a1;
+            xc[2 * r + 0] = 1.0;
+            xc[2 * r + 1] = cn[r] * eta[r];
+        }
+        if (stage_coef(c, wc) != HP_OK) return HP_EHIP;
+        {
+            const double* xs[3] = {z, wo, w};
+            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 3, xs, extra_of(c)->dcoef, wn));
+        }
+        if (stage_coef(c, xc) != HP_OK) return HP_EHIP;
+        {
+            const double* xs[2] = {x, wn};
+            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 2, xs, extra_of(c)->dcoef, x));
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            if (done[r]) continue;
+            eta[r] = -sn[r] * eta[r];
+            gamma_old[r] = gamma[r];
+            gamma[r] = gnew[r];
+            c0[r] = c1[r];
+            c1[r] = cn[r];
+            s0[r] = s1[r];
+            s1[r] = sn[r];
+            rel[r] = std::fabs(eta[r]) / beta0[r];
+            iters[r] = it;
+            if (rel[r] <= tol || gnew[r] == 0.0) done[r] = 1;
+        }
+        if (status == HP_ENOTSPD) break;
+        // rotate buffers
+        std::swap(vo, v);
+        std::swap(v, vn);  // v <- vn, vn <- old vo (free)
+        std::swap(z, zn);
+        std::swap(wo, w);
+        std::swap(w, wn);
+    }
+    if (info) {
+        info->iterations = 0;
+        info->relres = 0.0;
+        info->converged = 1;
+        for (int r = 0; r < nrhs; ++r) {
+            info->iterations = std::max(info->iterations, iters[r]);
+            info->relres = std::max(info->relres, rel[r]);
+            if (!done[r]) info->converged = 0;
+            if (r < 64) info->iters_per_rhs[r] = iters[r];
+        }
+    }
+    if (status != HP_OK) return status;
+    return all_done() ? HP_OK : HP_ENOCONV;
+}
+
+// ---- FGMRES(m), right preconditioned, CGS2 Arnoldi -----------------------------------
+hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp_solve_info* info) {
+    const long long N = c->N;
+    const int m = std::max(1, std::min(c->opts.restart, 128));
+    const long long V = N * nrhs;
+    if (ensure_krylov(c, (size_t)(2 * m + 2) * N * c->opts.max_rhs) != HP_OK) return HP_ENOMEM;
+    double* Vb = extra_of(c)->kv;            // (m+1) x V
+    double* Zb = Vb + (long long)(m + 1) * V;  // m x V
+    double* w = Zb + (long long)m * V;        // V
+    const int q = c->opts.order, k = c->opts.iters;
+    double* partial = c->d_red;
+    double* dres = c->d_red + vec_partial_doubles(m + 1, nrhs);
+    HIPCHK(vec_zero(c->stream, V, x));
+    std::vector<double> bn;
+    if (dots(c, b, b, nrhs, bn) != HP_OK) return HP_EHIP;
+    for (auto& t : bn) t = std::sqrt(t);
+    std::vector<int> done(nrhs, 0), iters(nrhs, 0);
+    std::vector<double> rel(nrhs, 1.0);
+    for (int r = 0; r < nrhs; ++r)
+        if (bn[r] == 0.0) done[r] = 1, rel[r] = 0.0;
+    int total = 0;
+    auto all_done = [&]() {
+        for (int r = 0; r < nrhs; ++r)
+            if (!done[r]) return false;
+        return true;
+    };
+    std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
+        g((size_t)nrhs * (m + 1));
+    std::vector<int> jr(nrhs);
+    std::vector<double> hv((size_t)nrhs * (m + 1)), h2((size_t)nrhs * (m + 1));
+    auto fetch = [&](int cnt, std::vector<double>& out) -> hp_status {
+        out.resize((size_t)nrhs * cnt);
+        if (hipMemcpyAsync(c->h_red, dres, sizeof(double) * nrhs * cnt, hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess)
+            return HP_EHIP;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return HP_EHIP;
+        std::memcpy(out.data(), c->h_red, sizeof(double) * nrhs * cnt);
+        return HP_OK;
+    };
+    while (!all_done() && total < c->opts.maxit) {
+        // r = b - K x ; V0 = r / ||r||
+        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr,
+                               nrhs));
+        HIPCHK(vec_axpby(c->stream, V, 1.0, b, -1.0, w));
+        std::vector<double> rn;
+        if (dots(c, w, w, nrhs, rn) != HP_OK) return HP_EHIP;
+        std::vector<double> sc(nrhs);
+        for (int r = 0; r < nrhs; ++r) {
+            rn[r] = std::sqrt(rn[r]);
+            sc[r] = (done[r] || rn[r] == 0.0) ? 0.0 : 1.0 / rn[r];
+            g[(size_t)r * (m + 1)] = done[r] ? 0.0 : rn[r];
+            for (int i = 1; i <= m; ++i) g[(size_t)r * (m + 1) + i] = 0.0;
+            jr[r] = 0;
+        }
+        if (stage_coef(c, sc) != HP_OK) return HP_EHIP;
+        {
+            const double* xs[1] = {w};
+            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, extra_of(c)->dcoef, Vb));
+        }
+        std::vector<int> active(nrhs);
+        for (int r = 0; r < nrhs; ++r) active[r] = !done[r];
+        int j = 0;
+        for (; j < m && total < c->opts.maxit; ++j) {
+            double* Vj = Vb + (long long)j * V;
+            double* Zj = Zb + (long long)j * V;
+            HIPCHK(apply_Pk(c, q, k, Vj, Zj, nrhs));
+            HIPCHK(launch_operator(c, OP_K, full_fields(c, Zj), full_fields(c, w), 1.0, 0.0,
+                                   nullptr, nrhs));
+            // CGS2: two passes of classical Gram-Schmidt
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(vec_multidot_async(c->stream, N, N, Vb, V, j + 1, w, nrhs, partial, dres));
+                std::vector<double>& hh = pass == 0 ? hv : h2;
+                if (fetch(j + 1, hh) != HP_OK) return HP_EHIP;
+                if (stage_coef(c, hh) != HP_OK) return HP_EHIP;
+                HIPCHK(vec_sub_combo(c->stream, N, N, Vb, V, j + 1, extra_of(c)->dcoef, j + 1,
+                                     nrhs, w));
+            }
+            std::vector<double> wn;
+            if (dots(c, w, w, nrhs, wn) != HP_OK) return HP_EHIP;
+            std::vector<double> sc2(nrhs);
+            ++total;
+            for (int r = 0; r < nrhs; ++r) {
+                double hn = std::sqrt(wn[r]);
+                sc2[r] = (active[r] && hn > 0.0) ? 1.0 / hn : 0.0;
+                if (!active[r]) continue;
+                double* Hr = H.data() + (size_t)r * (m + 1) * m;
+                double* gr = g.data() + (size_t)r * (m + 1);
+                for (int i = 0; i <= j; ++i)
+                    Hr[i * m + j] = hv[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
+                Hr[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    double c_ = cs[(size_t)r * m + i], s_ = sn[(size_t)r * m + i];
+                    double t = c_ * Hr[i * m + j] + s_ * Hr[(i + 1) * m + j];
+                    Hr[(i + 1) * m + j] = -s_ * Hr[i * m + j] + c_ * Hr[(i + 1) * m + j];
+                    Hr[i * m + j] = t;
+                }
+                double d = std::hypot(Hr[j * m + j], Hr[(j + 1) * m + j]);
+                if (d == 0.0) return HP_EBREAKDOWN;
+                cs[(size_t)r * m + j] = Hr[j * m + j] / d;
+                sn[(size_t)r * m + j] = Hr[(j + 1) * m + j] / d;
+                Hr[j * m + j] = d;
+                Hr[(j + 1) * m + j] = 0.0;
+                gr[j + 1] = -sn[(size_t)r * m + j] * gr[j];
+                gr[j] = cs[(size_t)r * m + j] * gr[j];
+                jr[r] = j + 1;
+                iters[r] = total;
+                rel[r] = std::fabs(gr[j + 1]) / bn[r];
+                if (rel[r] <= tol || hn == 0.0) active[r] = 0;
+            }
+            bool any = false;
+            for (int r = 0; r < nrhs; ++r) any = any || active[r];
+            if (!any) { ++j; break; }
+            if (stage_coef(c, sc2) != HP_OK) return HP_EHIP;
+            {
+                const double* xs[1] = {w};
+                HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, extra_of(c)->dcoef,
+                                   Vb + (long long)(j + 1) * V));
+            }
+        }
+        // x += Z y with H y = g (per rhs, first jr[r] columns)
+        int jmax = 0;
+        for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jr[r]);
+        if (jmax > 0) {
+            std::vector<double> y((size_t)nrhs * jmax, 0.0);
+            for (int r = 0; r < nrhs; ++r) {
+                int jj = jr[r];
+                const double* Hr = H.data() + (size_t)r * (m + 1) * m;
+                const double* gr = g.data() + (size_t)r * (m + 1);
+                for (int i = jj - 1; i >= 0; --i) {
+                    double s = gr[i];
+                    for (int l = i + 1; l < jj; ++l) s -= Hr[i * m + l] * y[(size_t)r * jmax + l];
+                    y[(size_t)r * jmax + i] = s / Hr[i * m + i];
+                }
+            }
+            if (stage_coef(c, y) != HP_OK) return HP_EHIP;
+            HIPCHK(vec_add_combo(c->stream, N, N, Zb, V, jmax, extra_of(c)->dcoef, jmax, nrhs, x));
+        }
+        // confirm with the true residual
+        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr,
+                               nrhs));
+        HIPCHK(vec_axpby(c->stream, V, 1.0, b, -1.0, w));
+        std::vector<double> tr;
+        if (dots(c, w, w, nrhs, tr) != HP_OK) return HP_EHIP;
+        for (int r = 0; r < nrhs; ++r) {
+            if (done[r]) continue;
+            rel[r] = std::sqrt(tr[r]) / bn[r];
+            if (rel[r] <= tol) done[r] = 1;
+        }
+    }
+    if (info) {
+        info->iterations = 0;
+        info->relres = 0.0;
+        info->converged = 1;
+        for (int r = 0; r < nrhs; ++r) {
+            info->iterations = std::max(info->iterations, iters[r]);
+            info->relres = std::max(info->relres, rel[r]);
+            if (!done[r]) info->converged = 0;
+            if (r < 64) info->iters_per_rhs[r] = iters[r];
+        }
+    }
+    return all_done() ? HP_OK : HP_ENOCONV;
+}
+
+// ---- right-hand side -------------------------------------------------------------------
+hp_status build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp, const int* waves,
+                    double* b, int nrhs) {
+    const Tables1D& T = c->tab;
+    const int nN = c->nN, nM = c->nM;
+    // per (rhs, component): factors s1, s2, s3 (each nt terms) assembled on the host
+    // from 1D quadrature; the 3D sums run on the device.
+    const int nt = nmodes + 1;
+    const int nmax = std::max(nN, nM);
+    std::vector<double> hs((size_t)3 * nt * nmax);
+    double* ds = nullptr;
+    if (alloc_device(&ds, hs.size()) != HP_OK) return HP_ENOMEM;
+    hp_status st = HP_OK;
+    HIPCHK(vec_zero(c->stream, c->N * nrhs, b));
+    for (int r = 0; r < nrhs && st == HP_OK; ++r) {
+        for (int comp = 0; comp < 3; ++comp) {
+            int n[3];
+            for (int d = 0; d < 3; ++d) n[d] = (int)c->dims[comp][d];
+            std::fill(hs.begin(), hs.end(), 0.0);
+            int cnt = 0;
+            double* s1 = hs.data();
+            double* s2 = s1 + (size_t)nt * nmax;
+            double* s3 = s2 + (size_t)nt * nmax;
+            if (comp == 0 && lid && lid[r] != 0.0) {
+                // F_u1 = 2 nu U (int N) (x) (int M) (x) (alpha M(1) - M'(1)/2)
+                for (int i = 0; i < nN; ++i) s1[cnt * n[0] + i] = T.int_N[i];
+                for (int i = 0; i < nM; ++i) s2[cnt * n[1] + i] = T.int_M[i];
+                for (int i = 0; i < nM; ++i) s3[cnt * n[2] + i] = 2.0 * c->nu * lid[r] * T.lid3[i];
+                ++cnt;
+            }
+            for (int mo = 0; mo < nmodes; ++mo) {
+                size_t id = ((size_t)r * 3 + comp) * nmodes + mo;
+                double a = amp[id];
+                if (a == 0.0) continue;
+                double* dst[3] = {s1 + (size_t)cnt * n[0], s2 + (size_t)cnt * n[1],
+                                  s3 + (size_t)cnt * n[2]};
+                for (int d = 0; d < 3; ++d) {
+                    std::vector<double> l = sine_load(T, d == comp ? 0 : 1, waves[id * 3 + d]);
+                    for (int i = 0; i < n[d]; ++i) dst[d][i] = (d == 2 ? a : 1.0) * l[i];
+                }
+                ++cnt;
+            }
+            if (cnt == 0) continue;
+            // pack contiguously: s1 (cnt x n0), s2 (cnt x n1), s3 (cnt x n2)
+            std::vector<double> pk;
+            pk.insert(pk.end(), s1, s1 + (size_t)cnt * n[0]);
+            pk.insert(pk.end(), s2, s2 + (size_t)cnt * n[1]);
+            pk.insert(pk.end(), s3, s3 + (size_t)cnt * n[2]);
+            if (hipMemcpyAsync(ds, pk.data(), pk.size() * sizeof(double), hipMemcpyHostToDevice,
+                               c->stream) != hipSuccess) { st = HP_EHIP; break; }
+            if (rank1_sum(c->stream, n[0], n[1], n[2], cnt, ds, ds + (size_t)cnt * n[0],
+                          ds + (size_t)cnt * (n[0] + n[1]), b + r * c->N + c->off[comp]) !=
+                hipSuccess) { st = HP_EHIP; break; }
+            if (hipStreamSynchronize(c->stream) != hipSuccess) { st = HP_EHIP; break; }
+        }
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(ds);
+    return st;
+}
+
+static void upload_band(const std::vector<double>& A, int n, int w, double* dst) {
+    const int W = 2 * w + 1;
+    std::vector<double> b((size_t)n * W, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int t = 0; t < W; ++t) {
+            int j = i + t - w;
+            if (j >= 0 && j < n) b[(size_t)i * W + t] = A[(size_t)i * n + j];
+        }
+    (void)hipMemcpy(dst, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice);
+}
+
+template <typename T>
+static std::vector<T> padded(const std::vector<double>& A, int n, int np, bool transpose) {
+    std::vector<T> out((size_t)np * np, (T)0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            out[(size_t)i * np + j] = (T)(transpose ? A[(size_t)j * n + i] : A[(size_t)i * n + j]);
+    return out;
+}
+
+}  // namespace
+
+// =====================================================================================
+extern "C" {
+
+void hp_default_opts(hp_opts* o) {
+    if (!o) return;
+    o->c_pen = 12.5;
+    o->schur_variant = HP_SCHUR_PCQ1;
+    o->l_schedule = HP_L_LITERAL;
+    o->precision = HP_PREC_FP64;
+    o->krylov = HP_MINRES;
+    o->restart = 50;
+    o->maxit = 1000;
+    o->order = 2;
+    o->iters = 1;
+    o->max_rhs = 1;
+    o->check_every = 6;
+    o->use_graph = 1;
+}
+
+const char* hp_status_string(hp_status s) {
+    switch (s) {
+        case HP_OK: return "ok";
+        case HP_EINVAL: return "invalid argument";
+        case HP_EHIP: return "HIP runtime error";
+        case HP_ENOMEM: return "out of device memory";
+        case HP_ENOTSPD: return "preconditioner not positive definite";
+        case HP_EBREAKDOWN: return "Krylov breakdown";
+        case HP_ENOCONV: return "not converged within maxit";
+        case HP_ENAN: return "NaN or Inf encountered";
+    }
+    return "unknown status";
+}
+
+hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, void* stream,
+                   hp_ctx** out) {
+    if (!out) return HP_EINVAL;
+    *out = nullptr;
+    if (elements < 1 || degree < 2 || degree > 4 || !(nu > 0.0)) return HP_EINVAL;
+    hp_opts o;
+    hp_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen > 0.0) ||
+        o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
+        o.restart < 1 || o.maxit < 1)
+        return HP_EINVAL;
+    const int nM = elements + degree - 1;
+    if (pad16(nM) > 128) return HP_EINVAL;  // fast-diagonalisation tiles hold <= 128 per direction
+    if (ops_init_attributes() != hipSuccess || fd_init_attributes() != hipSuccess) return HP_EHIP;
+    CtxExtra* ce = new (std::nothrow) CtxExtra();
+    if (!ce) return HP_ENOMEM;
+    hp_ctx* c = &ce->ctx;
+    c->opts = o;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete ce; return HP_EHIP; }
+    c->E = elements;
+    c->p = degree;
+    c->nu = nu;
+    try {
+        c->tab = build_tables(elements, degree, o.c_pen);
+    } catch (...) {
+        delete ce;
+        return HP_EINVAL;
+    }
+    const int nN = c->tab.nN;
+    c->nN = nN;
+    c->nM = nM;
+    long long d[4][3] = {{nN, nM, nM}, {nM, nN, nM}, {nM, nM, nN}, {nM, nM, nM}};
+    std::memcpy(c->dims, d, sizeof(d));
+    c->off[0] = 0;
+    for (int b = 0; b < 4; ++b) c->off[b + 1] = c->off[b] + d[b][0] * d[b][1] * d[b][2];
+    c->nV = c->off[3];
+    c->nQ = c->off[4] - c->off[3];
+    c->N = c->off[4];
+    // ---- tables
+    const int p = degree, wN = p, wM = p - 1;
+    const int NNp = pad16(nN), NMp = pad16(nM);
+    size_t nb = (size_t)2 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
+    size_t nfd = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM;
+    if (alloc_device(&c->d_tables, nb + nfd) != HP_OK) { delete ce; return HP_ENOMEM; }
+    double* tp = c->d_tables;
+    c->band.ptr[BK_N] = tp; upload_band(c->tab.K_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
+    c->band.ptr[BM_N] = tp; upload_band(c->tab.M_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
+    c->band.ptr[BM_C] = tp; upload_band(c->tab.Mc, nM, wM, tp); tp += (size_t)nM * (2 * wM + 1);
+    c->band.ptr[BT_C] = tp; upload_band(c->tab.Tc, nM, wM, tp); tp += (size_t)nM * (2 * wM + 1);
+    c->band.n[BK_N] = c->band.n[BM_N] = nN;
+    c->band.n[BM_C] = c->band.n[BT_C] = nM;
+    c->band.w[BK_N] = c->band.w[BM_N] = wN;
+    c->band.w[BM_C] = c->band.w[BT_C] = wM;
+    auto up64 = [&](const std::vector<double>& v) {
+        (void)hipMemcpy(tp, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);
+        const double* r = tp;
+        tp += v.size();
+        return r;
+    };
+    c->fd64.UK = up64(padded<double>(c->tab.UK, nN, NNp, false));
+    c->fd64.UKt = up64(padded<double>(c->tab.UK, nN, NNp, true));
+    c->fd64.UT = up64(padded<double>(c->tab.UT, nM, NMp, false));
+    c->fd64.UTt = up64(padded<double>(c->tab.UT, nM, NMp, true));
+    c->fd64.Mi = up64(padded<double>(c->tab.Mcinv, nM, NMp, false));
+    c->fd64.lamK = up64(c->tab.lamK);
+    c->fd64.lamT = up64(c->tab.lamT);
+    c->fd64.nN = nN; c->fd64.nM = nM; c->fd64.NNp = NNp; c->fd64.NMp = NMp;
+    // FP32 copies of the dense FD tables
+    size_t n32 = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp;
+    if (hipMalloc(reinterpret_cast<void**>(&c->d_tables32), n32 * sizeof(float)) != hipSuccess) {
+        hp_destroy(c);
+        return HP_ENOMEM;
+    }
+    float* fp = c->d_tables32;
+    auto up32 = [&](const std::vector<float>& v) {
+        (void)hipMemcpy(fp, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice);
+        const float* r = fp;
+        fp += v.size();
+        return r;
+    };
+    c->fd32.UK = up32(padded<float>(c->tab.UK, nN, NNp, false));
+    c->fd32.UKt = up32(padded<float>(c->tab.UK, nN, NNp, true));
+    c->fd32.UT = up32(padded<float>(c->tab.UT, nM, NMp, false));
+    c->fd32.UTt = up32(padded<float>(c->tab.UT, nM, NMp, true));
+    c->fd32.Mi = up32(padded<float>(c->tab.Mcinv, nM, NMp, false));
+    c->fd32.lamK = c->fd64.lamK;
+    c->fd32.lamT = c->fd64.lamT;
+    c->fd32.nN = nN; c->fd32.nM = nM; c->fd32.NNp = NNp; c->fd32.NMp = NMp;
+    // ---- workspace: operator intermediates + FD temporaries
+    const long long R = o.max_rhs;
+    c->ws_doubles = (size_t)((2 * c->nV + 3 * c->nQ) + 2 * c->N) * R;
+    if (alloc_device(&c->ws, c->ws_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    Extra* ex = &ce->ex;
+    if (alloc_device(&ex->hv, (size_t)3 * c->nV * R) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (alloc_device(&ex->hq, (size_t)3 * c->nQ * R * (KMAX + 1)) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    ex->coef_doubles = (size_t)std::max(4, 132) * R;
+    if (alloc_device(&ex->dcoef, ex->coef_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (hipHostMalloc(reinterpret_cast<void**>(&ex->hcoef), ex->coef_doubles * sizeof(double)) != hipSuccess) {
+        hp_destroy(c);
+        return HP_ENOMEM;
+    }
+    c->red_slots = (int)(vec_partial_doubles(130, (int)R) + 130 * R);
+    if (alloc_device(&c->d_red, c->red_slots) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), 130 * R * sizeof(double)) != hipSuccess) {
+        hp_destroy(c);
+        return HP_ENOMEM;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) { hp_destroy(c); return HP_EHIP; }
+    *out = c;
+    return HP_OK;
+}
+
+hp_status hp_set_nu(hp_ctx* c, double nu) {
+    if (!c || !(nu > 0.0)) return HP_EINVAL;
+    c->nu = nu;
+    return HP_OK;
+}
+
+hp_status hp_sizes(const hp_ctx* c, int64_t dims[4][3], int64_t offsets[5]) {
+    if (!c) return HP_EINVAL;
+    for (int b = 0; b < 4; ++b)
+        for (int d = 0; d < 3; ++d)
+            if (dims) dims[b][d] = c->dims[b][d];
+    for (int b = 0; b < 5; ++b)
+        if (offsets) offsets[b] = c->off[b];
+    return HP_OK;
+}
+
+hp_status hp_apply_K(hp_ctx* c, const double* x, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y) return HP_EINVAL;
+    HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, y), 1.0, 0.0, nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_A(hp_ctx* c, const double* u, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !u || !y || u == y) return HP_EINVAL;
+    HIPCHK(launch_operator(c, OP_A, vel_fields(c, u, c->nV), vel_fields(c, y, c->nV), 1.0, 0.0,
+                           nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_B(hp_ctx* c, const double* p, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !p || !y) return HP_EINVAL;
+    HIPCHK(launch_operator(c, OP_B, pres_fields(c, p, c->nQ), vel_fields(c, y, c->nV), 1.0, 0.0,
+                           nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_Bt(hp_ctx* c, const double* u, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !u || !y) return HP_EINVAL;
+    HIPCHK(launch_operator(c, OP_BT, vel_fields(c, u, c->nV), pres_fields(c, y, c->nQ), 1.0, 0.0,
+                           nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_MV(hp_ctx* c, const double* u, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !u || !y || u == y) return HP_EINVAL;
+    HIPCHK(launch_operator(c, OP_MV, vel_fields(c, u, c->nV), vel_fields(c, y, c->nV), 1.0, 0.0,
+                           nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_P0(hp_ctx* c, const double* x, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y) return HP_EINVAL;
+    HIPCHK(launch_P0(c, full_fields(c, x), full_fields(c, y), true, true, false, c->opts.precision,
+                     nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_hyperpower(hp_ctx* c, int order, int iters, const double* x, double* y,
+                              int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y || order < 2 || iters < 0 ||
+        iters > KMAX)
+        return HP_EINVAL;
+    HIPCHK(apply_Pk(c, order, iters, x, y, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
+                   hp_solve_info* info) {
+    if (check_rhs(c, nrhs) != HP_OK || !b || !x || b == x || !(tol > 0.0)) return HP_EINVAL;
+    if (c->opts.krylov == HP_MINRES && c->opts.precision != HP_PREC_FP64) return HP_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    hp_solve_info loc{};
+    hp_status s = c->opts.krylov == HP_MINRES ? minres(c, b, x, nrhs, tol, &loc)
+                                              : fgmres(c, b, x, nrhs, tol, &loc);
+    if (s == HP_EHIP || s == HP_ENOMEM) return s;
+    // true residual ||b - K x|| / ||b||
+    double* w = c->ws + (2 * c->nV + 3 * c->nQ) * (long long)c->opts.max_rhs;  // FD scratch, N * nrhs
+    if (launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs) !=
+            hipSuccess ||
+        vec_axpby(c->stream, c->N * nrhs, 1.0, b, -1.0, w) != hipSuccess)
+        return HP_EHIP;
+    std::vector<double> rr, bb;
+    if (dots(c, w, w, nrhs, rr) != HP_OK || dots(c, b, b, nrhs, bb) != HP_OK) return HP_EHIP;
+    loc.true_relres = 0.0;
+    for (int r = 0; r < nrhs; ++r)
+        loc.true_relres = std::max(loc.true_relres, bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0);
+    loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = loc;
+    return s;
+}
+
+hp_status hp_build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp,
+                       const int* waves, double* b, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !b || nmodes < 0 || (nmodes > 0 && (!amp || !waves)))
+        return HP_EINVAL;
+    return build_rhs(c, lid, nmodes, amp, waves, b, nrhs);
+}
+
+hp_status hp_grad(hp_ctx* c, const double* x, const double* lambda, const double* lid,
+                  double* dL_dbeta, double* dL_dnu, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !x || !lambda || !dL_dbeta || !dL_dnu) return HP_EINVAL;
+    // dL/dbeta = M_V lambda_u
+    HIPCHK(launch_operator(c, OP_MV, vel_of_full(c, lambda), vel_fields(c, dL_dbeta, c->nV), 1.0,
+                           0.0, nullptr, nrhs));
+    // dL/dnu = lambda_u . (F_lid - A u) / nu ; F_lid into t (full), A u into its velocity part
+    double* t = c->ws + (2 * c->nV + 3 * c->nQ) * (long long)c->opts.max_rhs;  // N * nrhs scratch
+    hp_status s = build_rhs(c, lid, 0, nullptr, nullptr, t, nrhs);
+    if (s != HP_OK) return s;
+    const Fields tv = vel_of_full(c, t);
+    HIPCHK(launch_operator(c, OP_A, vel_of_full(c, x), tv, -1.0, 1.0, &tv, nrhs));
+    std::vector<double> d(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        double out = 0.0;
+        if (vec_dots(c, c->nV, c->N, lambda + r * c->N, t + r * c->N, 1, &out) != hipSuccess)
+            return HP_EHIP;
+        dL_dnu[r] = out / c->nu;
+    }
+    return HP_OK;
+}
+
+void hp_destroy(hp_ctx* c) {
+    if (!c) return;
+    CtxExtra* ce = reinterpret_cast<CtxExtra*>(c);
+    Extra* ex = &ce->ex;
+    (void)hipDeviceSynchronize();
+    if (c->d_tables) (void)hipFree(c->d_tables);
+    if (c->d_tables32) (void)hipFree(c->d_tables32);
+    if (c->ws) (void)hipFree(c->ws);
+    if (c->d_red) (void)hipFree(c->d_red);
+    if (c->h_red) (void)hipHostFree(c->h_red);
+    if (ex->hv) (void)hipFree(ex->hv);
+    if (ex->hq) (void)hipFree(ex->hq);
+    if (ex->kv) (void)hipFree(ex->kv);
+    if (ex->dcoef) (void)hipFree(ex->dcoef);
+    if (ex->hcoef) (void)hipHostFree(ex->hcoef);
+    delete ce;
+}
+
+}  // extern "C"

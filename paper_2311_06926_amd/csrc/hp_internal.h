@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP sources of the solver library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/hyperpower.h"
+#include "setup1d.h"
+
+namespace hp {
+
+// Banded symmetric 1D matrices used by the sum-factorised operators.
+// Row i of band matrix `id` holds A[i][i-w .. i+w] (zeros outside range).
+enum BandId { BK_N = 0, BM_N = 1, BM_C = 2, BT_C = 3, NBAND = 4 };
+
+struct BandTables {
+    const double* ptr[NBAND];  // device pointers, row-major n x (2w+1)
+    int n[NBAND];
+    int w[NBAND];
+};
+
+// Dense (padded) matrices for fast diagonalisation on MFMA tiles.
+template <typename T>
+struct FDTables {
+    const T* UK;   // interior degree-p eigenvectors, NNp x NNp row-major (U)
+    const T* UKt;  // U^T
+    const T* UT;   // degree p-1 eigenvectors of (T^, M^)
+    const T* UTt;
+    const T* Mi;   // M^^{-1}, NMp x NMp
+    const double* lamK;  // nN eigenvalues
+    const double* lamT;  // nM eigenvalues
+    int nN, nM, NNp, NMp;
+};
+
+// A set of pointers to the four blocks of one (batched) vector.
+struct Fields {
+    double* f[4];       // u1, u2, u3, p (any may be null when unused)
+    long long stride[4];  // distance between right-hand sides, per block
+};
+
+struct Workspace {
+    double* base = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace hp
+
+struct hp_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hp_opts opts{};
+    int E = 0, p = 0, nN = 0, nM = 0;
+    double nu = 1.0;
+    long long dims[4][3]{};
+    long long off[5]{};
+    long long nV = 0, nQ = 0, N = 0;
+    hp::Tables1D tab;
+    // device tables
+    double* d_tables = nullptr;  // one allocation for bands + FD tables
+    float* d_tables32 = nullptr;
+    hp::BandTables band{};
+    hp::FDTables<double> fd64{};
+    hp::FDTables<float> fd32{};
+    // workspace (per right-hand side sizes scale with max_rhs)
+    double* ws = nullptr;
+    size_t ws_doubles = 0;
+    // reduction scratch
+    double* d_red = nullptr;
+    double* h_red = nullptr;  // pinned host mirror
+    int red_slots = 0;
+};
+
+namespace hp {
+
+// ---- operator kernels (ops.hip) -------------------------------------------
+// Modes of the sum-factorised operator:
+//  OP_K  : y_u = nu L u + D^T M_q (nu D u + p), y_p = M_q D u
+//  OP_A  : y_u = nu L u + D^T M_q (nu D u)
+//  OP_B  : y_u = D^T M_q p
+//  OP_BT : y_p = M_q D u
+//  OP_MV : y_u = M_V u (velocity mass matrix)
+enum OpMode { OP_K = 0, OP_A = 1, OP_B = 2, OP_BT = 3, OP_MV = 4 };
+
+// y_u := alpha * (op result) + beta * src_u  (src_u may alias y_u);
+// y_p := op result.
+hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Fields& out,
+                           double alpha, double beta, const Fields* src, int nrhs);
+
+hipError_t ops_init_attributes();
+
+// ---- fast diagonalisation (fd.hip) -----------------------------------------
+hipError_t fd_init_attributes();
+// y = P_0^{-1} x restricted to the selected blocks (velocity and/or pressure);
+// accumulate: y += result instead of y = result.
+hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
+                     bool accumulate, int precision, int nrhs);
+
+// ---- vector kernels (krylov.hip) ----------------------------------------------
+hipError_t vec_axpby(hipStream_t s, long long n, double a, const double* x, double b,
+                     double* y);  // y = a x + b y
+hipError_t vec_copy(hipStream_t s, long long n, const double* x, double* y);
+hipError_t vec_zero(hipStream_t s, long long n, double* y);
+// dot products of nrhs pairs of vectors (stride ld), results to host `out`
+hipError_t vec_dots(hp_ctx* c, long long n, long long ld, const double* x, const double* y,
+                    int nrhs, double* out);
+
+}  // namespace hp

@@ -1,0 +1,238 @@
+// Vector kernels for the Krylov solvers: fused linear combinations with
+// per-right-hand-side coefficients and deterministic dot products (fixed
+// grid, fixed reduction order: a wave64 shuffle tree, then an LDS tree, then
+// one ordered pass over the per-block partials), plus the right-hand-side
+// assembly of the cavity (Sec. 5).
+#include "hp_internal.h"
+#include "vec.h"
+
+namespace hp {
+
+namespace {
+
+constexpr int VT = 256;
+constexpr int DOT_BLOCKS = 240;  // partial sums per (pair, rhs)
+
+__global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b,
+                        double* __restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+__global__ void k_copy(long long n, const double* __restrict__ x, double* __restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = x[i];
+}
+
+__global__ void k_fill(long long n, double v, double* __restrict__ y) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) y[i] = v;
+}
+
+// y_r = sum_t coef[r*nt + t] * x_t[r*ld + i]  (up to 4 terms; y may alias one x_t)
+struct LinArgs {
+    const double* x[4];
+    double* y;
+    const double* coef;
+    int nt;
+    long long n, ld;
+};
+
+__global__ void k_lincomb(LinArgs a) {
+    const int r = blockIdx.y;
+    const double* cf = a.coef + (long long)r * a.nt;
+    double c0 = cf[0], c1 = a.nt > 1 ? cf[1] : 0.0, c2 = a.nt > 2 ? cf[2] : 0.0,
+           c3 = a.nt > 3 ? cf[3] : 0.0;
+    const long long off = (long long)r * a.ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < a.n; i += st) {
+        double v = c0 * a.x[0][off + i];
+        if (a.nt > 1) v += c1 * a.x[1][off + i];
+        if (a.nt > 2) v += c2 * a.x[2][off + i];
+        if (a.nt > 3) v += c3 * a.x[3][off + i];
+        a.y[off + i] = v;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+// partial[(r*npair + q)*DOT_BLOCKS + b] = sum over block b's chunk of x_q . y
+// (x_q = X + q*xstride, one y per rhs)
+__global__ void k_dot_partial(long long n, long long ld, const double* X, long long xstride,
+                              int npair, const double* Y, double* partial) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.z, q = blockIdx.y;
+    const double* x = X + (long long)q * xstride + (long long)r * ld;
+    const double* y = Y + (long long)r * ld;
+    const long long chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double s = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) s += x[i] * y[i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[((long long)r * npair + q) * DOT_BLOCKS + blockIdx.x] = s;
+}
+
+__global__ void k_dot_final(const double* partial, int count, double* out) {
+    __shared__ double sh[VT / 64];
+    const long long base = (long long)blockIdx.x * DOT_BLOCKS;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < DOT_BLOCKS; i += blockDim.x) s += partial[base + i];
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    (void)count;
+}
+
+// y_r -= sum_{q<nq} h[r*hld + q] * V_q   (V_q = V + q*vstride)
+__global__ void k_sub_combo(long long n, long long ld, const double* V, long long vstride, int nq,
+                            const double* h, int hld, double* Y) {
+    const int r = blockIdx.y;
+    const double* hr = h + (long long)r * hld;
+    double* y = Y + (long long)r * ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += hr[q] * V[(long long)q * vstride + (long long)r * ld + i];
+        y[i] -= s;
+    }
+}
+
+// y_r += sum_{q<nq} h[r*hld + q] * V_q
+__global__ void k_add_combo(long long n, long long ld, const double* V, long long vstride, int nq,
+                            const double* h, int hld, double* Y) {
+    const int r = blockIdx.y;
+    const double* hr = h + (long long)r * hld;
+    double* y = Y + (long long)r * ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += hr[q] * V[(long long)q * vstride + (long long)r * ld + i];
+        y[i] += s;
+    }
+}
+
+// rank-one sums  y[i1 + n1 (i2 + n2 i3)] += sum_m s1[m][i1] s2[m][i2] s3[m][i3]
+// (amplitudes folded into s3); one launch per (field, rhs)
+__global__ void k_rank1_sum(int n1, int n2, int n3, int nm, const double* s1, const double* s2,
+                            const double* s3, double* y) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long tot = (long long)n1 * n2 * n3;
+    if (idx >= tot) return;
+    int i1 = (int)(idx % n1);
+    long long t = idx / n1;
+    int i2 = (int)(t % n2);
+    int i3 = (int)(t / n2);
+    double s = 0.0;
+    for (int m = 0; m < nm; ++m) s += s1[m * n1 + i1] * s2[m * n2 + i2] * s3[m * n3 + i3];
+    y[idx] += s;
+}
+
+inline unsigned grid_for(long long n) {
+    long long g = (n + VT - 1) / VT;
+    if (g > 2048) g = 2048;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t vec_axpby(hipStream_t s, long long n, double a, const double* x, double b, double* y) {
+    hipLaunchKernelGGL(k_axpby, dim3(grid_for(n)), dim3(VT), 0, s, n, a, x, b, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_copy(hipStream_t s, long long n, const double* x, double* y) {
+    hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(VT), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_zero(hipStream_t s, long long n, double* y) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n)), dim3(VT), 0, s, n, 0.0, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_lincomb(hipStream_t s, long long n, long long ld, int nrhs, int nt,
+                       const double* const* x, const double* dcoef, double* y) {
+    LinArgs a{};
+    for (int t = 0; t < nt; ++t) a.x[t] = x[t];
+    a.y = y;
+    a.coef = dcoef;
+    a.nt = nt;
+    a.n = n;
+    a.ld = ld;
+    hipLaunchKernelGGL(k_lincomb, dim3(grid_for(n), nrhs), dim3(VT), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t vec_multidot_async(hipStream_t s, long long n, long long ld, const double* X,
+                              long long xstride, int npair, const double* Y, int nrhs,
+                              double* partial, double* dout) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, npair, nrhs), dim3(VT), 0, s, n, ld, X,
+                       xstride, npair, Y, partial);
+    hipLaunchKernelGGL(k_dot_final, dim3(npair * nrhs), dim3(VT), 0, s, partial, DOT_BLOCKS, dout);
+    return hipGetLastError();
+}
+
+size_t vec_partial_doubles(int npair, int nrhs) { return (size_t)npair * nrhs * DOT_BLOCKS; }
+
+hipError_t vec_sub_combo(hipStream_t s, long long n, long long ld, const double* V,
+                         long long vstride, int nq, const double* dh, int hld, int nrhs,
+                         double* Y) {
+    hipLaunchKernelGGL(k_sub_combo, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, V, vstride,
+                       nq, dh, hld, Y);
+    return hipGetLastError();
+}
+
+hipError_t vec_add_combo(hipStream_t s, long long n, long long ld, const double* V,
+                         long long vstride, int nq, const double* dh, int hld, int nrhs,
+                         double* Y) {
+    hipLaunchKernelGGL(k_add_combo, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, V, vstride,
+                       nq, dh, hld, Y);
+    return hipGetLastError();
+}
+
+hipError_t rank1_sum(hipStream_t s, int n1, int n2, int n3, int nm, const double* s1,
+                     const double* s2, const double* s3, double* y) {
+    long long tot = (long long)n1 * n2 * n3;
+    hipLaunchKernelGGL(k_rank1_sum, dim3((unsigned)((tot + VT - 1) / VT)), dim3(VT), 0, s, n1, n2,
+                       n3, nm, s1, s2, s3, y);
+    return hipGetLastError();
+}
+
+hipError_t vec_dots(hp_ctx* c, long long n, long long ld, const double* x, const double* y,
+                    int nrhs, double* out) {
+    double* partial = c->d_red;
+    double* dres = c->d_red + vec_partial_doubles(1, nrhs);
+    hipError_t e = vec_multidot_async(c->stream, n, ld, x, 0, 1, y, nrhs, partial, dres);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(c->h_red, dres, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    for (int r = 0; r < nrhs; ++r) out[r] = c->h_red[r];
+    return hipSuccess;
+}
+
+}  // namespace hp

@@ -1,0 +1,29 @@
+// Vector-kernel launchers (krylov.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace hp {
+
+// y_r = sum_t dcoef[r*nt + t] * x[t]_r over n entries, rhs stride ld
+hipError_t vec_lincomb(hipStream_t s, long long n, long long ld, int nrhs, int nt,
+                       const double* const* x, const double* dcoef, double* y);
+// dout[r*npair + q] = <X_q,r , Y_r>, X_q = X + q*xstride (deterministic order)
+hipError_t vec_multidot_async(hipStream_t s, long long n, long long ld, const double* X,
+                              long long xstride, int npair, const double* Y, int nrhs,
+                              double* partial, double* dout);
+size_t vec_partial_doubles(int npair, int nrhs);
+// Y_r -= sum_q dh[r*hld + q] V_q,r
+hipError_t vec_sub_combo(hipStream_t s, long long n, long long ld, const double* V,
+                         long long vstride, int nq, const double* dh, int hld, int nrhs,
+                         double* Y);
+// Y_r += sum_q dh[r*hld + q] V_q,r
+hipError_t vec_add_combo(hipStream_t s, long long n, long long ld, const double* V,
+                         long long vstride, int nq, const double* dh, int hld, int nrhs,
+                         double* Y);
+// y += sum_m s1[m] (x) s2[m] (x) s3[m]  (direction 1 fastest)
+hipError_t rank1_sum(hipStream_t s, int n1, int n2, int n3, int nm, const double* s1,
+                     const double* s2, const double* s3, double* y);
+
+}  // namespace hp

@@ -1,0 +1,179 @@
+"""Python front end of the MI355X hyper-power Stokes solver.
+
+``Solver`` owns one library context (``hp_setup``) and exposes the C-ABI
+calls with the same names on torch tensors that live on the GPU.  torch
+provides device memory and the stream only; every operation is a call into
+``libhyperpower.so``.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, hp_opts, hp_solve_info
+
+
+def _ptr(t):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("vectors must be contiguous float64 CUDA tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """Context for E^3 elements, velocity degree p, viscosity nu.
+
+    Options (see include/hyperpower.h): c_pen, schur ('Pcq1'|'Pcq2'),
+    schedule ('literal'|'prev'), precision ('fp64'|'fp32'|'bf16x3'),
+    krylov ('minres'|'fgmres'), restart, maxit, order, iters, max_rhs.
+    """
+
+    def __init__(self, E, p, nu=1.0, *, c_pen=12.5, schur="Pcq1", schedule="literal",
+                 precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
+                 iters=1, max_rhs=1, check_every=6, use_graph=True, device=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        o = hp_opts()
+        self.lib.hp_default_opts(ctypes.byref(o))
+        o.c_pen = c_pen
+        o.schur_variant = _lib.SCHUR[schur]
+        o.l_schedule = _lib.SCHEDULE[schedule]
+        o.precision = _lib.PREC[precision]
+        o.krylov = _lib.KRYLOV[krylov]
+        o.restart = restart
+        o.maxit = maxit
+        o.order = order
+        o.iters = iters
+        o.max_rhs = max_rhs
+        o.check_every = check_every
+        o.use_graph = int(bool(use_graph))
+        self.opts = o
+        self.E, self.p, self.nu = E, p, nu
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            ctx = ctypes.c_void_p()
+            check(self.lib.hp_setup(E, p, float(nu), ctypes.byref(o),
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)),
+                  "hp_setup")
+        self.ctx = ctx
+        dims = (ctypes.c_int64 * 12)()
+        offs = (ctypes.c_int64 * 5)()
+        check(self.lib.hp_sizes(self.ctx, ctypes.byref(dims), ctypes.byref(offs)), "hp_sizes")
+        self.dims = [tuple(dims[3 * b + d] for d in range(3)) for b in range(4)]
+        self.offsets = [offs[i] for i in range(5)]
+        self.nV = self.offsets[3]
+        self.nQ = self.offsets[4] - self.offsets[3]
+        self.N = self.offsets[4]
+        self.max_rhs = max_rhs
+
+    # -- memory helpers ------------------------------------------------------
+    def empty(self, n, nrhs=1):
+        return torch.empty(nrhs * n, dtype=torch.float64, device=self.device)
+
+    def zeros(self, n, nrhs=1):
+        return torch.zeros(nrhs * n, dtype=torch.float64, device=self.device)
+
+    def _nrhs(self, t, n):
+        if t.numel() % n:
+            raise ValueError(f"size {t.numel()} is not a multiple of {n}")
+        return t.numel() // n
+
+    # -- C-ABI calls ----------------------------------------------------------
+    def set_nu(self, nu):
+        check(self.lib.hp_set_nu(self.ctx, float(nu)), "hp_set_nu")
+        self.nu = nu
+
+    def apply_K(self, x, y=None):
+        nr = self._nrhs(x, self.N)
+        y = self.empty(self.N, nr) if y is None else y
+        check(self.lib.hp_apply_K(self.ctx, _ptr(x), _ptr(y), nr), "hp_apply_K")
+        return y
+
+    def apply_A(self, u, y=None):
+        nr = self._nrhs(u, self.nV)
+        y = self.empty(self.nV, nr) if y is None else y
+        check(self.lib.hp_apply_A(self.ctx, _ptr(u), _ptr(y), nr), "hp_apply_A")
+        return y
+
+    def apply_B(self, p, y=None):
+        nr = self._nrhs(p, self.nQ)
+        y = self.empty(self.nV, nr) if y is None else y
+        check(self.lib.hp_apply_B(self.ctx, _ptr(p), _ptr(y), nr), "hp_apply_B")
+        return y
+
+    def apply_Bt(self, u, y=None):
+        nr = self._nrhs(u, self.nV)
+        y = self.empty(self.nQ, nr) if y is None else y
+        check(self.lib.hp_apply_Bt(self.ctx, _ptr(u), _ptr(y), nr), "hp_apply_Bt")
+        return y
+
+    def apply_MV(self, u, y=None):
+        nr = self._nrhs(u, self.nV)
+        y = self.empty(self.nV, nr) if y is None else y
+        check(self.lib.hp_apply_MV(self.ctx, _ptr(u), _ptr(y), nr), "hp_apply_MV")
+        return y
+
+    def apply_P0(self, x, y=None):
+        nr = self._nrhs(x, self.N)
+        y = self.empty(self.N, nr) if y is None else y
+        check(self.lib.hp_apply_P0(self.ctx, _ptr(x), _ptr(y), nr), "hp_apply_P0")
+        return y
+
+    def apply_hyperpower(self, order, iters, x, y=None):
+        nr = self._nrhs(x, self.N)
+        y = self.empty(self.N, nr) if y is None else y
+        check(self.lib.hp_apply_hyperpower(self.ctx, order, iters, _ptr(x), _ptr(y), nr),
+              "hp_apply_hyperpower")
+        return y
+
+    def solve(self, b, tol=1e-8, x=None, raise_on_noconv=True):
+        nr = self._nrhs(b, self.N)
+        x = self.empty(self.N, nr) if x is None else x
+        info = hp_solve_info()
+        code = self.lib.hp_solve(self.ctx, _ptr(b), _ptr(x), nr, float(tol), ctypes.byref(info))
+        if code != 0 and (raise_on_noconv or code != -6):
+            check(code, "hp_solve")
+        return x, info
+
+    def build_rhs(self, lid, modes=None, b=None):
+        """Cavity right-hand sides: lid speeds (one per rhs) and optional
+        body-force modes (amp[nrhs, 3, m], waves[nrhs, 3, m, 3])."""
+        lid = np.ascontiguousarray(np.atleast_1d(np.asarray(lid, dtype=np.float64)))
+        nr = lid.size
+        b = self.empty(self.N, nr) if b is None else b
+        if modes is None:
+            nm, ap, wp = 0, None, None
+        else:
+            amp, wav = modes
+            amp = np.ascontiguousarray(amp, dtype=np.float64)
+            wav = np.ascontiguousarray(wav, dtype=np.int32)
+            nm = amp.shape[-1]
+            ap = amp.ctypes.data_as(ctypes.c_void_p)
+            wp = wav.ctypes.data_as(ctypes.c_void_p)
+        check(self.lib.hp_build_rhs(self.ctx, lid.ctypes.data_as(ctypes.c_void_p), nm, ap, wp,
+                                    _ptr(b), nr), "hp_build_rhs")
+        return b
+
+    def grad(self, x, lam, lid):
+        nr = self._nrhs(x, self.N)
+        lid = np.ascontiguousarray(np.atleast_1d(np.asarray(lid, dtype=np.float64)))
+        gb = self.empty(self.nV, nr)
+        gn = np.zeros(nr)
+        check(self.lib.hp_grad(self.ctx, _ptr(x), _ptr(lam), lid.ctypes.data_as(ctypes.c_void_p),
+                               _ptr(gb), gn.ctypes.data_as(ctypes.c_void_p), nr), "hp_grad")
+        return gb, gn
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

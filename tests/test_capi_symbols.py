@@ -1,0 +1,55 @@
+"""The C-ABI library loads on the CPU host and exports every function that
+include/hyperpower.h declares (no compute calls: there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hyperpower.h")
+LIB = os.path.join(ROOT, "paper_2311_06926_amd", "libhyperpower.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(hp_\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hp_setup", "hp_apply_K", "hp_apply_P0", "hp_apply_hyperpower", "hp_solve"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_signatures_cover_the_header():
+    from paper_2311_06926_amd import _lib
+    assert set(_lib.SIGNATURES) == set(declared_functions())
+    lib = _lib.load()
+    opts = _lib.hp_opts()
+    lib.hp_default_opts(ctypes.byref(opts))
+    assert opts.c_pen == 12.5 and opts.order == 2 and opts.max_rhs == 1
+    assert lib.hp_status_string(-6) == b"not converged within maxit"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_setup_rejects_bad_arguments_without_touching_the_gpu():
+    from paper_2311_06926_amd import _lib
+    lib = _lib.load()
+    ctx = ctypes.c_void_p()
+    # invalid degree / elements / viscosity are rejected before any HIP call
+    assert lib.hp_setup(8, 1, 1.0, None, None, ctypes.byref(ctx)) == -1
+    assert lib.hp_setup(0, 2, 1.0, None, None, ctypes.byref(ctx)) == -1
+    assert lib.hp_setup(8, 2, -1.0, None, None, ctypes.byref(ctx)) == -1
+    assert lib.hp_setup(8, 2, 1.0, None, None, None) == -1
+    assert lib.hp_apply_K(None, None, None, 1) == -1

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP64 everywhere on the GPU path):
+* sum-factorised operators (K, A, B, B^T, M_V): 1e-12 relative (max-norm);
+  the kernels sum the same products as the Kronecker assembly in another
+  order, so the gap is a few ulps times the band width;
+* P_0^{-1} and P_k^{-1}: 1e-11 relative -- fast diagonalisation (GPU)
+  against sparse LU (oracle); both are backward stable, and the forward gap
+  is bounded by eps * cond(A_cc) ~ 1e-13..1e-12 at these sizes;
+* MINRES/FGMRES: iteration counts within +-1 of the oracle's, solutions
+  agree to 1e-6 (tolerance 1e-8 on the residual).
+Sizes span several 8-row strips, 16-wide MFMA tiles and 64-row blocks, with
+ragged tails (n = 9, 10, 11, 13, 14, 17, 18).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2311_06926_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(3, 2), (8, 2), (5, 3), (8, 3), (12, 2), (15, 3), (4, 4)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+_ORACLE = {}
+
+
+def oracle_sys(E, p, nu=1.0):
+    from oracle.assemble import KronSystem
+    key = (E, p, nu)
+    if key not in _ORACLE:
+        _ORACLE[key] = KronSystem(E, p, nu)
+    return _ORACLE[key]
+
+
+def to_gpu(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def rel_err(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("E,p", CASES)
+def test_operators(dev, E, p):
+    from paper_2311_06926_amd.solver import Solver
+    from oracle.cases import velocity_mass
+    nu = 1.7
+    say(f"[parity] operators E={E} p={p} nu={nu}")
+    S = oracle_sys(E, p, nu)
+    sol = Solver(E, p, nu)
+    assert sol.N == S.N and sol.nV == S.nV
+    x = synth.random_vector(S.N, seed=E * 10 + p)
+    y = sol.apply_K(to_gpu(x, dev)).cpu().numpy()
+    assert rel_err(y, S.K @ x) < 1e-12
+    u, pr = x[:S.nV], x[S.nV:]
+    assert rel_err(sol.apply_A(to_gpu(u, dev)).cpu().numpy(), S.A @ u) < 1e-12
+    assert rel_err(sol.apply_B(to_gpu(pr, dev)).cpu().numpy(), S.B @ pr) < 1e-12
+    assert rel_err(sol.apply_Bt(to_gpu(u, dev)).cpu().numpy(), S.B.T @ u) < 1e-12
+    MV = velocity_mass(S)
+    assert rel_err(sol.apply_MV(to_gpu(u, dev)).cpu().numpy(), MV @ u) < 1e-12
+    sol.close()
+
+
+@pytest.mark.parametrize("E,p", CASES)
+def test_base_preconditioner(dev, E, p):
+    from oracle.precond import BasePreconditioner
+    from paper_2311_06926_amd.solver import Solver
+    nu = 0.8
+    say(f"[parity] P0 E={E} p={p}")
+    S = oracle_sys(E, p, nu)
+    P0 = BasePreconditioner(S)
+    sol = Solver(E, p, nu)
+    x = synth.random_vector(S.N, seed=100 + E * 10 + p)
+    y = sol.apply_P0(to_gpu(x, dev)).cpu().numpy()
+    assert rel_err(y, P0.apply(x)) < 1e-11
+    # backward error of the velocity blocks: A_cc y_c = x_c
+    o = S.offsets
+    for c, blk in enumerate([S.A11, S.A22, S.A33]):
+        r = blk @ y[o[c]:o[c + 1]] - x[o[c]:o[c + 1]]
+        assert np.abs(r).max() <= 1e-12 * np.abs(x).max() * 10
+    sol.close()
+
+
+@pytest.mark.parametrize("E,p", [(3, 2), (8, 3), (13, 2)])
+@pytest.mark.parametrize("q,k", [(2, 1), (2, 2), (3, 1), (3, 2), (2, 3)])
+@pytest.mark.parametrize("variant", ["Pcq1", "Pcq2"])
+def test_hyperpower(dev, E, p, q, k, variant):
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    if (E, p) == (13, 2) and q ** k > 4:
+        pytest.skip("large q^k only on the small meshes (oracle time)")
+    say(f"[parity] hyperpower E={E} p={p} q={q} k={k} {variant}")
+    S = oracle_sys(E, p)
+    H = HyperPower(S, q, k, variant=variant)
+    sol = Solver(E, p, 1.0, schur=variant)
+    x = synth.random_vector(S.N, seed=200 + q * 10 + k)
+    y = sol.apply_hyperpower(q, k, to_gpu(x, dev)).cpu().numpy()
+    assert rel_err(y, H.apply(x)) < 1e-11
+    sol.close()
+
+
+def test_hyperpower_prev_schedule(dev):
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] hyperpower schedule=prev")
+    S = oracle_sys(5, 3)
+    H = HyperPower(S, 2, 3, variant="Pcq1", schedule="prev")
+    sol = Solver(5, 3, 1.0, schedule="prev")
+    x = synth.random_vector(S.N, seed=301)
+    y = sol.apply_hyperpower(2, 3, to_gpu(x, dev)).cpu().numpy()
+    assert rel_err(y, H.apply(x)) < 1e-11
+    sol.close()
+
+
+def test_batched_apply_matches_single(dev):
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] batched apply_K / P_k, nrhs=3")
+    E, p = 7, 3
+    sol = Solver(E, p, 1.0, max_rhs=3)
+    xs = [synth.random_vector(sol.N, seed=400 + r) for r in range(3)]
+    xb = to_gpu(np.concatenate(xs), dev)
+    yb = sol.apply_K(xb).cpu().numpy().reshape(3, -1)
+    hb = sol.apply_hyperpower(2, 2, xb).cpu().numpy().reshape(3, -1)
+    for r in range(3):
+        y1 = sol.apply_K(to_gpu(xs[r], dev)).cpu().numpy()
+        h1 = sol.apply_hyperpower(2, 2, to_gpu(xs[r], dev)).cpu().numpy()
+        assert np.array_equal(yb[r], y1)
+        assert np.array_equal(hb[r], h1)
+    sol.close()
+
+
+def test_rhs_matches_oracle(dev):
+    from oracle.assemble import KronSystem
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] rhs build (lid + body force), nrhs=2")
+    E, p = 6, 3
+    sol = Solver(E, p, 1.3, max_rhs=2)
+    S = KronSystem(E, p, 1.3)
+    lids, amps, wavs, refs = [], [], [], []
+    for r in range(2):
+        modes, U = synth.body_force_modes(r, nmodes=4)
+        amp, wav = synth.modes_to_arrays(modes)
+        lids.append(U)
+        amps.append(amp)
+        wavs.append(wav)
+        refs.append(S.lid_rhs(U) + S.body_force_rhs(modes))
+    b = sol.build_rhs(np.array(lids), (np.stack(amps), np.stack(wavs))).cpu().numpy()
+    assert rel_err(b, np.concatenate(refs)) < 1e-12
+    sol.close()
+
+
+@pytest.mark.parametrize("k", [0, 1, 2])
+def test_minres_config1(dev, k):
+    """8^3 elements, degree 2, q = 2: iteration counts within +-1 of the oracle."""
+    from oracle.cases import cavity
+    from oracle.direct import mean_zero_pressure
+    from oracle.krylov import minres
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] MINRES 8^3 p=2 k={k}")
+    S, b = cavity(8, 2)
+    ref = minres(lambda v: S.K @ v, HyperPower(S, 2, k).apply, b, tol=1e-8)
+    sol = Solver(8, 2, 1.0, iters=k)
+    bg = sol.build_rhs([1.0])
+    assert rel_err(bg.cpu().numpy(), b) < 1e-13
+    x, info = sol.solve(bg, tol=1e-8)
+    assert abs(info.iterations - ref.iters) <= 1
+    assert info.converged == 1
+    assert info.true_relres < 1e-6
+    xg = mean_zero_pressure(x.cpu().numpy(), S.nV)
+    xr = mean_zero_pressure(ref.x, S.nV)
+    assert np.linalg.norm(xg[:S.nV] - xr[:S.nV]) <= 1e-6 * np.linalg.norm(xr[:S.nV])
+    sol.close()
+
+
+def test_fgmres_matches_oracle(dev):
+    from oracle.cases import cavity
+    from oracle.krylov import fgmres
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] FGMRES 6^3 p=3 k=1")
+    S, b = cavity(6, 3)
+    H = HyperPower(S, 2, 1)
+    ref = fgmres(lambda v: S.K @ v, lambda v, j: H.apply(v), b, tol=1e-8, restart=50)
+    sol = Solver(6, 3, 1.0, iters=1, krylov="fgmres")
+    x, info = sol.solve(sol.build_rhs([1.0]), tol=1e-8)
+    assert abs(info.iterations - ref.iters) <= 1
+    assert info.true_relres <= 1e-8 * 1.01
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs[:S.nV] - ref.x[:S.nV]) <= 1e-6 * np.linalg.norm(ref.x[:S.nV])
+    sol.close()
+
+
+def test_fp32_preconditioner_error_is_small(dev):
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] FP32 P0 vs FP64 P0")
+    E, p = 9, 3
+    s64 = Solver(E, p, 1.0)
+    s32 = Solver(E, p, 1.0, precision="fp32", krylov="fgmres")
+    x = to_gpu(synth.random_vector(s64.N, seed=501), dev)
+    y64 = s64.apply_P0(x).cpu().numpy()
+    y32 = s32.apply_P0(x).cpu().numpy()
+    assert rel_err(y32, y64) < 1e-5
+    s64.close()
+    s32.close()
+
+
+def test_gradient_matches_oracle(dev):
+    from oracle.cases import CavityLoss, cavity
+    from oracle.direct import DirectSolver
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] adjoint gradient pieces 4^3 p=2")
+    E, p, nu = 4, 2, 1.2
+    St, bt = cavity(E, p, U=1.5)
+    ut = DirectSolver(St).solve(bt)[:St.nV]
+    loss = CavityLoss(E, p, U=1.0, u_target=ut)
+    beta = synth.random_vector(St.nV, seed=601, scale=0.3)
+    L, gb_ref, gn_ref = loss.gradient(beta, nu)
+    S, MV, b, x = loss.solve(beta, nu)
+    d = x[:S.nV] - ut
+    rhs = np.zeros(S.N)
+    rhs[:S.nV] = 2.0 * (MV @ d)
+    lam = DirectSolver(S).solve(rhs)
+    sol = Solver(E, p, nu)
+    gb, gn = sol.grad(to_gpu(x, dev), to_gpu(lam, dev), [1.0])
+    assert rel_err(gb.cpu().numpy(), gb_ref) < 1e-12
+    assert abs(gn[0] - gn_ref) <= 1e-10 * max(abs(gn_ref), 1e-12)
+    sol.close()
+
+
+def test_invalid_arguments(dev):
+    from paper_2311_06926_amd._lib import HPError
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] invalid arguments")
+    sol = Solver(3, 2, 1.0)
+    x = torch.zeros(sol.N, dtype=torch.float64, device=dev)
+    with pytest.raises(HPError):
+        sol.apply_hyperpower(1, 1, x)          # order < 2
+    with pytest.raises(HPError):
+        sol.apply_K(x, x)                      # aliasing
+    with pytest.raises(HPError):
+        sol.apply_K(torch.zeros(2 * sol.N, dtype=torch.float64, device=dev))  # nrhs > max_rhs
+    with pytest.raises(HPError):
+        Solver(3, 2, 1.0, precision="fp32").solve(x)    # MINRES needs FP64
+    sol.close()
