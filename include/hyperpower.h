@@ -107,7 +107,11 @@ void hp_default_opts(hp_opts* o);
 /* Build the univariate tables (App. B.3, Sec. 3.3), the generalised
  * eigen-decompositions for fast diagonalisation (App. A.3-A.4) and the
  * workspace.  elements >= 1, 2 <= degree <= 4, nu > 0.  opts may be NULL
- * (defaults).  stream: a hipStream_t or NULL.  *out receives the context. */
+ * (defaults).  stream: a hipStream_t or NULL.  *out receives the context.
+ * Fast diagonalisation holds a whole direction in MFMA tiles, so P_0,
+ * P_k and the solve need E + degree - 1 <= 128; above that the context
+ * serves the operators (hp_apply_K/A/B/Bt/MV) only and the preconditioner
+ * and solve calls return HP_EINVAL. */
 hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts,
                    void* stream, hp_ctx** out);
 

@@ -42,6 +42,19 @@ struct Extra {
     double* dcoef = nullptr;  // device coefficient staging
     double* hcoef = nullptr;  // pinned host coefficients
     size_t coef_doubles = 0;
+    // device-side MINRES state: scalars, coefficient slots, dot partials
+    MinresScalars* msc = nullptr;
+    MinresScalars* hmsc[2] = {nullptr, nullptr};  // pinned host mirrors
+    double* mcoef = nullptr;   // 8 per rhs: v (3), w (3), x (2)
+    double* mpart = nullptr;   // 2 x DOT partials per rhs
+    hipEvent_t mev[2] = {nullptr, nullptr};
+    hipStream_t cap = nullptr;  // non-blocking stream used only for graph capture
+    // cached iteration graphs (one per buffer-rotation phase)
+    bool g_valid = false;
+    hipGraphExec_t g_exec[6] = {};
+    int g_q = 0, g_k = 0, g_nrhs = 0, g_var = 0, g_sched = 0, g_prec = 0;
+    double g_tol = 0, g_nu = 0;
+    const double* g_kv = nullptr;
 };
 
 Extra* extra_of(hp_ctx* c);
@@ -244,140 +257,181 @@ hp_status dots(hp_ctx* c, const double* x, const double* y, int nrhs, std::vecto
 }
 
 // ---- MINRES (preconditioned; Lanczos in the P^{-1} inner product) ------------------
+// All recurrence scalars live on the device (k_minres_* kernels), so one
+// iteration is a fixed sequence of launches: it is captured once per
+// buffer-rotation phase (period 6) as a HIP graph and replayed.  The host
+// reads the per-rhs convergence flags one iteration behind the GPU.
+struct MinresBufs {
+    double *vo, *v, *vn, *z, *zn, *wo, *w, *wn, *Kz, *x;
+};
+
+MinresBufs minres_bufs(hp_ctx* c, int phase, int nrhs) {
+    const long long V = c->N * (long long)c->opts.max_rhs;
+    double* base = extra_of(c)->kv;
+    double* vb[3] = {base, base + V, base + 2 * V};
+    double* zb[2] = {base + 3 * V, base + 4 * V};
+    double* wb[3] = {base + 5 * V, base + 6 * V, base + 7 * V};
+    MinresBufs b;
+    b.vo = vb[phase % 3];
+    b.v = vb[(phase + 1) % 3];
+    b.vn = vb[(phase + 2) % 3];
+    b.z = zb[phase % 2];
+    b.zn = zb[(phase + 1) % 2];
+    b.wo = wb[phase % 3];
+    b.w = wb[(phase + 1) % 3];
+    b.wn = wb[(phase + 2) % 3];
+    b.Kz = base + 8 * V;
+    b.x = base + 9 * V;
+    (void)nrhs;
+    return b;
+}
+
+hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol) {
+    Extra* ex = extra_of(c);
+    const long long N = c->N;
+    const int R = c->opts.max_rhs;
+    double* cv = ex->mcoef;
+    double* cw = ex->mcoef + 3 * R;
+    double* cx = ex->mcoef + 6 * R;
+    double* p0 = ex->mpart;
+    double* p1 = ex->mpart + vec_partial_doubles(1, R);
+    hipError_t e;
+    if ((e = launch_operator(c, OP_K, full_fields(c, b.z), full_fields(c, b.Kz), 1.0, 0.0, nullptr,
+                             nrhs)) != hipSuccess) return e;
+    if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
+    if ((e = minres_a(c->stream, ex->msc, p0, cv, nrhs)) != hipSuccess) return e;
+    {
+        const double* xs[3] = {b.Kz, b.v, b.vo};
+        if ((e = vec_lincomb(c->stream, N, N, nrhs, 3, xs, cv, b.vn)) != hipSuccess) return e;
+    }
+    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs)) != hipSuccess) return e;
+    if ((e = vec_dot_partials(c->stream, N, N, b.zn, b.vn, nrhs, p1)) != hipSuccess) return e;
+    if ((e = minres_b(c->stream, ex->msc, p1, cw, cx, tol, nrhs)) != hipSuccess) return e;
+    {
+        const double* xs[3] = {b.z, b.wo, b.w};
+        if ((e = vec_lincomb(c->stream, N, N, nrhs, 3, xs, cw, b.wn)) != hipSuccess) return e;
+    }
+    {
+        const double* xs[2] = {b.x, b.wn};
+        if ((e = vec_lincomb(c->stream, N, N, nrhs, 2, xs, cx, b.x)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void drop_graphs(Extra* ex) {
+    for (auto& g : ex->g_exec)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+    ex->g_valid = false;
+}
+
+hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
+    Extra* ex = extra_of(c);
+    const hp_opts& o = c->opts;
+    if (ex->g_valid && ex->g_q == o.order && ex->g_k == o.iters && ex->g_nrhs == nrhs &&
+        ex->g_var == o.schur_variant && ex->g_sched == o.l_schedule && ex->g_prec == o.precision &&
+        ex->g_tol == tol && ex->g_nu == c->nu && ex->g_kv == ex->kv)
+        return HP_OK;
+    drop_graphs(ex);
+    hipStream_t user = c->stream;
+    c->stream = ex->cap;
+    hp_status st = HP_OK;
+    for (int ph = 0; ph < 6 && st == HP_OK; ++ph) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(ex->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            st = HP_EHIP;
+            break;
+        }
+        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol);
+        hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
+        if (st == HP_OK && hipGraphInstantiate(&ex->g_exec[ph], g, nullptr, nullptr, 0) != hipSuccess)
+            st = HP_EHIP;
+        if (g) (void)hipGraphDestroy(g);
+    }
+    c->stream = user;
+    if (st != HP_OK) {
+        drop_graphs(ex);
+        return st;
+    }
+    ex->g_valid = true;
+    ex->g_q = o.order;
+    ex->g_k = o.iters;
+    ex->g_nrhs = nrhs;
+    ex->g_var = o.schur_variant;
+    ex->g_sched = o.l_schedule;
+    ex->g_prec = o.precision;
+    ex->g_tol = tol;
+    ex->g_nu = c->nu;
+    ex->g_kv = ex->kv;
+    return HP_OK;
+}
+
 hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp_solve_info* info) {
+    Extra* ex = extra_of(c);
     const long long N = c->N;
     const long long V = N * nrhs;
-    if (ensure_krylov(c, 9 * N * (size_t)c->opts.max_rhs) != HP_OK) return HP_ENOMEM;
-    double* base = extra_of(c)->kv;
-    double* vo = base;
-    double* v = base + V;
-    double* vn = base + 2 * V;
-    double* z = base + 3 * V;
-    double* zn = base + 4 * V;
-    double* wo = base + 5 * V;
-    double* w = base + 6 * V;
-    double* wn = base + 7 * V;
-    double* Kz = base + 8 * V;
-    const int q = c->opts.order, k = c->opts.iters;
-    HIPCHK(vec_zero(c->stream, V, x));
-    HIPCHK(vec_zero(c->stream, V, vo));
-    HIPCHK(vec_zero(c->stream, V, wo));
-    HIPCHK(vec_zero(c->stream, V, w));
-    HIPCHK(vec_copy(c->stream, V, b, v));
-    HIPCHK(apply_Pk(c, q, k, v, z, nrhs));
-    std::vector<double> zv, dl;
-    if (dots(c, z, v, nrhs, zv) != HP_OK) return HP_EHIP;
-    std::vector<double> gamma(nrhs), gamma_old(nrhs, 1.0), beta0(nrhs), eta(nrhs), c0(nrhs, 1.0),
-        c1(nrhs, 1.0), s0(nrhs, 0.0), s1(nrhs, 0.0), rel(nrhs, 1.0);
-    std::vector<int> done(nrhs, 0), iters(nrhs, 0);
-    for (int r = 0; r < nrhs; ++r) {
-        if (!(zv[r] >= 0.0) || !std::isfinite(zv[r])) return zv[r] < 0 ? HP_ENOTSPD : HP_ENAN;
-        gamma[r] = std::sqrt(zv[r]);
-        beta0[r] = gamma[r];
-        eta[r] = gamma[r];
-        if (gamma[r] == 0.0) done[r] = 1, rel[r] = 0.0;
-    }
-    hp_status status = HP_OK;
-    int it = 0;
-    std::vector<double> cf(4 * nrhs);
-    auto all_done = [&]() {
+    if (ensure_krylov(c, 10 * N * (size_t)c->opts.max_rhs) != HP_OK) return HP_ENOMEM;
+    const bool graphs = c->opts.use_graph != 0;
+    if (graphs && build_graphs(c, nrhs, tol) != HP_OK) return HP_EHIP;
+    MinresBufs b0 = minres_bufs(c, 0, nrhs);
+    HIPCHK(vec_zero(c->stream, V, b0.x));
+    HIPCHK(vec_zero(c->stream, V, b0.vo));
+    HIPCHK(vec_zero(c->stream, V, b0.wo));
+    HIPCHK(vec_zero(c->stream, V, b0.w));
+    HIPCHK(vec_copy(c->stream, V, b, b0.v));
+    HIPCHK(apply_Pk(c, c->opts.order, c->opts.iters, b0.v, b0.z, nrhs));
+    HIPCHK(vec_dot_partials(c->stream, N, N, b0.z, b0.v, nrhs, ex->mpart));
+    HIPCHK(minres_init(c->stream, ex->msc, ex->mpart, nrhs));
+    const size_t sbytes = sizeof(MinresScalars) * nrhs;
+    auto all_done = [&](const MinresScalars* h) {
         for (int r = 0; r < nrhs; ++r)
-            if (!done[r]) return false;
+            if (!h[r].done) return false;
         return true;
     };
-    while (!all_done() && it < c->opts.maxit) {
+    HIPCHK(hipMemcpyAsync(ex->hmsc[0], ex->msc, sbytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int it = 0;
+    bool finished = all_done(ex->hmsc[0]);
+    while (!finished && it < c->opts.maxit) {
+        const int ph = it % 6;
         ++it;
-        HIPCHK(launch_operator(c, OP_K, full_fields(c, z), full_fields(c, Kz), 1.0, 0.0, nullptr,
-                               nrhs));
-        if (dots(c, Kz, z, nrhs, dl) != HP_OK) return HP_EHIP;
-        std::vector<double> delta(nrhs);
-        for (int r = 0; r < nrhs; ++r) {
-            delta[r] = done[r] ? 0.0 : dl[r] / (gamma[r] * gamma[r]);
-            cf[3 * r + 0] = done[r] ? 0.0 : 1.0 / gamma[r];
-            cf[3 * r + 1] = done[r] ? 0.0 : -delta[r] / gamma[r];
-            cf[3 * r + 2] = done[r] ? 0.0 : -gamma[r] / gamma_old[r];
+        if (graphs) {
+            HIPCHK(hipGraphLaunch(ex->g_exec[ph], c->stream));
+        } else {
+            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol));
         }
-        std::vector<double> cc(cf.begin(), cf.begin() + 3 * nrhs);
-        if (stage_coef(c, cc) != HP_OK) return HP_EHIP;
-        {
-            const double* xs[3] = {Kz, v, vo};
-            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 3, xs, extra_of(c)->dcoef, vn));
+        HIPCHK(hipMemcpyAsync(ex->hmsc[it & 1], ex->msc, sbytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipEventRecord(ex->mev[it & 1], c->stream));
+        if (it >= 2) {
+            HIPCHK(hipEventSynchronize(ex->mev[(it - 1) & 1]));
+            finished = all_done(ex->hmsc[(it - 1) & 1]);
         }
-        HIPCHK(apply_Pk(c, q, k, vn, zn, nrhs));
-        if (dots(c, zn, vn, nrhs, zv) != HP_OK) return HP_EHIP;
-        std::vector<double> wc(3 * nrhs), xc(2 * nrhs);
-        std::vector<double> gnew(nrhs), cn(nrhs), sn(nrhs);
-        for (int r = 0; r < nrhs; ++r) {
-            if (done[r]) {
-                wc[3 * r] = wc[3 * r + 1] = wc[3 * r + 2] = 0.0;
-                xc[2 * r] = 1.0;
-                xc[2 * r + 1] = 0.0;
-                gnew[r] = gamma[r];
-                cn[r] = c1[r];
-                sn[r] = s1[r];
-                continue;
-            }
-            if (!std::isfinite(zv[r])) return HP_ENAN;
-            if (zv[r] < 0.0) { status = HP_ENOTSPD; zv[r] = 0.0; }
-            gnew[r] = std::sqrt(zv[r]);
-            double g = gamma[r];
-            double a0 = c1[r] * delta[r] - c0[r] * s1[r] * g;
-            double a1 = std::hypot(a0, gnew[r]);
-            double a2 = s1[r] * delta[r] + c0[r] * c1[r] * g;
-            double a3 = s0[r] * g;
-            if (a1 == 0.0) return HP_EBREAKDOWN;
-            cn[r] = a0 / a1;
-            sn[r] = gnew[r] / a1;
-            wc[3 * r + 0] = 1.0 / (g * a1);
-            wc[3 * r + 1] = -a3 / a1;
-            wc[3 * r + 2] = -a2 / a1;
-            xc[2 * r + 0] = 1.0;
-            xc[2 * r + 1] = cn[r] * eta[r];
-        }
-        if (stage_coef(c, wc) != HP_OK) return HP_EHIP;
-        {
-            const double* xs[3] = {z, wo, w};
-            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 3, xs, extra_of(c)->dcoef, wn));
-        }
-        if (stage_coef(c, xc) != HP_OK) return HP_EHIP;
-        {
-            const double* xs[2] = {x, wn};
-            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 2, xs, extra_of(c)->dcoef, x));
-        }
-        for (int r = 0; r < nrhs; ++r) {
-            if (done[r]) continue;
-            eta[r] = -sn[r] * eta[r];
-            gamma_old[r] = gamma[r];
-            gamma[r] = gnew[r];
-            c0[r] = c1[r];
-            c1[r] = cn[r];
-            s0[r] = s1[r];
-            s1[r] = sn[r];
-            rel[r] = std::fabs(eta[r]) / beta0[r];
-            iters[r] = it;
-            if (rel[r] <= tol || gnew[r] == 0.0) done[r] = 1;
-        }
-        if (status == HP_ENOTSPD) break;
-        // rotate buffers
-        std::swap(vo, v);
-        std::swap(v, vn);  // v <- vn, vn <- old vo (free)
-        std::swap(z, zn);
-        std::swap(wo, w);
-        std::swap(w, wn);
     }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const MinresScalars* h = ex->hmsc[it & 1];
+    HIPCHK(hipMemcpy(ex->hmsc[it & 1], ex->msc, sbytes, hipMemcpyDeviceToHost));
+    HIPCHK(vec_copy(c->stream, V, b0.x, x));
+    hp_status status = HP_OK;
+    bool conv = true;
     if (info) {
         info->iterations = 0;
         info->relres = 0.0;
-        info->converged = 1;
-        for (int r = 0; r < nrhs; ++r) {
-            info->iterations = std::max(info->iterations, iters[r]);
-            info->relres = std::max(info->relres, rel[r]);
-            if (!done[r]) info->converged = 0;
-            if (r < 64) info->iters_per_rhs[r] = iters[r];
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        if (h[r].status != 0 && status == HP_OK) status = (hp_status)h[r].status;
+        if (!h[r].done) conv = false;
+        if (info) {
+            info->iterations = std::max(info->iterations, h[r].iters);
+            info->relres = std::max(info->relres, h[r].rel);
+            if (r < 64) info->iters_per_rhs[r] = h[r].iters;
         }
     }
+    if (info) info->converged = conv && status == HP_OK;
     if (status != HP_OK) return status;
-    return all_done() ? HP_OK : HP_ENOCONV;
+    return conv ? HP_OK : HP_ENOCONV;
 }
 
 // ---- FGMRES(m), right preconditioned, CGS2 Arnoldi -----------------------------------
@@ -672,7 +726,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.restart < 1 || o.maxit < 1)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
-    if (pad16(nM) > 128) return HP_EINVAL;  // fast-diagonalisation tiles hold <= 128 per direction
+    if (nM > 4096) return HP_EINVAL;
     if (ops_init_attributes() != hipSuccess || fd_init_attributes() != hipSuccess) return HP_EHIP;
     CtxExtra* ce = new (std::nothrow) CtxExtra();
     if (!ce) return HP_ENOMEM;
@@ -703,7 +757,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     const int p = degree, wN = p, wM = p - 1;
     const int NNp = pad16(nN), NMp = pad16(nM);
     size_t nb = (size_t)2 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
-    size_t nfd = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM;
+    size_t nfd = NMp <= 128 ? (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM : 0;
     if (alloc_device(&c->d_tables, nb + nfd) != HP_OK) { delete ce; return HP_ENOMEM; }
     double* tp = c->d_tables;
     c->band.ptr[BK_N] = tp; upload_band(c->tab.K_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
@@ -720,6 +774,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         tp += v.size();
         return r;
     };
+    c->fd_ok = NMp <= 128;  // fast-diagonalisation tiles hold <= 128 per direction
+    if (c->fd_ok) {
     c->fd64.UK = up64(padded<double>(c->tab.UK, nN, NNp, false));
     c->fd64.UKt = up64(padded<double>(c->tab.UK, nN, NNp, true));
     c->fd64.UT = up64(padded<double>(c->tab.UT, nM, NMp, false));
@@ -730,6 +786,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->fd64.nN = nN; c->fd64.nM = nM; c->fd64.NNp = NNp; c->fd64.NMp = NMp;
     // FP32 copies of the dense FD tables
     size_t n32 = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp;
+    if (!c->fd_ok) n32 = 1;
     if (hipMalloc(reinterpret_cast<void**>(&c->d_tables32), n32 * sizeof(float)) != hipSuccess) {
         hp_destroy(c);
         return HP_ENOMEM;
@@ -749,6 +806,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->fd32.lamK = c->fd64.lamK;
     c->fd32.lamT = c->fd64.lamT;
     c->fd32.nN = nN; c->fd32.nM = nM; c->fd32.NNp = NNp; c->fd32.NMp = NMp;
+    }
     // ---- workspace: operator intermediates + FD temporaries
     const long long R = o.max_rhs;
     c->ws_doubles = (size_t)((2 * c->nV + 3 * c->nQ) + 2 * c->N) * R;
@@ -759,6 +817,17 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     ex->coef_doubles = (size_t)std::max(4, 132) * R;
     if (alloc_device(&ex->dcoef, ex->coef_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     if (hipHostMalloc(reinterpret_cast<void**>(&ex->hcoef), ex->coef_doubles * sizeof(double)) != hipSuccess) {
+        hp_destroy(c);
+        return HP_ENOMEM;
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&ex->msc), sizeof(MinresScalars) * R) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[0]), sizeof(MinresScalars) * R) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[1]), sizeof(MinresScalars) * R) != hipSuccess ||
+        alloc_device(&ex->mcoef, 8 * R) != HP_OK ||
+        alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
+        hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&ex->cap, hipStreamNonBlocking) != hipSuccess) {
         hp_destroy(c);
         return HP_ENOMEM;
     }
@@ -824,7 +893,7 @@ hp_status hp_apply_MV(hp_ctx* c, const double* u, double* y, int nrhs) {
 }
 
 hp_status hp_apply_P0(hp_ctx* c, const double* x, double* y, int nrhs) {
-    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y) return HP_EINVAL;
+    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y || !c->fd_ok) return HP_EINVAL;
     HIPCHK(launch_P0(c, full_fields(c, x), full_fields(c, y), true, true, false, c->opts.precision,
                      nrhs));
     return HP_OK;
@@ -833,7 +902,7 @@ hp_status hp_apply_P0(hp_ctx* c, const double* x, double* y, int nrhs) {
 hp_status hp_apply_hyperpower(hp_ctx* c, int order, int iters, const double* x, double* y,
                               int nrhs) {
     if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y || order < 2 || iters < 0 ||
-        iters > KMAX)
+        iters > KMAX || !c->fd_ok)
         return HP_EINVAL;
     HIPCHK(apply_Pk(c, order, iters, x, y, nrhs));
     return HP_OK;
@@ -841,7 +910,8 @@ hp_status hp_apply_hyperpower(hp_ctx* c, int order, int iters, const double* x, 
 
 hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
                    hp_solve_info* info) {
-    if (check_rhs(c, nrhs) != HP_OK || !b || !x || b == x || !(tol > 0.0)) return HP_EINVAL;
+    if (check_rhs(c, nrhs) != HP_OK || !b || !x || b == x || !(tol > 0.0) || !c->fd_ok)
+        return HP_EINVAL;
     if (c->opts.krylov == HP_MINRES && c->opts.precision != HP_PREC_FP64) return HP_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     hp_solve_info loc{};
@@ -907,6 +977,15 @@ void hp_destroy(hp_ctx* c) {
     if (ex->hq) (void)hipFree(ex->hq);
     if (ex->kv) (void)hipFree(ex->kv);
     if (ex->dcoef) (void)hipFree(ex->dcoef);
+    drop_graphs(ex);
+    if (ex->msc) (void)hipFree(ex->msc);
+    if (ex->hmsc[0]) (void)hipHostFree(ex->hmsc[0]);
+    if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);
+    if (ex->mcoef) (void)hipFree(ex->mcoef);
+    if (ex->mpart) (void)hipFree(ex->mpart);
+    if (ex->mev[0]) (void)hipEventDestroy(ex->mev[0]);
+    if (ex->mev[1]) (void)hipEventDestroy(ex->mev[1]);
+    if (ex->cap) (void)hipStreamDestroy(ex->cap);
     if (ex->hcoef) (void)hipHostFree(ex->hcoef);
     delete ce;
 }

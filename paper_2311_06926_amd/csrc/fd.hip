@@ -11,6 +11,7 @@
 // (FP64 or FP32 operands, same-precision accumulation):
 //   xy : one i3-plane (n1 x n2) staged in LDS: T = L X, Y = T R (modes 1, 2)
 //   z  : 64 (i1,i2)-rows x n3 staged in LDS: Y = X U3, scale, Z = Y U3^T
+//        (16 rows per wave)
 //        (mode 3 both ways, fused with the eigenvalue scaling)
 // Forward: L = U1^T, R = U2.  Inverse: L = U1, R = U2^T.
 #include "hp_internal.h"
@@ -47,6 +48,53 @@ struct Mfma<float> {
     static __device__ __forceinline__ int row(int lk, int i) { return 4 * lk + i; }
 };
 
+// acc[b] += sum over k of the 16x16 tile product for output tiles b < nb:
+// one operand (`s`, this lane's value at k-step base kk) is shared by all
+// tiles, the other (`v(b, kk)`) differs per tile.  SHARED_A selects which of
+// the two is the MFMA A operand.  Operands are fetched 16 k-values (4 MFMA
+// k-steps) at a time and the next chunk is fetched while the current one
+// is multiplied, so the L2 latency of the matrix operand overlaps compute.
+template <typename T, bool SHARED_A, typename FS, typename FV>
+__device__ __forceinline__ void mfma_row(typename Mfma<T>::V (&acc)[MAXB], int nb, int K, FS s,
+                                         FV v) {
+    using M = Mfma<T>;
+    T sc[4], vc[4][MAXB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        sc[u] = s(4 * u);
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) vc[u][b] = (b < nb) ? v(b, 4 * u) : T(0);
+    }
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        T sn[4], vn[4][MAXB];
+        const bool more = k0 + 16 < K;
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sn[u] = s(k0 + 16 + 4 * u);
+#pragma unroll
+                for (int b = 0; b < MAXB; ++b) vn[u][b] = (b < nb) ? v(b, k0 + 16 + 4 * u) : T(0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int b = 0; b < MAXB; ++b)
+                if (b < nb) {
+                    if (SHARED_A) acc[b] = M::mma(sc[u], vc[u][b], acc[b]);
+                    else acc[b] = M::mma(vc[u][b], sc[u], acc[b]);
+                }
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sc[u] = sn[u];
+#pragma unroll
+                for (int b = 0; b < MAXB; ++b) vc[u][b] = vn[u][b];
+            }
+        }
+    }
+}
+
 struct XYArgs {
     const void* in[4];
     void* out[4];
@@ -70,7 +118,7 @@ __device__ __forceinline__ const T* xy_right(const FDTables<T>& t, int f, int in
     return f == 1 ? t.UK : t.UT;
 }
 
-template <typename T, typename TI, typename TO>
+template <typename T, typename TI, typename TO, bool STAGE>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     using V = typename M::V;
@@ -101,20 +149,24 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
     const T* R = xy_right(t, f, a.inverse);
     const int ldL = (f == 0) ? t.NNp : t.NMp;
     const int ldR = (f == 1) ? t.NNp : t.NMp;
+    if (STAGE) {
+        // small directions: the two dense 1D matrices move to LDS once
+        T* Ls = S + N2 * ld;
+        T* Rs = Ls + N1 * N1;
+        for (int idx = threadIdx.x; idx < N1 * N1; idx += FD_THREADS) Ls[idx] = L[idx];
+        for (int idx = threadIdx.x; idx < N2 * N2; idx += FD_THREADS) Rs[idx] = R[idx];
+        L = Ls;
+        R = Rs;
+        __syncthreads();
+    }
     // step 1: T = L X, in place by column blocks
     for (int cb = wave; cb < nb2; cb += 4) {
         V acc[MAXB];
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) acc[b] = V{0, 0, 0, 0};
-        for (int kk = 0; kk < N1; kk += 4) {
-            const T bv = S[(cb * 16 + lr) * ld + kk + lk];
-#pragma unroll
-            for (int b = 0; b < MAXB; ++b)
-                if (b < nb1) {
-                    const T av = L[(b * 16 + lr) * ldL + kk + lk];
-                    acc[b] = M::mma(av, bv, acc[b]);
-                }
-        }
+        mfma_row<T, false>(
+            acc, nb1, N1, [&](int kk) { return S[(cb * 16 + lr) * ld + kk + lk]; },
+            [&](int b, int kk) { return L[(b * 16 + lr) * ldL + kk + lk]; });
 #pragma unroll
         for (int b = 0; b < MAXB; ++b)
             if (b < nb1) {
@@ -129,15 +181,9 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
         V acc[MAXB];
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) acc[b] = V{0, 0, 0, 0};
-        for (int kk = 0; kk < N2; kk += 4) {
-            const T av = S[(kk + lk) * ld + rb * 16 + lr];
-#pragma unroll
-            for (int b = 0; b < MAXB; ++b)
-                if (b < nb2) {
-                    const T bv = R[(kk + lk) * ldR + b * 16 + lr];
-                    acc[b] = M::mma(av, bv, acc[b]);
-                }
-        }
+        mfma_row<T, true>(
+            acc, nb2, N2, [&](int kk) { return S[(kk + lk) * ld + rb * 16 + lr]; },
+            [&](int b, int kk) { return R[(kk + lk) * ldR + b * 16 + lr]; });
 #pragma unroll
         for (int b = 0; b < MAXB; ++b)
             if (b < nb2) {
@@ -166,9 +212,9 @@ struct ZArgs {
     double two_nu;
 };
 
-constexpr int ZROWS = 64;
+constexpr int ZROWS = 64;      // (i1,i2)-rows per z workgroup: 16 per wave
 
-template <typename T, typename TI, typename TO>
+template <typename T, typename TI, typename TO, bool STAGE>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     using V = typename M::V;
@@ -193,31 +239,38 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
         if (kk < n3 && r0 + row < plane) v = (T)x[r0 + row + (long long)kk * plane];
         S[row * ld + kk] = v;
     }
-    __syncthreads();
     const bool pres = (f == 3);
     const T* U3 = pres ? t.Mi : (f == 2 ? t.UK : t.UT);
+    const T* U3t = pres ? t.Mi : (f == 2 ? t.UKt : t.UTt);
     const int ldU = (f == 2) ? t.NNp : t.NMp;
+    if (STAGE) {
+        T* Us = S + ZROWS * ld;
+        T* Uts = Us + N3 * N3;
+        for (int idx = threadIdx.x; idx < N3 * N3; idx += FD_THREADS) {
+            Us[idx] = U3[idx];
+            if (!pres) Uts[idx] = U3t[idx];
+        }
+        U3 = Us;
+        U3t = Uts;
+    }
+    __syncthreads();
     T* Sw = S + wave * 16 * ld;  // this wave's 16 rows
+    const long long w0 = r0 + wave * 16;
     // Y = X U3
     V acc[MAXB];
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) acc[b] = V{0, 0, 0, 0};
-    for (int kk = 0; kk < N3; kk += 4) {
-        const T av = Sw[lr * ld + kk + lk];
-#pragma unroll
-        for (int b = 0; b < MAXB; ++b)
-            if (b < nb3) {
-                const T bv = U3[(kk + lk) * ldU + b * 16 + lr];
-                acc[b] = M::mma(av, bv, acc[b]);
-            }
-    }
+    if (w0 < plane)
+        mfma_row<T, true>(
+            acc, nb3, N3, [&](int kk) { return Sw[lr * ld + kk + lk]; },
+            [&](int b, int kk) { return U3[(kk + lk) * ldU + b * 16 + lr]; });
     if (pres) {
 #pragma unroll
         for (int b = 0; b < MAXB; ++b)
             if (b < nb3)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    Sw[(M::row(lk, i)) * ld + b * 16 + lr] = (T)(a.two_nu * (double)acc[b][i]);
+                    Sw[M::row(lk, i) * ld + b * 16 + lr] = (T)(a.two_nu * (double)acc[b][i]);
     } else {
         // scale by 1 / (2 nu (l1 + l2 + l3)) and transform back: Z = Y U3^T
         const double* l1 = (f == 0) ? t.lamK : t.lamT;
@@ -229,32 +282,26 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int row = M::row(lk, i);
-                    const long long rr = r0 + wave * 16 + row;
+                    const long long rr = w0 + row;
                     const int col = b * 16 + lr;
-                    double s = 0.0;
+                    double sc = 0.0;
                     if (rr < plane && col < n3) {
                         const int i1 = (int)(rr % n1), i2 = (int)(rr / n1);
-                        s = 1.0 / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
+                        sc = 1.0 / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
                     }
-                    Sw[row * ld + col] = (T)(s * (double)acc[b][i]);
+                    Sw[row * ld + col] = (T)(sc * (double)acc[b][i]);
                 }
-        const T* U3t = (f == 2) ? t.UKt : t.UTt;
 #pragma unroll
         for (int b = 0; b < MAXB; ++b) acc[b] = V{0, 0, 0, 0};
-        for (int kk = 0; kk < N3; kk += 4) {
-            const T av = Sw[lr * ld + kk + lk];
-#pragma unroll
-            for (int b = 0; b < MAXB; ++b)
-                if (b < nb3) {
-                    const T bv = U3t[(kk + lk) * ldU + b * 16 + lr];
-                    acc[b] = M::mma(av, bv, acc[b]);
-                }
-        }
+        if (w0 < plane)
+            mfma_row<T, true>(
+                acc, nb3, N3, [&](int kk) { return Sw[lr * ld + kk + lk]; },
+                [&](int b, int kk) { return U3t[(kk + lk) * ldU + b * 16 + lr]; });
 #pragma unroll
         for (int b = 0; b < MAXB; ++b)
             if (b < nb3)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) Sw[(M::row(lk, i)) * ld + b * 16 + lr] = acc[b][i];
+                for (int i = 0; i < 4; ++i) Sw[M::row(lk, i) * ld + b * 16 + lr] = acc[b][i];
     }
     __syncthreads();
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
@@ -266,6 +313,213 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
         if (a.accumulate) y[o] += v;
         else y[o] = v;
     }
+}
+
+// ---- tile-per-wave variants ----------------------------------------------------------
+// Each wave owns one 16x16 output tile at a time (16 waves per workgroup), so
+// every dependency chain is one tile's k-loop; the two GEMM steps use
+// separate LDS buffers.  Used when both buffers (and, when small enough,
+// the two dense 1D matrices) fit in LDS.
+constexpr int FD_WIDE = 1024;   // 16 waves
+
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* A, int lda_row, int lda_k,
+                                                         const T* B, int ldb_k, int ldb_col,
+                                                         int K, int lr, int lk) {
+    // D[16x16] = A[16 x K] B[K x 16]; A(row, k) = A[row*lda_row + k*lda_k],
+    // B(k, col) = B[k*ldb_k + col*ldb_col]; this lane supplies row/col lr, k-offset lk.
+    using M = Mfma<T>;
+    typename M::V acc = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = 0; kk < K; kk += 4) {
+        const T av = A[lr * lda_row + (kk + lk) * lda_k];
+        const T bv = B[(kk + lk) * ldb_k + lr * ldb_col];
+        acc = M::mma(av, bv, acc);
+    }
+    return acc;
+}
+
+template <typename T, typename TI, typename TO, bool STAGE>
+__global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
+    using M = Mfma<T>;
+    extern __shared__ unsigned char smem_raw[];
+    T* S = reinterpret_cast<T*>(smem_raw);
+    const int nf = a.fields_hi - a.fields_lo;
+    const int f = a.fields_lo + (int)(blockIdx.y % nf);
+    const int r = (int)(blockIdx.y / nf);
+    const int k = blockIdx.x;
+    const int n1 = a.dims[f][0], n2 = a.dims[f][1], n3 = a.dims[f][2];
+    if (k >= n3) return;
+    const int N1 = (n1 + 15) & ~15, N2 = (n2 + 15) & ~15;
+    const int ld = N1 + 1;  // column-major planes
+    const int nb1 = N1 >> 4, nb2 = N2 >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = FD_WIDE / 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    T* Tb = S + N2 * ld;
+    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] +
+                  (long long)k * n1 * n2;
+    for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_WIDE) {
+        int col = idx / N1, row = idx - col * N1;
+        T v = 0;
+        if (row < n1 && col < n2) v = (T)x[row + (long long)col * n1];
+        S[col * ld + row] = v;
+    }
+    const T* L = xy_left(t, f, a.inverse);
+    const T* R = xy_right(t, f, a.inverse);
+    int ldL = (f == 0) ? t.NNp : t.NMp;
+    int ldR = (f == 1) ? t.NNp : t.NMp;
+    if (STAGE) {
+        T* Ls = Tb + N2 * ld;
+        T* Rs = Ls + N1 * N1;
+        for (int idx = threadIdx.x; idx < N1 * N1; idx += FD_WIDE) Ls[idx] = L[idx];
+        for (int idx = threadIdx.x; idx < N2 * N2; idx += FD_WIDE) Rs[idx] = R[idx];
+        L = Ls;
+        R = Rs;
+    }
+    __syncthreads();
+    // step 1: T = L X  (tile (rb, cb): rows of L, columns of X)
+    for (int tt = wave; tt < nb1 * nb2; tt += nw) {
+        const int rb = tt % nb1, cb = tt / nb1;
+        auto acc = tile_gemm<T>(L + rb * 16 * ldL, ldL, 1, S + cb * 16 * ld, 1, ld, N1, lr, lk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) Tb[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
+    }
+    __syncthreads();
+    // step 2: Y = T R
+    for (int tt = wave; tt < nb1 * nb2; tt += nw) {
+        const int rb = tt % nb1, cb = tt / nb1;
+        auto acc = tile_gemm<T>(Tb + rb * 16, 1, ld, R + cb * 16, ldR, 1, N2, lr, lk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
+    }
+    __syncthreads();
+    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
+    for (int idx = threadIdx.x; idx < n1 * n2; idx += FD_WIDE) {
+        int col = idx / n1, row = idx - col * n1;
+        TO v = (TO)S[col * ld + row];
+        if (a.accumulate) y[idx] += v;
+        else y[idx] = v;
+    }
+}
+
+// z: 64 (i1,i2)-rows x n3 per workgroup, tiles of Y = X U3 and Z = Y U3^T
+// dealt to 16 waves; the scaling by 1/(2 nu (l1 + l2 + l3)) is applied to Y.
+template <typename T, typename TI, typename TO, bool STAGE>
+__global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
+    using M = Mfma<T>;
+    extern __shared__ unsigned char smem_raw[];
+    T* S = reinterpret_cast<T*>(smem_raw);
+    const int nf = a.fields_hi - a.fields_lo;
+    const int f = a.fields_lo + (int)(blockIdx.y % nf);
+    const int r = (int)(blockIdx.y / nf);
+    const int n1 = a.dims[f][0], n2 = a.dims[f][1], n3 = a.dims[f][2];
+    const long long plane = (long long)n1 * n2;
+    const long long r0 = (long long)blockIdx.x * ZROWS;
+    if (r0 >= plane) return;
+    const int N3 = (n3 + 15) & ~15;
+    const int ld = N3 + 1;  // row-major [row][k]
+    const int nb3 = N3 >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = FD_WIDE / 64;
+    const int lr = lane & 15, lk = lane >> 4;
+    T* Y = S + ZROWS * ld;
+    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f];
+    for (int idx = threadIdx.x; idx < ZROWS * N3; idx += FD_WIDE) {
+        int kk = idx / ZROWS, row = idx - kk * ZROWS;
+        T v = 0;
+        if (kk < n3 && r0 + row < plane) v = (T)x[r0 + row + (long long)kk * plane];
+        S[row * ld + kk] = v;
+    }
+    const bool pres = (f == 3);
+    const T* U3 = pres ? t.Mi : (f == 2 ? t.UK : t.UT);
+    const T* U3t = pres ? t.Mi : (f == 2 ? t.UKt : t.UTt);
+    const int ldU = (f == 2) ? t.NNp : t.NMp;
+    if (STAGE) {
+        T* Us = Y + ZROWS * ld;
+        T* Uts = Us + N3 * N3;
+        for (int idx = threadIdx.x; idx < N3 * N3; idx += FD_WIDE) {
+            Us[idx] = U3[idx];
+            if (!pres) Uts[idx] = U3t[idx];
+        }
+        U3 = Us;
+        U3t = Uts;
+    }
+    __syncthreads();
+    const int ntile = (ZROWS / 16) * nb3;
+    const double* l1 = (f == 0) ? t.lamK : t.lamT;
+    const double* l2 = (f == 1) ? t.lamK : t.lamT;
+    const double* l3 = (f == 2) ? t.lamK : t.lamT;
+    for (int tt = wave; tt < ntile; tt += nw) {
+        const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
+        auto acc = tile_gemm<T>(S + rb * 16 * ld, ld, 1, U3 + cb * 16, ldU, 1, N3, lr, lk);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = rb * 16 + M::row(lk, i);
+            const int col = cb * 16 + lr;
+            double sc;
+            if (pres) {
+                sc = a.two_nu;
+            } else {
+                sc = 0.0;
+                const long long rr = r0 + row;
+                if (rr < plane && col < n3) {
+                    const int i1 = (int)(rr % n1), i2 = (int)(rr / n1);
+                    sc = 1.0 / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
+                }
+            }
+            Y[row * ld + col] = (T)(sc * (double)acc[i]);
+        }
+    }
+    __syncthreads();
+    T* Out = Y;
+    if (!pres) {
+        for (int tt = wave; tt < ntile; tt += nw) {
+            const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
+            auto acc = tile_gemm<T>(Y + rb * 16 * ld, ld, 1, U3t + cb * 16, ldU, 1, N3, lr, lk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S[(rb * 16 + M::row(lk, i)) * ld + cb * 16 + lr] = acc[i];
+        }
+        __syncthreads();
+        Out = S;
+    }
+    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
+    for (int idx = threadIdx.x; idx < ZROWS * n3; idx += FD_WIDE) {
+        int kk = idx / ZROWS, row = idx - kk * ZROWS;
+        if (r0 + row >= plane) continue;
+        TO v = (TO)Out[row * ld + kk];
+        long long o = r0 + row + (long long)kk * plane;
+        if (a.accumulate) y[o] += v;
+        else y[o] = v;
+    }
+}
+
+// LDS plan for a direction of padded size np: wide (two buffers) or in place,
+// and whether the dense 1D matrices are staged in LDS as well.
+struct FDPlan {
+    bool wide, stage_xy, stage_z;
+    size_t shm_xy, shm_z;
+};
+
+template <typename T>
+FDPlan fd_plan(int np) {
+    const size_t lim = 160 * 1024, e = sizeof(T);
+    FDPlan pl{};
+    const size_t plane = (size_t)np * (np + 1) * e, mats = (size_t)2 * np * np * e;
+    const size_t zbuf = (size_t)ZROWS * (np + 1) * e;
+    pl.wide = 2 * plane <= lim && 2 * zbuf <= lim;
+    if (pl.wide) {
+        pl.stage_xy = 2 * plane + mats <= 140 * 1024;
+        pl.stage_z = 2 * zbuf + mats <= 140 * 1024;
+        pl.shm_xy = 2 * plane + (pl.stage_xy ? mats : 0);
+        pl.shm_z = 2 * zbuf + (pl.stage_z ? mats : 0);
+    } else {
+        pl.stage_xy = plane + mats <= 96 * 1024;
+        pl.stage_z = zbuf + mats <= 96 * 1024;
+        pl.shm_xy = plane + (pl.stage_xy ? mats : 0);
+        pl.shm_z = zbuf + (pl.stage_z ? mats : 0);
+    }
+    return pl;
 }
 
 template <typename T>
@@ -292,9 +546,52 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     xa.fields_hi = hi;
     xa.inverse = 0;
     xa.accumulate = 0;
-    size_t shm_xy = (size_t)NMp * (NMp + 1) * sizeof(T);
-    dim3 gxy(nM, nf * nrhs);
-    hipLaunchKernelGGL((k_fd_xy<T, double, T>), gxy, dim3(FD_THREADS), shm_xy, c->stream, xa, t);
+    const FDPlan pl = fd_plan<T>(NMp);
+    const dim3 bxy(pl.wide ? FD_WIDE : FD_THREADS);
+    auto launch_xy = [&](const XYArgs& xa_, bool to_double, int nfields) {
+        dim3 g(nM, nfields * nrhs);
+        if (pl.wide) {
+            if (to_double) {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            } else {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, double, T, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, double, T, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            }
+        } else {
+            if (to_double) {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy<T, T, double, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy<T, T, double, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            } else {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy<T, double, T, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy<T, double, T, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            }
+        }
+    };
+    auto launch_z = [&](const ZArgs& za_, bool to_double, int nfields) {
+        const long long maxplane = (long long)nM * nM;
+        dim3 g((unsigned)((maxplane + ZROWS - 1) / ZROWS), nfields * nrhs);
+        if (pl.wide) {
+            dim3 b(FD_WIDE);
+            if (to_double) {
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, double, true>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z_w<T, T, double, false>), g, b, pl.shm_z, c->stream, za_, t);
+            } else {
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, T, true>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z_w<T, T, T, false>), g, b, pl.shm_z, c->stream, za_, t);
+            }
+        } else {
+            dim3 b(FD_THREADS);
+            if (to_double) {
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z<T, T, double, true>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z<T, T, double, false>), g, b, pl.shm_z, c->stream, za_, t);
+            } else {
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z<T, T, T, true>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z<T, T, T, false>), g, b, pl.shm_z, c->stream, za_, t);
+            }
+        }
+    };
+    launch_xy(xa, false, nf);
     ZArgs za{};
     for (int f = 0; f < 4; ++f) {
         for (int d = 0; d < 3; ++d) za.dims[f][d] = (int)c->dims[f][d];
@@ -303,18 +600,13 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         za.out[f] = tmp2 + c->off[f];
         za.sout[f] = N;
     }
-    za.fields_lo = lo;
-    za.fields_hi = hi;
-    za.accumulate = 0;
     za.two_nu = 2.0 * c->nu;
-    size_t shm_z = (size_t)ZROWS * (NMp + 1) * sizeof(T);
-    long long maxplane = (long long)nM * nM;
     if (vel) {
         ZArgs zv = za;
         zv.fields_lo = 0;
         zv.fields_hi = 3;
-        dim3 g((unsigned)((maxplane + ZROWS - 1) / ZROWS), 3 * nrhs);
-        hipLaunchKernelGGL((k_fd_z<T, T, T>), g, dim3(FD_THREADS), shm_z, c->stream, zv, t);
+        zv.accumulate = 0;
+        launch_z(zv, false, 3);
     }
     if (pres) {
         ZArgs zp = za;
@@ -323,8 +615,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         zp.out[3] = out.f[3];
         zp.sout[3] = out.stride[3];
         zp.accumulate = accumulate ? 1 : 0;
-        dim3 g((unsigned)((maxplane + ZROWS - 1) / ZROWS), nrhs);
-        hipLaunchKernelGGL((k_fd_z<T, T, double>), g, dim3(FD_THREADS), shm_z, c->stream, zp, t);
+        launch_z(zp, true, 1);
     }
     if (vel) {
         XYArgs xi = xa;
@@ -338,8 +629,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         xi.fields_hi = 3;
         xi.inverse = 1;
         xi.accumulate = accumulate ? 1 : 0;
-        dim3 g(nM, 3 * nrhs);
-        hipLaunchKernelGGL((k_fd_xy<T, T, double>), g, dim3(FD_THREADS), shm_xy, c->stream, xi, t);
+        launch_xy(xi, true, 3);
     }
     return hipGetLastError();
 }
@@ -347,18 +637,28 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
 template <typename T>
 hipError_t set_fd_attrs() {
     const int bytes = 160 * 1024;
-    hipError_t e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_xy<T, double, T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_xy<T, T, double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_z<T, T, T>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fd_z<T, T, double>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void* ks[] = {
+        reinterpret_cast<const void*>(&k_fd_xy<T, double, T, true>),
+        reinterpret_cast<const void*>(&k_fd_xy<T, double, T, false>),
+        reinterpret_cast<const void*>(&k_fd_xy<T, T, double, true>),
+        reinterpret_cast<const void*>(&k_fd_xy<T, T, double, false>),
+        reinterpret_cast<const void*>(&k_fd_z<T, T, T, true>),
+        reinterpret_cast<const void*>(&k_fd_z<T, T, T, false>),
+        reinterpret_cast<const void*>(&k_fd_z<T, T, double, true>),
+        reinterpret_cast<const void*>(&k_fd_z<T, T, double, false>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, double, T, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, double, T, false>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, false>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, false>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, false>)};
+    for (const void* k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace

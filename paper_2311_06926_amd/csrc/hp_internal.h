@@ -62,6 +62,7 @@ struct hp_ctx {
     hp::BandTables band{};
     hp::FDTables<double> fd64{};
     hp::FDTables<float> fd32{};
+    bool fd_ok = false;  // fast-diagonalisation tables present (<= 128 per direction)
     // workspace (per right-hand side sizes scale with max_rhs)
     double* ws = nullptr;
     size_t ws_doubles = 0;

@@ -236,3 +236,139 @@ hipError_t vec_dots(hp_ctx* c, long long n, long long ld, const double* x, const
 }
 
 }  // namespace hp
+
+// =====================================================================================
+// MINRES with device-resident scalars (one thread per right-hand side).  The
+// Lanczos/Givens recurrences of preconditioned MINRES run in these kernels,
+// so an iteration needs no host round trip and can be replayed as a graph.
+// Dot products are finished here from the fixed-order per-block partials.
+namespace hp {
+namespace {
+
+__device__ double sum_partials(const double* part, int q) {
+    double s = 0.0;
+    for (int i = 0; i < DOT_BLOCKS; ++i) s += part[(long long)q * DOT_BLOCKS + i];
+    return s;
+}
+
+// after z = P^{-1} b:  gamma = sqrt(z.v), beta0 = eta = gamma, c = 1, s = 0
+__global__ void k_minres_init(MinresScalars* sc, const double* part_zv, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    MinresScalars& m = sc[r];
+    const double zv = sum_partials(part_zv, r);
+    m = MinresScalars{};
+    m.status = 0;
+    if (!(zv >= 0.0) || !isfinite(zv)) {
+        m.status = zv < 0.0 ? -4 : -7;
+        m.done = 1;
+        return;
+    }
+    m.gamma = sqrt(zv);
+    m.gamma_old = 1.0;
+    m.beta0 = m.gamma;
+    m.eta = m.gamma;
+    m.c0 = m.c1 = 1.0;
+    m.s0 = m.s1 = 0.0;
+    m.rel = 1.0;
+    m.done = (m.gamma == 0.0);
+    if (m.done) m.rel = 0.0;
+}
+
+// after Kz = K z:  delta = (Kz.z)/gamma^2; coefficients of v_new = Kz/gamma - (delta/gamma) v - (gamma/gamma_old) v_old
+__global__ void k_minres_a(MinresScalars* sc, const double* part_kz, double* coef_v, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    MinresScalars& m = sc[r];
+    double* cv = coef_v + 3 * r;
+    if (m.done) {
+        cv[0] = cv[1] = cv[2] = 0.0;
+        return;
+    }
+    const double g = m.gamma;
+    m.delta = sum_partials(part_kz, r) / (g * g);
+    cv[0] = 1.0 / g;
+    cv[1] = -m.delta / g;
+    cv[2] = -g / m.gamma_old;
+}
+
+// after z_new = P^{-1} v_new: gamma_new, the Givens rotation, coefficients of
+// w_new = (z/gamma - a3 w_old - a2 w)/a1 and x += c_new eta w_new, then shift.
+__global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coef_w,
+                           double* coef_x, double tol, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    MinresScalars& m = sc[r];
+    double* cw = coef_w + 3 * r;
+    double* cx = coef_x + 2 * r;
+    cx[0] = 1.0;
+    if (m.done) {
+        cw[0] = cw[1] = cw[2] = 0.0;
+        cx[1] = 0.0;
+        return;
+    }
+    double zv = sum_partials(part_zv, r);
+    if (!isfinite(zv)) {
+        m.status = -7;
+        m.done = 1;
+        cw[0] = cw[1] = cw[2] = 0.0;
+        cx[1] = 0.0;
+        return;
+    }
+    if (zv < 0.0) {
+        m.status = -4;
+        zv = 0.0;
+    }
+    const double gn = sqrt(zv), g = m.gamma;
+    const double a0 = m.c1 * m.delta - m.c0 * m.s1 * g;
+    const double a1 = hypot(a0, gn);
+    const double a2 = m.s1 * m.delta + m.c0 * m.c1 * g;
+    const double a3 = m.s0 * g;
+    if (a1 == 0.0) {
+        m.status = -5;
+        m.done = 1;
+        cw[0] = cw[1] = cw[2] = 0.0;
+        cx[1] = 0.0;
+        return;
+    }
+    const double cn = a0 / a1, sn = gn / a1;
+    cw[0] = 1.0 / (g * a1);
+    cw[1] = -a3 / a1;
+    cw[2] = -a2 / a1;
+    cx[1] = cn * m.eta;
+    m.eta = -sn * m.eta;
+    m.gamma_old = g;
+    m.gamma = gn;
+    m.c0 = m.c1;
+    m.c1 = cn;
+    m.s0 = m.s1;
+    m.s1 = sn;
+    m.rel = fabs(m.eta) / m.beta0;
+    m.iters += 1;
+    if (m.rel <= tol || gn == 0.0 || m.status != 0) m.done = 1;
+}
+
+}  // namespace
+
+hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs) {
+    hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
+    return hipGetLastError();
+}
+hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double* coef_v, int nrhs) {
+    hipLaunchKernelGGL(k_minres_a, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, coef_v, nrhs);
+    return hipGetLastError();
+}
+hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
+                    double* coef_x, double tol, int nrhs) {
+    hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, coef_w,
+                       coef_x, tol, nrhs);
+    return hipGetLastError();
+}
+hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
+                            const double* Y, int nrhs, double* partial) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, 1, nrhs), dim3(VT), 0, s, n, ld, X, 0LL, 1, Y,
+                       partial);
+    return hipGetLastError();
+}
+
+}  // namespace hp

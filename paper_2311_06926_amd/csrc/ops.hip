@@ -12,22 +12,24 @@
 // the degree p-1 ones), so one application costs O(N p) flops.
 //
 // Three kernels:
-//   xy : per (row strip, i3-plane, field): directions 1 and 2 of every
-//        Kronecker term, staged through LDS.  Velocity component c yields two
-//        partial sums Ga, Gb grouped by their direction-3 factor; the pressure
-//        field forms g = D u and z = nu g + p on the fly and yields M^ (x) M^ g,
-//        M^ (x) M^ z.
+//   xy : per (64-column x 16-row tile, i3-plane, field): directions 1 and 2
+//        of every Kronecker term, the tile and its halo staged in LDS.  Velocity component c yields two partial sums Ga,
+//        Gb grouped by their direction-3 factor; the pressure field forms
+//        g = D u and z = nu g + p on the fly and yields M^ (x) M^ g, M^ (x) M^ z.
 //   zp : direction 3 for the pressure: y_p = M^_3 G_g, w = M^_3 G_z.
 //   zv : direction 3 for the velocity and the coupling:
 //        y_c = nu (A3a Ga + A3b Gb) + D_c^T w, with an axpby epilogue.
+//   Both z kernels give each thread one (i1, i2) point and 8 output planes;
+//   the planes and their halo are loaded into registers up front, and the
+//   band coefficients are uniform across the wave.
 #include "hp_internal.h"
 
 namespace hp {
 
 namespace {
 
-constexpr int XY_ROWS = 8;      // output rows (direction 2) per xy workgroup
-constexpr int XY_THREADS = 256;
+constexpr int XY_CHUNK = 16;    // output rows (direction 2) per xy workgroup
+constexpr int ZCHUNK = 8;       // output planes (direction 3) per z thread
 constexpr int Z_THREADS = 256;
 
 struct OpArgs {
@@ -44,19 +46,177 @@ struct OpArgs {
     int mode;
 };
 
-__device__ __forceinline__ double band_at(const double* tab, int w, int row, int t) {
-    return tab[row * (2 * w + 1) + t];
+// ---- xy pass -----------------------------------------------------------------------
+// A workgroup owns a tile of XY_T1 direction-1 columns x XY_CHUNK direction-2
+// rows of one i3-plane.  The tile plus its halo (w1 columns, w2 rows on each
+// side) is staged in LDS; thread (column c, row group g) applies the
+// direction-1 band with its row of coefficients held in registers, then the
+// direction-2 band whose row is the same for the whole wave (rows are dealt to
+// waves), so its coefficients are scalar loads.  Two barriers per tile.
+constexpr int XY_T1 = 64;                 // direction-1 columns per tile
+constexpr int XY_THREADS = 256;           // 4 waves = 4 row groups
+constexpr int XY_GROUPS = XY_THREADS / XY_T1;
+
+template <int P, int C>
+__device__ void xy_velocity(const OpArgs& a, int r, int k, int i0, int j0, double* lds) {
+    constexpr int W1 = (C == 0) ? P : P - 1;
+    constexpr int W2 = (C == 1) ? P : P - 1;
+    constexpr int TW = XY_T1 + 2 * W1;        // staged columns
+    constexpr int TR = XY_CHUNK + 2 * W2;     // staged rows
+    const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
+    if (k >= n3 || j0 >= n2 || i0 >= n1) return;
+    const bool mv = (a.mode == OP_MV);
+    double* xs = lds;                 // TR x TW
+    double* pa = xs + TR * TW;        // TR x XY_T1
+    double* pb = pa + TR * XY_T1;
+    const double* x = a.u[C] + (long long)r * a.su + (long long)k * n1 * n2;
+    for (int idx = threadIdx.x; idx < TR * TW; idx += XY_THREADS) {
+        const int rr = idx / TW, cc = idx - rr * TW;
+        const int j = j0 - W2 + rr, i = i0 - W1 + cc;
+        xs[idx] = (j >= 0 && j < n2 && i >= 0 && i < n1) ? x[(long long)j * n1 + i] : 0.0;
+    }
+    const int c = threadIdx.x % XY_T1, g = threadIdx.x / XY_T1;
+    const int i = i0 + c;
+    const bool act = i < n1;
+    const double* t1a = a.bt.ptr[C == 0 ? (mv ? BM_N : BK_N) : BM_C];
+    const double* t1b = a.bt.ptr[C == 0 ? BM_N : BT_C];
+    double ca[2 * W1 + 1], cb[2 * W1 + 1];
+#pragma unroll
+    for (int t = 0; t <= 2 * W1; ++t) {
+        ca[t] = act ? t1a[i * (2 * W1 + 1) + t] : 0.0;
+        cb[t] = (act && !mv) ? t1b[i * (2 * W1 + 1) + t] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = g; rr < TR; rr += XY_GROUPS) {
+        const double* row = xs + rr * TW + c;
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W1; ++t) {
+            sa += ca[t] * row[t];
+            sb += cb[t] * row[t];
+        }
+        pa[rr * XY_T1 + c] = sa;
+        pb[rr * XY_T1 + c] = sb;
+    }
+    __syncthreads();
+    if (!act) return;
+    const double* m2 = a.bt.ptr[C == 1 ? BM_N : BM_C];   // mass of direction 2
+    const double* k2 = a.bt.ptr[C == 1 ? BK_N : BT_C];   // K (C==1) or T^ (C==0, 2)
+    double* ws = a.ws + (long long)r * a.ws_stride;
+    double* Ga = ws + a.wsGa[C] + (long long)k * n1 * n2;
+    double* Gb = ws + a.wsGb[C] + (long long)k * n1 * n2;
+    for (int o = g; o < XY_CHUNK; o += XY_GROUPS) {
+        const int j = j0 + o;
+        if (j >= n2) break;
+        const double* rm = m2 + j * (2 * W2 + 1);
+        const double* rk = k2 + j * (2 * W2 + 1);
+        double am = 0.0, ak = 0.0, bm = 0.0, bk = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W2; ++t) {
+            const double va = pa[(o + t) * XY_T1 + c], vb = pb[(o + t) * XY_T1 + c];
+            am += rm[t] * va;
+            ak += rk[t] * va;
+            bm += rm[t] * vb;
+            bk += rk[t] * vb;
+        }
+        double ga, gb = 0.0;
+        if (mv) {
+            ga = am;
+        } else if (C == 0) {          // M^2 K1 + 2 T^2 M1  |  2 M^2 M1
+            ga = am + 2.0 * bk;
+            gb = 2.0 * bm;
+        } else if (C == 1) {          // K2 M^1 + 2 M2 T^1  |  2 M2 M^1
+            ga = ak + 2.0 * bm;
+            gb = 2.0 * am;
+        } else {                      // M^2 M^1  |  2 (T^2 M^1 + M^2 T^1)
+            ga = am;
+            gb = 2.0 * (ak + bm);
+        }
+        Ga[(long long)j * n1 + i] = ga;
+        if (!mv) Gb[(long long)j * n1 + i] = gb;
+    }
 }
 
-// direction-1 banded product of one row held in LDS: out[i] = sum_t A[i][t] in[i+t-w]
-__device__ __forceinline__ double dir1(const double* tab, int w, const double* row, int n1,
-                                       int i) {
-    double s = 0.0;
-    for (int t = 0; t <= 2 * w; ++t) {
-        int j = i + t - w;
-        if (j >= 0 && j < n1) s += tab[i * (2 * w + 1) + t] * row[j];
+// pressure: g = D u, z = nu g + p on the tile and halo, then M^ (x) M^ on both
+template <int P>
+__device__ void xy_pressure(const OpArgs& a, int r, int k, int i0, int j0, double* lds) {
+    constexpr int W = P - 1;
+    constexpr int TW = XY_T1 + 2 * W;
+    constexpr int TR = XY_CHUNK + 2 * W;
+    const int mode = a.mode;
+    const bool need_g = (mode == OP_K || mode == OP_BT);
+    const bool need_z = (mode != OP_BT);
+    const bool use_u = (mode != OP_B);
+    const bool use_p = (mode == OP_K || mode == OP_B);
+    const int nM = a.nM, nN = a.nN;
+    if (k >= nM || j0 >= nM || i0 >= nM) return;
+    double* gs = lds;              // TR x TW
+    double* zs = gs + TR * TW;
+    double* pg = zs + TR * TW;     // TR x XY_T1
+    double* pz = pg + TR * XY_T1;
+    const double* u1 = use_u ? a.u[0] + (long long)r * a.su : nullptr;
+    const double* u2 = use_u ? a.u[1] + (long long)r * a.su : nullptr;
+    const double* u3 = use_u ? a.u[2] + (long long)r * a.su : nullptr;
+    const double* pp = use_p ? a.p + (long long)r * a.sp : nullptr;
+    for (int idx = threadIdx.x; idx < TR * TW; idx += XY_THREADS) {
+        const int rr = idx / TW, cc = idx - rr * TW;
+        const int j = j0 - W + rr, i = i0 - W + cc;
+        double g = 0.0, z = 0.0;
+        if (j >= 0 && j < nM && i >= 0 && i < nM) {
+            if (use_u) {
+                // u1: (nN, nM, nM); u2: (nM, nN, nM); u3: (nM, nM, nN)
+                const long long b1 = (long long)nN * (j + (long long)nM * k);
+                if (i < nN) g += u1[b1 + i];
+                if (i >= 1) g -= u1[b1 + i - 1];
+                if (j < nN) g += u2[i + (long long)nM * (j + (long long)nN * k)];
+                if (j >= 1) g -= u2[i + (long long)nM * ((j - 1) + (long long)nN * k)];
+                if (k < nN) g += u3[i + (long long)nM * (j + (long long)nM * k)];
+                if (k >= 1) g -= u3[i + (long long)nM * (j + (long long)nM * (k - 1))];
+            }
+            const double pv = use_p ? pp[i + (long long)nM * (j + (long long)nM * k)] : 0.0;
+            z = (mode == OP_B) ? pv : a.nu * g + pv;
+        }
+        gs[idx] = g;
+        zs[idx] = z;
     }
-    return s;
+    const int c = threadIdx.x % XY_T1, grp = threadIdx.x / XY_T1;
+    const int i = i0 + c;
+    const bool act = i < nM;
+    const double* tm = a.bt.ptr[BM_C];
+    double cm[2 * W + 1];
+#pragma unroll
+    for (int t = 0; t <= 2 * W; ++t) cm[t] = act ? tm[i * (2 * W + 1) + t] : 0.0;
+    __syncthreads();
+    for (int rr = grp; rr < TR; rr += XY_GROUPS) {
+        const double* rg = gs + rr * TW + c;
+        const double* rz = zs + rr * TW + c;
+        double sg = 0.0, sz = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            sg += cm[t] * rg[t];
+            sz += cm[t] * rz[t];
+        }
+        pg[rr * XY_T1 + c] = sg;
+        pz[rr * XY_T1 + c] = sz;
+    }
+    __syncthreads();
+    if (!act) return;
+    double* ws = a.ws + (long long)r * a.ws_stride;
+    double* Gg = ws + a.wsGg + (long long)k * nM * nM;
+    double* Gz = ws + a.wsGz + (long long)k * nM * nM;
+    for (int o = grp; o < XY_CHUNK; o += XY_GROUPS) {
+        const int j = j0 + o;
+        if (j >= nM) break;
+        const double* rm = tm + j * (2 * W + 1);
+        double sg = 0.0, sz = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            sg += rm[t] * pg[(o + t) * XY_T1 + c];
+            sz += rm[t] * pz[(o + t) * XY_T1 + c];
+        }
+        if (need_g) Gg[(long long)j * nM + i] = sg;
+        if (need_z) Gz[(long long)j * nM + i] = sz;
+    }
 }
 
 template <int P>
@@ -65,224 +225,134 @@ __global__ __launch_bounds__(XY_THREADS) void k_xy(OpArgs a) {
     const int f = blockIdx.z & 3;
     const int r = blockIdx.z >> 2;
     const int k = blockIdx.y;
-    const int j0 = blockIdx.x * XY_ROWS;
-    const int WN = P, WM = P - 1;
+    const int ntile1 = (a.nM + XY_T1 - 1) / XY_T1;
+    const int i0 = (blockIdx.x % ntile1) * XY_T1;
+    const int j0 = (blockIdx.x / ntile1) * XY_CHUNK;
     const int mode = a.mode;
-    const BandTables& bt = a.bt;
-    double* ws = a.ws + (long long)r * a.ws_stride;
-
     if (f < 3) {
         if (mode != OP_K && mode != OP_A && mode != OP_MV) return;
-        const int c = f;
-        const int n1 = a.dims[c][0], n2 = a.dims[c][1], n3 = a.dims[c][2];
-        if (k >= n3 || j0 >= n2) return;
-        const int w1 = (c == 0) ? WN : WM;
-        const int w2 = (c == 1) ? WN : WM;
-        const int R = XY_ROWS + 2 * w2;
-        const int rows_out = min(XY_ROWS, n2 - j0);
-        double* xs = lds;
-        double* pa = xs + R * n1;
-        double* pb = pa + R * n1;
-        const double* x = a.u[c] + (long long)r * a.su + (long long)k * n1 * n2;
-        for (int idx = threadIdx.x; idx < R * n1; idx += blockDim.x) {
-            int jj = idx / n1, i = idx - jj * n1;
-            int j = j0 - w2 + jj;
-            xs[idx] = (j >= 0 && j < n2) ? x[(long long)j * n1 + i] : 0.0;
-        }
-        __syncthreads();
-        const bool mv = (mode == OP_MV);
-        const double* t1a = bt.ptr[c == 0 ? (mv ? BM_N : BK_N) : BM_C];
-        const double* t1b = bt.ptr[c == 0 ? BM_N : BT_C];
-        for (int idx = threadIdx.x; idx < R * n1; idx += blockDim.x) {
-            int jj = idx / n1, i = idx - jj * n1;
-            const double* row = xs + jj * n1;
-            pa[idx] = dir1(t1a, w1, row, n1, i);
-            if (!mv) pb[idx] = dir1(t1b, w1, row, n1, i);
-        }
-        __syncthreads();
-        double* Ga = ws + a.wsGa[c] + (long long)k * n1 * n2;
-        double* Gb = ws + a.wsGb[c] + (long long)k * n1 * n2;
-        for (int idx = threadIdx.x; idx < rows_out * n1; idx += blockDim.x) {
-            int jo = idx / n1, i = idx - jo * n1;
-            int j = j0 + jo;
-            double ga = 0.0, gb = 0.0;
-            const int W = 2 * w2 + 1;
-            for (int t = 0; t < W; ++t) {
-                const int jj = jo + t;  // row j + t - w2 in strip coordinates
-                const double xa = pa[jj * n1 + i];
-                if (mv) {
-                    ga += bt.ptr[c == 1 ? BM_N : BM_C][j * W + t] * xa;
-                    continue;
-                }
-                const double xb = pb[jj * n1 + i];
-                if (c == 0) {
-                    const double m = bt.ptr[BM_C][j * W + t], tt = bt.ptr[BT_C][j * W + t];
-                    ga += m * xa + 2.0 * tt * xb;
-                    gb += 2.0 * m * xb;
-                } else if (c == 1) {
-                    const double kk = bt.ptr[BK_N][j * W + t], mm = bt.ptr[BM_N][j * W + t];
-                    ga += kk * xa + 2.0 * mm * xb;
-                    gb += 2.0 * mm * xa;
-                } else {
-                    const double m = bt.ptr[BM_C][j * W + t], tt = bt.ptr[BT_C][j * W + t];
-                    ga += m * xa;
-                    gb += 2.0 * (tt * xa + m * xb);
-                }
-            }
-            Ga[(long long)j * n1 + i] = ga;
-            if (!mv) Gb[(long long)j * n1 + i] = gb;
-        }
+        if (f == 0) xy_velocity<P, 0>(a, r, k, i0, j0, lds);
+        else if (f == 1) xy_velocity<P, 1>(a, r, k, i0, j0, lds);
+        else xy_velocity<P, 2>(a, r, k, i0, j0, lds);
     } else {
-        // pressure field: g = D u, z = nu g + p, then M^ (x) M^ on both
         if (mode == OP_MV) return;
-        const bool need_g = (mode == OP_K || mode == OP_BT);
-        const bool need_z = (mode != OP_BT);
-        const bool use_u = (mode != OP_B);
-        const int nM = a.nM, nN = a.nN;
-        if (k >= nM || j0 >= nM) return;
-        const int w = WM;
-        const int R = XY_ROWS + 2 * w;
-        const int rows_out = min(XY_ROWS, nM - j0);
-        double* gs = lds;
-        double* zs = gs + R * nM;
-        double* pg = zs + R * nM;
-        double* pz = pg + R * nM;
-        const double* u1 = use_u ? a.u[0] + (long long)r * a.su : nullptr;
-        const double* u2 = use_u ? a.u[1] + (long long)r * a.su : nullptr;
-        const double* u3 = use_u ? a.u[2] + (long long)r * a.su : nullptr;
-        const double* pp = (mode == OP_K || mode == OP_B) ? a.p + (long long)r * a.sp : nullptr;
-        for (int idx = threadIdx.x; idx < R * nM; idx += blockDim.x) {
-            int jj = idx / nM, i = idx - jj * nM;
-            int j = j0 - w + jj;
-            double g = 0.0, z = 0.0;
-            if (j >= 0 && j < nM) {
-                if (use_u) {
-                    // u1: (nN, nM, nM); u2: (nM, nN, nM); u3: (nM, nM, nN)
-                    if (i < nN) g += u1[i + (long long)nN * (j + (long long)nM * k)];
-                    if (i >= 1) g -= u1[(i - 1) + (long long)nN * (j + (long long)nM * k)];
-                    if (j < nN) g += u2[i + (long long)nM * (j + (long long)nN * k)];
-                    if (j >= 1) g -= u2[i + (long long)nM * ((j - 1) + (long long)nN * k)];
-                    if (k < nN) g += u3[i + (long long)nM * (j + (long long)nM * k)];
-                    if (k >= 1) g -= u3[i + (long long)nM * (j + (long long)nM * (k - 1))];
-                }
-                if (mode == OP_K) z = a.nu * g + pp[i + (long long)nM * (j + (long long)nM * k)];
-                else if (mode == OP_A) z = a.nu * g;
-                else if (mode == OP_B) z = pp[i + (long long)nM * (j + (long long)nM * k)];
-            }
-            gs[idx] = g;
-            zs[idx] = z;
-        }
-        __syncthreads();
-        const double* tm = bt.ptr[BM_C];
-        for (int idx = threadIdx.x; idx < R * nM; idx += blockDim.x) {
-            int jj = idx / nM, i = idx - jj * nM;
-            if (need_g) pg[idx] = dir1(tm, w, gs + jj * nM, nM, i);
-            if (need_z) pz[idx] = dir1(tm, w, zs + jj * nM, nM, i);
-        }
-        __syncthreads();
-        double* Gg = ws + a.wsGg + (long long)k * nM * nM;
-        double* Gz = ws + a.wsGz + (long long)k * nM * nM;
-        const int W = 2 * w + 1;
-        for (int idx = threadIdx.x; idx < rows_out * nM; idx += blockDim.x) {
-            int jo = idx / nM, i = idx - jo * nM;
-            int j = j0 + jo;
-            double sg = 0.0, sz = 0.0;
-            for (int t = 0; t < W; ++t) {
-                const double m = tm[j * W + t];
-                sg += m * pg[(jo + t) * nM + i];
-                sz += m * pz[(jo + t) * nM + i];
-            }
-            if (need_g) Gg[(long long)j * nM + i] = sg;
-            if (need_z) Gz[(long long)j * nM + i] = sz;
-        }
+        xy_pressure<P>(a, r, k, i0, j0, lds);
     }
 }
 
-// direction 3 for the pressure: y_p = M^_3 G_g (modes K, BT), w = M^_3 G_z
+// ---- direction 3, pressure: y_p = M^_3 G_g, w = M^_3 G_z --------------------------
+// Thread = one (i1, i2) point; it loads the ZCHUNK planes it outputs plus a
+// halo of W on each side into registers, then forms the band products.
 template <int P>
 __global__ __launch_bounds__(Z_THREADS) void k_zp(OpArgs a, double* yp, long long syp) {
-    const int r = blockIdx.y;
+    constexpr int W = P - 1;
+    constexpr int R = ZCHUNK + 2 * W;
+    const int r = blockIdx.z;
     const int nM = a.nM;
-    const long long nQ = (long long)nM * nM * nM;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nQ) return;
-    const int w = P - 1, W = 2 * w + 1;
     const long long plane = (long long)nM * nM;
-    const int k = (int)(idx / plane);
-    const double* ws = a.ws + (long long)r * a.ws_stride;
+    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k0 = blockIdx.y * ZCHUNK;
+    if (k0 >= nM || pidx >= plane) return;
+    double* ws = a.ws + (long long)r * a.ws_stride;
     const double* tm = a.bt.ptr[BM_C];
     const bool need_g = (a.mode == OP_K || a.mode == OP_BT);
     const bool need_z = (a.mode != OP_BT);
-    double sg = 0.0, sz = 0.0;
-    for (int t = 0; t < W; ++t) {
-        const int kk = k + t - w;
-        if (kk < 0 || kk >= nM) continue;
-        const double m = tm[k * W + t];
-        const long long src = idx + (long long)(t - w) * plane;
-        if (need_g) sg += m * ws[a.wsGg + src];
-        if (need_z) sz += m * ws[a.wsGz + src];
+    double g[R], z[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int kk = k0 - W + s;
+        const bool in = kk >= 0 && kk < nM;
+        const long long src = pidx + (long long)kk * plane;
+        g[s] = (need_g && in) ? ws[a.wsGg + src] : 0.0;
+        z[s] = (need_z && in) ? ws[a.wsGz + src] : 0.0;
     }
-    if (need_g) yp[(long long)r * syp + idx] = sg;
-    if (need_z) a.ws[(long long)r * a.ws_stride + a.wsW + idx] = sz;
+#pragma unroll
+    for (int o = 0; o < ZCHUNK; ++o) {
+        const int k = k0 + o;
+        if (k >= nM) break;
+        const double* rm = tm + k * (2 * W + 1);
+        double sg = 0.0, sz = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            sg += rm[t] * g[o + t];
+            sz += rm[t] * z[o + t];
+        }
+        const long long o3 = pidx + (long long)k * plane;
+        if (need_g) yp[(long long)r * syp + o3] = sg;
+        if (need_z) ws[a.wsW + o3] = sz;
+    }
 }
 
-// direction 3 for the velocity + D^T w; y = alpha * v + beta * src
+// ---- direction 3, velocity + D^T w; y = alpha v + beta src -------------------------
+template <int P, int C>
+__device__ void zv_component(const OpArgs& a, const Fields& out, const Fields& src, double alpha,
+                             double beta, int r) {
+    constexpr int W3 = (C == 2) ? P : P - 1;
+    constexpr int R = ZCHUNK + 2 * W3;
+    const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
+    const long long plane = (long long)n1 * n2;
+    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k0 = blockIdx.y * ZCHUNK;
+    if (k0 >= n3 || pidx >= plane) return;
+    const int i = (int)(pidx % n1);
+    const int j = (int)(pidx / n1);
+    const double* ws = a.ws + (long long)r * a.ws_stride;
+    const bool mv = (a.mode == OP_MV);
+    const bool lop = (a.mode == OP_K || a.mode == OP_A);
+    const bool cpl = !mv && a.mode != OP_BT;
+    const double* ta = a.bt.ptr[C == 2 ? (mv ? BM_N : BK_N) : BM_C];
+    const double* tb = a.bt.ptr[C == 2 ? BM_N : BT_C];
+    const double* Ga = ws + a.wsGa[C];
+    const double* Gb = ws + a.wsGb[C];
+    const double* wv = ws + a.wsW;
+    const int nM = a.nM;
+    const long long wstep = (C == 0) ? 1 : (C == 1) ? nM : (long long)nM * nM;
+    double* y = out.f[C] + (long long)r * out.stride[C];
+    const double* sv = (beta != 0.0) ? src.f[C] + (long long)r * src.stride[C] : nullptr;
+    double ga[R], gb[R];
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+        const int kk = k0 - W3 + s;
+        const bool in = (lop || mv) && kk >= 0 && kk < n3;
+        const long long sidx = pidx + (long long)kk * plane;
+        ga[s] = in ? Ga[sidx] : 0.0;
+        gb[s] = (in && lop) ? Gb[sidx] : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < ZCHUNK; ++o) {
+        const int k = k0 + o;
+        if (k >= n3) break;
+        double v = 0.0;
+        if (lop || mv) {
+            const double* ra = ta + k * (2 * W3 + 1);
+            const double* rb = tb + k * (2 * W3 + 1);
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * W3; ++t) {
+                sa += ra[t] * ga[o + t];
+                sb += rb[t] * gb[o + t];
+            }
+            v = mv ? sa : a.nu * (sa + sb);
+        }
+        if (cpl) {
+            const long long wi = i + (long long)nM * (j + (long long)nM * k);
+            v += wv[wi] - wv[wi + wstep];
+        }
+        const long long o3 = pidx + (long long)k * plane;
+        double res = alpha * v;
+        if (sv) res += beta * sv[o3];
+        y[o3] = res;
+    }
+}
+
 template <int P>
 __global__ __launch_bounds__(Z_THREADS) void k_zv(OpArgs a, Fields out, Fields src, double alpha,
                                                   double beta) {
-    const int c = blockIdx.y;
-    const int r = blockIdx.z;
-    const int n1 = a.dims[c][0], n2 = a.dims[c][1], n3 = a.dims[c][2];
-    const long long nc = (long long)n1 * n2 * n3;
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nc) return;
-    const long long plane = (long long)n1 * n2;
-    const int k = (int)(idx / plane);
-    const long long rem = idx - (long long)k * plane;
-    const int j = (int)(rem / n1);
-    const int i = (int)(rem - (long long)j * n1);
-    const double* ws = a.ws + (long long)r * a.ws_stride;
-    double v = 0.0;
-    if (a.mode == OP_MV) {
-        const int w3 = (c == 2) ? P : P - 1;
-        const int W = 2 * w3 + 1;
-        const double* ta = a.bt.ptr[c == 2 ? BM_N : BM_C];
-        const double* Ga = ws + a.wsGa[c];
-        double s = 0.0;
-        for (int t = 0; t < W; ++t) {
-            const int kk = k + t - w3;
-            if (kk < 0 || kk >= n3) continue;
-            s += ta[k * W + t] * Ga[idx + (long long)(t - w3) * plane];
-        }
-        v = s;
-    } else if (a.mode == OP_K || a.mode == OP_A) {
-        const int w3 = (c == 2) ? P : P - 1;
-        const int W = 2 * w3 + 1;
-        const double* ta = a.bt.ptr[c == 2 ? BK_N : BM_C];
-        const double* tb = a.bt.ptr[c == 2 ? BM_N : BT_C];
-        const double* Ga = ws + a.wsGa[c];
-        const double* Gb = ws + a.wsGb[c];
-        double s = 0.0;
-        for (int t = 0; t < W; ++t) {
-            const int kk = k + t - w3;
-            if (kk < 0 || kk >= n3) continue;
-            const long long sidx = idx + (long long)(t - w3) * plane;
-            s += ta[k * W + t] * Ga[sidx] + tb[k * W + t] * Gb[sidx];
-        }
-        v = a.nu * s;
-    }
-    if (a.mode != OP_BT && a.mode != OP_MV) {
-        // D_c^T w: (D^T w)[j] = w[j] - w[j+1] along direction c
-        const int nM = a.nM;
-        const double* wv = ws + a.wsW;
-        const long long wi = i + (long long)nM * (j + (long long)nM * k);
-        long long step = (c == 0) ? 1 : (c == 1) ? nM : (long long)nM * nM;
-        v += wv[wi] - wv[wi + step];
-    }
-    double* y = out.f[c] + (long long)r * out.stride[c];
-    double res = alpha * v;
-    if (beta != 0.0) res += beta * src.f[c][(long long)r * src.stride[c] + idx];
-    y[idx] = res;
+    const int c = blockIdx.z % 3;
+    const int r = blockIdx.z / 3;
+    if (c == 0) zv_component<P, 0>(a, out, src, alpha, beta, r);
+    else if (c == 1) zv_component<P, 1>(a, out, src, alpha, beta, r);
+    else zv_component<P, 2>(a, out, src, alpha, beta, r);
 }
 
 }  // namespace
@@ -325,19 +395,22 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     a.mode = mode;
     const int nM = c->nM;
     const int P = c->p;
-    // xy
+    // xy: tiles of 64 columns x 16 rows (+ halo)
     {
-        int strips = (nM + XY_ROWS - 1) / XY_ROWS;
-        dim3 grid(strips, nM, 4 * nrhs);
-        int R = XY_ROWS + 2 * P;
-        size_t shm = (size_t)4 * R * nM * sizeof(double);
+        const int ntile1 = (nM + XY_T1 - 1) / XY_T1;
+        const int strips = (nM + XY_CHUNK - 1) / XY_CHUNK;
+        dim3 grid(ntile1 * strips, nM, 4 * nrhs);
+        const int TR = XY_CHUNK + 2 * P, TW = XY_T1 + 2 * P;
+        size_t shm = (size_t)(2 * TR * TW + 2 * TR * XY_T1) * sizeof(double);
         if (P == 2) hipLaunchKernelGGL(k_xy<2>, grid, dim3(XY_THREADS), shm, c->stream, a);
         else if (P == 3) hipLaunchKernelGGL(k_xy<3>, grid, dim3(XY_THREADS), shm, c->stream, a);
         else hipLaunchKernelGGL(k_xy<4>, grid, dim3(XY_THREADS), shm, c->stream, a);
     }
     // zp
     if (mode != OP_MV) {
-        dim3 grid((unsigned)((nQ + Z_THREADS - 1) / Z_THREADS), nrhs);
+        const long long plane = (long long)nM * nM;
+        dim3 grid((unsigned)((plane + Z_THREADS - 1) / Z_THREADS),
+                  (unsigned)((nM + ZCHUNK - 1) / ZCHUNK), nrhs);
         double* yp = out.f[3];
         long long syp = out.stride[3];
         if (P == 2) hipLaunchKernelGGL(k_zp<2>, grid, dim3(Z_THREADS), 0, c->stream, a, yp, syp);
@@ -346,10 +419,9 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     }
     // zv
     if (mode != OP_BT) {
-        long long maxc = 0;
-        for (int b = 0; b < 3; ++b)
-            maxc = std::max(maxc, c->dims[b][0] * c->dims[b][1] * c->dims[b][2]);
-        dim3 grid((unsigned)((maxc + Z_THREADS - 1) / Z_THREADS), 3, nrhs);
+        const long long plane = (long long)nM * nM;  // largest plane of the three components
+        dim3 grid((unsigned)((plane + Z_THREADS - 1) / Z_THREADS),
+                  (unsigned)((nM + ZCHUNK - 1) / ZCHUNK), 3 * nrhs);
         Fields s = src ? *src : out;
         if (!src) beta = 0.0;
         if (P == 2) hipLaunchKernelGGL(k_zv<2>, grid, dim3(Z_THREADS), 0, c->stream, a, out, s, alpha, beta);

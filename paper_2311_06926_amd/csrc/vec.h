@@ -26,4 +26,17 @@ hipError_t vec_add_combo(hipStream_t s, long long n, long long ld, const double*
 hipError_t rank1_sum(hipStream_t s, int n1, int n2, int n3, int nm, const double* s1,
                      const double* s2, const double* s3, double* y);
 
+// Per-right-hand-side state of device-side MINRES.
+struct MinresScalars {
+    double gamma, gamma_old, beta0, eta, c0, c1, s0, s1, delta, rel;
+    int iters, done, status, pad;
+};
+hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs);
+hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double* coef_v, int nrhs);
+hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
+                    double* coef_x, double tol, int nrhs);
+// partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
+hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
+                            const double* Y, int nrhs, double* partial);
+
 }  // namespace hp
