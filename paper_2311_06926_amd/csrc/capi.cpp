@@ -55,6 +55,22 @@ struct Extra {
     int g_q = 0, g_k = 0, g_nrhs = 0, g_var = 0, g_sched = 0, g_prec = 0;
     double g_tol = 0, g_nu = 0;
     const double* g_kv = nullptr;
+    // device-side FGMRES state (restart length up to 128)
+    FgScalars* fsc = nullptr;
+    FgScalars* hfsc[2] = {nullptr, nullptr};
+    double* fH = nullptr;      // R x 129 x 128
+    double* fcs = nullptr;     // R x 128
+    double* fsn = nullptr;     // R x 128
+    double* fg = nullptr;      // R x 129
+    double* fy = nullptr;      // R x 128
+    double* fhc = nullptr;     // R x 129 Gram-Schmidt coefficients
+    double* fvs = nullptr;     // R
+    double* fpart = nullptr;   // partials for up to 129 pairs x R
+    bool f_valid = false;
+    std::vector<hipGraphExec_t> f_exec;
+    int f_q = 0, f_k = 0, f_nrhs = 0, f_var = 0, f_sched = 0, f_prec = 0, f_m = 0;
+    double f_tol = 0, f_nu = 0;
+    const double* f_kv = nullptr;
 };
 
 Extra* extra_of(hp_ctx* c);
@@ -435,166 +451,173 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
 }
 
 // ---- FGMRES(m), right preconditioned, CGS2 Arnoldi -----------------------------------
-hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp_solve_info* info) {
+// Hessenberg matrix, Givens rotations and the small least-squares solve run
+// on the device (k_fg_* kernels); iteration j of a cycle is captured as graph
+// j and replayed.  The true residual is checked at the end of every cycle.
+constexpr int FG_MMAX = 128;
+
+hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol) {
+    Extra* ex = extra_of(c);
     const long long N = c->N;
-    const int m = std::max(1, std::min(c->opts.restart, 128));
-    const long long V = N * nrhs;
-    if (ensure_krylov(c, (size_t)(2 * m + 2) * N * c->opts.max_rhs) != HP_OK) return HP_ENOMEM;
-    double* Vb = extra_of(c)->kv;            // (m+1) x V
-    double* Zb = Vb + (long long)(m + 1) * V;  // m x V
-    double* w = Zb + (long long)m * V;        // V
-    const int q = c->opts.order, k = c->opts.iters;
-    double* partial = c->d_red;
-    double* dres = c->d_red + vec_partial_doubles(m + 1, nrhs);
-    HIPCHK(vec_zero(c->stream, V, x));
-    std::vector<double> bn;
-    if (dots(c, b, b, nrhs, bn) != HP_OK) return HP_EHIP;
-    for (auto& t : bn) t = std::sqrt(t);
-    std::vector<int> done(nrhs, 0), iters(nrhs, 0);
-    std::vector<double> rel(nrhs, 1.0);
-    for (int r = 0; r < nrhs; ++r)
-        if (bn[r] == 0.0) done[r] = 1, rel[r] = 0.0;
-    int total = 0;
-    auto all_done = [&]() {
+    const long long V = N * (long long)c->opts.max_rhs;
+    double* Vb = ex->kv;
+    double* Zb = Vb + (long long)(m + 1) * V;
+    double* w = Zb + (long long)m * V;
+    double* Vj = Vb + (long long)j * V;
+    double* Zj = Zb + (long long)j * V;
+    hipError_t e;
+    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, Vj, Zj, nrhs)) != hipSuccess) return e;
+    if ((e = launch_operator(c, OP_K, full_fields(c, Zj), full_fields(c, w), 1.0, 0.0, nullptr,
+                             nrhs)) != hipSuccess) return e;
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((e = vec_multidot_partials(c->stream, N, N, Vb, V, j + 1, w, nrhs, ex->fpart)) != hipSuccess)
+            return e;
+        if ((e = fg_h(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fhc, j, pass, m, nrhs)) != hipSuccess)
+            return e;
+        if ((e = vec_sub_combo(c->stream, N, N, Vb, V, j + 1, ex->fhc, m + 1, nrhs, w)) != hipSuccess)
+            return e;
+    }
+    if ((e = vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart)) != hipSuccess) return e;
+    if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol, j,
+                    m, nrhs)) != hipSuccess)
+        return e;
+    const double* xs[1] = {w};
+    return vec_lincomb(c->stream, N, N, nrhs, 1, xs, ex->fvs, Vb + (long long)(j + 1) * V);
+}
+
+void drop_fg_graphs(Extra* ex) {
+    for (auto& g : ex->f_exec)
+        if (g) (void)hipGraphExecDestroy(g);
+    ex->f_exec.clear();
+    ex->f_valid = false;
+}
+
+hp_status build_fg_graphs(hp_ctx* c, int m, int nrhs, double tol) {
+    Extra* ex = extra_of(c);
+    const hp_opts& o = c->opts;
+    if (ex->f_valid && ex->f_q == o.order && ex->f_k == o.iters && ex->f_nrhs == nrhs &&
+        ex->f_var == o.schur_variant && ex->f_sched == o.l_schedule && ex->f_prec == o.precision &&
+        ex->f_m == m && ex->f_tol == tol && ex->f_nu == c->nu && ex->f_kv == ex->kv)
+        return HP_OK;
+    drop_fg_graphs(ex);
+    hipStream_t user = c->stream;
+    c->stream = ex->cap;
+    hp_status st = HP_OK;
+    ex->f_exec.assign(m, nullptr);
+    for (int j = 0; j < m && st == HP_OK; ++j) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(ex->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            st = HP_EHIP;
+            break;
+        }
+        hipError_t e = fgmres_iteration(c, j, m, nrhs, tol);
+        hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
+        if (st == HP_OK && hipGraphInstantiate(&ex->f_exec[j], g, nullptr, nullptr, 0) != hipSuccess)
+            st = HP_EHIP;
+        if (g) (void)hipGraphDestroy(g);
+    }
+    c->stream = user;
+    if (st != HP_OK) {
+        drop_fg_graphs(ex);
+        return st;
+    }
+    ex->f_valid = true;
+    ex->f_q = o.order;
+    ex->f_k = o.iters;
+    ex->f_nrhs = nrhs;
+    ex->f_var = o.schur_variant;
+    ex->f_sched = o.l_schedule;
+    ex->f_prec = o.precision;
+    ex->f_m = m;
+    ex->f_tol = tol;
+    ex->f_nu = c->nu;
+    ex->f_kv = ex->kv;
+    return HP_OK;
+}
+
+hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp_solve_info* info) {
+    Extra* ex = extra_of(c);
+    const long long N = c->N;
+    const int m = std::max(1, std::min(c->opts.restart, FG_MMAX));
+    const long long Vn = N * nrhs;
+    const long long V = N * (long long)c->opts.max_rhs;
+    if (ensure_krylov(c, (size_t)(2 * m + 2) * V) != HP_OK) return HP_ENOMEM;
+    const bool graphs = c->opts.use_graph != 0;
+    if (graphs && build_fg_graphs(c, m, nrhs, tol) != HP_OK) return HP_EHIP;
+    double* Vb = ex->kv;
+    double* Zb = Vb + (long long)(m + 1) * V;
+    double* w = Zb + (long long)m * V;
+    const size_t sbytes = sizeof(FgScalars) * nrhs;
+    HIPCHK(vec_dot_partials(c->stream, N, N, b, b, nrhs, ex->fpart));
+    HIPCHK(fg_init(c->stream, ex->fsc, ex->fpart, nrhs));
+    HIPCHK(vec_zero(c->stream, Vn, x));
+    auto all = [&](const FgScalars* h, bool active) {
         for (int r = 0; r < nrhs; ++r)
-            if (!done[r]) return false;
+            if (active ? h[r].active : !h[r].done) return false;
         return true;
     };
-    std::vector<double> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
-        g((size_t)nrhs * (m + 1));
-    std::vector<int> jr(nrhs);
-    std::vector<double> hv((size_t)nrhs * (m + 1)), h2((size_t)nrhs * (m + 1));
-    auto fetch = [&](int cnt, std::vector<double>& out) -> hp_status {
-        out.resize((size_t)nrhs * cnt);
-        if (hipMemcpyAsync(c->h_red, dres, sizeof(double) * nrhs * cnt, hipMemcpyDeviceToHost,
-                           c->stream) != hipSuccess)
-            return HP_EHIP;
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return HP_EHIP;
-        std::memcpy(out.data(), c->h_red, sizeof(double) * nrhs * cnt);
-        return HP_OK;
-    };
-    while (!all_done() && total < c->opts.maxit) {
-        // r = b - K x ; V0 = r / ||r||
-        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr,
-                               nrhs));
-        HIPCHK(vec_axpby(c->stream, V, 1.0, b, -1.0, w));
-        std::vector<double> rn;
-        if (dots(c, w, w, nrhs, rn) != HP_OK) return HP_EHIP;
-        std::vector<double> sc(nrhs);
-        for (int r = 0; r < nrhs; ++r) {
-            rn[r] = std::sqrt(rn[r]);
-            sc[r] = (done[r] || rn[r] == 0.0) ? 0.0 : 1.0 / rn[r];
-            g[(size_t)r * (m + 1)] = done[r] ? 0.0 : rn[r];
-            for (int i = 1; i <= m; ++i) g[(size_t)r * (m + 1) + i] = 0.0;
-            jr[r] = 0;
-        }
-        if (stage_coef(c, sc) != HP_OK) return HP_EHIP;
+    HIPCHK(hipMemcpyAsync(ex->hfsc[0], ex->fsc, sbytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    bool done = all(ex->hfsc[0], false);
+    int total = 0;
+    while (!done && total < c->opts.maxit) {
+        // cycle start: w = b - K x, V0 = w / ||w||
+        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs));
+        HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
+        HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
+        HIPCHK(fg_begin(c->stream, ex->fsc, ex->fpart, ex->fg, ex->fvs, m, nrhs));
         {
             const double* xs[1] = {w};
-            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, extra_of(c)->dcoef, Vb));
+            HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, ex->fvs, Vb));
         }
-        std::vector<int> active(nrhs);
-        for (int r = 0; r < nrhs; ++r) active[r] = !done[r];
-        int j = 0;
-        for (; j < m && total < c->opts.maxit; ++j) {
-            double* Vj = Vb + (long long)j * V;
-            double* Zj = Zb + (long long)j * V;
-            HIPCHK(apply_Pk(c, q, k, Vj, Zj, nrhs));
-            HIPCHK(launch_operator(c, OP_K, full_fields(c, Zj), full_fields(c, w), 1.0, 0.0,
-                                   nullptr, nrhs));
-            // CGS2: two passes of classical Gram-Schmidt
-            for (int pass = 0; pass < 2; ++pass) {
-                HIPCHK(vec_multidot_async(c->stream, N, N, Vb, V, j + 1, w, nrhs, partial, dres));
-                std::vector<double>& hh = pass == 0 ? hv : h2;
-                if (fetch(j + 1, hh) != HP_OK) return HP_EHIP;
-                if (stage_coef(c, hh) != HP_OK) return HP_EHIP;
-                HIPCHK(vec_sub_combo(c->stream, N, N, Vb, V, j + 1, extra_of(c)->dcoef, j + 1,
-                                     nrhs, w));
+        int jl = 0;
+        bool stop = false;
+        while (jl < m && total < c->opts.maxit && !stop) {
+            if (graphs) {
+                HIPCHK(hipGraphLaunch(ex->f_exec[jl], c->stream));
+            } else {
+                HIPCHK(fgmres_iteration(c, jl, m, nrhs, tol));
             }
-            std::vector<double> wn;
-            if (dots(c, w, w, nrhs, wn) != HP_OK) return HP_EHIP;
-            std::vector<double> sc2(nrhs);
+            ++jl;
             ++total;
-            for (int r = 0; r < nrhs; ++r) {
-                double hn = std::sqrt(wn[r]);
-                sc2[r] = (active[r] && hn > 0.0) ? 1.0 / hn : 0.0;
-                if (!active[r]) continue;
-                double* Hr = H.data() + (size_t)r * (m + 1) * m;
-                double* gr = g.data() + (size_t)r * (m + 1);
-                for (int i = 0; i <= j; ++i)
-                    Hr[i * m + j] = hv[(size_t)r * (j + 1) + i] + h2[(size_t)r * (j + 1) + i];
-                Hr[(j + 1) * m + j] = hn;
-                for (int i = 0; i < j; ++i) {
-                    double c_ = cs[(size_t)r * m + i], s_ = sn[(size_t)r * m + i];
-                    double t = c_ * Hr[i * m + j] + s_ * Hr[(i + 1) * m + j];
-                    Hr[(i + 1) * m + j] = -s_ * Hr[i * m + j] + c_ * Hr[(i + 1) * m + j];
-                    Hr[i * m + j] = t;
-                }
-                double d = std::hypot(Hr[j * m + j], Hr[(j + 1) * m + j]);
-                if (d == 0.0) return HP_EBREAKDOWN;
-                cs[(size_t)r * m + j] = Hr[j * m + j] / d;
-                sn[(size_t)r * m + j] = Hr[(j + 1) * m + j] / d;
-                Hr[j * m + j] = d;
-                Hr[(j + 1) * m + j] = 0.0;
-                gr[j + 1] = -sn[(size_t)r * m + j] * gr[j];
-                gr[j] = cs[(size_t)r * m + j] * gr[j];
-                jr[r] = j + 1;
-                iters[r] = total;
-                rel[r] = std::fabs(gr[j + 1]) / bn[r];
-                if (rel[r] <= tol || hn == 0.0) active[r] = 0;
-            }
-            bool any = false;
-            for (int r = 0; r < nrhs; ++r) any = any || active[r];
-            if (!any) { ++j; break; }
-            if (stage_coef(c, sc2) != HP_OK) return HP_EHIP;
-            {
-                const double* xs[1] = {w};
-                HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, extra_of(c)->dcoef,
-                                   Vb + (long long)(j + 1) * V));
+            HIPCHK(hipMemcpyAsync(ex->hfsc[jl & 1], ex->fsc, sbytes, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(hipEventRecord(ex->mev[jl & 1], c->stream));
+            if (jl >= 2) {
+                HIPCHK(hipEventSynchronize(ex->mev[(jl - 1) & 1]));
+                stop = all(ex->hfsc[(jl - 1) & 1], true);
             }
         }
-        // x += Z y with H y = g (per rhs, first jr[r] columns)
-        int jmax = 0;
-        for (int r = 0; r < nrhs; ++r) jmax = std::max(jmax, jr[r]);
-        if (jmax > 0) {
-            std::vector<double> y((size_t)nrhs * jmax, 0.0);
-            for (int r = 0; r < nrhs; ++r) {
-                int jj = jr[r];
-                const double* Hr = H.data() + (size_t)r * (m + 1) * m;
-                const double* gr = g.data() + (size_t)r * (m + 1);
-                for (int i = jj - 1; i >= 0; --i) {
-                    double s = gr[i];
-                    for (int l = i + 1; l < jj; ++l) s -= Hr[i * m + l] * y[(size_t)r * jmax + l];
-                    y[(size_t)r * jmax + i] = s / Hr[i * m + i];
-                }
-            }
-            if (stage_coef(c, y) != HP_OK) return HP_EHIP;
-            HIPCHK(vec_add_combo(c->stream, N, N, Zb, V, jmax, extra_of(c)->dcoef, jmax, nrhs, x));
-        }
-        // confirm with the true residual
-        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr,
-                               nrhs));
-        HIPCHK(vec_axpby(c->stream, V, 1.0, b, -1.0, w));
-        std::vector<double> tr;
-        if (dots(c, w, w, nrhs, tr) != HP_OK) return HP_EHIP;
-        for (int r = 0; r < nrhs; ++r) {
-            if (done[r]) continue;
-            rel[r] = std::sqrt(tr[r]) / bn[r];
-            if (rel[r] <= tol) done[r] = 1;
-        }
+        // x += Z y with H y = g
+        HIPCHK(fg_solve(c->stream, ex->fsc, ex->fH, ex->fg, ex->fy, m, jl, nrhs));
+        HIPCHK(vec_add_combo(c->stream, N, N, Zb, V, jl, ex->fy, m, nrhs, x));
+        // true residual
+        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs));
+        HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
+        HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
+        HIPCHK(fg_check(c->stream, ex->fsc, ex->fpart, tol, nrhs));
+        HIPCHK(hipMemcpyAsync(ex->hfsc[0], ex->fsc, sbytes, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        done = all(ex->hfsc[0], false);
     }
+    const FgScalars* h = ex->hfsc[0];
+    hp_status status = HP_OK;
     if (info) {
         info->iterations = 0;
         info->relres = 0.0;
         info->converged = 1;
-        for (int r = 0; r < nrhs; ++r) {
-            info->iterations = std::max(info->iterations, iters[r]);
-            info->relres = std::max(info->relres, rel[r]);
-            if (!done[r]) info->converged = 0;
-            if (r < 64) info->iters_per_rhs[r] = iters[r];
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        if (h[r].status != 0 && status == HP_OK) status = (hp_status)h[r].status;
+        if (info) {
+            info->iterations = std::max(info->iterations, h[r].iters);
+            info->relres = std::max(info->relres, h[r].rel);
+            if (!h[r].done) info->converged = 0;
+            if (r < 64) info->iters_per_rhs[r] = h[r].iters;
         }
     }
-    return all_done() ? HP_OK : HP_ENOCONV;
+    if (status != HP_OK) return status;
+    return done ? HP_OK : HP_ENOCONV;
 }
 
 // ---- right-hand side -------------------------------------------------------------------
@@ -831,6 +854,20 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hp_destroy(c);
         return HP_ENOMEM;
     }
+    {
+        const size_t M1 = FG_MMAX + 1;
+        if (hipMalloc(reinterpret_cast<void**>(&ex->fsc), sizeof(FgScalars) * R) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[0]), sizeof(FgScalars) * R) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[1]), sizeof(FgScalars) * R) != hipSuccess ||
+            alloc_device(&ex->fH, M1 * FG_MMAX * R) != HP_OK ||
+            alloc_device(&ex->fcs, FG_MMAX * R) != HP_OK || alloc_device(&ex->fsn, FG_MMAX * R) != HP_OK ||
+            alloc_device(&ex->fg, M1 * R) != HP_OK || alloc_device(&ex->fy, FG_MMAX * R) != HP_OK ||
+            alloc_device(&ex->fhc, M1 * R) != HP_OK || alloc_device(&ex->fvs, R) != HP_OK ||
+            alloc_device(&ex->fpart, vec_partial_doubles((int)M1, (int)R)) != HP_OK) {
+            hp_destroy(c);
+            return HP_ENOMEM;
+        }
+    }
     c->red_slots = (int)(vec_partial_doubles(130, (int)R) + 130 * R);
     if (alloc_device(&c->d_red, c->red_slots) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_red), 130 * R * sizeof(double)) != hipSuccess) {
@@ -978,6 +1015,12 @@ void hp_destroy(hp_ctx* c) {
     if (ex->kv) (void)hipFree(ex->kv);
     if (ex->dcoef) (void)hipFree(ex->dcoef);
     drop_graphs(ex);
+    drop_fg_graphs(ex);
+    for (double* p : {ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fy, ex->fhc, ex->fvs, ex->fpart})
+        if (p) (void)hipFree(p);
+    if (ex->fsc) (void)hipFree(ex->fsc);
+    if (ex->hfsc[0]) (void)hipHostFree(ex->hfsc[0]);
+    if (ex->hfsc[1]) (void)hipHostFree(ex->hfsc[1]);
     if (ex->msc) (void)hipFree(ex->msc);
     if (ex->hmsc[0]) (void)hipHostFree(ex->hmsc[0]);
     if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);

@@ -339,7 +339,52 @@ __device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* A, int lda_row
     return acc;
 }
 
-template <typename T, typename TI, typename TO, bool STAGE>
+// Split-BF16 ("bf16x3") product for FP32 data: each operand is written as
+// hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even), and
+// A B ~= A_hi B_hi + A_hi B_lo + A_lo B_hi, three 16x16x16 BF16 MFMAs per
+// 16-wide k step accumulated in FP32 (the lo*lo term is below FP32
+// rounding of the sum and is dropped).  The k index of the four values a
+// lane supplies is the same for both operands, which is all the
+// instruction requires; result rows are 4 (l/16) + i as for FP32.
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f4 tile_gemm_bf16x3(const float* A, int lda_row, int lda_k,
+                                               const float* B, int ldb_k, int ldb_col, int K,
+                                               int lr, int lk) {
+    f4 acc = {0, 0, 0, 0};
+    for (int kk = 0; kk < K; kk += 16) {
+        bf4 ahi, alo, bhi, blo;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kk + 4 * lk + j;
+            const float a = A[lr * lda_row + k * lda_k];
+            const float b = B[k * ldb_k + lr * ldb_col];
+            const __bf16 ah = (__bf16)a, bh = (__bf16)b;
+            ahi[j] = ah;
+            bhi[j] = bh;
+            alo[j] = (__bf16)(a - (float)ah);
+            blo[j] = (__bf16)(b - (float)bh);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// dispatch of a 16x16 tile product: native MFMA of T, or split BF16 (T = float)
+template <typename T, bool SPLIT>
+__device__ __forceinline__ typename Mfma<T>::V tile_mm(const T* A, int lda_row, int lda_k,
+                                                       const T* B, int ldb_k, int ldb_col, int K,
+                                                       int lr, int lk) {
+    if constexpr (SPLIT) {
+        return tile_gemm_bf16x3(A, lda_row, lda_k, B, ldb_k, ldb_col, K, lr, lk);
+    } else {
+        return tile_gemm<T>(A, lda_row, lda_k, B, ldb_k, ldb_col, K, lr, lk);
+    }
+}
+
+template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false>
 __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     extern __shared__ unsigned char smem_raw[];
@@ -381,7 +426,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     // step 1: T = L X  (tile (rb, cb): rows of L, columns of X)
     for (int tt = wave; tt < nb1 * nb2; tt += nw) {
         const int rb = tt % nb1, cb = tt / nb1;
-        auto acc = tile_gemm<T>(L + rb * 16 * ldL, ldL, 1, S + cb * 16 * ld, 1, ld, N1, lr, lk);
+        auto acc = tile_mm<T, SPLIT>(L + rb * 16 * ldL, ldL, 1, S + cb * 16 * ld, 1, ld, N1, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) Tb[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
     }
@@ -389,7 +434,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     // step 2: Y = T R
     for (int tt = wave; tt < nb1 * nb2; tt += nw) {
         const int rb = tt % nb1, cb = tt / nb1;
-        auto acc = tile_gemm<T>(Tb + rb * 16, 1, ld, R + cb * 16, ldR, 1, N2, lr, lk);
+        auto acc = tile_mm<T, SPLIT>(Tb + rb * 16, 1, ld, R + cb * 16, ldR, 1, N2, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
     }
@@ -405,7 +450,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
 
 // z: 64 (i1,i2)-rows x n3 per workgroup, tiles of Y = X U3 and Z = Y U3^T
 // dealt to 16 waves; the scaling by 1/(2 nu (l1 + l2 + l3)) is applied to Y.
-template <typename T, typename TI, typename TO, bool STAGE>
+template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false>
 __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     extern __shared__ unsigned char smem_raw[];
@@ -452,7 +497,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const double* l3 = (f == 2) ? t.lamK : t.lamT;
     for (int tt = wave; tt < ntile; tt += nw) {
         const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-        auto acc = tile_gemm<T>(S + rb * 16 * ld, ld, 1, U3 + cb * 16, ldU, 1, N3, lr, lk);
+        auto acc = tile_mm<T, SPLIT>(S + rb * 16 * ld, ld, 1, U3 + cb * 16, ldU, 1, N3, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = rb * 16 + M::row(lk, i);
@@ -476,7 +521,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     if (!pres) {
         for (int tt = wave; tt < ntile; tt += nw) {
             const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-            auto acc = tile_gemm<T>(Y + rb * 16 * ld, ld, 1, U3t + cb * 16, ldU, 1, N3, lr, lk);
+            auto acc = tile_mm<T, SPLIT>(Y + rb * 16 * ld, ld, 1, U3t + cb * 16, ldU, 1, N3, lr, lk);
 #pragma unroll
             for (int i = 0; i < 4; ++i) S[(rb * 16 + M::row(lk, i)) * ld + cb * 16 + lr] = acc[i];
         }
@@ -522,7 +567,7 @@ FDPlan fd_plan(int np) {
     return pl;
 }
 
-template <typename T>
+template <typename T, bool SPLIT = false>
 hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Fields& out, bool vel,
                   bool pres, bool accumulate, int nrhs) {
     // scratch for the two intermediate tensors (precision T), per rhs N values each
@@ -552,11 +597,11 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         dim3 g(nM, nfields * nrhs);
         if (pl.wide) {
             if (to_double) {
-                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
-                else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
             } else {
-                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, double, T, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
-                else hipLaunchKernelGGL((k_fd_xy_w<T, double, T, false>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, double, T, true, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, double, T, false, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
             }
         } else {
             if (to_double) {
@@ -574,11 +619,11 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         if (pl.wide) {
             dim3 b(FD_WIDE);
             if (to_double) {
-                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, double, true>), g, b, pl.shm_z, c->stream, za_, t);
-                else hipLaunchKernelGGL((k_fd_z_w<T, T, double, false>), g, b, pl.shm_z, c->stream, za_, t);
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, double, true, SPLIT>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z_w<T, T, double, false, SPLIT>), g, b, pl.shm_z, c->stream, za_, t);
             } else {
-                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, T, true>), g, b, pl.shm_z, c->stream, za_, t);
-                else hipLaunchKernelGGL((k_fd_z_w<T, T, T, false>), g, b, pl.shm_z, c->stream, za_, t);
+                if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, T, true, SPLIT>), g, b, pl.shm_z, c->stream, za_, t);
+                else hipLaunchKernelGGL((k_fd_z_w<T, T, T, false, SPLIT>), g, b, pl.shm_z, c->stream, za_, t);
             }
         } else {
             dim3 b(FD_THREADS);
@@ -666,12 +711,29 @@ hipError_t set_fd_attrs() {
 hipError_t fd_init_attributes() {
     hipError_t e = set_fd_attrs<double>();
     if (e != hipSuccess) return e;
-    return set_fd_attrs<float>();
+    e = set_fd_attrs<float>();
+    if (e != hipSuccess) return e;
+    const void* ks[] = {
+        reinterpret_cast<const void*>(&k_fd_xy_w<float, double, float, true, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<float, double, float, false, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<float, float, double, true, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<float, float, double, false, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, float, true, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, float, false, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, true, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, false, true>)};
+    for (const void* k : ks) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
                      bool accumulate, int precision, int nrhs) {
     if (precision == HP_PREC_FP64) return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs);
+    if (precision == HP_PREC_BF16X3)
+        return run_P0<float, true>(c, c->fd32, in, out, vel, pres, accumulate, nrhs);
     return run_P0<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs);
 }
 

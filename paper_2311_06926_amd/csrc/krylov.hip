@@ -372,3 +372,161 @@ hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const doub
 }
 
 }  // namespace hp
+
+// =====================================================================================
+// FGMRES(m) with device-resident Hessenberg matrix, Givens rotations and
+// least-squares solve (one thread per right-hand side).  Iteration j of a
+// restart cycle is a fixed launch sequence (its j is a kernel argument), so
+// the m iterations are captured as m graphs and replayed.
+namespace hp {
+namespace {
+
+__global__ void k_fg_init(FgScalars* sc, const double* part_bb, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    FgScalars& s = sc[r];
+    s = FgScalars{};
+    s.bnorm = sqrt(sum_partials(part_bb, r));
+    s.done = (s.bnorm == 0.0);
+    s.rel = s.done ? 0.0 : 1.0;
+}
+
+// cycle start: w = b - K x;  beta = ||w||, g = beta e1, vscale = 1/beta
+__global__ void k_fg_begin(FgScalars* sc, const double* part_ww, double* g, double* vscale, int m,
+                           int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    FgScalars& s = sc[r];
+    const double beta = sqrt(sum_partials(part_ww, r));
+    double* gr = g + (long long)r * (m + 1);
+    for (int i = 0; i <= m; ++i) gr[i] = 0.0;
+    s.jr = 0;
+    s.active = !s.done && beta > 0.0;
+    gr[0] = s.active ? beta : 0.0;
+    vscale[r] = s.active ? 1.0 / beta : 0.0;
+}
+
+// Gram-Schmidt pass: h_i = <V_i, w> for i <= j (sum of partials); H[:, j] (+)= h
+__global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hcoef, int j, int pass,
+                       int m, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const FgScalars& s = sc[r];
+    double* Hr = H + (long long)r * (m + 1) * m;
+    for (int i = 0; i <= j; ++i) {
+        const double h = sum_partials(part, r * (j + 1) + i);
+        if (s.active) Hr[i * m + j] = (pass == 0 ? 0.0 : Hr[i * m + j]) + h;
+        hcoef[(long long)r * (m + 1) + i] = s.active ? h : 0.0;
+    }
+}
+
+// h_{j+1,j} = ||w||, previous rotations on column j, new rotation, residual estimate
+__global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
+                         double* g, double* vscale, double tol, int j, int m, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    FgScalars& s = sc[r];
+    if (!s.active) {
+        vscale[r] = 0.0;
+        return;
+    }
+    double* Hr = H + (long long)r * (m + 1) * m;
+    double* cr = cs + (long long)r * m;
+    double* sr = sn + (long long)r * m;
+    double* gr = g + (long long)r * (m + 1);
+    const double hn = sqrt(sum_partials(part_ww, r));
+    Hr[(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double t = cr[i] * Hr[i * m + j] + sr[i] * Hr[(i + 1) * m + j];
+        Hr[(i + 1) * m + j] = -sr[i] * Hr[i * m + j] + cr[i] * Hr[(i + 1) * m + j];
+        Hr[i * m + j] = t;
+    }
+    const double d = hypot(Hr[j * m + j], Hr[(j + 1) * m + j]);
+    if (d == 0.0) {
+        s.status = -5;
+        s.active = 0;
+        vscale[r] = 0.0;
+        return;
+    }
+    cr[j] = Hr[j * m + j] / d;
+    sr[j] = Hr[(j + 1) * m + j] / d;
+    Hr[j * m + j] = d;
+    Hr[(j + 1) * m + j] = 0.0;
+    gr[j + 1] = -sr[j] * gr[j];
+    gr[j] = cr[j] * gr[j];
+    s.jr = j + 1;
+    s.iters += 1;
+    s.rel = fabs(gr[j + 1]) / s.bnorm;
+    if (s.rel <= tol || hn == 0.0) s.active = 0;
+    vscale[r] = s.active ? 1.0 / hn : 0.0;
+}
+
+// y = H(1:jr,1:jr)^{-1} g(1:jr), zero beyond jr (padded to jmax)
+__global__ void k_fg_solve(const FgScalars* sc, const double* H, const double* g, double* y, int m,
+                           int jmax, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const int jj = sc[r].jr;
+    const double* Hr = H + (long long)r * (m + 1) * m;
+    const double* gr = g + (long long)r * (m + 1);
+    double* yr = y + (long long)r * m;
+    for (int i = jj; i < jmax; ++i) yr[i] = 0.0;
+    for (int i = jj - 1; i >= 0; --i) {
+        double t = gr[i];
+        for (int l = i + 1; l < jj; ++l) t -= Hr[i * m + l] * yr[l];
+        yr[i] = t / Hr[i * m + i];
+    }
+}
+
+// cycle end: relative true residual
+__global__ void k_fg_check(FgScalars* sc, const double* part_rr, double tol, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    FgScalars& s = sc[r];
+    if (s.done) return;
+    s.rel = sqrt(sum_partials(part_rr, r)) / s.bnorm;
+    if (s.rel <= tol) s.done = 1;
+}
+
+inline dim3 rhs_block(int nrhs) { return dim3(64 * ((nrhs + 63) / 64)); }
+
+}  // namespace
+
+hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int nrhs) {
+    hipLaunchKernelGGL(k_fg_init, dim3(1), rhs_block(nrhs), 0, s, sc, part, nrhs);
+    return hipGetLastError();
+}
+hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g, double* vscale,
+                    int m, int nrhs) {
+    hipLaunchKernelGGL(k_fg_begin, dim3(1), rhs_block(nrhs), 0, s, sc, part, g, vscale, m, nrhs);
+    return hipGetLastError();
+}
+hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
+                int pass, int m, int nrhs) {
+    hipLaunchKernelGGL(k_fg_h, dim3(1), rhs_block(nrhs), 0, s, sc, part, H, hcoef, j, pass, m, nrhs);
+    return hipGetLastError();
+}
+hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
+                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs) {
+    hipLaunchKernelGGL(k_fg_rot, dim3(1), rhs_block(nrhs), 0, s, sc, part, H, cs, sn, g, vscale, tol,
+                       j, m, nrhs);
+    return hipGetLastError();
+}
+hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
+                    int m, int jmax, int nrhs) {
+    hipLaunchKernelGGL(k_fg_solve, dim3(1), rhs_block(nrhs), 0, s, sc, H, g, y, m, jmax, nrhs);
+    return hipGetLastError();
+}
+hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs) {
+    hipLaunchKernelGGL(k_fg_check, dim3(1), rhs_block(nrhs), 0, s, sc, part, tol, nrhs);
+    return hipGetLastError();
+}
+hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
+                                 long long xstride, int npair, const double* Y, int nrhs,
+                                 double* partial) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, npair, nrhs), dim3(VT), 0, s, n, ld, X,
+                       xstride, npair, Y, partial);
+    return hipGetLastError();
+}
+
+}  // namespace hp

@@ -39,4 +39,24 @@ hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
 
+// Per-right-hand-side state of device-side FGMRES.
+struct FgScalars {
+    double bnorm, rel;
+    int done, active, jr, iters, status, pad;
+};
+hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int nrhs);
+hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g, double* vscale,
+                    int m, int nrhs);
+hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
+                int pass, int m, int nrhs);
+hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
+                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs);
+hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
+                    int m, int jmax, int nrhs);
+hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs);
+// partial[((r*npair + q)*DOT_BLOCKS + b] of <X_q,r , Y_r>
+hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
+                                 long long xstride, int npair, const double* Y, int nrhs,
+                                 double* partial);
+
 }  // namespace hp

@@ -259,3 +259,112 @@ def test_invalid_arguments(dev):
     with pytest.raises(HPError):
         Solver(3, 2, 1.0, precision="fp32").solve(x)    # MINRES needs FP64
     sol.close()
+
+
+@pytest.mark.parametrize("krylov", ["minres", "fgmres"])
+def test_graph_replay_equals_eager_and_is_deterministic(dev, krylov):
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] graph vs eager {krylov}")
+    E, p = 7, 3
+    sg = Solver(E, p, 1.0, iters=2, krylov=krylov, use_graph=True)
+    se = Solver(E, p, 1.0, iters=2, krylov=krylov, use_graph=False)
+    b = sg.build_rhs([1.0])
+    xg, ig = sg.solve(b, 1e-8)
+    xg2, ig2 = sg.solve(b, 1e-8)
+    xe, ie = se.solve(b, 1e-8)
+    assert ig.iterations == ie.iterations == ig2.iterations
+    assert torch.equal(xg, xe) and torch.equal(xg, xg2)
+    sg.close()
+    se.close()
+
+
+@pytest.mark.parametrize("krylov", ["minres", "fgmres"])
+def test_batched_solve_matches_single(dev, krylov):
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] batched solve nrhs=3 {krylov}")
+    E, p, R = 6, 2, 3
+    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=R)
+    ss = Solver(E, p, 1.0, iters=1, krylov=krylov)
+    lids, amps, wavs = [], [], []
+    for r in range(R):
+        modes, U = synth.body_force_modes(r, nmodes=16)
+        amp, wav = synth.modes_to_arrays(modes)
+        lids.append(U)
+        amps.append(amp)
+        wavs.append(wav)
+    b = sb.build_rhs(np.array(lids), (np.stack(amps), np.stack(wavs)))
+    xb, ib = sb.solve(b, 1e-8)
+    assert ib.converged == 1
+    for r in range(R):
+        br = b[r * sb.N:(r + 1) * sb.N].clone()
+        xs, is_ = ss.solve(br, 1e-8)
+        assert ib.iters_per_rhs[r] == is_.iterations
+        assert torch.equal(xb[r * sb.N:(r + 1) * sb.N], xs)
+    sb.close()
+    ss.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fgmres_mixed_preconditioner_solves_to_fp64_tolerance(dev, prec):
+    """Mixed precision: FP32 (or split-BF16) fast diagonalisation inside FP64
+    FGMRES reaches 1e-8 in the true FP64 residual; the solution matches the
+    FP64 solve."""
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] FGMRES with {prec} preconditioner")
+    E, p = 10, 3
+    s64 = Solver(E, p, 1.0, iters=1, krylov="fgmres")
+    s32 = Solver(E, p, 1.0, iters=1, krylov="fgmres", precision=prec)
+    b = s64.build_rhs([1.0])
+    x64, i64 = s64.solve(b, 1e-8)
+    x32, i32 = s32.solve(b, 1e-8)
+    assert i32.true_relres <= 1e-8 * 1.01 and i64.true_relres <= 1e-8 * 1.01
+    nv = s64.nV
+    assert abs(i32.iterations - i64.iterations) <= 2
+    err = (x32[:nv] - x64[:nv]).norm() / x64[:nv].norm()
+    assert err < 1e-6
+    s64.close()
+    s32.close()
+
+
+def test_bf16x3_preconditioner(dev):
+    """Split-BF16 fast diagonalisation: error vs FP64 well below FP16 levels,
+    and FGMRES with it still reaches 1e-8 in the FP64 residual."""
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] bf16x3 P0 and FGMRES")
+    E, p = 9, 3
+    s64 = Solver(E, p, 1.0)
+    sbf = Solver(E, p, 1.0, precision="bf16x3", krylov="fgmres", iters=1)
+    x = to_gpu(synth.random_vector(s64.N, seed=502), dev)
+    y64 = s64.apply_P0(x).cpu().numpy()
+    ybf = sbf.apply_P0(x).cpu().numpy()
+    err = rel_err(ybf, y64)
+    assert 1e-9 < err < 5e-4
+    xs, info = sbf.solve(sbf.build_rhs([1.0]), 1e-8)
+    assert info.converged == 1 and info.true_relres <= 1e-8 * 1.01
+    s64.close()
+    sbf.close()
+
+
+def test_autograd_adjoint_matches_oracle(dev):
+    """HyperPowerSolve backward (adjoint solve + gradient kernels) against the
+    oracle's dense-direct gradient at 4^3 elements, degree 2."""
+    from oracle.cases import CavityLoss, cavity
+    from oracle.direct import DirectSolver
+    from paper_2311_06926_amd.autograd import cavity_loss
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] autograd adjoint vs oracle gradient 4^3 p=2")
+    E, p, nu = 4, 2, 1.1
+    St, bt = cavity(E, p, U=1.5)
+    ut = DirectSolver(St).solve(bt)[:St.nV]
+    ref = CavityLoss(E, p, U=1.0, u_target=ut)
+    beta_np = synth.random_vector(St.nV, seed=603, scale=0.4)
+    L_ref, gb_ref, gn_ref = ref.gradient(beta_np, nu)
+    sol = Solver(E, p, nu, krylov="fgmres", iters=1, maxit=400)
+    beta = to_gpu(beta_np, dev).requires_grad_(True)
+    nu_t = torch.tensor(nu, dtype=torch.float64, device=dev, requires_grad=True)
+    L = cavity_loss(beta, nu_t, sol, to_gpu(ut, dev), lid=1.0, tol=1e-12)
+    L.backward()
+    assert abs(L.item() - L_ref) <= 1e-9 * abs(L_ref)
+    assert rel_err(beta.grad.cpu().numpy(), gb_ref) < 1e-8
+    assert abs(nu_t.grad.item() - gn_ref) <= 1e-8 * abs(gn_ref)
+    sol.close()
