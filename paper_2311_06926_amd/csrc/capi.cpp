@@ -832,7 +832,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     }
     // ---- workspace: operator intermediates + FD temporaries
     const long long R = o.max_rhs;
-    c->ws_doubles = (size_t)((2 * c->nV + 3 * c->nQ) + 2 * c->N) * R;
+    c->ws_doubles = (size_t)(ops_ws_stride(c) + 2 * c->N) * R;
     if (alloc_device(&c->ws, c->ws_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     Extra* ex = &ce->ex;
     if (alloc_device(&ex->hv, (size_t)3 * c->nV * R) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
@@ -909,14 +909,14 @@ hp_status hp_apply_A(hp_ctx* c, const double* u, double* y, int nrhs) {
 }
 
 hp_status hp_apply_B(hp_ctx* c, const double* p, double* y, int nrhs) {
-    if (check_rhs(c, nrhs) != HP_OK || !p || !y) return HP_EINVAL;
+    if (check_rhs(c, nrhs) != HP_OK || !p || !y || (const void*)p == (const void*)y) return HP_EINVAL;
     HIPCHK(launch_operator(c, OP_B, pres_fields(c, p, c->nQ), vel_fields(c, y, c->nV), 1.0, 0.0,
                            nullptr, nrhs));
     return HP_OK;
 }
 
 hp_status hp_apply_Bt(hp_ctx* c, const double* u, double* y, int nrhs) {
-    if (check_rhs(c, nrhs) != HP_OK || !u || !y) return HP_EINVAL;
+    if (check_rhs(c, nrhs) != HP_OK || !u || !y || (const void*)u == (const void*)y) return HP_EINVAL;
     HIPCHK(launch_operator(c, OP_BT, vel_fields(c, u, c->nV), pres_fields(c, y, c->nQ), 1.0, 0.0,
                            nullptr, nrhs));
     return HP_OK;
@@ -956,7 +956,7 @@ hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
                                               : fgmres(c, b, x, nrhs, tol, &loc);
     if (s == HP_EHIP || s == HP_ENOMEM) return s;
     // true residual ||b - K x|| / ||b||
-    double* w = c->ws + (2 * c->nV + 3 * c->nQ) * (long long)c->opts.max_rhs;  // FD scratch, N * nrhs
+    double* w = c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs;  // FD scratch, N * nrhs
     if (launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs) !=
             hipSuccess ||
         vec_axpby(c->stream, c->N * nrhs, 1.0, b, -1.0, w) != hipSuccess)
@@ -985,7 +985,7 @@ hp_status hp_grad(hp_ctx* c, const double* x, const double* lambda, const double
     HIPCHK(launch_operator(c, OP_MV, vel_of_full(c, lambda), vel_fields(c, dL_dbeta, c->nV), 1.0,
                            0.0, nullptr, nrhs));
     // dL/dnu = lambda_u . (F_lid - A u) / nu ; F_lid into t (full), A u into its velocity part
-    double* t = c->ws + (2 * c->nV + 3 * c->nQ) * (long long)c->opts.max_rhs;  // N * nrhs scratch
+    double* t = c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs;  // N * nrhs scratch
     hp_status s = build_rhs(c, lid, 0, nullptr, nullptr, t, nrhs);
     if (s != HP_OK) return s;
     const Fields tv = vel_of_full(c, t);

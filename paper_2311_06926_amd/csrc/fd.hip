@@ -572,7 +572,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
                   bool pres, bool accumulate, int nrhs) {
     // scratch for the two intermediate tensors (precision T), per rhs N values each
     const long long N = c->N;
-    T* tmp1 = reinterpret_cast<T*>(c->ws + (2 * c->nV + 3 * c->nQ) * (long long)c->opts.max_rhs);
+    T* tmp1 = reinterpret_cast<T*>(c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs);
     T* tmp2 = tmp1 + N * (long long)c->opts.max_rhs;
     const int lo = vel ? 0 : 3, hi = pres ? 4 : 3;
     if (lo >= hi) return hipSuccess;

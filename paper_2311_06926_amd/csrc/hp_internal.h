@@ -89,6 +89,9 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
                            double alpha, double beta, const Fields* src, int nrhs);
 
 hipError_t ops_init_attributes();
+// doubles of workspace per right-hand side used by launch_operator (holds w);
+// the fast-diagonalisation scratch follows at ops_ws_stride(c) * max_rhs
+long long ops_ws_stride(const hp_ctx* c);
 
 // ---- fast diagonalisation (fd.hip) -----------------------------------------
 hipError_t fd_init_attributes();

@@ -7,117 +7,407 @@
 //     L_1 = M^ (x) M^ (x) K + 2 M^ (x) T^ (x) M + 2 T^ (x) M^ (x) M   (dir 3 (x) dir 2 (x) dir 1)
 // (L_2, L_3 by permuting directions), M_q = M^ (x) M^ (x) M^ and D the
 // +-1 coefficient difference (the discrete divergence, App. B.2).  Hence
-//     K [u; p] = [ nu L u + D^T M_q (nu D u + p) ;  M_q D u ].
+//     K [u; p] = [ nu L u + D^T w ;  M_q D u ],   w = M_q (nu D u + p).
 // Every factor is banded (half-width p for the degree-p factors, p-1 for
-// the degree p-1 ones), so one application costs O(N p) flops.
+// the degree p-1 ones), so one application costs O(N p) flops and is bound
+// by HBM traffic at large sizes.
 //
-// Three kernels:
-//   xy : per (64-column x 16-row tile, i3-plane, field): directions 1 and 2
-//        of every Kronecker term, the tile and its halo staged in LDS.  Velocity component c yields two partial sums Ga,
-//        Gb grouped by their direction-3 factor; the pressure field forms
-//        g = D u and z = nu g + p on the fly and yields M^ (x) M^ g, M^ (x) M^ z.
-//   zp : direction 3 for the pressure: y_p = M^_3 G_g, w = M^_3 G_z.
-//   zv : direction 3 for the velocity and the coupling:
-//        y_c = nu (A3a Ga + A3b Gb) + D_c^T w, with an axpby epilogue.
-//   Both z kernels give each thread one (i1, i2) point and 8 output planes;
-//   the planes and their halo are loaded into registers up front, and the
-//   band coefficients are uniform across the wave.
+// Two streaming kernels; each reads its inputs and writes its outputs once:
+//   k_pres : the pressure chain.  g = D u and z = nu g + p are formed while
+//            staging; y_p = M_q g and w = M_q z.
+//   k_vel  : per velocity component, y_c = nu L_c u_c + D_c^T w (with an
+//            axpby epilogue), or y_c = M_V u_c for the velocity mass matrix.
+// A workgroup owns a T1 x T2 tile of the (i1, i2) plane, one point per
+// thread, and streams a chunk of i3-planes.  Per plane the tile and its halo
+// are staged in LDS; the direction-1 band is applied to the tile's rows and
+// halo rows (the thread's column of coefficients in registers), then the
+// direction-2 band to the thread's own point (its row of coefficients in
+// registers).  The results enter a register window over the last 2w+1 planes,
+// from which the direction-3 band (coefficients uniform over the workgroup)
+// gives the output plane w planes behind the stream.  The staging loads of
+// the next plane are issued before the current plane is processed, so their
+// latency overlaps the LDS work.  Tiles are numbered so that neighbouring
+// tiles run on the same XCD and share their halo through its L2.
+#include <algorithm>
+
 #include "hp_internal.h"
 
 namespace hp {
 
 namespace {
 
-constexpr int XY_CHUNK = 16;    // output rows (direction 2) per xy workgroup
-constexpr int ZCHUNK = 8;       // output planes (direction 3) per z thread
-constexpr int Z_THREADS = 256;
+constexpr int T1 = 32;         // direction-1 points per tile
+constexpr int T2 = 16;         // direction-2 points per tile
+constexpr int NT = T1 * T2;    // threads per workgroup, one tile point each
+constexpr int PF = 1;          // planes in flight ahead of the one processed
 
 struct OpArgs {
     BandTables bt;
     const double* u[3];  // velocity inputs (may be null)
     const double* p;     // pressure input (may be null)
-    long long su, sp;    // per-rhs strides of the inputs (applied to all u blocks / p)
-    double* ws;          // workspace base
+    long long su, sp;    // per-rhs strides of the inputs (all u blocks / p)
+    double* ws;          // workspace base (holds w)
     long long ws_stride;  // per-rhs workspace stride
-    long long wsGa[3], wsGb[3], wsGg, wsGz, wsW;  // workspace offsets
     int dims[4][3];
     int nN, nM;
     double nu;
     int mode;
+    int kchunk;          // i3-planes per workgroup
+    int ntile1, ntile2, nchunk;
+    int nblocks;         // workgroups in the launch
 };
 
-// ---- xy pass -----------------------------------------------------------------------
-// A workgroup owns a tile of XY_T1 direction-1 columns x XY_CHUNK direction-2
-// rows of one i3-plane.  The tile plus its halo (w1 columns, w2 rows on each
-// side) is staged in LDS; thread (column c, row group g) applies the
-// direction-1 band with its row of coefficients held in registers, then the
-// direction-2 band whose row is the same for the whole wave (rows are dealt to
-// waves), so its coefficients are scalar loads.  Two barriers per tile.
-constexpr int XY_T1 = 64;                 // direction-1 columns per tile
-constexpr int XY_THREADS = 256;           // 4 waves = 4 row groups
-constexpr int XY_GROUPS = XY_THREADS / XY_T1;
+// Workgroups are dealt round-robin to the 8 XCDs in launch order.  Renumber
+// them so that XCD x receives one contiguous range of logical block ids.
+__device__ __forceinline__ int xcd_block(int L, int total) {
+    const int per = total / 8, rem = total % 8;
+    const int x = L % 8, q = L / 8;
+    return x * per + min(x, rem) + q;
+}
 
+// Register window of the last 2W+1 values along the streamed direction.
+template <int W>
+struct Window {
+    double v[2 * W + 1];
+    __device__ __forceinline__ void clear() {
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) v[t] = 0.0;
+    }
+    __device__ __forceinline__ void push(double x) {
+#pragma unroll
+        for (int t = 0; t < 2 * W; ++t) v[t] = v[t + 1];
+        v[2 * W] = x;
+    }
+    // sum_t row[t] v[t] for a row of a band table (A[k][k-W .. k+W]); the
+    // row index is uniform, so the row is read through the scalar cache
+    __device__ __forceinline__ double dot(const double* row_generic) const {
+        const auto* row = reinterpret_cast<const __attribute__((address_space(4))) double*>(
+            reinterpret_cast<uintptr_t>(row_generic));
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) s += row[t] * v[t];
+        return s;
+    }
+};
+
+template <int W>
+__device__ __forceinline__ void load_band_row(const double* tab, int row, bool ok,
+                                              double (&c)[2 * W + 1]) {
+#pragma unroll
+    for (int t = 0; t <= 2 * W; ++t) c[t] = ok ? tab[row * (2 * W + 1) + t] : 0.0;
+}
+
+// ---- memory access ---------------------------------------------------------------------
+// The streaming loops read and write through buffer resources: a per-plane
+// base address and byte size in scalar registers plus a per-lane 32-bit byte
+// offset that is loop-invariant.  Reads outside the size return zero and
+// writes outside it are dropped, so the zero padding of the staged halos,
+// planes outside the mesh, fields a mode does not use and lanes without an
+// output are all expressed through sizes and offsets: the loop body has no
+// branches around memory operations.  The loads for plane kk+PF are issued
+// into the registers plane kk has just left (PF register sets, the loop
+// unrolled PF times), so no load result is copied while in flight and each
+// wait covers only loads issued PF steps earlier;
+// an output is stored in the step after it is computed, before that step's
+// loads, so that waiting for loaded data never waits for a store issued just
+// before it.
+constexpr uint32_t OOB = 0x80000000u;  // an offset beyond any buffer size
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    // raw buffer (stride 0), 32-bit data format
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+__device__ __forceinline__ double bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)off, 0, 0);
+}
+
+// ---- pressure chain --------------------------------------------------------------------
+// Staged per plane kk: g = D u and z = nu g + p (z = p for B) on the tile and
+// a halo of W = p-1.  u3 at plane kk-1 is the previous plane's u3 value of the
+// same staging slot, so each plane reads u3 once.
+template <int P>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 3))) void k_pres(OpArgs a, double* yp, long long syp) {
+    constexpr int W = P - 1;
+    constexpr int SW = T1 + 2 * W, SR = T2 + 2 * W;
+    constexpr int NS = (SR * SW + NT - 1) / NT;  // staging slots per thread
+    __shared__ double gs[SR * SW], zs[SR * SW], pg[SR * T1], pz[SR * T1];
+    const int nM = a.nM, nN = a.nN;
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    const int r = id / a.nchunk;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = ch * a.kchunk;
+    const int kend = min(k0 + a.kchunk, nM);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const bool act = i < nM && j < nM;
+    const int mode = a.mode;
+    const bool need_g = (mode == OP_K || mode == OP_BT);
+    const bool need_z = (mode != OP_BT);
+    const bool use_u = (mode != OP_B);
+    const bool use_p = (mode == OP_K || mode == OP_B);
+    const double zg = (mode == OP_B) ? 0.0 : a.nu;   // z = zg g + p
+    double* wv = a.ws + (long long)r * a.ws_stride;
+    const double* pp = use_p ? a.p + (long long)r * a.sp : wv;
+    const double* u1 = use_u ? a.u[0] + (long long)r * a.su : pp;
+    const double* u2 = use_u ? a.u[1] + (long long)r * a.su : pp;
+    const double* u3 = use_u ? a.u[2] + (long long)r * a.su : pp;
+    double* ypr = need_g ? yp + (long long)r * syp : wv;
+    const double* tm = a.bt.ptr[BM_C];
+    const long long P1 = (long long)nN * nM;   // plane of u1 (nN, nM, nM)
+    const long long P2 = (long long)nM * nN;   // plane of u2 (nM, nN, nM)
+    const long long P3 = (long long)nM * nM;   // plane of u3 (nM, nM, nN) and of p
+    const uint32_t B1 = use_u ? 8u * (uint32_t)P1 : 0u, B2 = use_u ? 8u * (uint32_t)P2 : 0u;
+    const uint32_t B3 = use_u ? 8u * (uint32_t)P3 : 0u, BP = use_p ? 8u * (uint32_t)P3 : 0u;
+    // staging slots: byte offsets of u1[ii], u1[ii-1], u2[jj], u2[jj-1], and
+    // of u3/p, each OOB where the value lies outside its field
+    uint32_t oa[NS], ob[NS], oc[NS], od[NS], oe[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int idx = threadIdx.x + s * NT;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W + rr, ii = i0 - W + cc;
+        const bool ok = idx < SR * SW && jj >= 0 && jj < nM && ii >= 0 && ii < nM;
+        oa[s] = (ok && ii < nN) ? 8u * (nN * jj + ii) : OOB;
+        ob[s] = (ok && ii >= 1) ? 8u * (nN * jj + ii - 1) : OOB;
+        oc[s] = (ok && jj < nN) ? 8u * (ii + nM * jj) : OOB;
+        od[s] = (ok && jj >= 1) ? 8u * (ii + nM * (jj - 1)) : OOB;
+        oe[s] = ok ? 8u * (ii + nM * jj) : OOB;
+    }
+    // raw values of plane kk (zero outside the mesh)
+    auto fetch = [&](int kk, double (&v)[NS][6]) {
+        const bool kin = kk >= 0 && kk < nM;
+        const bool k3in = kk >= 0 && kk < nN;
+        const int kc = kin ? kk : 0, k3 = k3in ? kk : 0;
+        const auto r1 = make_rsrc(u1 + P1 * kc, kin ? B1 : 0u);
+        const auto r2 = make_rsrc(u2 + P2 * kc, kin ? B2 : 0u);
+        const auto r3 = make_rsrc(u3 + P3 * k3, k3in ? B3 : 0u);
+        const auto rp = make_rsrc(pp + P3 * kc, kin ? BP : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v[s][0] = bload(r1, oa[s]);
+            v[s][1] = bload(r1, ob[s]);
+            v[s][2] = bload(r2, oc[s]);
+            v[s][3] = bload(r2, od[s]);
+            v[s][4] = bload(r3, oe[s]);
+            v[s][5] = bload(rp, oe[s]);
+        }
+    };
+    double c1[2 * W + 1], c2[2 * W + 1];
+    load_band_row<W>(tm, i, i < nM, c1);
+    load_band_row<W>(tm, j, j < nM, c2);
+    const uint32_t oo = act ? 8u * (i + nM * j) : OOB;  // this thread's output
+    Window<W> wg, wz;
+    wg.clear();
+    wz.clear();
+    double buf[PF][NS][6], a3prev[NS];
+    {
+        double t[NS][6];
+        fetch(k0 - W - 1, t);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a3prev[s] = t[s][4];
+    }
+#pragma unroll
+    for (int d = 0; d < PF; ++d) fetch(k0 - W + d, buf[d]);
+    int pk = -1;  // plane of the pending output (none yet)
+    double py = 0.0, pw = 0.0;
+    // one step: consume plane kk, store the pending output, refill the
+    // registers with plane kk + PF, then process plane kk
+    auto step = [&](int kk, double (&b)[NS][6]) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int idx = threadIdx.x + s * NT;
+            if (idx < SR * SW) {
+                const double gv = (b[s][0] - b[s][1]) + (b[s][2] - b[s][3]) + (b[s][4] - a3prev[s]);
+                gs[idx] = gv;
+                zs[idx] = zg * gv + b[s][5];
+            }
+            a3prev[s] = b[s][4];
+        }
+        {
+            const bool on = pk >= 0;
+            const int kc = on ? pk : 0;
+            bstore(make_rsrc(ypr + P3 * kc, (on && need_g) ? 8u * (uint32_t)P3 : 0u), oo, py);
+            bstore(make_rsrc(wv + P3 * kc, (on && need_z) ? 8u * (uint32_t)P3 : 0u), oo, pw);
+        }
+        fetch(kk + PF, b);
+        __syncthreads();
+        for (int rr = g; rr < SR; rr += T2) {
+            double sg = 0.0, sz = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * W; ++t) {
+                sg += c1[t] * gs[rr * SW + c + t];
+                sz += c1[t] * zs[rr * SW + c + t];
+            }
+            pg[rr * T1 + c] = sg;
+            pz[rr * T1 + c] = sz;
+        }
+        __syncthreads();
+        double sg = 0.0, sz = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            sg += c2[t] * pg[(g + t) * T1 + c];
+            sz += c2[t] * pz[(g + t) * T1 + c];
+        }
+        wg.push(sg);
+        wz.push(sz);
+        const int k = kk - W;
+        pk = (k >= k0 && k < kend) ? k : -1;
+        if (pk >= 0) {
+            const double* rm = tm + k * (2 * W + 1);
+            py = wg.dot(rm);
+            pw = wz.dot(rm);
+        }
+    };
+    // steps past kend + W - 1 (when the count is not a multiple of PF) output nothing
+    for (int kk = k0 - W; kk < kend + W; kk += PF) {
+#pragma unroll
+        for (int d = 0; d < PF; ++d) step(kk + d, buf[d]);
+    }
+    if (pk >= 0) {
+        bstore(make_rsrc(ypr + P3 * pk, need_g ? 8u * (uint32_t)P3 : 0u), oo, py);
+        bstore(make_rsrc(wv + P3 * pk, need_z ? 8u * (uint32_t)P3 : 0u), oo, pw);
+    }
+}
+
+// ---- velocity component C --------------------------------------------------------------
 template <int P, int C>
-__device__ void xy_velocity(const OpArgs& a, int r, int k, int i0, int j0, double* lds) {
+__device__ void vel_component(const OpArgs& a, const Fields& out, const Fields& src, double alpha,
+                              double beta, int r, int i0, int j0, int k0, double* lds) {
     constexpr int W1 = (C == 0) ? P : P - 1;
     constexpr int W2 = (C == 1) ? P : P - 1;
-    constexpr int TW = XY_T1 + 2 * W1;        // staged columns
-    constexpr int TR = XY_CHUNK + 2 * W2;     // staged rows
+    constexpr int W3 = (C == 2) ? P : P - 1;
+    constexpr int SW = T1 + 2 * W1, SR = T2 + 2 * W2;
+    constexpr int NS = (SR * SW + NT - 1) / NT;
     const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
-    if (k >= n3 || j0 >= n2 || i0 >= n1) return;
-    const bool mv = (a.mode == OP_MV);
-    double* xs = lds;                 // TR x TW
-    double* pa = xs + TR * TW;        // TR x XY_T1
-    double* pb = pa + TR * XY_T1;
-    const double* x = a.u[C] + (long long)r * a.su + (long long)k * n1 * n2;
-    for (int idx = threadIdx.x; idx < TR * TW; idx += XY_THREADS) {
-        const int rr = idx / TW, cc = idx - rr * TW;
-        const int j = j0 - W2 + rr, i = i0 - W1 + cc;
-        xs[idx] = (j >= 0 && j < n2 && i >= 0 && i < n1) ? x[(long long)j * n1 + i] : 0.0;
+    if (i0 >= n1 || j0 >= n2 || k0 >= n3) return;
+    const int kend = min(k0 + a.kchunk, n3);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const bool act = i < n1 && j < n2;
+    const int mode = a.mode;
+    const bool mv = (mode == OP_MV);
+    const bool lop = (mode == OP_K || mode == OP_A);
+    const int nM = a.nM;
+    const double* wv = a.ws + (long long)r * a.ws_stride;
+    const long long plane = (long long)n1 * n2;
+    const long long wplane = (long long)nM * nM;
+    const uint32_t YB = 8u * (uint32_t)plane, WB = 8u * (uint32_t)wplane;
+    double* y = out.f[C] + (long long)r * out.stride[C];
+    const bool has_src = beta != 0.0;
+    const double* sv = has_src ? src.f[C] + (long long)r * src.stride[C] : y;
+    const uint32_t SB = has_src ? YB : 0u;
+    const uint32_t WBm = mv ? 0u : WB;  // the mass mode has no coupling term
+    // this thread's point: byte offsets in the pressure plane (w at i, j and at
+    // the +1 neighbour in direction C) and in the component plane
+    const uint32_t wo = act ? 8u * (i + nM * j) : OOB;
+    const uint32_t wo1 = act ? wo + (C == 0 ? 8u : C == 1 ? 8u * nM : 0u) : OOB;
+    const uint32_t yo = act ? 8u * (i + n1 * j) : OOB;
+    if (!lop && !mv) {
+        // coupling only (B): y = alpha D_c^T w + beta src
+        if (!act) return;
+        for (int k = k0; k < kend; ++k) {
+            const auto rw = make_rsrc(wv + wplane * k, WB);
+            const auto rw1 = make_rsrc(wv + wplane * (C == 2 ? k + 1 : k), WB);
+            double res = alpha * (bload(rw, wo) - bload(rw1, wo1));
+            res += beta * bload(make_rsrc(sv + plane * k, SB), yo);
+            bstore(make_rsrc(y + plane * k, YB), yo, res);
+        }
+        return;
     }
-    const int c = threadIdx.x % XY_T1, g = threadIdx.x / XY_T1;
-    const int i = i0 + c;
-    const bool act = i < n1;
+    double* xs = lds;             // SR x SW
+    double* pa = xs + SR * SW;    // SR x T1
+    double* pb = pa + SR * T1;
     const double* t1a = a.bt.ptr[C == 0 ? (mv ? BM_N : BK_N) : BM_C];
     const double* t1b = a.bt.ptr[C == 0 ? BM_N : BT_C];
-    double ca[2 * W1 + 1], cb[2 * W1 + 1];
+    const double* m2t = a.bt.ptr[C == 1 ? BM_N : BM_C];   // mass of direction 2
+    const double* k2t = a.bt.ptr[C == 1 ? BK_N : BT_C];   // K (C==1) or T^ (C==0, 2)
+    const double* ta = a.bt.ptr[C == 2 ? (mv ? BM_N : BK_N) : BM_C];
+    const double* tb = a.bt.ptr[C == 2 ? BM_N : BT_C];
+    const double* x = a.u[C] + (long long)r * a.su;
+    uint32_t so[NS];  // staging byte offsets, OOB outside the component
 #pragma unroll
-    for (int t = 0; t <= 2 * W1; ++t) {
-        ca[t] = act ? t1a[i * (2 * W1 + 1) + t] : 0.0;
-        cb[t] = (act && !mv) ? t1b[i * (2 * W1 + 1) + t] : 0.0;
+    for (int s = 0; s < NS; ++s) {
+        const int idx = threadIdx.x + s * NT;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W2 + rr, ii = i0 - W1 + cc;
+        const bool ok = idx < SR * SW && jj >= 0 && jj < n2 && ii >= 0 && ii < n1;
+        so[s] = ok ? 8u * (jj * n1 + ii) : OOB;
     }
-    __syncthreads();
-    for (int rr = g; rr < TR; rr += XY_GROUPS) {
-        const double* row = xs + rr * TW + c;
-        double sa = 0.0, sb = 0.0;
+    auto fetch_x = [&](int kk, double (&v)[NS]) {
+        const bool kin = kk >= 0 && kk < n3;
+        const auto rx = make_rsrc(x + plane * (kin ? kk : 0), kin ? YB : 0u);
 #pragma unroll
-        for (int t = 0; t <= 2 * W1; ++t) {
-            sa += ca[t] * row[t];
-            sb += cb[t] * row[t];
+        for (int s = 0; s < NS; ++s) v[s] = bload(rx, so[s]);
+    };
+    // coupling (w at the point and at its +1 neighbour) and source of plane k
+    auto fetch_out = [&](int k, double& w0, double& w1, double& sd) {
+        const bool kin = k >= 0 && k < n3;
+        const int kc = kin ? k : 0;
+        w0 = bload(make_rsrc(wv + wplane * kc, kin ? WBm : 0u), wo);
+        w1 = bload(make_rsrc(wv + wplane * (C == 2 ? kc + 1 : kc), kin ? WBm : 0u), wo1);
+        sd = bload(make_rsrc(sv + plane * kc, kin ? SB : 0u), yo);
+    };
+    double ca[2 * W1 + 1], cb[2 * W1 + 1], cm[2 * W2 + 1], ck[2 * W2 + 1];
+    load_band_row<W1>(t1a, i, i < n1, ca);
+    load_band_row<W1>(t1b, i, i < n1 && !mv, cb);
+    load_band_row<W2>(m2t, j, j < n2, cm);
+    load_band_row<W2>(k2t, j, j < n2 && !mv, ck);
+    Window<W3> wa, wb;
+    wa.clear();
+    wb.clear();
+    struct OutTerms {
+        double w0, w1, sd;
+    };
+    double xb[PF][NS];
+    OutTerms ft[PF];
+#pragma unroll
+    for (int d = 0; d < PF; ++d) {
+        fetch_x(k0 - W3 + d, xb[d]);
+        fetch_out(k0 - 2 * W3 + d, ft[d].w0, ft[d].w1, ft[d].sd);
+    }
+    int pk = -1;  // plane of the pending output (none yet)
+    double pv = 0.0;
+    // one step: consume plane kk, store the pending output, refill the
+    // registers with plane kk + PF, process plane kk, form the output of
+    // plane kk - W3 and refill its coupling/source registers for kk - W3 + PF
+    auto step = [&](int kk, double (&xr)[NS], OutTerms& f) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int idx = threadIdx.x + s * NT;
+            if (idx < SR * SW) xs[idx] = xr[s];
         }
-        pa[rr * XY_T1 + c] = sa;
-        pb[rr * XY_T1 + c] = sb;
-    }
-    __syncthreads();
-    if (!act) return;
-    const double* m2 = a.bt.ptr[C == 1 ? BM_N : BM_C];   // mass of direction 2
-    const double* k2 = a.bt.ptr[C == 1 ? BK_N : BT_C];   // K (C==1) or T^ (C==0, 2)
-    double* ws = a.ws + (long long)r * a.ws_stride;
-    double* Ga = ws + a.wsGa[C] + (long long)k * n1 * n2;
-    double* Gb = ws + a.wsGb[C] + (long long)k * n1 * n2;
-    for (int o = g; o < XY_CHUNK; o += XY_GROUPS) {
-        const int j = j0 + o;
-        if (j >= n2) break;
-        const double* rm = m2 + j * (2 * W2 + 1);
-        const double* rk = k2 + j * (2 * W2 + 1);
+        bstore(make_rsrc(y + plane * (pk >= 0 ? pk : 0), pk >= 0 ? YB : 0u), yo, pv);
+        fetch_x(kk + PF, xr);
+        __syncthreads();
+        for (int rr = g; rr < SR; rr += T2) {
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * W1; ++t) {
+                const double xv = xs[rr * SW + c + t];
+                sa += ca[t] * xv;
+                sb += cb[t] * xv;
+            }
+            pa[rr * T1 + c] = sa;
+            pb[rr * T1 + c] = sb;
+        }
+        __syncthreads();
         double am = 0.0, ak = 0.0, bm = 0.0, bk = 0.0;
 #pragma unroll
         for (int t = 0; t <= 2 * W2; ++t) {
-            const double va = pa[(o + t) * XY_T1 + c], vb = pb[(o + t) * XY_T1 + c];
-            am += rm[t] * va;
-            ak += rk[t] * va;
-            bm += rm[t] * vb;
-            bk += rk[t] * vb;
+            const double va = pa[(g + t) * T1 + c], vb = pb[(g + t) * T1 + c];
+            am += cm[t] * va;
+            ak += ck[t] * va;
+            bm += cm[t] * vb;
+            bk += ck[t] * vb;
         }
         double ga, gb = 0.0;
         if (mv) {
@@ -132,245 +422,62 @@ __device__ void xy_velocity(const OpArgs& a, int r, int k, int i0, int j0, doubl
             ga = am;
             gb = 2.0 * (ak + bm);
         }
-        Ga[(long long)j * n1 + i] = ga;
-        if (!mv) Gb[(long long)j * n1 + i] = gb;
-    }
-}
-
-// pressure: g = D u, z = nu g + p on the tile and halo, then M^ (x) M^ on both
-template <int P>
-__device__ void xy_pressure(const OpArgs& a, int r, int k, int i0, int j0, double* lds) {
-    constexpr int W = P - 1;
-    constexpr int TW = XY_T1 + 2 * W;
-    constexpr int TR = XY_CHUNK + 2 * W;
-    const int mode = a.mode;
-    const bool need_g = (mode == OP_K || mode == OP_BT);
-    const bool need_z = (mode != OP_BT);
-    const bool use_u = (mode != OP_B);
-    const bool use_p = (mode == OP_K || mode == OP_B);
-    const int nM = a.nM, nN = a.nN;
-    if (k >= nM || j0 >= nM || i0 >= nM) return;
-    double* gs = lds;              // TR x TW
-    double* zs = gs + TR * TW;
-    double* pg = zs + TR * TW;     // TR x XY_T1
-    double* pz = pg + TR * XY_T1;
-    const double* u1 = use_u ? a.u[0] + (long long)r * a.su : nullptr;
-    const double* u2 = use_u ? a.u[1] + (long long)r * a.su : nullptr;
-    const double* u3 = use_u ? a.u[2] + (long long)r * a.su : nullptr;
-    const double* pp = use_p ? a.p + (long long)r * a.sp : nullptr;
-    for (int idx = threadIdx.x; idx < TR * TW; idx += XY_THREADS) {
-        const int rr = idx / TW, cc = idx - rr * TW;
-        const int j = j0 - W + rr, i = i0 - W + cc;
-        double g = 0.0, z = 0.0;
-        if (j >= 0 && j < nM && i >= 0 && i < nM) {
-            if (use_u) {
-                // u1: (nN, nM, nM); u2: (nM, nN, nM); u3: (nM, nM, nN)
-                const long long b1 = (long long)nN * (j + (long long)nM * k);
-                if (i < nN) g += u1[b1 + i];
-                if (i >= 1) g -= u1[b1 + i - 1];
-                if (j < nN) g += u2[i + (long long)nM * (j + (long long)nN * k)];
-                if (j >= 1) g -= u2[i + (long long)nM * ((j - 1) + (long long)nN * k)];
-                if (k < nN) g += u3[i + (long long)nM * (j + (long long)nM * k)];
-                if (k >= 1) g -= u3[i + (long long)nM * (j + (long long)nM * (k - 1))];
-            }
-            const double pv = use_p ? pp[i + (long long)nM * (j + (long long)nM * k)] : 0.0;
-            z = (mode == OP_B) ? pv : a.nu * g + pv;
+        wa.push(ga);
+        wb.push(gb);
+        const int k = kk - W3;
+        pk = (k >= k0 && k < kend) ? k : -1;
+        if (pk >= 0) {
+            double v;
+            if (mv) v = wa.dot(ta + k * (2 * W3 + 1));
+            else v = a.nu * (wa.dot(ta + k * (2 * W3 + 1)) + wb.dot(tb + k * (2 * W3 + 1))) + (f.w0 - f.w1);
+            pv = alpha * v + beta * f.sd;
         }
-        gs[idx] = g;
-        zs[idx] = z;
-    }
-    const int c = threadIdx.x % XY_T1, grp = threadIdx.x / XY_T1;
-    const int i = i0 + c;
-    const bool act = i < nM;
-    const double* tm = a.bt.ptr[BM_C];
-    double cm[2 * W + 1];
+        fetch_out(k + PF, f.w0, f.w1, f.sd);
+    };
+    // steps past kend + W3 - 1 (when the count is not a multiple of PF) output nothing
+    for (int kk = k0 - W3; kk < kend + W3; kk += PF) {
 #pragma unroll
-    for (int t = 0; t <= 2 * W; ++t) cm[t] = act ? tm[i * (2 * W + 1) + t] : 0.0;
-    __syncthreads();
-    for (int rr = grp; rr < TR; rr += XY_GROUPS) {
-        const double* rg = gs + rr * TW + c;
-        const double* rz = zs + rr * TW + c;
-        double sg = 0.0, sz = 0.0;
-#pragma unroll
-        for (int t = 0; t <= 2 * W; ++t) {
-            sg += cm[t] * rg[t];
-            sz += cm[t] * rz[t];
-        }
-        pg[rr * XY_T1 + c] = sg;
-        pz[rr * XY_T1 + c] = sz;
+        for (int d = 0; d < PF; ++d) step(kk + d, xb[d], ft[d]);
     }
-    __syncthreads();
-    if (!act) return;
-    double* ws = a.ws + (long long)r * a.ws_stride;
-    double* Gg = ws + a.wsGg + (long long)k * nM * nM;
-    double* Gz = ws + a.wsGz + (long long)k * nM * nM;
-    for (int o = grp; o < XY_CHUNK; o += XY_GROUPS) {
-        const int j = j0 + o;
-        if (j >= nM) break;
-        const double* rm = tm + j * (2 * W + 1);
-        double sg = 0.0, sz = 0.0;
-#pragma unroll
-        for (int t = 0; t <= 2 * W; ++t) {
-            sg += rm[t] * pg[(o + t) * XY_T1 + c];
-            sz += rm[t] * pz[(o + t) * XY_T1 + c];
-        }
-        if (need_g) Gg[(long long)j * nM + i] = sg;
-        if (need_z) Gz[(long long)j * nM + i] = sz;
-    }
+    if (pk >= 0) bstore(make_rsrc(y + plane * pk, YB), yo, pv);
 }
 
 template <int P>
-__global__ __launch_bounds__(XY_THREADS) void k_xy(OpArgs a) {
-    extern __shared__ double lds[];
-    const int f = blockIdx.z & 3;
-    const int r = blockIdx.z >> 2;
-    const int k = blockIdx.y;
-    const int ntile1 = (a.nM + XY_T1 - 1) / XY_T1;
-    const int i0 = (blockIdx.x % ntile1) * XY_T1;
-    const int j0 = (blockIdx.x / ntile1) * XY_CHUNK;
-    const int mode = a.mode;
-    if (f < 3) {
-        if (mode != OP_K && mode != OP_A && mode != OP_MV) return;
-        if (f == 0) xy_velocity<P, 0>(a, r, k, i0, j0, lds);
-        else if (f == 1) xy_velocity<P, 1>(a, r, k, i0, j0, lds);
-        else xy_velocity<P, 2>(a, r, k, i0, j0, lds);
-    } else {
-        if (mode == OP_MV) return;
-        xy_pressure<P>(a, r, k, i0, j0, lds);
-    }
-}
-
-// ---- direction 3, pressure: y_p = M^_3 G_g, w = M^_3 G_z --------------------------
-// Thread = one (i1, i2) point; it loads the ZCHUNK planes it outputs plus a
-// halo of W on each side into registers, then forms the band products.
-template <int P>
-__global__ __launch_bounds__(Z_THREADS) void k_zp(OpArgs a, double* yp, long long syp) {
-    constexpr int W = P - 1;
-    constexpr int R = ZCHUNK + 2 * W;
-    const int r = blockIdx.z;
-    const int nM = a.nM;
-    const long long plane = (long long)nM * nM;
-    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k0 = blockIdx.y * ZCHUNK;
-    if (k0 >= nM || pidx >= plane) return;
-    double* ws = a.ws + (long long)r * a.ws_stride;
-    const double* tm = a.bt.ptr[BM_C];
-    const bool need_g = (a.mode == OP_K || a.mode == OP_BT);
-    const bool need_z = (a.mode != OP_BT);
-    double g[R], z[R];
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-        const int kk = k0 - W + s;
-        const bool in = kk >= 0 && kk < nM;
-        const long long src = pidx + (long long)kk * plane;
-        g[s] = (need_g && in) ? ws[a.wsGg + src] : 0.0;
-        z[s] = (need_z && in) ? ws[a.wsGz + src] : 0.0;
-    }
-#pragma unroll
-    for (int o = 0; o < ZCHUNK; ++o) {
-        const int k = k0 + o;
-        if (k >= nM) break;
-        const double* rm = tm + k * (2 * W + 1);
-        double sg = 0.0, sz = 0.0;
-#pragma unroll
-        for (int t = 0; t <= 2 * W; ++t) {
-            sg += rm[t] * g[o + t];
-            sz += rm[t] * z[o + t];
-        }
-        const long long o3 = pidx + (long long)k * plane;
-        if (need_g) yp[(long long)r * syp + o3] = sg;
-        if (need_z) ws[a.wsW + o3] = sz;
-    }
-}
-
-// ---- direction 3, velocity + D^T w; y = alpha v + beta src -------------------------
-template <int P, int C>
-__device__ void zv_component(const OpArgs& a, const Fields& out, const Fields& src, double alpha,
-                             double beta, int r) {
-    constexpr int W3 = (C == 2) ? P : P - 1;
-    constexpr int R = ZCHUNK + 2 * W3;
-    const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
-    const long long plane = (long long)n1 * n2;
-    const long long pidx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k0 = blockIdx.y * ZCHUNK;
-    if (k0 >= n3 || pidx >= plane) return;
-    const int i = (int)(pidx % n1);
-    const int j = (int)(pidx / n1);
-    const double* ws = a.ws + (long long)r * a.ws_stride;
-    const bool mv = (a.mode == OP_MV);
-    const bool lop = (a.mode == OP_K || a.mode == OP_A);
-    const bool cpl = !mv && a.mode != OP_BT;
-    const double* ta = a.bt.ptr[C == 2 ? (mv ? BM_N : BK_N) : BM_C];
-    const double* tb = a.bt.ptr[C == 2 ? BM_N : BT_C];
-    const double* Ga = ws + a.wsGa[C];
-    const double* Gb = ws + a.wsGb[C];
-    const double* wv = ws + a.wsW;
-    const int nM = a.nM;
-    const long long wstep = (C == 0) ? 1 : (C == 1) ? nM : (long long)nM * nM;
-    double* y = out.f[C] + (long long)r * out.stride[C];
-    const double* sv = (beta != 0.0) ? src.f[C] + (long long)r * src.stride[C] : nullptr;
-    double ga[R], gb[R];
-#pragma unroll
-    for (int s = 0; s < R; ++s) {
-        const int kk = k0 - W3 + s;
-        const bool in = (lop || mv) && kk >= 0 && kk < n3;
-        const long long sidx = pidx + (long long)kk * plane;
-        ga[s] = in ? Ga[sidx] : 0.0;
-        gb[s] = (in && lop) ? Gb[sidx] : 0.0;
-    }
-#pragma unroll
-    for (int o = 0; o < ZCHUNK; ++o) {
-        const int k = k0 + o;
-        if (k >= n3) break;
-        double v = 0.0;
-        if (lop || mv) {
-            const double* ra = ta + k * (2 * W3 + 1);
-            const double* rb = tb + k * (2 * W3 + 1);
-            double sa = 0.0, sb = 0.0;
-#pragma unroll
-            for (int t = 0; t <= 2 * W3; ++t) {
-                sa += ra[t] * ga[o + t];
-                sb += rb[t] * gb[o + t];
-            }
-            v = mv ? sa : a.nu * (sa + sb);
-        }
-        if (cpl) {
-            const long long wi = i + (long long)nM * (j + (long long)nM * k);
-            v += wv[wi] - wv[wi + wstep];
-        }
-        const long long o3 = pidx + (long long)k * plane;
-        double res = alpha * v;
-        if (sv) res += beta * sv[o3];
-        y[o3] = res;
-    }
+constexpr int vel_lds_doubles() {
+    // the widest component: halo P in one of the two tile directions
+    return (T2 + 2 * P) * (T1 + 2 * P) + 2 * (T2 + 2 * P) * T1;
 }
 
 template <int P>
-__global__ __launch_bounds__(Z_THREADS) void k_zv(OpArgs a, Fields out, Fields src, double alpha,
-                                                  double beta) {
-    const int c = blockIdx.z % 3;
-    const int r = blockIdx.z / 3;
-    if (c == 0) zv_component<P, 0>(a, out, src, alpha, beta, r);
-    else if (c == 1) zv_component<P, 1>(a, out, src, alpha, beta, r);
-    else zv_component<P, 2>(a, out, src, alpha, beta, r);
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 3))) void k_vel(OpArgs a, Fields out, Fields src, double alpha,
+                                            double beta) {
+    __shared__ double lds[vel_lds_doubles<P>()];
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    // the component is the fastest index, so that the three components of one
+    // tile and chunk run together on one XCD and read w through its L2 once
+    const int comp = id % 3;
+    id /= 3;
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    const int r = id / a.nchunk;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = ch * a.kchunk;
+    if (comp == 0) vel_component<P, 0>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
+    else if (comp == 1) vel_component<P, 1>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
+    else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
 }
 
 }  // namespace
 
-hipError_t ops_init_attributes() {
-    const int bytes = 160 * 1024;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xy<2>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xy<3>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xy<4>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
+hipError_t ops_init_attributes() { return hipSuccess; }
+
+long long ops_ws_stride(const hp_ctx* c) { return c->nQ; }
 
 hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Fields& out,
                            double alpha, double beta, const Fields* src, int nrhs) {
+    if (c->p < 2 || c->p > 4 || nrhs < 1) return hipErrorInvalidValue;
     OpArgs a{};
     a.bt = c->band;
     for (int i = 0; i < 3; ++i) a.u[i] = in.f[i];
@@ -378,15 +485,7 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     a.su = in.stride[0];
     a.sp = in.stride[3];
     a.ws = c->ws;
-    const long long nV = c->nV, nQ = c->nQ;
-    a.ws_stride = 2 * nV + 3 * nQ;
-    for (int i = 0; i < 3; ++i) {
-        a.wsGa[i] = c->off[i];
-        a.wsGb[i] = nV + c->off[i];
-    }
-    a.wsGg = 2 * nV;
-    a.wsGz = 2 * nV + nQ;
-    a.wsW = 2 * nV + 2 * nQ;
+    a.ws_stride = ops_ws_stride(c);
     for (int b = 0; b < 4; ++b)
         for (int d = 0; d < 3; ++d) a.dims[b][d] = (int)c->dims[b][d];
     a.nN = c->nN;
@@ -395,38 +494,46 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     a.mode = mode;
     const int nM = c->nM;
     const int P = c->p;
-    // xy: tiles of 64 columns x 16 rows (+ halo)
+    a.ntile1 = (nM + T1 - 1) / T1;
+    a.ntile2 = (nM + T2 - 1) / T2;
     {
-        const int ntile1 = (nM + XY_T1 - 1) / XY_T1;
-        const int strips = (nM + XY_CHUNK - 1) / XY_CHUNK;
-        dim3 grid(ntile1 * strips, nM, 4 * nrhs);
-        const int TR = XY_CHUNK + 2 * P, TW = XY_T1 + 2 * P;
-        size_t shm = (size_t)(2 * TR * TW + 2 * TR * XY_T1) * sizeof(double);
-        if (P == 2) hipLaunchKernelGGL(k_xy<2>, grid, dim3(XY_THREADS), shm, c->stream, a);
-        else if (P == 3) hipLaunchKernelGGL(k_xy<3>, grid, dim3(XY_THREADS), shm, c->stream, a);
-        else hipLaunchKernelGGL(k_xy<4>, grid, dim3(XY_THREADS), shm, c->stream, a);
+        // planes per workgroup: a workgroup takes kchunk + 2p steps, and the
+        // velocity launch runs in ceil(blocks / resident) rounds (two 512-thread
+        // workgroups per CU, one for degree 4); minimise rounds x steps
+        const long long per_chunk = (long long)a.ntile1 * a.ntile2 * 3 * nrhs;
+        const long long resident = 256LL * (P < 4 ? 2 : 1);
+        long long best = -1, best_kc = 1;
+        for (int kc = 2; kc <= 64; ++kc) {
+            const long long nch = (nM + kc - 1) / kc;
+            const long long cost = ((per_chunk * nch + resident - 1) / resident) * (kc + 2 * P);
+            if (best < 0 || cost < best) {
+                best = cost;
+                best_kc = kc;
+            }
+            if (nch == 1) break;
+        }
+        a.kchunk = (int)best_kc;
+        a.nchunk = (nM + a.kchunk - 1) / a.kchunk;
     }
-    // zp
+    // pressure chain (w = M_q z and/or y_p = M_q g)
     if (mode != OP_MV) {
-        const long long plane = (long long)nM * nM;
-        dim3 grid((unsigned)((plane + Z_THREADS - 1) / Z_THREADS),
-                  (unsigned)((nM + ZCHUNK - 1) / ZCHUNK), nrhs);
+        a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
         double* yp = out.f[3];
         long long syp = out.stride[3];
-        if (P == 2) hipLaunchKernelGGL(k_zp<2>, grid, dim3(Z_THREADS), 0, c->stream, a, yp, syp);
-        else if (P == 3) hipLaunchKernelGGL(k_zp<3>, grid, dim3(Z_THREADS), 0, c->stream, a, yp, syp);
-        else hipLaunchKernelGGL(k_zp<4>, grid, dim3(Z_THREADS), 0, c->stream, a, yp, syp);
+        dim3 grid(a.nblocks);
+        if (P == 2) hipLaunchKernelGGL(k_pres<2>, grid, dim3(NT), 0, c->stream, a, yp, syp);
+        else if (P == 3) hipLaunchKernelGGL(k_pres<3>, grid, dim3(NT), 0, c->stream, a, yp, syp);
+        else hipLaunchKernelGGL(k_pres<4>, grid, dim3(NT), 0, c->stream, a, yp, syp);
     }
-    // zv
+    // velocity (not for B^T)
     if (mode != OP_BT) {
-        const long long plane = (long long)nM * nM;  // largest plane of the three components
-        dim3 grid((unsigned)((plane + Z_THREADS - 1) / Z_THREADS),
-                  (unsigned)((nM + ZCHUNK - 1) / ZCHUNK), 3 * nrhs);
+        a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * 3 * nrhs;
         Fields s = src ? *src : out;
         if (!src) beta = 0.0;
-        if (P == 2) hipLaunchKernelGGL(k_zv<2>, grid, dim3(Z_THREADS), 0, c->stream, a, out, s, alpha, beta);
-        else if (P == 3) hipLaunchKernelGGL(k_zv<3>, grid, dim3(Z_THREADS), 0, c->stream, a, out, s, alpha, beta);
-        else hipLaunchKernelGGL(k_zv<4>, grid, dim3(Z_THREADS), 0, c->stream, a, out, s, alpha, beta);
+        dim3 grid(a.nblocks);
+        if (P == 2) hipLaunchKernelGGL(k_vel<2>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
+        else if (P == 3) hipLaunchKernelGGL(k_vel<3>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
+        else hipLaunchKernelGGL(k_vel<4>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
     }
     return hipGetLastError();
 }
