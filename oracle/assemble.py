@@ -83,19 +83,8 @@ class KronSystem:
         self.offsets = block_offsets(E, p)
 
     def lid_rhs(self, U=1.0):
-        """Nitsche right-hand side of the moving lid g = (U, 0, 0) on x3 = 1.
-
-        The weakly imposed tangential data enter through the penalty and
-        consistency parts of sigma (Sec. 3.1):
-            F(v) = int_{x3=1} 2 nu (alpha g.v - ((grad^s v) n).g).
-        Only component 1 is non-zero (v3 = 0 on x3 = 1 strongly).
-        """
-        m = self.m
-        f3 = m.alpha * m.M_at1 - 0.5 * m.dM_at1
-        f1 = 2 * self.nu * U * np.kron(f3, np.kron(m.int_M, m.int_N))
-        F = np.zeros(self.N)
-        F[: f1.size] = f1
-        return F
+        """Nitsche right-hand side of the moving lid (see ``lid_rhs_vector``)."""
+        return lid_rhs_vector(self.m, self.nu, U, self.N)
 
     def body_force_rhs(self, modes):
         """Load vector int b.v for a separable body force.
@@ -121,6 +110,98 @@ class KronSystem:
                 acc = acc + a * np.kron(s[2], np.kron(s[1], s[0]))
             F[off[c]:off[c + 1]] = acc
         return F
+
+
+def lid_rhs_vector(m, nu, U, N):
+    """Nitsche right-hand side of the moving lid g = (U, 0, 0) on x3 = 1.
+
+    The weakly imposed tangential data enter through the penalty and
+    consistency parts of sigma (Sec. 3.1):
+        F(v) = int_{x3=1} 2 nu (alpha g.v - ((grad^s v) n).g).
+    Only component 1 is non-zero (v3 = 0 on x3 = 1 strongly).  ``m`` holds
+    the univariate matrices, N is the system size.
+    """
+    f3 = m.alpha * m.M_at1 - 0.5 * m.dM_at1
+    f1 = 2 * nu * U * np.kron(f3, np.kron(m.int_M, m.int_N))
+    F = np.zeros(N)
+    F[: f1.size] = f1
+    return F
+
+
+class KronRows:
+    """Selected entries of K x without assembling K, for meshes too large to
+    assemble (Sec. 3.3).
+
+    Every block of K is a sum of Kronecker products c * A3 (x) A2 (x) A1 of
+    the univariate matrices (the same blocks as ``KronSystem``), and row
+    (i1, i2, i3) of A3 (x) A2 (x) A1 is the outer product of rows i3, i2, i1
+    of the factors, so one entry of the product costs a few hundred flops.
+    """
+
+    def __init__(self, E, p, nu=1.0, c_pen=None):
+        self.E, self.p, self.nu = E, p, nu
+        self.c_pen = default_c_pen(p) if c_pen is None else c_pen
+        m = Matrices1D(E, p, self.c_pen)
+        self.m = m
+        Mc, Tc, M, K, C, Cc = m.Mc, m.Tc, m.M_int, m.K_int, m.C_int, m.Cc_int
+        t = {}
+        t[0, 0] = [(2 * nu, Mc, Mc, K), (2 * nu, Mc, Tc, M), (2 * nu, Tc, Mc, M)]
+        t[1, 1] = [(2 * nu, Mc, M, Tc), (2 * nu, Mc, K, Mc), (2 * nu, Tc, M, Mc)]
+        t[2, 2] = [(2 * nu, M, Mc, Tc), (2 * nu, M, Tc, Mc), (2 * nu, K, Mc, Mc)]
+        t[0, 1] = [(nu, Mc, C.T, C)]
+        t[0, 2] = [(nu, C.T, Mc, C)]
+        t[1, 2] = [(nu, C.T, C, Mc)]
+        t[0, 3] = [(1.0, Mc, Mc, Cc)]
+        t[1, 3] = [(1.0, Mc, Cc, Mc)]
+        t[2, 3] = [(1.0, Cc, Mc, Mc)]
+        # the lower triangle: (A3 (x) A2 (x) A1)^T = A3^T (x) A2^T (x) A1^T
+        for (r, c) in list(t):
+            t[c, r] = [(a, B3.T, B2.T, B1.T) for (a, B3, B2, B1) in t[r, c]]
+        self.terms = t
+        self.mq_terms = [(1.0, Mc, Mc, Mc)]   # the pressure mass M_q
+        self.shapes = field_shapes(E, p)
+        self.offsets = block_offsets(E, p)
+        self.N = int(self.offsets[-1])
+
+    def block_entries(self, rb, cb, xc, local, terms=None):
+        """Entries ``local`` (indices within row block rb) of K_{rb,cb} xc
+        (or of the sum of ``terms`` applied to xc)."""
+        n1, n2, _ = self.shapes[rb]
+        X = np.asarray(xc).reshape(self.shapes[cb][::-1])
+        out = np.zeros(len(local))
+        for n, li in enumerate(local):
+            i1, i2, i3 = li % n1, (li // n1) % n2, li // (n1 * n2)
+            acc = 0.0
+            for a, A3, A2, A1 in (self.terms.get((rb, cb), []) if terms is None else terms):
+                r3, r2, r1 = A3[i3], A2[i2], A1[i1]
+                s3, s2, s1 = np.nonzero(r3)[0], np.nonzero(r2)[0], np.nonzero(r1)[0]
+                acc += a * np.einsum("k,j,i,kji->", r3[s3], r2[s2], r1[s1],
+                                     X[np.ix_(s3, s2, s1)])
+            out[n] = acc
+        return out
+
+    def mass_q_entries(self, xq, local):
+        """Entries ``local`` of M_q xq (pressure mass, M^ (x) M^ (x) M^)."""
+        return self.block_entries(3, 3, xq, local, terms=self.mq_terms)
+
+    def lid_rhs(self, U=1.0):
+        """The moving-lid right-hand side (as ``KronSystem.lid_rhs``)."""
+        return lid_rhs_vector(self.m, self.nu, U, self.N)
+
+    def rows(self, x, idx):
+        """(K x)[idx] for a full vector x."""
+        idx = np.asarray(idx)
+        off = self.offsets
+        out = np.zeros(len(idx))
+        for rb in range(4):
+            sel = np.nonzero((idx >= off[rb]) & (idx < off[rb + 1]))[0]
+            if sel.size == 0:
+                continue
+            local = idx[sel] - off[rb]
+            for cb in range(4):
+                if (rb, cb) in self.terms:
+                    out[sel] += self.block_entries(rb, cb, x[off[cb]:off[cb + 1]], local)
+        return out
 
 
 C_PEN_DEFAULT = 12.5

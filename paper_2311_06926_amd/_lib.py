@@ -41,6 +41,21 @@ class hp_opts(ctypes.Structure):
         ("max_rhs", ctypes.c_int),
         ("check_every", ctypes.c_int),
         ("use_graph", ctypes.c_int),
+        ("autotune", ctypes.c_int),
+        ("op_kchunk", ctypes.c_int),
+        ("op_order", ctypes.c_int),
+        ("fd_plan", ctypes.c_int),
+    ]
+
+
+class hp_tuning(ctypes.Structure):
+    _fields_ = [
+        ("op_kchunk", ctypes.c_int),
+        ("op_order", ctypes.c_int),
+        ("op_tuned", ctypes.c_int),
+        ("fd_plan", ctypes.c_int * 3),
+        ("op_us", ctypes.c_double),
+        ("fd_us", ctypes.c_double * 3),
     ]
 
 
@@ -76,6 +91,7 @@ SIGNATURES = {
     "hp_build_rhs": (I, [P, P, I, P, P, P, I]),
     "hp_apply_MV": (I, [P, P, P, I]),
     "hp_grad": (I, [P, P, P, P, P, P, I]),
+    "hp_get_tuning": (I, [P, I, ctypes.POINTER(hp_tuning)]),
     "hp_destroy": (None, [P]),
     "hp_status_string": (ctypes.c_char_p, [I]),
 }

@@ -701,6 +701,96 @@ static std::vector<T> padded(const std::vector<double>& A, int n, int np, bool t
     return out;
 }
 
+// ---- autotuner ----------------------------------------------------------------------
+// Times fn() (reps launches after one warm-up) on the context stream, in us.
+template <typename F>
+double time_launches(hp_ctx* c, hipEvent_t e0, hipEvent_t e1, int reps, F fn) {
+    if (fn() != hipSuccess) return -1.0;
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return -1.0;
+    for (int i = 0; i < reps; ++i)
+        if (fn() != hipSuccess) return -1.0;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        return -1.0;
+    return 1e3 * ms / reps;
+}
+
+// Picks the operator launch shape (for 1 and max_rhs right-hand sides) and
+// the P_0 plan (per precision) by timing them on zero vectors.  Only the
+// launch configuration changes, never the arithmetic of a point.
+hp_status autotune(hp_ctx* c) {
+    const long long R = c->opts.max_rhs, N = c->N;
+    double *x = nullptr, *y = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&x), sizeof(double) * N * R) != hipSuccess) return HP_ENOMEM;
+    if (hipMalloc(reinterpret_cast<void**>(&y), sizeof(double) * N * R) != hipSuccess) {
+        (void)hipFree(x);
+        return HP_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hp_status st = HP_OK;
+    if (hipMemsetAsync(x, 0, sizeof(double) * N * R, c->stream) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        st = HP_EHIP;
+    const Fields fx = full_fields(c, x), fy = full_fields(c, y);
+    // operator: chunk lengths x the two velocity workgroup orders
+    const int nrhs_list[2] = {1, (int)R};
+    for (int e = 0; e < (R > 1 ? 2 : 1) && st == HP_OK && c->opts.op_kchunk == 0; ++e) {
+        const int nr = nrhs_list[e];
+        static const int cand[] = {2, 3, 4, 6, 8, 12, 16, 20, 25, 32, 40, 48, 64};
+        double best = -1.0;
+        OpShape best_sh = op_model_shape(c, nr);
+        for (int kc : cand) {
+            if (kc > c->nM) break;
+            for (int order = 0; order <= 1; ++order) {
+                if (c->opts.op_order >= 0 && order != c->opts.op_order) continue;
+                c->op_force = OpShape{kc, order};
+                const double us = time_launches(c, e0, e1, 3, [&]() {
+                    return launch_operator(c, OP_K, fx, fy, 1.0, 0.0, nullptr, nr);
+                });
+                if (us < 0.0) st = HP_EHIP;
+                if (us >= 0.0 && (best < 0.0 || us < best)) {
+                    best = us;
+                    best_sh = c->op_force;
+                }
+            }
+        }
+        c->op_force = OpShape{0, 1};
+        c->op_tuned[e].nrhs = nr;
+        c->op_tuned[e].kchunk = best_sh.kchunk;
+        c->op_tuned[e].shape = best_sh;
+        c->op_tuned_us[e] = best;
+    }
+    // P_0: every plan that fits, per precision (velocity and pressure blocks)
+    for (int prec = 0; prec < 3 && st == HP_OK && c->fd_ok && c->opts.fd_plan < 0; ++prec) {
+        double best = -1.0;
+        int best_plan = -1;
+        for (int plan = 0; plan <= 3; ++plan) {
+            if (!fd_plan_valid(c, prec, plan)) continue;
+            c->fd_force = plan;
+            const double us = time_launches(c, e0, e1, 3, [&]() {
+                return launch_P0(c, fx, fy, true, true, false, prec, 1);
+            });
+            if (us < 0.0) st = HP_EHIP;
+            if (us >= 0.0 && (best < 0.0 || us < best)) {
+                best = us;
+                best_plan = plan;
+            }
+        }
+        c->fd_force = -1;
+        c->fd_tuned[prec] = best_plan;
+        c->fd_tuned_us[prec] = best;
+    }
+    c->op_force = OpShape{0, 1};
+    c->fd_force = -1;
+    if (hipStreamSynchronize(c->stream) != hipSuccess && st == HP_OK) st = HP_EHIP;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(y);
+    return st;
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -720,6 +810,10 @@ void hp_default_opts(hp_opts* o) {
     o->max_rhs = 1;
     o->check_every = 6;
     o->use_graph = 1;
+    o->autotune = 1;
+    o->op_kchunk = 0;
+    o->op_order = -1;
+    o->fd_plan = -1;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -746,7 +840,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (opts) o = *opts;
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen > 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
-        o.restart < 1 || o.maxit < 1)
+        o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
+        o.fd_plan < -1 || o.fd_plan > 3)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -875,7 +970,33 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         return HP_ENOMEM;
     }
     if (hipDeviceSynchronize() != hipSuccess) { hp_destroy(c); return HP_EHIP; }
+    if (c->opts.autotune) {
+        const hp_status ts = autotune(c);
+        if (ts != HP_OK) {
+            hp_destroy(c);
+            return ts;
+        }
+    }
     *out = c;
+    return HP_OK;
+}
+
+hp_status hp_get_tuning(const hp_ctx* c, int nrhs, hp_tuning* out) {
+    if (!c || !out || nrhs < 1 || nrhs > c->opts.max_rhs) return HP_EINVAL;
+    const OpShape sh = op_shape(c, nrhs);
+    out->op_kchunk = std::max(1, std::min(sh.kchunk, c->nM));
+    out->op_order = sh.comp_fast;
+    out->op_tuned = 0;
+    out->op_us = 0.0;
+    for (int e = 0; e < 2; ++e)
+        if (c->op_tuned[e].kchunk > 0 && c->op_tuned[e].nrhs == nrhs) {
+            out->op_tuned = 1;
+            out->op_us = c->op_tuned_us[e];
+        }
+    for (int prec = 0; prec < 3; ++prec) {
+        out->fd_plan[prec] = fd_plan_in_use(c, prec);
+        out->fd_us[prec] = c->fd_tuned_us[prec];
+    }
     return HP_OK;
 }
 

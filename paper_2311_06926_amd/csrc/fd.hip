@@ -14,6 +14,8 @@
 //        (16 rows per wave)
 //        (mode 3 both ways, fused with the eigenvalue scaling)
 // Forward: L = U1^T, R = U2.  Inverse: L = U1, R = U2^T.
+#include <type_traits>
+
 #include "hp_internal.h"
 
 namespace hp {
@@ -546,25 +548,47 @@ struct FDPlan {
     size_t shm_xy, shm_z;
 };
 
+// The plan of plan code `code` (bit 0: wide kernels, bit 1: stage the 1D
+// matrices in LDS when they fit); code < 0 gives the default plan: wide when
+// two planes fit in LDS, staging when it leaves room for a second workgroup.
 template <typename T>
-FDPlan fd_plan(int np) {
+FDPlan fd_plan(int np, int code) {
     const size_t lim = 160 * 1024, e = sizeof(T);
     FDPlan pl{};
     const size_t plane = (size_t)np * (np + 1) * e, mats = (size_t)2 * np * np * e;
     const size_t zbuf = (size_t)ZROWS * (np + 1) * e;
-    pl.wide = 2 * plane <= lim && 2 * zbuf <= lim;
-    if (pl.wide) {
-        pl.stage_xy = 2 * plane + mats <= 140 * 1024;
-        pl.stage_z = 2 * zbuf + mats <= 140 * 1024;
-        pl.shm_xy = 2 * plane + (pl.stage_xy ? mats : 0);
-        pl.shm_z = 2 * zbuf + (pl.stage_z ? mats : 0);
+    const bool wide_fits = 2 * plane <= lim && 2 * zbuf <= lim;
+    if (code < 0) {
+        pl.wide = wide_fits;
+        if (pl.wide) {
+            pl.stage_xy = 2 * plane + mats <= 140 * 1024;
+            pl.stage_z = 2 * zbuf + mats <= 140 * 1024;
+        } else {
+            pl.stage_xy = plane + mats <= 96 * 1024;
+            pl.stage_z = zbuf + mats <= 96 * 1024;
+        }
     } else {
-        pl.stage_xy = plane + mats <= 96 * 1024;
-        pl.stage_z = zbuf + mats <= 96 * 1024;
-        pl.shm_xy = plane + (pl.stage_xy ? mats : 0);
-        pl.shm_z = zbuf + (pl.stage_z ? mats : 0);
+        pl.wide = (code & 1) != 0;
+        const size_t nb = pl.wide ? 2 : 1;
+        pl.stage_xy = (code & 2) && nb * plane + mats <= lim;
+        pl.stage_z = (code & 2) && nb * zbuf + mats <= lim;
     }
+    const size_t nb = pl.wide ? 2 : 1;
+    pl.shm_xy = nb * plane + (pl.stage_xy ? mats : 0);
+    pl.shm_z = nb * zbuf + (pl.stage_z ? mats : 0);
     return pl;
+}
+
+template <typename T>
+bool fd_plan_fits(int np, int code) {
+    if (code < 0) return true;
+    if (code > 3) return false;
+    const size_t lim = 160 * 1024, e = sizeof(T);
+    const size_t plane = (size_t)np * (np + 1) * e, zbuf = (size_t)ZROWS * (np + 1) * e;
+    const size_t nb = (code & 1) ? 2 : 1;
+    // a staging plan must actually stage something to differ from its pair
+    const FDPlan pl = fd_plan<T>(np, code);
+    return nb * plane <= lim && nb * zbuf <= lim && (!(code & 2) || pl.stage_xy || pl.stage_z);
 }
 
 template <typename T, bool SPLIT = false>
@@ -591,7 +615,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     xa.fields_hi = hi;
     xa.inverse = 0;
     xa.accumulate = 0;
-    const FDPlan pl = fd_plan<T>(NMp);
+    const FDPlan pl = fd_plan<T>(NMp, fd_plan_in_use(c, std::is_same<T, double>::value ? 0 : (SPLIT ? 2 : 1)));
     const dim3 bxy(pl.wide ? FD_WIDE : FD_THREADS);
     auto launch_xy = [&](const XYArgs& xa_, bool to_double, int nfields) {
         dim3 g(nM, nfields * nrhs);
@@ -727,6 +751,17 @@ hipError_t fd_init_attributes() {
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+bool fd_plan_valid(const hp_ctx* c, int precision, int plan) {
+    const int NMp = (c->nM + 15) & ~15;
+    return precision == HP_PREC_FP64 ? fd_plan_fits<double>(NMp, plan) : fd_plan_fits<float>(NMp, plan);
+}
+
+int fd_plan_in_use(const hp_ctx* c, int precision) {
+    if (c->fd_force >= 0) return c->fd_force;
+    if (c->opts.fd_plan >= 0 && fd_plan_valid(c, precision, c->opts.fd_plan)) return c->opts.fd_plan;
+    return c->fd_tuned[precision];
 }
 
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,

@@ -44,6 +44,18 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Launch shape of the operator kernels: i3-planes per workgroup and the
+// order of the velocity workgroups (1: component fastest).
+struct OpShape {
+    int kchunk = 0;
+    int comp_fast = 1;
+};
+struct OpTuned {
+    int nrhs = 0;
+    int kchunk = 0;  // 0: not tuned
+    OpShape shape;
+};
+
 }  // namespace hp
 
 struct hp_ctx {
@@ -70,6 +82,15 @@ struct hp_ctx {
     double* d_red = nullptr;
     double* h_red = nullptr;  // pinned host mirror
     int red_slots = 0;
+    // launch shapes picked by the autotuner (for 1 and max_rhs right-hand
+    // sides), a shape forced while tuning, and the fast-diagonalisation plan
+    // per precision (-1: the default plan)
+    hp::OpTuned op_tuned[2];
+    hp::OpShape op_force{};
+    int fd_tuned[3] = {-1, -1, -1};
+    int fd_force = -1;
+    double op_tuned_us[2] = {0.0, 0.0};
+    double fd_tuned_us[3] = {0.0, 0.0, 0.0};
 };
 
 namespace hp {
@@ -89,6 +110,10 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
                            double alpha, double beta, const Fields* src, int nrhs);
 
 hipError_t ops_init_attributes();
+// the shape launch_operator uses for nrhs right-hand sides (forced, user
+// option, tuned, else the cost model) and the cost model alone
+OpShape op_shape(const hp_ctx* c, int nrhs);
+OpShape op_model_shape(const hp_ctx* c, int nrhs);
 // doubles of workspace per right-hand side used by launch_operator (holds w);
 // the fast-diagonalisation scratch follows at ops_ws_stride(c) * max_rhs
 long long ops_ws_stride(const hp_ctx* c);
@@ -99,6 +124,11 @@ hipError_t fd_init_attributes();
 // accumulate: y += result instead of y = result.
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
                      bool accumulate, int precision, int nrhs);
+// fast-diagonalisation plans: bit 0 = one MFMA tile per wave (wide kernels),
+// bit 1 = stage the 1D matrices in LDS.  Whether plan `plan` fits the LDS for
+// `precision`, and the plan launch_P0 uses (forced, option, tuned, default).
+bool fd_plan_valid(const hp_ctx* c, int precision, int plan);
+int fd_plan_in_use(const hp_ctx* c, int precision);
 
 // ---- vector kernels (krylov.hip) ----------------------------------------------
 hipError_t vec_axpby(hipStream_t s, long long n, double a, const double* x, double b,

@@ -55,6 +55,7 @@ struct OpArgs {
     int kchunk;          // i3-planes per workgroup
     int ntile1, ntile2, nchunk;
     int nblocks;         // workgroups in the launch
+    int comp_fast;       // velocity block order (see k_vel)
 };
 
 // Workgroups are dealt round-robin to the 8 XCDs in launch order.  Renumber
@@ -453,16 +454,25 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 
                                             double beta) {
     __shared__ double lds[vel_lds_doubles<P>()];
     int id = xcd_block(blockIdx.x, a.nblocks);
-    // the component is the fastest index, so that the three components of one
-    // tile and chunk run together on one XCD and read w through its L2 once
-    const int comp = id % 3;
-    id /= 3;
+    // order 1: the component is the fastest index, so that the three
+    // components of one tile and chunk run together on one XCD and read w
+    // through its L2 once; order 0: tiles fastest, components slowest
+    int comp;
+    if (a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
     const int t1 = id % a.ntile1;
     id /= a.ntile1;
     const int t2 = id % a.ntile2;
     id /= a.ntile2;
     const int ch = id % a.nchunk;
-    const int r = id / a.nchunk;
+    id /= a.nchunk;
+    if (!a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
+    const int r = id;
     const int i0 = t1 * T1, j0 = t2 * T2, k0 = ch * a.kchunk;
     if (comp == 0) vel_component<P, 0>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
     else if (comp == 1) vel_component<P, 1>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
@@ -474,6 +484,37 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 
 hipError_t ops_init_attributes() { return hipSuccess; }
 
 long long ops_ws_stride(const hp_ctx* c) { return c->nQ; }
+
+OpShape op_model_shape(const hp_ctx* c, int nrhs) {
+    // planes per workgroup: a workgroup takes kchunk + 2p steps, and the
+    // velocity launch runs in ceil(blocks / resident) rounds (two 512-thread
+    // workgroups per CU, one for degree 4); minimise rounds x steps
+    const int nM = c->nM, P = c->p;
+    const long long per_chunk =
+        (long long)((nM + T1 - 1) / T1) * ((nM + T2 - 1) / T2) * 3 * nrhs;
+    const long long resident = 256LL * (P < 4 ? 2 : 1);
+    long long best = -1, best_kc = 1;
+    for (int kc = 2; kc <= 64; ++kc) {
+        const long long nch = (nM + kc - 1) / kc;
+        const long long cost = ((per_chunk * nch + resident - 1) / resident) * (kc + 2 * P);
+        if (best < 0 || cost < best) {
+            best = cost;
+            best_kc = kc;
+        }
+        if (nch == 1) break;
+    }
+    return OpShape{(int)best_kc, 1};
+}
+
+OpShape op_shape(const hp_ctx* c, int nrhs) {
+    OpShape sh = op_model_shape(c, nrhs);
+    for (int e = 0; e < 2; ++e)
+        if (c->op_tuned[e].kchunk > 0 && c->op_tuned[e].nrhs == nrhs) sh = c->op_tuned[e].shape;
+    if (c->opts.op_kchunk > 0) sh.kchunk = c->opts.op_kchunk;
+    if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
+    if (c->op_force.kchunk > 0) sh = c->op_force;
+    return sh;
+}
 
 hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Fields& out,
                            double alpha, double beta, const Fields* src, int nrhs) {
@@ -496,25 +537,10 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     const int P = c->p;
     a.ntile1 = (nM + T1 - 1) / T1;
     a.ntile2 = (nM + T2 - 1) / T2;
-    {
-        // planes per workgroup: a workgroup takes kchunk + 2p steps, and the
-        // velocity launch runs in ceil(blocks / resident) rounds (two 512-thread
-        // workgroups per CU, one for degree 4); minimise rounds x steps
-        const long long per_chunk = (long long)a.ntile1 * a.ntile2 * 3 * nrhs;
-        const long long resident = 256LL * (P < 4 ? 2 : 1);
-        long long best = -1, best_kc = 1;
-        for (int kc = 2; kc <= 64; ++kc) {
-            const long long nch = (nM + kc - 1) / kc;
-            const long long cost = ((per_chunk * nch + resident - 1) / resident) * (kc + 2 * P);
-            if (best < 0 || cost < best) {
-                best = cost;
-                best_kc = kc;
-            }
-            if (nch == 1) break;
-        }
-        a.kchunk = (int)best_kc;
-        a.nchunk = (nM + a.kchunk - 1) / a.kchunk;
-    }
+    const OpShape sh = op_shape(c, nrhs);
+    a.kchunk = std::max(1, std::min(sh.kchunk, nM));
+    a.nchunk = (nM + a.kchunk - 1) / a.kchunk;
+    a.comp_fast = sh.comp_fast;
     // pressure chain (w = M_q z and/or y_p = M_q g)
     if (mode != OP_MV) {
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;

@@ -32,7 +32,8 @@ class Solver:
 
     def __init__(self, E, p, nu=1.0, *, c_pen=12.5, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
-                 iters=1, max_rhs=1, check_every=6, use_graph=True, device=None):
+                 iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
+                 op_kchunk=0, op_order=-1, fd_plan=-1, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -51,6 +52,10 @@ class Solver:
         o.max_rhs = max_rhs
         o.check_every = check_every
         o.use_graph = int(bool(use_graph))
+        o.autotune = int(bool(autotune))
+        o.op_kchunk = op_kchunk
+        o.op_order = op_order
+        o.fd_plan = fd_plan
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -69,6 +74,13 @@ class Solver:
         self.nQ = self.offsets[4] - self.offsets[3]
         self.N = self.offsets[4]
         self.max_rhs = max_rhs
+
+    def tuning(self, nrhs=1):
+        """Launch shapes used for batches of `nrhs` (see hp_get_tuning)."""
+        t = _lib.hp_tuning()
+        check(self.lib.hp_get_tuning(self.ctx, nrhs, ctypes.byref(t)), "hp_get_tuning")
+        return {"op_kchunk": t.op_kchunk, "op_order": t.op_order, "op_tuned": bool(t.op_tuned),
+                "op_us": t.op_us, "fd_plan": list(t.fd_plan), "fd_us": list(t.fd_us)}
 
     # -- memory helpers ------------------------------------------------------
     def empty(self, n, nrhs=1):

@@ -1,0 +1,184 @@
+"""GPU checks at the benchmark sizes and of the launch-shape choices.
+
+* Full-size parity: apply_K on the 32^3 and 192^3 (p = 3) meshes in the
+  launch configuration the benchmark times (autotuned shapes), checked on
+  sampled entries that the oracle evaluates one by one (``KronRows``: a row
+  of a Kronecker product is the outer product of the factors' rows), with
+  every block's first and last entries among the samples.  Tolerance 1e-12
+  relative to max |K x|, as for the small meshes.
+* P_0 at 32^3: the backward error of each velocity block, A_cc y_c = x_c,
+  and of the pressure block, M_q y_p = 2 nu x_p, on sampled rows.
+* The solve at 32^3 (q = 2, k = 1, MINRES): the oracle's lid right-hand side
+  in, and on sampled rows |b - K x|_i <= ||b - K x||_2 <= tol ||b||_2.
+* Launch shapes: every i3-chunk length and workgroup order, and every P_0
+  plan that fits, gives the same result (bit for bit for the operators,
+  whose per-point arithmetic does not depend on the shape; within the P_0
+  tolerance for the plans); the autotuner reports shapes in range.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2311_06926_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def samples(offsets, n_random, seed):
+    """Random indices plus the first and last three entries of each block."""
+    rng = np.random.default_rng(seed)
+    idx = [rng.integers(0, offsets[-1], n_random)]
+    for b in range(len(offsets) - 1):
+        lo, hi = offsets[b], offsets[b + 1]
+        idx.append(np.arange(lo, min(lo + 3, hi)))
+        idx.append(np.arange(max(hi - 3, lo), hi))
+    return np.unique(np.concatenate(idx))
+
+
+@pytest.mark.parametrize("E", [32, 192])
+def test_apply_K_full_size_sampled(dev, E):
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    p, nu = 3, 1.0
+    say(f"[fullsize] apply_K E={E} p={p}")
+    R = KronRows(E, p, nu)
+    sol = Solver(E, p, nu)
+    assert sol.N == R.N
+    x = synth.random_vector(R.N, seed=3)
+    y = sol.apply_K(torch.from_numpy(x).to(dev)).cpu().numpy()
+    idx = samples(R.offsets, 3000 if E == 32 else 1500, seed=E)
+    ref = R.rows(x, idx)
+    scale = np.abs(y).max()
+    err = np.abs(y[idx] - ref).max() / scale
+    say(f"[fullsize]   {idx.size} samples, max rel err {err:.2e}, tuning {sol.tuning(1)}")
+    assert err < 1e-12
+    sol.close()
+
+
+def test_P0_full_size_backward_error(dev):
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, nu = 32, 3, 0.7
+    say(f"[fullsize] P0 E={E} p={p}")
+    R = KronRows(E, p, nu)
+    sol = Solver(E, p, nu)
+    x = synth.random_vector(R.N, seed=11)
+    y = sol.apply_P0(torch.from_numpy(x).to(dev)).cpu().numpy()
+    o = R.offsets
+    rng = np.random.default_rng(5)
+    for c in range(3):
+        n = o[c + 1] - o[c]
+        loc = np.unique(np.concatenate([rng.integers(0, n, 800), [0, n - 1]]))
+        r = R.block_entries(c, c, y[o[c]:o[c + 1]], loc) - x[o[c] + loc]
+        assert np.abs(r).max() <= 1e-10 * np.abs(x[o[c]:o[c + 1]]).max(), c
+    nq = o[4] - o[3]
+    loc = np.unique(np.concatenate([rng.integers(0, nq, 800), [0, nq - 1]]))
+    r = R.mass_q_entries(y[o[3]:], loc) - 2.0 * nu * x[o[3] + loc]
+    assert np.abs(r).max() <= 1e-10 * 2.0 * nu * np.abs(x[o[3]:]).max()
+    sol.close()
+
+
+def test_solve_full_size_residual_on_samples(dev):
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, tol = 32, 3, 1e-8
+    say(f"[fullsize] solve E={E} p={p} q=2 k=1 MINRES")
+    R = KronRows(E, p, 1.0)
+    b = R.lid_rhs(1.0)
+    sol = Solver(E, p, 1.0, order=2, iters=1)
+    xg, info = sol.solve(torch.from_numpy(b).to(dev), tol)
+    x = xg.cpu().numpy()
+    say(f"[fullsize]   {info.iterations} iterations, true relres {info.true_relres:.2e}")
+    assert info.converged and info.true_relres <= tol
+    idx = samples(R.offsets, 3000, seed=9)
+    r = b[idx] - R.rows(x, idx)
+    assert np.abs(r).max() <= 1.01 * tol * np.linalg.norm(b)
+    sol.close()
+
+
+@pytest.mark.parametrize("E,p", [(8, 3), (15, 3), (5, 2), (4, 4)])
+def test_operator_shapes_agree_bitwise(dev, E, p):
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[shapes] operators E={E} p={p}")
+    nu = 1.3
+    base = Solver(E, p, nu, autotune=False, max_rhs=2)
+    x = torch.from_numpy(synth.random_vector(2 * base.N, seed=E + p)).to(dev)
+    u = x[:base.nV].contiguous()
+    q = x[base.N:base.N + base.nQ].contiguous()
+
+    def run(s):
+        return [s.apply_K(x), s.apply_K(x[:s.N].contiguous()), s.apply_A(u), s.apply_B(q),
+                s.apply_Bt(u), s.apply_MV(u)]
+
+    ref = run(base)
+    nM = E + p - 1
+    for kc in sorted({1, 2, 5, nM}):
+        for order in (0, 1):
+            s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order)
+            t = s.tuning(1)
+            assert t["op_kchunk"] == kc and t["op_order"] == order
+            for a, b in zip(run(s), ref):
+                assert torch.equal(a, b), (kc, order)
+            s.close()
+    base.close()
+
+
+@pytest.mark.parametrize("E,p", [(8, 3), (13, 2), (4, 4)])
+def test_fd_plans_agree(dev, E, p):
+    from oracle.assemble import KronSystem
+    from oracle.precond import BasePreconditioner
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[shapes] P0 plans E={E} p={p}")
+    nu = 0.9
+    S = KronSystem(E, p, nu)
+    ref = BasePreconditioner(S).apply(synth.random_vector(S.N, seed=21))
+    x = torch.from_numpy(synth.random_vector(S.N, seed=21)).to(dev)
+    seen = set()
+    for plan in range(4):
+        s = Solver(E, p, nu, autotune=False, fd_plan=plan)
+        used = s.tuning(1)["fd_plan"][0]
+        if used != plan:          # the plan does not fit in LDS at this size
+            s.close()
+            continue
+        seen.add(plan)
+        y = s.apply_P0(x).cpu().numpy()
+        assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-11, plan
+        s.close()
+        s32 = Solver(E, p, nu, autotune=False, fd_plan=plan, precision="fp32", krylov="fgmres")
+        y32 = s32.apply_P0(x).cpu().numpy()
+        assert np.abs(y32 - ref).max() / np.abs(ref).max() < 1e-5, plan
+        s32.close()
+    assert seen, "no P0 plan fits"
+
+
+def test_autotuner_reports_shapes_in_range(dev):
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 12, 3
+    say(f"[shapes] autotune E={E} p={p}")
+    s = Solver(E, p, 1.0, max_rhs=3)
+    plain = Solver(E, p, 1.0, autotune=False, max_rhs=3)
+    for nr in (1, 3):
+        t = s.tuning(nr)
+        say(f"[shapes]   nrhs={nr}: {t}")
+        assert t["op_tuned"] and 1 <= t["op_kchunk"] <= E + p - 1 and t["op_order"] in (0, 1)
+        assert t["op_us"] > 0
+        assert all(0 <= f <= 3 for f in t["fd_plan"]) and all(us > 0 for us in t["fd_us"])
+        x = torch.from_numpy(synth.random_vector(nr * s.N, seed=nr)).to(dev)
+        assert torch.equal(s.apply_K(x), plain.apply_K(x))
+    assert not s.tuning(2)["op_tuned"]      # a batch size the tuner did not time
+    s.close()
+    plain.close()

@@ -94,3 +94,25 @@ def test_sizes_match_the_complex():
             assert S.nV == 3 * nN * nM * nM and S.nQ == nM ** 3
     assert 3 * 8 * 81 + 729 == 2673
     assert 3 * 33 * 34 ** 2 + 34 ** 3 == 153748
+
+
+@pytest.mark.parametrize("E,p", [(4, 2), (3, 3), (5, 4), (2, 2)])
+def test_kron_rows_match_the_assembled_matrix(E, p):
+    """Row-by-row evaluation of K x (used for sampled checks on meshes too
+    large to assemble) equals the assembled Kronecker system on every row."""
+    from oracle.assemble import KronRows, KronSystem
+    S = KronSystem(E, p, 1.3)
+    R = KronRows(E, p, 1.3)
+    assert R.N == S.N
+    x = np.random.default_rng(7).standard_normal(S.N)
+    y = R.rows(x, np.arange(S.N))
+    ref = S.K @ x
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    # a single velocity block on its own: rows of A_22 u_2
+    o = S.offsets
+    loc = np.arange(o[2] - o[1])
+    y22 = R.block_entries(1, 1, x[o[1]:o[2]], loc)
+    assert np.allclose(y22, S.A22 @ x[o[1]:o[2]], rtol=0, atol=1e-13 * np.abs(y22).max())
+    xq = x[o[3]:]
+    yq = R.mass_q_entries(xq, np.arange(xq.size))
+    assert np.allclose(yq, S.Mq @ xq, rtol=0, atol=1e-13 * np.abs(yq).max())
