@@ -83,6 +83,58 @@ def timed_solve(sol, b, reps):
     return x, info, float(np.median(ts))
 
 
+def differentiable_leg(E, p, tol=1e-10, h=1e-6):
+    """Loss ||u(beta, nu) - u_t||^2 over the cavity at E^3 (u_t: the solution
+    for lid speed 1.5), FP32 P_k inside FP64 FGMRES: forward solve, adjoint
+    backward, and the adjoint gradients against central differences along nu
+    and along a random direction of the body-force field (step h); the same
+    forward + backward with an FP64 P_k for the speed-up."""
+    import torch
+    from paper_2311_06926_amd import synth
+    from paper_2311_06926_amd.autograd import cavity_loss
+    from paper_2311_06926_amd.solver import Solver
+    out = {"E": E, "p": p, "tol": tol}
+    for prec in ("fp32", "fp64"):
+        sol = Solver(E, p, 1.0, krylov="fgmres", precision=prec, iters=1, maxit=2000)
+        ut, _ = sol.solve(sol.build_rhs([1.5]), tol)
+        ut = ut[:sol.nV].clone()
+        beta0 = torch.from_numpy(synth.random_vector(sol.nV, seed=961, scale=0.3)).to("cuda")
+        nu_t = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+        beta = beta0.clone().requires_grad_(True)
+        cavity_loss(beta, nu_t, sol, ut, tol=tol).backward()      # warm-up
+        beta.grad = None
+        nu_t.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = cavity_loss(beta, nu_t, sol, ut, tol=tol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r = {"forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1), "loss": L.item(),
+             "dL_dnu": nu_t.grad.item()}
+        if prec == "fp32":
+            d = torch.from_numpy(synth.random_vector(sol.nV, seed=962)).to("cuda")
+            g_dir = float((beta.grad * d).sum())
+
+            def loss(b, n):
+                with torch.no_grad():
+                    return cavity_loss(b, torch.tensor(n, dtype=torch.float64, device="cuda"),
+                                       sol, ut, tol=tol).item()
+
+            fd_nu = (loss(beta0, 1.0 + h) - loss(beta0, 1.0 - h)) / (2 * h)
+            fd_dir = (loss(beta0 + h * d, 1.0) - loss(beta0 - h * d, 1.0)) / (2 * h)
+            r.update({"N": sol.N, "fd_dL_dnu": fd_nu,
+                      "dnu_rel_gap_vs_fd": abs(r["dL_dnu"] - fd_nu) / abs(fd_nu),
+                      "dbeta_dir_rel_gap_vs_fd": abs(g_dir - fd_dir) / abs(fd_dir)})
+        out[prec] = r
+        sol.close()
+    out["speedup_fp32_vs_fp64"] = ((out["fp64"]["forward_ms"] + out["fp64"]["backward_ms"]) /
+                                   (out["fp32"]["forward_ms"] + out["fp32"]["backward_ms"]))
+    return out
+
+
 def source_hash(*names):
     h = hashlib.sha256()
     for n in names:
@@ -164,6 +216,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip mixed/batched/hbm legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--hbm-E", type=int, default=192)
+    ap.add_argument("--diff-E", type=int, default=96)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -254,7 +307,7 @@ def main():
             log(f"[bench] sweep q={qq} k={kk}: {sweep[f'q{qq}_k{kk}']}")
             s2.close()
 
-    mixed, batched, hbm = {}, {}, {}
+    mixed, batched, hbm, diff = {}, {}, {}, {}
     if not args.no_extra:
         # ---- mixed precision, 64^3 degree 3, FGMRES(50), q = 2, k = 1
         Em, pm = 64, 3
@@ -311,6 +364,9 @@ def main():
         log(f"[bench] hbm: {hbm}")
         sh.close()
         del xh, yh
+        # ---- differentiable solve, 96^3 degree 3: forward + adjoint backward
+        diff = differentiable_leg(args.diff_E, 3)
+        log(f"[bench] differentiable: {diff}")
 
     cpu = None
     if not args.no_cpu:
@@ -342,6 +398,7 @@ def main():
         "mixed": mixed,
         "batched": batched,
         "hbm": hbm,
+        "differentiable": diff,
     }
     print(json.dumps(out), flush=True)
     sol.close()

@@ -34,7 +34,13 @@ int pad16(int n) { return (n + 15) & ~15; }
 // ---- buffers -------------------------------------------------------------------
 struct Extra {
     // hyper-power temporaries
-    double* hv = nullptr;  // 3 velocity vectors x max_rhs
+    double* hv = nullptr;  // 4 velocity vectors x max_rhs
+    int pv_slot = 0;       // hv slot of the P_V Richardson residual (0: V block, 3: Q block)
+    // the Q block of P_k runs beside the V block: a second stream, fork/join
+    // events and a second operator / fast-diagonalisation workspace
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    double* ws2 = nullptr;
     double* hq = nullptr;  // 3 pressure vectors per level x (KMAX+1) x max_rhs
     // Krylov vectors
     double* kv = nullptr;
@@ -146,7 +152,7 @@ hipError_t apply_PV(hp_ctx* c, int q, int level, const Fields& x, const Fields& 
     if (e != hipSuccess) return e;
     long long steps = 1;
     for (int i = 0; i < level; ++i) steps *= q;
-    Fields r = vel_fields(c, ex->hv, c->nV);  // hv slot 0
+    Fields r = vel_fields(c, ex->hv + (size_t)ex->pv_slot * c->nV * c->opts.max_rhs, c->nV);
     for (long long j = 1; j < steps; ++j) {
         e = launch_operator(c, OP_A, y, r, -1.0, 1.0, &x, nrhs);  // r = x - A y
         if (e != hipSuccess) return e;
@@ -224,13 +230,41 @@ hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields&
     return hipSuccess;
 }
 
+// P_k^{-1} = blockdiag(P_{V,k}^{-1}, P_{Q,k}^{-1}) (Sec. 4): the two blocks are
+// independent, so the Q block is issued on a second stream with its own
+// workspace and residual slot (fork/join through events, which also holds
+// under stream capture) while the V block runs on the context stream.
 hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs) {
     const int prec = c->opts.precision;
-    hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+    Extra* ex = extra_of(c);
+    auto q_block = [&]() {
+        if (c->opts.schur_variant == HP_SCHUR_PCQ2)
+            return apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+        return apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+    };
+    if (!ex->side) {
+        hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+        return e != hipSuccess ? e : q_block();
+    }
+    hipStream_t main = c->stream;
+    double* ws_main = c->ws;
+    hipError_t e = hipEventRecord(ex->fork_ev, main);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ex->side, ex->fork_ev, 0);
     if (e != hipSuccess) return e;
-    if (c->opts.schur_variant == HP_SCHUR_PCQ2)
-        return apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-    return apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+    c->stream = ex->side;
+    c->ws = ex->ws2;
+    ex->pv_slot = 3;
+    hipError_t eq = q_block();
+    c->stream = main;
+    c->ws = ws_main;
+    ex->pv_slot = 0;
+    // join even after an error, so that a capture on `main` stays well formed
+    e = hipEventRecord(ex->join_ev, ex->side);
+    hipError_t ev = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+    if (e == hipSuccess) e = hipStreamWaitEvent(main, ex->join_ev, 0);
+    if (eq != hipSuccess) return eq;
+    if (ev != hipSuccess) return ev;
+    return e;
 }
 
 // ---- device memory --------------------------------------------------------------------
@@ -930,7 +964,16 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->ws_doubles = (size_t)(ops_ws_stride(c) + 2 * c->N) * R;
     if (alloc_device(&c->ws, c->ws_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     Extra* ex = &ce->ex;
-    if (alloc_device(&ex->hv, (size_t)3 * c->nV * R) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (alloc_device(&ex->hv, (size_t)4 * c->nV * R) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (c->fd_ok) {
+        if (alloc_device(&ex->ws2, c->ws_doubles) != HP_OK ||
+            hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ex->fork_ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&ex->join_ev, hipEventDisableTiming) != hipSuccess) {
+            hp_destroy(c);
+            return HP_ENOMEM;
+        }
+    }
     if (alloc_device(&ex->hq, (size_t)3 * c->nQ * R * (KMAX + 1)) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     ex->coef_doubles = (size_t)std::max(4, 132) * R;
     if (alloc_device(&ex->dcoef, ex->coef_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
@@ -1132,6 +1175,10 @@ void hp_destroy(hp_ctx* c) {
     if (c->d_red) (void)hipFree(c->d_red);
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (ex->hv) (void)hipFree(ex->hv);
+    if (ex->ws2) (void)hipFree(ex->ws2);
+    if (ex->side) (void)hipStreamDestroy(ex->side);
+    if (ex->fork_ev) (void)hipEventDestroy(ex->fork_ev);
+    if (ex->join_ev) (void)hipEventDestroy(ex->join_ev);
     if (ex->hq) (void)hipFree(ex->hq);
     if (ex->kv) (void)hipFree(ex->kv);
     if (ex->dcoef) (void)hipFree(ex->dcoef);

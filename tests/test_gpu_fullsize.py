@@ -14,6 +14,8 @@
   plan that fits, gives the same result (bit for bit for the operators,
   whose per-point arithmetic does not depend on the shape; within the P_0
   tolerance for the plans); the autotuner reports shapes in range.
+* The differentiable solve at 96^3 (FP32 P_k in FP64 FGMRES): adjoint
+  gradients against central differences with step 1e-6.
 """
 import sys
 
@@ -182,3 +184,40 @@ def test_autotuner_reports_shapes_in_range(dev):
     assert not s.tuning(2)["op_tuned"]      # a batch size the tuner did not time
     s.close()
     plain.close()
+
+
+def test_differentiable_solve_96_matches_central_differences(dev):
+    """The differentiable-solve workload at 96^3, degree 3, FP32 P_k inside
+    FP64 FGMRES: dL/dnu and the derivative of L along a random direction of
+    the body-force field (adjoint) against central differences with step
+    1e-6.  L is quadratic in beta, so the central difference along beta is
+    exact up to the solve tolerance; along nu its truncation error is
+    O(h^2).  With tol 1e-11 the gap is ~tol |L| / h ~ 1e-5 relative."""
+    from paper_2311_06926_amd.autograd import cavity_loss
+    from paper_2311_06926_amd.solver import Solver
+    E, p, nu, h, tol = 96, 3, 1.0, 1e-6, 1e-11
+    say(f"[fullsize] differentiable solve E={E} p={p} (fp32 P_k, FGMRES)")
+    sol = Solver(E, p, nu, krylov="fgmres", precision="fp32", iters=1, maxit=2000)
+    ut, _ = sol.solve(sol.build_rhs([1.5]), tol)          # target: another lid speed
+    ut = ut[:sol.nV].clone()
+    beta0 = torch.from_numpy(synth.random_vector(sol.nV, seed=961, scale=0.3)).to(dev)
+    d = torch.from_numpy(synth.random_vector(sol.nV, seed=962)).to(dev)
+    beta = beta0.clone().requires_grad_(True)
+    nu_t = torch.tensor(nu, dtype=torch.float64, device=dev, requires_grad=True)
+    L = cavity_loss(beta, nu_t, sol, ut, lid=1.0, tol=tol)
+    L.backward()
+    g_nu = nu_t.grad.item()
+    g_dir = float((beta.grad * d).sum())
+
+    def loss(b, n):
+        with torch.no_grad():
+            return cavity_loss(b, torch.tensor(n, dtype=torch.float64, device=dev), sol, ut,
+                               lid=1.0, tol=tol).item()
+
+    fd_nu = (loss(beta0, nu + h) - loss(beta0, nu - h)) / (2 * h)
+    fd_dir = (loss(beta0 + h * d, nu) - loss(beta0 - h * d, nu)) / (2 * h)
+    say(f"[fullsize]   L={L.item():.6e} dL/dnu adjoint {g_nu:.8e} fd {fd_nu:.8e}; "
+        f"dL/dbeta.d adjoint {g_dir:.8e} fd {fd_dir:.8e}")
+    assert abs(g_nu - fd_nu) <= 1e-4 * abs(fd_nu)
+    assert abs(g_dir - fd_dir) <= 1e-4 * abs(fd_dir)
+    sol.close()

@@ -345,15 +345,17 @@ def test_bf16x3_preconditioner(dev):
     sbf.close()
 
 
-def test_autograd_adjoint_matches_oracle(dev):
+@pytest.mark.parametrize("E,p", [(4, 2), (8, 3)])
+def test_autograd_adjoint_matches_oracle(dev, E, p):
     """HyperPowerSolve backward (adjoint solve + gradient kernels) against the
-    oracle's dense-direct gradient at 4^3 elements, degree 2."""
+    oracle's dense-direct gradient (8^3 is the size the differentiable-solve
+    workload is checked at)."""
     from oracle.cases import CavityLoss, cavity
     from oracle.direct import DirectSolver
     from paper_2311_06926_amd.autograd import cavity_loss
     from paper_2311_06926_amd.solver import Solver
-    say("[parity] autograd adjoint vs oracle gradient 4^3 p=2")
-    E, p, nu = 4, 2, 1.1
+    say(f"[parity] autograd adjoint vs oracle gradient {E}^3 p={p}")
+    nu = 1.1
     St, bt = cavity(E, p, U=1.5)
     ut = DirectSolver(St).solve(bt)[:St.nV]
     ref = CavityLoss(E, p, U=1.0, u_target=ut)
