@@ -247,7 +247,8 @@ def main():
         yr = sol.empty(sol.N)
         fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
         t = timed_loop(lambda: fn(xr, yr), args.reps, sol.stream)
-        log(f"[bench] {args.only} E={E} p={p} N={sol.N}: {t * 1e6:.2f} us per call")
+        log(f"[bench] {args.only} E={E} p={p} N={sol.N}: {t * 1e6:.2f} us per call "
+            f"({args.reps} timed calls after 1 warm-up; tuning {sol.tuning(1)})")
         return
 
     log(f"[bench] setup E={E} p={p} q={q} k={k} N={N}")
