@@ -51,6 +51,7 @@ struct Extra {
     // device-side MINRES state: scalars, coefficient slots, dot partials
     MinresScalars* msc = nullptr;
     MinresScalars* hmsc[2] = {nullptr, nullptr};  // pinned host mirrors
+    MinresScalars* dmsc[2] = {nullptr, nullptr};  // their device addresses
     double* mcoef = nullptr;   // 8 per rhs: v (3), w (3), x (2)
     double* mpart = nullptr;   // 2 x DOT partials per rhs
     hipEvent_t mev[2] = {nullptr, nullptr};
@@ -131,13 +132,18 @@ hipError_t fields_axpby(hp_ctx* c, const Fields& x, const Fields& y, double a, d
                         bool vel, bool pres, int nrhs) {
     for (int blk = vel ? 0 : 3; blk < (pres ? 4 : 3); ++blk) {
         long long n = c->dims[blk][0] * c->dims[blk][1] * c->dims[blk][2];
-        for (int r = 0; r < nrhs; ++r) {
-            hipError_t e = vec_axpby(c->stream, n, a, x.f[blk] + r * x.stride[blk], b,
-                                     y.f[blk] + r * y.stride[blk]);
-            if (e != hipSuccess) return e;
-        }
+        hipError_t e = vec_axpbypcz(c->stream, n, nrhs, a, x.f[blk], x.stride[blk], b, y.f[blk],
+                                    y.stride[blk], 0.0, nullptr, 0, y.f[blk], y.stride[blk]);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// out = a x + b y + g z on the pressure block (batched)
+hipError_t pres_axpbypcz(hp_ctx* c, double a, const Fields& x, double b, const Fields& y, double g,
+                         const Fields& z, const Fields& out, int nrhs) {
+    return vec_axpbypcz(c->stream, c->nQ, nrhs, a, x.f[3], x.stride[3], b, y.f[3], y.stride[3], g,
+                        z.f[3], z.stride[3], out.f[3], out.stride[3]);
 }
 
 // ---- hyper-power preconditioner (Secs. 2, 4.1) ------------------------------------
@@ -187,28 +193,28 @@ Fields hq_slot(hp_ctx* c, int level, int slot) {
     return pres_fields(c, ex->hq + ((long long)level * 3 + slot) * nQ * R, nQ);
 }
 
-// y = P^_{Q,level}^{-1} x by the literal recursion of eq. Pcq1:
-// X_k = X_{k-1} sum_{i<q} (I - S~_{l(k)} X_{k-1})^i.
+// y = P^_{Q,level}^{-1} x by the recursion of eq. Pcq1:
+//   X_k = X_{k-1} sum_{i<q} (I - S~_{l(k)} X_{k-1})^i,
+// with the sum evaluated in Horner form, s_1 = x, s_{i+1} = x + (I - S X) s_i,
+// so that y = X_{k-1} s_q (one fused update per term instead of two).
 hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
                      int prec) {
     if (level == 0) return launch_P0(c, x, y, false, true, false, prec, nrhs);
-    Fields z = hq_slot(c, level, 0), s = hq_slot(c, level, 1), t = hq_slot(c, level, 2);
-    hipError_t e = fields_axpby(c, x, z, 1.0, 0.0, false, true, nrhs);
-    if (e != hipSuccess) return e;
-    e = fields_axpby(c, x, s, 1.0, 0.0, false, true, nrhs);
-    if (e != hipSuccess) return e;
+    Fields sa = hq_slot(c, level, 0), sb = hq_slot(c, level, 1), t = hq_slot(c, level, 2);
     const int lv = l_of(c, level);
+    const Fields* s = &x;  // s_1 = x
+    hipError_t e = hipSuccess;
     for (int i = 1; i < q; ++i) {
-        e = apply_PQ1(c, q, level - 1, z, t, nrhs, prec);      // t = X_{k-1} z
+        e = apply_PQ1(c, q, level - 1, *s, t, nrhs, prec);     // t = X_{k-1} s_i
         if (e != hipSuccess) return e;
         e = apply_Stilde(c, q, lv, t, t, nrhs, prec);          // t = S~ t (B reads t first)
         if (e != hipSuccess) return e;
-        e = fields_axpby(c, t, z, -1.0, 1.0, false, true, nrhs);  // z -= t
+        const Fields* sn = (s == &sa) ? &sb : &sa;
+        e = pres_axpbypcz(c, 1.0, x, 1.0, *s, -1.0, t, *sn, nrhs);  // s_{i+1} = x + s_i - t
         if (e != hipSuccess) return e;
-        e = fields_axpby(c, z, s, 1.0, 1.0, false, true, nrhs);   // s += z
-        if (e != hipSuccess) return e;
+        s = sn;
     }
-    return apply_PQ1(c, q, level - 1, s, y, nrhs, prec);
+    return apply_PQ1(c, q, level - 1, *s, y, nrhs, prec);
 }
 
 // y = P_{Q,level}^{-1} x for eq. Pcq2 (fixed S~_0): q^level Richardson steps.
@@ -336,7 +342,10 @@ MinresBufs minres_bufs(hp_ctx* c, int phase, int nrhs) {
     return b;
 }
 
-hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol) {
+// One MINRES iteration; the updated scalars are also written to the host
+// mirror `mirror` (device address of pinned host memory).
+hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
+                            MinresScalars* mirror) {
     Extra* ex = extra_of(c);
     const long long N = c->N;
     const int R = c->opts.max_rhs;
@@ -356,16 +365,8 @@ hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol
     }
     if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.zn, b.vn, nrhs, p1)) != hipSuccess) return e;
-    if ((e = minres_b(c->stream, ex->msc, p1, cw, cx, tol, nrhs)) != hipSuccess) return e;
-    {
-        const double* xs[3] = {b.z, b.wo, b.w};
-        if ((e = vec_lincomb(c->stream, N, N, nrhs, 3, xs, cw, b.wn)) != hipSuccess) return e;
-    }
-    {
-        const double* xs[2] = {b.x, b.wn};
-        if ((e = vec_lincomb(c->stream, N, N, nrhs, 2, xs, cx, b.x)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if ((e = minres_b(c->stream, ex->msc, p1, cw, cx, tol, nrhs, mirror)) != hipSuccess) return e;
+    return minres_update(c->stream, N, N, nrhs, b.z, b.wo, b.w, cw, b.wn, b.x, cx);
 }
 
 void drop_graphs(Extra* ex) {
@@ -394,7 +395,8 @@ hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
             st = HP_EHIP;
             break;
         }
-        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol);
+        // iteration it (phase (it-1) % 6) is polled through mirror it & 1
+        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[(ph + 1) & 1]);
         hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
         if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
         if (st == HP_OK && hipGraphInstantiate(&ex->g_exec[ph], g, nullptr, nullptr, 0) != hipSuccess)
@@ -451,9 +453,8 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         if (graphs) {
             HIPCHK(hipGraphLaunch(ex->g_exec[ph], c->stream));
         } else {
-            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol));
+            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1]));
         }
-        HIPCHK(hipMemcpyAsync(ex->hmsc[it & 1], ex->msc, sbytes, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipEventRecord(ex->mev[it & 1], c->stream));
         if (it >= 2) {
             HIPCHK(hipEventSynchronize(ex->mev[(it - 1) & 1]));
@@ -982,8 +983,12 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         return HP_ENOMEM;
     }
     if (hipMalloc(reinterpret_cast<void**>(&ex->msc), sizeof(MinresScalars) * R) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[0]), sizeof(MinresScalars) * R) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[1]), sizeof(MinresScalars) * R) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[0]), sizeof(MinresScalars) * R,
+                      hipHostMallocMapped) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[1]), sizeof(MinresScalars) * R,
+                      hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[0]), ex->hmsc[0], 0) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[1]), ex->hmsc[1], 0) != hipSuccess ||
         alloc_device(&ex->mcoef, 8 * R) != HP_OK ||
         alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||

@@ -32,6 +32,26 @@ __global__ void k_fill(long long n, double v, double* __restrict__ y) {
     for (; i < n; i += st) y[i] = v;
 }
 
+// out_r = a x_r + b y_r + g z_r for every right-hand side r (blockIdx.y); a
+// term whose coefficient is zero is not read.  out may alias x, y or z.
+__global__ void k_axpbypcz(long long n, double a, const double* x, long long sx, double b,
+                           const double* y, long long sy, double g, const double* z, long long sz,
+                           double* out, long long so) {
+    const int r = blockIdx.y;
+    x += (long long)r * sx;
+    if (y) y += (long long)r * sy;
+    if (z) z += (long long)r * sz;
+    out += (long long)r * so;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double v = a * x[i];
+        if (b != 0.0) v += b * y[i];
+        if (g != 0.0) v += g * z[i];
+        out[i] = v;
+    }
+}
+
 // y_r = sum_t coef[r*nt + t] * x_t[r*ld + i]  (up to 4 terms; y may alias one x_t)
 struct LinArgs {
     const double* x[4];
@@ -163,6 +183,14 @@ hipError_t vec_axpby(hipStream_t s, long long n, double a, const double* x, doub
     return hipGetLastError();
 }
 
+hipError_t vec_axpbypcz(hipStream_t s, long long n, int nrhs, double a, const double* x,
+                        long long sx, double b, const double* y, long long sy, double g,
+                        const double* z, long long sz, double* out, long long so) {
+    hipLaunchKernelGGL(k_axpbypcz, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, a, x, sx, b, y, sy,
+                       g, z, sz, out, so);
+    return hipGetLastError();
+}
+
 hipError_t vec_copy(hipStream_t s, long long n, const double* x, double* y) {
     hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(VT), 0, s, n, x, y);
     return hipGetLastError();
@@ -276,9 +304,7 @@ __global__ void k_minres_init(MinresScalars* sc, const double* part_zv, int nrhs
 }
 
 // after Kz = K z:  delta = (Kz.z)/gamma^2; coefficients of v_new = Kz/gamma - (delta/gamma) v - (gamma/gamma_old) v_old
-__global__ void k_minres_a(MinresScalars* sc, const double* part_kz, double* coef_v, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+__device__ void minres_a_one(MinresScalars* sc, const double* part_kz, double* coef_v, int r) {
     MinresScalars& m = sc[r];
     double* cv = coef_v + 3 * r;
     if (m.done) {
@@ -294,10 +320,8 @@ __global__ void k_minres_a(MinresScalars* sc, const double* part_kz, double* coe
 
 // after z_new = P^{-1} v_new: gamma_new, the Givens rotation, coefficients of
 // w_new = (z/gamma - a3 w_old - a2 w)/a1 and x += c_new eta w_new, then shift.
-__global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coef_w,
-                           double* coef_x, double tol, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+__device__ void minres_b_one(MinresScalars* sc, const double* part_zv, double* coef_w,
+                             double* coef_x, double tol, int r) {
     MinresScalars& m = sc[r];
     double* cw = coef_w + 3 * r;
     double* cx = coef_x + 2 * r;
@@ -348,6 +372,40 @@ __global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coe
     if (m.rel <= tol || gn == 0.0 || m.status != 0) m.done = 1;
 }
 
+__global__ void k_minres_a(MinresScalars* sc, const double* part_kz, double* coef_v, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < nrhs) minres_a_one(sc, part_kz, coef_v, r);
+}
+
+// mirror: host-mapped copy of the scalars (may be null), written after the
+// update so that the host can poll convergence without a copy launch
+__global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coef_w,
+                           double* coef_x, double tol, int nrhs, MinresScalars* mirror) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    minres_b_one(sc, part_zv, coef_w, coef_x, tol, r);
+    if (mirror) mirror[r] = sc[r];
+}
+
+// MINRES tail: w_new = cw0 z + cw1 w_old + cw2 w and x = cx0 x + cx1 w_new in one pass
+__global__ void k_minres_update(long long n, long long ld, const double* z, const double* wo,
+                                const double* w, const double* cw, double* wn, double* x,
+                                const double* cx) {
+    const int r = blockIdx.y;
+    const double c0 = cw[3 * r], c1 = cw[3 * r + 1], c2 = cw[3 * r + 2];
+    const double d0 = cx[2 * r], d1 = cx[2 * r + 1];
+    const long long off = (long long)r * ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) {
+        double v = c0 * z[off + i];
+        v += c1 * wo[off + i];
+        v += c2 * w[off + i];
+        wn[off + i] = v;
+        x[off + i] = d0 * x[off + i] + d1 * v;
+    }
+}
+
 }  // namespace
 
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs) {
@@ -359,9 +417,16 @@ hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double
     return hipGetLastError();
 }
 hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
-                    double* coef_x, double tol, int nrhs) {
+                    double* coef_x, double tol, int nrhs, MinresScalars* mirror) {
     hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, coef_w,
-                       coef_x, tol, nrhs);
+                       coef_x, tol, nrhs, mirror);
+    return hipGetLastError();
+}
+hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
+                         const double* wo, const double* w, const double* cw, double* wn,
+                         double* x, const double* cx) {
+    hipLaunchKernelGGL(k_minres_update, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, z, wo, w,
+                       cw, wn, x, cx);
     return hipGetLastError();
 }
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,

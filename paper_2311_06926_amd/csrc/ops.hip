@@ -313,14 +313,27 @@ __device__ void vel_component(const OpArgs& a, const Fields& out, const Fields& 
     const uint32_t wo1 = act ? wo + (C == 0 ? 8u : C == 1 ? 8u * nM : 0u) : OOB;
     const uint32_t yo = act ? 8u * (i + n1 * j) : OOB;
     if (!lop && !mv) {
-        // coupling only (B): y = alpha D_c^T w + beta src
+        // coupling only (B): y = alpha D_c^T w + beta src, four planes per
+        // step with all their loads issued before the first is used
         if (!act) return;
-        for (int k = k0; k < kend; ++k) {
-            const auto rw = make_rsrc(wv + wplane * k, WB);
-            const auto rw1 = make_rsrc(wv + wplane * (C == 2 ? k + 1 : k), WB);
-            double res = alpha * (bload(rw, wo) - bload(rw1, wo1));
-            res += beta * bload(make_rsrc(sv + plane * k, SB), yo);
-            bstore(make_rsrc(y + plane * k, YB), yo, res);
+        constexpr int U = 4;
+        for (int k = k0; k < kend; k += U) {
+            double a0[U], a1[U], sd[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k + u < kend;
+                const int kc = ok ? k + u : k0;
+                a0[u] = bload(make_rsrc(wv + wplane * kc, ok ? WB : 0u), wo);
+                a1[u] = bload(make_rsrc(wv + wplane * (C == 2 ? kc + 1 : kc), ok ? WB : 0u), wo1);
+                sd[u] = bload(make_rsrc(sv + plane * kc, ok ? SB : 0u), yo);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k + u < kend;
+                const int kc = ok ? k + u : k0;
+                bstore(make_rsrc(y + plane * kc, ok ? YB : 0u), yo,
+                       alpha * (a0[u] - a1[u]) + beta * sd[u]);
+            }
         }
         return;
     }

@@ -6,6 +6,11 @@
 
 namespace hp {
 
+// out_r = a x_r + b y_r + g z_r over n entries (strides sx, sy, so per rhs);
+// terms with a zero coefficient are not read; out may alias an input
+hipError_t vec_axpbypcz(hipStream_t s, long long n, int nrhs, double a, const double* x,
+                        long long sx, double b, const double* y, long long sy, double g,
+                        const double* z, long long sz, double* out, long long so);
 // y_r = sum_t dcoef[r*nt + t] * x[t]_r over n entries, rhs stride ld
 hipError_t vec_lincomb(hipStream_t s, long long n, long long ld, int nrhs, int nt,
                        const double* const* x, const double* dcoef, double* y);
@@ -33,8 +38,13 @@ struct MinresScalars {
 };
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs);
 hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double* coef_v, int nrhs);
+// mirror: device pointer of a host-mapped copy of sc (or null), refreshed by the kernel
 hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
-                    double* coef_x, double tol, int nrhs);
+                    double* coef_x, double tol, int nrhs, MinresScalars* mirror);
+// w_new = cw . (z, w_old, w) and x = cx . (x, w_new), per rhs, in one pass
+hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
+                         const double* wo, const double* w, const double* cw, double* wn,
+                         double* x, const double* cx);
 // partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
