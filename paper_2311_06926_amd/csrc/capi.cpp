@@ -65,6 +65,7 @@ struct Extra {
     // device-side FGMRES state (restart length up to 128)
     FgScalars* fsc = nullptr;
     FgScalars* hfsc[2] = {nullptr, nullptr};
+    FgScalars* dfsc[2] = {nullptr, nullptr};  // device addresses of the mapped mirrors
     double* fH = nullptr;      // R x 129 x 128
     double* fcs = nullptr;     // R x 128
     double* fsn = nullptr;     // R x 128
@@ -491,7 +492,9 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
 // j and replayed.  The true residual is checked at the end of every cycle.
 constexpr int FG_MMAX = 128;
 
-hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol) {
+// One Arnoldi step j of FGMRES(m); the updated scalars are also written to
+// the host mirror `mirror` (device address of pinned host memory).
+hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol, FgScalars* mirror) {
     Extra* ex = extra_of(c);
     const long long N = c->N;
     const long long V = N * (long long)c->opts.max_rhs;
@@ -514,7 +517,7 @@ hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol) {
     }
     if ((e = vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart)) != hipSuccess) return e;
     if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol, j,
-                    m, nrhs)) != hipSuccess)
+                    m, nrhs, mirror)) != hipSuccess)
         return e;
     const double* xs[1] = {w};
     return vec_lincomb(c->stream, N, N, nrhs, 1, xs, ex->fvs, Vb + (long long)(j + 1) * V);
@@ -545,7 +548,8 @@ hp_status build_fg_graphs(hp_ctx* c, int m, int nrhs, double tol) {
             st = HP_EHIP;
             break;
         }
-        hipError_t e = fgmres_iteration(c, j, m, nrhs, tol);
+        // step j is polled through mirror (j + 1) & 1
+        hipError_t e = fgmres_iteration(c, j, m, nrhs, tol, ex->dfsc[(j + 1) & 1]);
         hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
         if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
         if (st == HP_OK && hipGraphInstantiate(&ex->f_exec[j], g, nullptr, nullptr, 0) != hipSuccess)
@@ -612,11 +616,10 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
             if (graphs) {
                 HIPCHK(hipGraphLaunch(ex->f_exec[jl], c->stream));
             } else {
-                HIPCHK(fgmres_iteration(c, jl, m, nrhs, tol));
+                HIPCHK(fgmres_iteration(c, jl, m, nrhs, tol, ex->dfsc[(jl + 1) & 1]));
             }
             ++jl;
             ++total;
-            HIPCHK(hipMemcpyAsync(ex->hfsc[jl & 1], ex->fsc, sbytes, hipMemcpyDeviceToHost, c->stream));
             HIPCHK(hipEventRecord(ex->mev[jl & 1], c->stream));
             if (jl >= 2) {
                 HIPCHK(hipEventSynchronize(ex->mev[(jl - 1) & 1]));
@@ -1000,8 +1003,12 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     {
         const size_t M1 = FG_MMAX + 1;
         if (hipMalloc(reinterpret_cast<void**>(&ex->fsc), sizeof(FgScalars) * R) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[0]), sizeof(FgScalars) * R) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[1]), sizeof(FgScalars) * R) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[0]), sizeof(FgScalars) * R,
+                          hipHostMallocMapped) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&ex->hfsc[1]), sizeof(FgScalars) * R,
+                          hipHostMallocMapped) != hipSuccess ||
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dfsc[0]), ex->hfsc[0], 0) != hipSuccess ||
+            hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dfsc[1]), ex->hfsc[1], 0) != hipSuccess ||
             alloc_device(&ex->fH, M1 * FG_MMAX * R) != HP_OK ||
             alloc_device(&ex->fcs, FG_MMAX * R) != HP_OK || alloc_device(&ex->fsn, FG_MMAX * R) != HP_OK ||
             alloc_device(&ex->fg, M1 * R) != HP_OK || alloc_device(&ex->fy, FG_MMAX * R) != HP_OK ||

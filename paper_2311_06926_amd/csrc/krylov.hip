@@ -486,10 +486,8 @@ __global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hco
 }
 
 // h_{j+1,j} = ||w||, previous rotations on column j, new rotation, residual estimate
-__global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
-                         double* g, double* vscale, double tol, int j, int m, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+__device__ void fg_rot_one(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
+                           double* g, double* vscale, double tol, int j, int m, int r) {
     FgScalars& s = sc[r];
     if (!s.active) {
         vscale[r] = 0.0;
@@ -524,6 +522,16 @@ __global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double
     s.rel = fabs(gr[j + 1]) / s.bnorm;
     if (s.rel <= tol || hn == 0.0) s.active = 0;
     vscale[r] = s.active ? 1.0 / hn : 0.0;
+}
+
+// mirror: host-mapped copy of the scalars (may be null), refreshed after the step
+__global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
+                         double* g, double* vscale, double tol, int j, int m, int nrhs,
+                         FgScalars* mirror) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    fg_rot_one(sc, part_ww, H, cs, sn, g, vscale, tol, j, m, r);
+    if (mirror) mirror[r] = sc[r];
 }
 
 // y = H(1:jr,1:jr)^{-1} g(1:jr), zero beyond jr (padded to jmax)
@@ -572,9 +580,10 @@ hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, dou
     return hipGetLastError();
 }
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs) {
+                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs,
+                  FgScalars* mirror) {
     hipLaunchKernelGGL(k_fg_rot, dim3(1), rhs_block(nrhs), 0, s, sc, part, H, cs, sn, g, vscale, tol,
-                       j, m, nrhs);
+                       j, m, nrhs, mirror);
     return hipGetLastError();
 }
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,

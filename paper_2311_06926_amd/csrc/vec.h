@@ -59,8 +59,10 @@ hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g,
                     int m, int nrhs);
 hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
                 int pass, int m, int nrhs);
+// mirror: device pointer of a host-mapped copy of sc (or null), refreshed by the kernel
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs);
+                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs,
+                  FgScalars* mirror);
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
                     int m, int jmax, int nrhs);
 hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs);
