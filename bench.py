@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--schur", default="Pcq1")
     ap.add_argument("--only", default=None, choices=["solve", "apply_K", "apply_P0", "copy"])
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="preconditioner precision for --only apply_P0")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip mixed/batched/hbm legs")
     ap.add_argument("--no-cpu", action="store_true")
@@ -242,7 +244,8 @@ def main():
         log(f"[bench] copied {args.reps} x {8 * n} bytes")
         return
     if args.only in ("apply_K", "apply_P0"):
-        sol = Solver(E, p, 1.0)
+        sol = Solver(E, p, 1.0, precision=args.prec,
+                     krylov="minres" if args.prec == "fp64" else "fgmres")
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
         fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
@@ -308,7 +311,7 @@ def main():
             log(f"[bench] sweep q={qq} k={kk}: {sweep[f'q{qq}_k{kk}']}")
             s2.close()
 
-    mixed, batched, hbm, diff = {}, {}, {}, {}
+    mixed, batched, hbm, diff, large = {}, {}, {}, {}, {}
     if not args.no_extra:
         # ---- mixed precision, 64^3 degree 3, FGMRES(50), q = 2, k = 1
         Em, pm = 64, 3
@@ -365,6 +368,23 @@ def main():
         log(f"[bench] hbm: {hbm}")
         sh.close()
         del xh, yh
+        # ---- the same kernels on the 96^3, degree-3 mesh (MFMA-sized direction tiles)
+        El = args.diff_E
+        sl = Solver(El, p, 1.0)
+        xl = torch.from_numpy(synth.random_vector(sl.N, 5)).to("cuda")
+        yl = sl.empty(sl.N)
+        tlk = timed_loop(lambda: sl.apply_K(xl, yl), 20, sl.stream)
+        tlp = timed_loop(lambda: sl.apply_P0(xl, yl), 20, sl.stream)
+        fl = p0_flops(El, p)
+        large = {"E": El, "p": p, "N": sl.N, "apply_K_us": tlk * 1e6,
+                 "apply_K_algorithmic_GBps": 16.0 * sl.N / tlk / 1e9,
+                 "apply_K_hbm_frac": 16.0 * sl.N / tlk / 1e9 / HBM_PEAK_GBS,
+                 "apply_P0_us": tlp * 1e6, "apply_P0_TFLOPs": fl / tlp / 1e12,
+                 "apply_P0_mfma_frac": fl / tlp / 1e12 / FP64_PEAK_TFLOPS,
+                 "tuning": sl.tuning(1)}
+        log(f"[bench] large mesh: {large}")
+        sl.close()
+        del xl, yl
         # ---- differentiable solve, 96^3 degree 3: forward + adjoint backward
         diff = differentiable_leg(args.diff_E, 3)
         log(f"[bench] differentiable: {diff}")
@@ -399,6 +419,7 @@ def main():
         "mixed": mixed,
         "batched": batched,
         "hbm": hbm,
+        "large_mesh": large,
         "differentiable": diff,
     }
     print(json.dumps(out), flush=True)

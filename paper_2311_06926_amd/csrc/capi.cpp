@@ -913,7 +913,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     const int p = degree, wN = p, wM = p - 1;
     const int NNp = pad16(nN), NMp = pad16(nM);
     size_t nb = (size_t)2 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
-    size_t nfd = NMp <= 128 ? (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM : 0;
+    // (+32: the dense tables start on a 256-byte boundary, for vector loads)
+    size_t nfd = NMp <= 128 ? (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM + 32 : 0;
     if (alloc_device(&c->d_tables, nb + nfd) != HP_OK) { delete ce; return HP_ENOMEM; }
     double* tp = c->d_tables;
     c->band.ptr[BK_N] = tp; upload_band(c->tab.K_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
@@ -932,6 +933,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     };
     c->fd_ok = NMp <= 128;  // fast-diagonalisation tiles hold <= 128 per direction
     if (c->fd_ok) {
+    tp += (32 - (size_t)(tp - c->d_tables) % 32) % 32;  // 256-byte alignment of the dense tables
     c->fd64.UK = up64(padded<double>(c->tab.UK, nN, NNp, false));
     c->fd64.UKt = up64(padded<double>(c->tab.UK, nN, NNp, true));
     c->fd64.UT = up64(padded<double>(c->tab.UT, nM, NMp, false));

@@ -119,6 +119,13 @@ __device__ __forceinline__ const T* xy_right(const FDTables<T>& t, int f, int in
     if (inverse) return f == 1 ? t.UKt : t.UTt;
     return f == 1 ? t.UK : t.UT;
 }
+// the transpose of xy_right (M^^{-1} is symmetric)
+template <typename T>
+__device__ __forceinline__ const T* xy_right_t(const FDTables<T>& t, int f, int inverse) {
+    if (f == 3) return t.Mi;
+    if (inverse) return f == 1 ? t.UK : t.UT;
+    return f == 1 ? t.UKt : t.UTt;
+}
 
 template <typename T, typename TI, typename TO, bool STAGE>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
@@ -253,7 +260,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
             if (!pres) Uts[idx] = U3t[idx];
         }
         U3 = Us;
-        U3t = Uts;
+        U3t = pres ? Us : Uts;  // M^^{-1} is symmetric: one staged copy serves both
     }
     __syncthreads();
     T* Sw = S + wave * 16 * ld;  // this wave's 16 rows
@@ -324,19 +331,45 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
 // the two dense 1D matrices) fit in LDS.
 constexpr int FD_WIDE = 1024;   // 16 waves
 
+// D = A B on one 16x16 tile, K <= 128 (a multiple of 16).  One operand, G,
+// is stored with contiguous k: G(idx, k) = G[idx*ldg + k] (global memory or
+// an LDS copy); the other, H, is in LDS: H(k, idx) = H[k*h_k + idx*h_i].
+// GA: G is the A operand (rows of D), else the B operand (columns of D).
+// The contraction order over k is free as long as both operands use the same
+// one: in k-chunk c (16 wide), MFMA step s, lane (lr, lk) supplies
+// k = 16c + 4 lk + s, so its four G values of a chunk are contiguous and
+// arrive in one vector load, issued one chunk ahead of their products.
 template <typename T>
-__device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* A, int lda_row, int lda_k,
-                                                         const T* B, int ldb_k, int ldb_col,
-                                                         int K, int lr, int lk) {
-    // D[16x16] = A[16 x K] B[K x 16]; A(row, k) = A[row*lda_row + k*lda_k],
-    // B(k, col) = B[k*ldb_k + col*ldb_col]; this lane supplies row/col lr, k-offset lk.
+struct Vec4T;
+template <>
+struct Vec4T<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec4T<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+};
+
+template <typename T, bool GA>
+__device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* G, int ldg, const T* H, int h_k,
+                                                         int h_i, int K, int lr, int lk) {
     using M = Mfma<T>;
+    using V4 = typename Vec4T<T>::V;
+    const T* gp = G + lr * ldg + 4 * lk;
+    const T* hp = H + lr * h_i + 4 * lk * h_k;
+    V4 g[2];
+    g[0] = *reinterpret_cast<const V4*>(gp);
     typename M::V acc = {0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = 0; kk < K; kk += 4) {
-        const T av = A[lr * lda_row + (kk + lk) * lda_k];
-        const T bv = B[(kk + lk) * ldb_k + lr * ldb_col];
-        acc = M::mma(av, bv, acc);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (16 * c >= K) break;
+        if (16 * (c + 1) < K) g[(c + 1) & 1] = *reinterpret_cast<const V4*>(gp + 16 * (c + 1));
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const T h = hp[(16 * c + s) * h_k];
+            const T gv = g[c & 1][s];
+            acc = GA ? M::mma(gv, h, acc) : M::mma(h, gv, acc);
+        }
     }
     return acc;
 }
@@ -345,50 +378,70 @@ __device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* A, int lda_row
 // hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even), and
 // A B ~= A_hi B_hi + A_hi B_lo + A_lo B_hi, three 16x16x16 BF16 MFMAs per
 // 16-wide k step accumulated in FP32 (the lo*lo term is below FP32
-// rounding of the sum and is dropped).  The k index of the four values a
-// lane supplies is the same for both operands, which is all the
-// instruction requires; result rows are 4 (l/16) + i as for FP32.
+// rounding of the sum and is dropped).  A lane supplies the four values
+// k = 16c + 4 lk + j, j < 4, of both operands (the instruction only needs
+// the same k for both); result rows are 4 (l/16) + i as for FP32.  Operand
+// roles and layouts as in tile_gemm.
 typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ f4 tile_gemm_bf16x3(const float* A, int lda_row, int lda_k,
-                                               const float* B, int ldb_k, int ldb_col, int K,
-                                               int lr, int lk) {
+template <bool GA>
+__device__ __forceinline__ f4 tile_gemm_bf16x3(const float* G, int ldg, const float* H, int h_k,
+                                               int h_i, int K, int lr, int lk) {
+    const float* gp = G + lr * ldg + 4 * lk;
+    const float* hp = H + lr * h_i + 4 * lk * h_k;
+    f4 g[2];
+    g[0] = *reinterpret_cast<const f4*>(gp);
     f4 acc = {0, 0, 0, 0};
-    for (int kk = 0; kk < K; kk += 16) {
-        bf4 ahi, alo, bhi, blo;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (16 * c >= K) break;
+        if (16 * (c + 1) < K) g[(c + 1) & 1] = *reinterpret_cast<const f4*>(gp + 16 * (c + 1));
+        bf4 ghi, glo, hhi, hlo;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int k = kk + 4 * lk + j;
-            const float a = A[lr * lda_row + k * lda_k];
-            const float b = B[k * ldb_k + lr * ldb_col];
-            const __bf16 ah = (__bf16)a, bh = (__bf16)b;
-            ahi[j] = ah;
-            bhi[j] = bh;
-            alo[j] = (__bf16)(a - (float)ah);
-            blo[j] = (__bf16)(b - (float)bh);
+            const float gv = g[c & 1][j];
+            const float hv = hp[(16 * c + j) * h_k];
+            const __bf16 gh = (__bf16)gv, hh = (__bf16)hv;
+            ghi[j] = gh;
+            hhi[j] = hh;
+            glo[j] = (__bf16)(gv - (float)gh);
+            hlo[j] = (__bf16)(hv - (float)hh);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, bhi, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, blo, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, bhi, acc, 0, 0, 0);
+        if (GA) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ghi, hhi, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ghi, hlo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(glo, hhi, acc, 0, 0, 0);
+        } else {
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hhi, ghi, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hhi, glo, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hlo, ghi, acc, 0, 0, 0);
+        }
     }
     return acc;
 }
 
 // dispatch of a 16x16 tile product: native MFMA of T, or split BF16 (T = float)
-template <typename T, bool SPLIT>
-__device__ __forceinline__ typename Mfma<T>::V tile_mm(const T* A, int lda_row, int lda_k,
-                                                       const T* B, int ldb_k, int ldb_col, int K,
-                                                       int lr, int lk) {
+template <typename T, bool SPLIT, bool GA>
+__device__ __forceinline__ typename Mfma<T>::V tile_mm(const T* G, int ldg, const T* H, int h_k,
+                                                       int h_i, int K, int lr, int lk) {
     if constexpr (SPLIT) {
-        return tile_gemm_bf16x3(A, lda_row, lda_k, B, ldb_k, ldb_col, K, lr, lk);
+        return tile_gemm_bf16x3<GA>(G, ldg, H, h_k, h_i, K, lr, lk);
     } else {
-        return tile_gemm<T>(A, lda_row, lda_k, B, ldb_k, ldb_col, K, lr, lk);
+        return tile_gemm<T, GA>(G, ldg, H, h_k, h_i, K, lr, lk);
     }
 }
+
+// One i3-plane per workgroup, one buffer: the plane is transformed in place.
+// Each wave computes its (at most XY_MT) output tiles into registers, the
+// workgroup synchronises, and only then are the tiles written back, so the
+// two steps need a single plane of LDS (which leaves room to stage the two
+// dense 1D matrices, or lets FP64 planes up to 128 x 128 use 16 waves).
+constexpr int XY_MT = 4;        // tiles per wave: 8 x 8 tiles over 16 waves
 
 template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false>
 __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     using M = Mfma<T>;
+    using V = typename M::V;
     extern __shared__ unsigned char smem_raw[];
     T* S = reinterpret_cast<T*>(smem_raw);
     const int nf = a.fields_hi - a.fields_lo;
@@ -398,12 +451,11 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     const int n1 = a.dims[f][0], n2 = a.dims[f][1], n3 = a.dims[f][2];
     if (k >= n3) return;
     const int N1 = (n1 + 15) & ~15, N2 = (n2 + 15) & ~15;
-    const int ld = N1 + 1;  // column-major planes
+    const int ld = N1 + 1;  // column-major plane
     const int nb1 = N1 >> 4, nb2 = N2 >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = FD_WIDE / 64;
     const int lr = lane & 15, lk = lane >> 4;
-    T* Tb = S + N2 * ld;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] +
                   (long long)k * n1 * n2;
     for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_WIDE) {
@@ -412,33 +464,62 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
         if (row < n1 && col < n2) v = (T)x[row + (long long)col * n1];
         S[col * ld + row] = v;
     }
+    // L (rows contiguous) for step 1 and R^T (rows of R^T = columns of R) for step 2
     const T* L = xy_left(t, f, a.inverse);
-    const T* R = xy_right(t, f, a.inverse);
-    int ldL = (f == 0) ? t.NNp : t.NMp;
-    int ldR = (f == 1) ? t.NNp : t.NMp;
+    const T* Rt = xy_right_t(t, f, a.inverse);
+    const int ldL = (f == 0) ? t.NNp : t.NMp;
+    const int ldR = (f == 1) ? t.NNp : t.NMp;
     if (STAGE) {
-        T* Ls = Tb + N2 * ld;
+        T* Ls = S + N2 * ld;
         T* Rs = Ls + N1 * N1;
         for (int idx = threadIdx.x; idx < N1 * N1; idx += FD_WIDE) Ls[idx] = L[idx];
-        for (int idx = threadIdx.x; idx < N2 * N2; idx += FD_WIDE) Rs[idx] = R[idx];
+        for (int idx = threadIdx.x; idx < N2 * N2; idx += FD_WIDE) Rs[idx] = Rt[idx];
         L = Ls;
-        R = Rs;
+        Rt = Rs;
     }
     __syncthreads();
+    const int ntile = nb1 * nb2;
+    V acc[XY_MT];
     // step 1: T = L X  (tile (rb, cb): rows of L, columns of X)
-    for (int tt = wave; tt < nb1 * nb2; tt += nw) {
-        const int rb = tt % nb1, cb = tt / nb1;
-        auto acc = tile_mm<T, SPLIT>(L + rb * 16 * ldL, ldL, 1, S + cb * 16 * ld, 1, ld, N1, lr, lk);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) Tb[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
+    for (int m = 0; m < XY_MT; ++m) {
+        const int tt = wave + m * nw;
+        if (tt < ntile) {
+            const int rb = tt % nb1, cb = tt / nb1;
+            acc[m] = tile_mm<T, SPLIT, true>(L + rb * 16 * ldL, ldL, S + cb * 16 * ld, 1, ld, N1,
+                                             lr, lk);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < XY_MT; ++m) {
+        const int tt = wave + m * nw;
+        if (tt < ntile) {
+            const int rb = tt % nb1, cb = tt / nb1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[m][i];
+        }
     }
     __syncthreads();
     // step 2: Y = T R
-    for (int tt = wave; tt < nb1 * nb2; tt += nw) {
-        const int rb = tt % nb1, cb = tt / nb1;
-        auto acc = tile_mm<T, SPLIT>(Tb + rb * 16, 1, ld, R + cb * 16, ldR, 1, N2, lr, lk);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[i];
+    for (int m = 0; m < XY_MT; ++m) {
+        const int tt = wave + m * nw;
+        if (tt < ntile) {
+            const int rb = tt % nb1, cb = tt / nb1;
+            acc[m] = tile_mm<T, SPLIT, false>(Rt + cb * 16 * ldR, ldR, S + rb * 16, ld, 1, N2, lr,
+                                              lk);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < XY_MT; ++m) {
+        const int tt = wave + m * nw;
+        if (tt < ntile) {
+            const int rb = tt % nb1, cb = tt / nb1;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = acc[m][i];
+        }
     }
     __syncthreads();
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
@@ -490,7 +571,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
             if (!pres) Uts[idx] = U3t[idx];
         }
         U3 = Us;
-        U3t = Uts;
+        U3t = pres ? Us : Uts;  // M^^{-1} is symmetric: one staged copy serves both
     }
     __syncthreads();
     const int ntile = (ZROWS / 16) * nb3;
@@ -499,7 +580,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const double* l3 = (f == 2) ? t.lamK : t.lamT;
     for (int tt = wave; tt < ntile; tt += nw) {
         const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-        auto acc = tile_mm<T, SPLIT>(S + rb * 16 * ld, ld, 1, U3 + cb * 16, ldU, 1, N3, lr, lk);
+        auto acc = tile_mm<T, SPLIT, false>(U3t + cb * 16 * ldU, ldU, S + rb * 16 * ld, 1, ld, N3, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = rb * 16 + M::row(lk, i);
@@ -523,7 +604,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     if (!pres) {
         for (int tt = wave; tt < ntile; tt += nw) {
             const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-            auto acc = tile_mm<T, SPLIT>(Y + rb * 16 * ld, ld, 1, U3t + cb * 16, ldU, 1, N3, lr, lk);
+            auto acc = tile_mm<T, SPLIT, false>(U3 + cb * 16 * ldU, ldU, Y + rb * 16 * ld, 1, ld, N3, lr, lk);
 #pragma unroll
             for (int i = 0; i < 4; ++i) S[(rb * 16 + M::row(lk, i)) * ld + cb * 16 + lr] = acc[i];
         }
@@ -553,15 +634,17 @@ struct FDPlan {
 // two planes fit in LDS, staging when it leaves room for a second workgroup.
 template <typename T>
 FDPlan fd_plan(int np, int code) {
+    // wide kernels: the xy kernel transforms one plane in place (one plane of
+    // LDS), the z kernel keeps its input and intermediate rows (two buffers)
     const size_t lim = 160 * 1024, e = sizeof(T);
     FDPlan pl{};
     const size_t plane = (size_t)np * (np + 1) * e, mats = (size_t)2 * np * np * e;
     const size_t zbuf = (size_t)ZROWS * (np + 1) * e;
-    const bool wide_fits = 2 * plane <= lim && 2 * zbuf <= lim;
+    const bool wide_fits = plane <= lim && 2 * zbuf <= lim;
     if (code < 0) {
         pl.wide = wide_fits;
         if (pl.wide) {
-            pl.stage_xy = 2 * plane + mats <= 140 * 1024;
+            pl.stage_xy = plane + mats <= 140 * 1024;
             pl.stage_z = 2 * zbuf + mats <= 140 * 1024;
         } else {
             pl.stage_xy = plane + mats <= 96 * 1024;
@@ -569,13 +652,11 @@ FDPlan fd_plan(int np, int code) {
         }
     } else {
         pl.wide = (code & 1) != 0;
-        const size_t nb = pl.wide ? 2 : 1;
-        pl.stage_xy = (code & 2) && nb * plane + mats <= lim;
-        pl.stage_z = (code & 2) && nb * zbuf + mats <= lim;
+        pl.stage_xy = (code & 2) && plane + mats <= lim;
+        pl.stage_z = (code & 2) && (pl.wide ? 2 : 1) * zbuf + mats <= lim;
     }
-    const size_t nb = pl.wide ? 2 : 1;
-    pl.shm_xy = nb * plane + (pl.stage_xy ? mats : 0);
-    pl.shm_z = nb * zbuf + (pl.stage_z ? mats : 0);
+    pl.shm_xy = plane + (pl.stage_xy ? mats : 0);
+    pl.shm_z = (pl.wide ? 2 : 1) * zbuf + (pl.stage_z ? mats : 0);
     return pl;
 }
 
@@ -585,10 +666,10 @@ bool fd_plan_fits(int np, int code) {
     if (code > 3) return false;
     const size_t lim = 160 * 1024, e = sizeof(T);
     const size_t plane = (size_t)np * (np + 1) * e, zbuf = (size_t)ZROWS * (np + 1) * e;
-    const size_t nb = (code & 1) ? 2 : 1;
     // a staging plan must actually stage something to differ from its pair
     const FDPlan pl = fd_plan<T>(np, code);
-    return nb * plane <= lim && nb * zbuf <= lim && (!(code & 2) || pl.stage_xy || pl.stage_z);
+    const bool fits = (code & 1) ? plane <= lim && 2 * zbuf <= lim : plane <= lim && zbuf <= lim;
+    return fits && (!(code & 2) || pl.stage_xy || pl.stage_z);
 }
 
 template <typename T, bool SPLIT = false>
