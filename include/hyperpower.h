@@ -94,8 +94,10 @@ typedef struct hp_opts {
     int op_kchunk;      /* operator kernels: i3-planes per workgroup, 0 = tuned/model */
     int op_order;       /* operator kernels: velocity workgroup order, -1 = tuned/model,
                            0 = tiles fastest, 1 = components fastest */
-    int fd_plan;        /* P_0 kernels: -1 = tuned/default, else bit 0 = one MFMA tile
-                           per wave, bit 1 = 1D matrices staged in LDS (if they fit) */
+    int fd_plan;        /* P_0 kernels: -1 = tuned/default, else bit 0 = 16-wave
+                           kernels, bit 1 = 1D matrices staged in LDS (if they fit) */
+    int op_slabs;       /* operator: i3-slabs run one after the other (pressure chain
+                           then velocity per slab), 0 = tuned/model */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -103,6 +105,7 @@ typedef struct hp_tuning {
     int op_kchunk;      /* operator i3-planes per workgroup for this nrhs */
     int op_order;       /* operator velocity workgroup order for this nrhs */
     int op_tuned;       /* 1 if the autotuner timed the operator shapes for this nrhs */
+    int op_slabs;       /* operator i3-slabs for this nrhs */
     int fd_plan[3];     /* P_0 plan per precision (HP_PREC_*), -1 = default plan */
     double op_us;       /* tuned apply_K time (microseconds), 0 if not tuned */
     double fd_us[3];    /* tuned apply_P0 time per precision, 0 if not tuned */
@@ -123,7 +126,7 @@ void hp_default_opts(hp_opts* o);
 
 /* The launch shapes used for batches of nrhs right-hand sides.  The
  * autotuner (hp_opts.autotune) times apply_K for nrhs = 1 and nrhs =
- * max_rhs over i3-chunk lengths and workgroup orders, and apply_P0 per
+ * max_rhs over i3-chunk lengths, workgroup orders and i3-slab counts, and apply_P0 per
  * precision over the plans that fit in LDS (a batch size or precision the
  * tuner did not time uses the cost model / default plan).  Every shape and
  * plan computes the same result; only the time differs. */

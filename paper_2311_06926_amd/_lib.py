@@ -45,6 +45,7 @@ class hp_opts(ctypes.Structure):
         ("op_kchunk", ctypes.c_int),
         ("op_order", ctypes.c_int),
         ("fd_plan", ctypes.c_int),
+        ("op_slabs", ctypes.c_int),
     ]
 
 
@@ -53,6 +54,7 @@ class hp_tuning(ctypes.Structure):
         ("op_kchunk", ctypes.c_int),
         ("op_order", ctypes.c_int),
         ("op_tuned", ctypes.c_int),
+        ("op_slabs", ctypes.c_int),
         ("fd_plan", ctypes.c_int * 3),
         ("op_us", ctypes.c_double),
         ("fd_us", ctypes.c_double * 3),

@@ -780,9 +780,12 @@ hp_status autotune(hp_ctx* c) {
         OpShape best_sh = op_model_shape(c, nr);
         for (int kc : cand) {
             if (kc > c->nM) break;
-            for (int order = 0; order <= 1; ++order) {
+            for (int order = 0; order <= 1; ++order)
+            for (int slabs = 1; slabs <= 4; slabs *= 2) {
                 if (c->opts.op_order >= 0 && order != c->opts.op_order) continue;
-                c->op_force = OpShape{kc, order};
+                if (c->opts.op_slabs > 0 ? slabs != c->opts.op_slabs : (slabs > 1 && c->nM < 64))
+                    continue;
+                c->op_force = OpShape{kc, order, slabs};
                 const double us = time_launches(c, e0, e1, 3, [&]() {
                     return launch_operator(c, OP_K, fx, fy, 1.0, 0.0, nullptr, nr);
                 });
@@ -793,7 +796,7 @@ hp_status autotune(hp_ctx* c) {
                 }
             }
         }
-        c->op_force = OpShape{0, 1};
+        c->op_force = OpShape{0, 1, 1};
         c->op_tuned[e].nrhs = nr;
         c->op_tuned[e].kchunk = best_sh.kchunk;
         c->op_tuned[e].shape = best_sh;
@@ -819,7 +822,7 @@ hp_status autotune(hp_ctx* c) {
         c->fd_tuned[prec] = best_plan;
         c->fd_tuned_us[prec] = best;
     }
-    c->op_force = OpShape{0, 1};
+    c->op_force = OpShape{0, 1, 1};
     c->fd_force = -1;
     if (hipStreamSynchronize(c->stream) != hipSuccess && st == HP_OK) st = HP_EHIP;
     if (e0) (void)hipEventDestroy(e0);
@@ -852,6 +855,7 @@ void hp_default_opts(hp_opts* o) {
     o->op_kchunk = 0;
     o->op_order = -1;
     o->fd_plan = -1;
+    o->op_slabs = 0;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -879,7 +883,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen > 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
-        o.fd_plan < -1 || o.fd_plan > 3)
+        o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1043,6 +1047,7 @@ hp_status hp_get_tuning(const hp_ctx* c, int nrhs, hp_tuning* out) {
     const OpShape sh = op_shape(c, nrhs);
     out->op_kchunk = std::max(1, std::min(sh.kchunk, c->nM));
     out->op_order = sh.comp_fast;
+    out->op_slabs = std::max(1, std::min(sh.slabs, c->nM));
     out->op_tuned = 0;
     out->op_us = 0.0;
     for (int e = 0; e < 2; ++e)

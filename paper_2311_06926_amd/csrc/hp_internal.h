@@ -49,6 +49,7 @@ struct Workspace {
 struct OpShape {
     int kchunk = 0;
     int comp_fast = 1;
+    int slabs = 1;  // i3-slabs, each running the pressure then the velocity kernel
 };
 struct OpTuned {
     int nrhs = 0;

@@ -56,6 +56,7 @@ struct OpArgs {
     int ntile1, ntile2, nchunk;
     int nblocks;         // workgroups in the launch
     int comp_fast;       // velocity block order (see k_vel)
+    int kbase, klim;     // i3-planes [kbase, klim) of this launch (a slab)
 };
 
 // Workgroups are dealt round-robin to the 8 XCDs in launch order.  Renumber
@@ -145,8 +146,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 
     id /= a.ntile2;
     const int ch = id % a.nchunk;
     const int r = id / a.nchunk;
-    const int i0 = t1 * T1, j0 = t2 * T2, k0 = ch * a.kchunk;
-    const int kend = min(k0 + a.kchunk, nM);
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    const int kend = min(min(k0 + a.kchunk, a.klim), nM);
     const int c = threadIdx.x % T1, g = threadIdx.x / T1;
     const int i = i0 + c, j = j0 + g;
     const bool act = i < nM && j < nM;
@@ -290,7 +291,7 @@ __device__ void vel_component(const OpArgs& a, const Fields& out, const Fields& 
     constexpr int NS = (SR * SW + NT - 1) / NT;
     const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
     if (i0 >= n1 || j0 >= n2 || k0 >= n3) return;
-    const int kend = min(k0 + a.kchunk, n3);
+    const int kend = min(min(k0 + a.kchunk, a.klim), n3);
     const int c = threadIdx.x % T1, g = threadIdx.x / T1;
     const int i = i0 + c, j = j0 + g;
     const bool act = i < n1 && j < n2;
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 
         id /= 3;
     }
     const int r = id;
-    const int i0 = t1 * T1, j0 = t2 * T2, k0 = ch * a.kchunk;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
     if (comp == 0) vel_component<P, 0>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
     else if (comp == 1) vel_component<P, 1>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
     else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
@@ -516,7 +517,7 @@ OpShape op_model_shape(const hp_ctx* c, int nrhs) {
         }
         if (nch == 1) break;
     }
-    return OpShape{(int)best_kc, 1};
+    return OpShape{(int)best_kc, 1, 1};
 }
 
 OpShape op_shape(const hp_ctx* c, int nrhs) {
@@ -524,6 +525,7 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
     for (int e = 0; e < 2; ++e)
         if (c->op_tuned[e].kchunk > 0 && c->op_tuned[e].nrhs == nrhs) sh = c->op_tuned[e].shape;
     if (c->opts.op_kchunk > 0) sh.kchunk = c->opts.op_kchunk;
+    if (c->opts.op_slabs > 0) sh.slabs = c->opts.op_slabs;
     if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
     if (c->op_force.kchunk > 0) sh = c->op_force;
     return sh;
@@ -552,27 +554,47 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     a.ntile2 = (nM + T2 - 1) / T2;
     const OpShape sh = op_shape(c, nrhs);
     a.kchunk = std::max(1, std::min(sh.kchunk, nM));
-    a.nchunk = (nM + a.kchunk - 1) / a.kchunk;
     a.comp_fast = sh.comp_fast;
-    // pressure chain (w = M_q z and/or y_p = M_q g)
-    if (mode != OP_MV) {
+    Fields s = src ? *src : out;
+    if (!src) beta = 0.0;
+    double* yp = out.f[3];
+    const long long syp = out.stride[3];
+    auto pres = [&](int lo, int hi) {
+        a.kbase = lo;
+        a.klim = hi;
+        a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
-        double* yp = out.f[3];
-        long long syp = out.stride[3];
         dim3 grid(a.nblocks);
         if (P == 2) hipLaunchKernelGGL(k_pres<2>, grid, dim3(NT), 0, c->stream, a, yp, syp);
         else if (P == 3) hipLaunchKernelGGL(k_pres<3>, grid, dim3(NT), 0, c->stream, a, yp, syp);
         else hipLaunchKernelGGL(k_pres<4>, grid, dim3(NT), 0, c->stream, a, yp, syp);
-    }
-    // velocity (not for B^T)
-    if (mode != OP_BT) {
+    };
+    auto vel = [&](int lo, int hi) {
+        a.kbase = lo;
+        a.klim = hi;
+        a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * 3 * nrhs;
-        Fields s = src ? *src : out;
-        if (!src) beta = 0.0;
         dim3 grid(a.nblocks);
         if (P == 2) hipLaunchKernelGGL(k_vel<2>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
         else if (P == 3) hipLaunchKernelGGL(k_vel<3>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
         else hipLaunchKernelGGL(k_vel<4>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
+    };
+    if (mode == OP_BT) {
+        pres(0, nM);
+    } else if (mode == OP_MV) {
+        vel(0, nM);
+    } else {
+        // slabs of i3-planes, each pressure chain then velocity, so that the
+        // second read of u and the round trip of w can stay in the Infinity
+        // Cache; the pressure launch of a slab also produces w on the first
+        // plane of the next slab, which D_3^T needs
+        const int S = std::max(1, std::min(sh.slabs, nM));
+        for (int sl = 0; sl < S; ++sl) {
+            const int lo = (int)((long long)nM * sl / S), hi = (int)((long long)nM * (sl + 1) / S);
+            if (hi <= lo) continue;
+            pres(lo, std::min(hi + 1, nM));
+            vel(lo, hi);
+        }
     }
     return hipGetLastError();
 }

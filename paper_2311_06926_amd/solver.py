@@ -33,7 +33,7 @@ class Solver:
     def __init__(self, E, p, nu=1.0, *, c_pen=12.5, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
-                 op_kchunk=0, op_order=-1, fd_plan=-1, device=None):
+                 op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -56,6 +56,7 @@ class Solver:
         o.op_kchunk = op_kchunk
         o.op_order = op_order
         o.fd_plan = fd_plan
+        o.op_slabs = op_slabs
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -79,7 +80,8 @@ class Solver:
         """Launch shapes used for batches of `nrhs` (see hp_get_tuning)."""
         t = _lib.hp_tuning()
         check(self.lib.hp_get_tuning(self.ctx, nrhs, ctypes.byref(t)), "hp_get_tuning")
-        return {"op_kchunk": t.op_kchunk, "op_order": t.op_order, "op_tuned": bool(t.op_tuned),
+        return {"op_kchunk": t.op_kchunk, "op_order": t.op_order, "op_slabs": t.op_slabs,
+                "op_tuned": bool(t.op_tuned),
                 "op_us": t.op_us, "fd_plan": list(t.fd_plan), "fd_us": list(t.fd_us)}
 
     # -- memory helpers ------------------------------------------------------

@@ -40,6 +40,7 @@ def test_binding_signatures_cover_the_header():
     lib.hp_default_opts(ctypes.byref(opts))
     assert opts.c_pen == 12.5 and opts.order == 2 and opts.max_rhs == 1
     assert opts.autotune == 1 and opts.op_kchunk == 0 and opts.op_order == -1 and opts.fd_plan == -1
+    assert opts.op_slabs == 0
     assert lib.hp_status_string(-6) == b"not converged within maxit"
 
 
@@ -56,7 +57,8 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.hp_apply_K(None, None, None, 1) == -1
     assert lib.hp_get_tuning(None, 1, ctypes.byref(_lib.hp_tuning())) == -1
     # out-of-range launch-shape options are rejected before any HIP call
-    for field, bad in (("op_kchunk", -1), ("op_order", 2), ("fd_plan", 4), ("fd_plan", -2)):
+    for field, bad in (("op_kchunk", -1), ("op_order", 2), ("fd_plan", 4), ("fd_plan", -2),
+                       ("op_slabs", -1)):
         opts = _lib.hp_opts()
         lib.hp_default_opts(ctypes.byref(opts))
         setattr(opts, field, bad)

@@ -130,12 +130,14 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
     nM = E + p - 1
     for kc in sorted({1, 2, 5, nM}):
         for order in (0, 1):
-            s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order)
-            t = s.tuning(1)
-            assert t["op_kchunk"] == kc and t["op_order"] == order
-            for a, b in zip(run(s), ref):
-                assert torch.equal(a, b), (kc, order)
-            s.close()
+            for slabs in (1, 3):
+                s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order,
+                           op_slabs=slabs)
+                t = s.tuning(1)
+                assert t["op_kchunk"] == kc and t["op_order"] == order and t["op_slabs"] == slabs
+                for a, b in zip(run(s), ref):
+                    assert torch.equal(a, b), (kc, order, slabs)
+                s.close()
     base.close()
 
 
