@@ -83,6 +83,28 @@ def timed_solve(sol, b, reps):
     return x, info, float(np.median(ts))
 
 
+def measured_peaks():
+    """Reference rates measured on this GPU with library kernels: a 1 GiB
+    device-to-device copy (HBM) and a large FP64 / FP32 GEMM (rocBLAS or
+    hipBLASLt through torch.matmul; MFMA)."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    t = timed_loop(lambda: b.copy_(a), 10, stream)
+    out = {"copy_GBps": 2 * 8.0 * n / t / 1e9}
+    del a, b
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32)):
+        m = 8192
+        x = torch.randn(m, m, dtype=dt, device="cuda")
+        y = torch.randn(m, m, dtype=dt, device="cuda")
+        t = timed_loop(lambda: torch.matmul(x, y), 5, stream)
+        out[f"gemm_{name}_TFLOPs"] = 2.0 * m ** 3 / t / 1e12
+        del x, y
+    return out
+
+
 def differentiable_leg(E, p, tol=1e-10, h=1e-6):
     """Loss ||u(beta, nu) - u_t||^2 over the cavity at E^3 (u_t: the solution
     for lid speed 1.5), FP32 P_k inside FP64 FGMRES: forward solve, adjoint
@@ -368,6 +390,24 @@ def main():
         log(f"[bench] hbm: {hbm}")
         sh.close()
         del xh, yh
+        # ---- HBM sweep of apply_K (vectors of 17 MB .. 550 MB) and measured peaks
+        sweep_hbm = []
+        for Es in (128, 192, 256):
+            for ps in (2, 3):
+                ss = Solver(Es, ps, 1.0)
+                xs = torch.from_numpy(synth.random_vector(ss.N, 6)).to("cuda")
+                ys = ss.empty(ss.N)
+                ts = timed_loop(lambda: ss.apply_K(xs, ys), 10, ss.stream)
+                gs = 16.0 * ss.N / ts / 1e9
+                sweep_hbm.append({"E": Es, "p": ps, "N": ss.N, "vector_MB": 8.0 * ss.N / 1e6,
+                                  "apply_K_us": ts * 1e6, "algorithmic_GBps": gs,
+                                  "hbm_frac": gs / HBM_PEAK_GBS, "tuning": ss.tuning(1)})
+                log(f"[bench] hbm sweep: {sweep_hbm[-1]}")
+                ss.close()
+                del xs, ys
+        hbm["sweep"] = sweep_hbm
+        hbm["measured_peaks"] = measured_peaks()
+        log(f"[bench] measured peaks: {hbm['measured_peaks']}")
         # ---- the same kernels on the 96^3, degree-3 mesh (MFMA-sized direction tiles)
         El = args.diff_E
         sl = Solver(El, p, 1.0)
