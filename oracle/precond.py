@@ -21,7 +21,11 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 * Q block with inner updates: eq. ``Pcq1``, S~_l = B^T P_{V,l}^{-1} B at the
   k-th update, with l = 0 for k = 1 and l = k for k > 1 (the schedule of
   option (5) in Sec. 4.1); ``schedule='prev'`` uses l = k - 1 instead.
-* Q block without inner updates: eq. ``Pcq2`` with P_V = P_{V,0}.
+* Q block without inner updates: eq. ``Pcq2`` with P_V = P_{V,0} (option
+  (1) of Sec. 4.1); ``fixed_level=l`` takes the fixed P_{V,l} instead
+  (option (2)).
+* Q block with the exact Schur complement: eq. ``Pcq_exact``,
+  S = B^T A^{-1} B with A^{-1} applied by sparse LU (``variant='Pcq_exact'``).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -97,14 +101,17 @@ def hyperpower_apply(X_prev, Aop, q, x):
 class HyperPower:
     """P_k^{-1} = diag(P_{V,k}^{-1}, P_{Q,k}^{-1}) for order q and k updates."""
 
-    def __init__(self, sysm, q=2, k=1, variant="Pcq1", schedule="literal", base=None):
-        if q < 2 or k < 0:
-            raise ValueError("order q >= 2 and k >= 0 required")
+    def __init__(self, sysm, q=2, k=1, variant="Pcq1", schedule="literal", base=None,
+                 fixed_level=0):
+        if q < 2 or k < 0 or fixed_level < 0:
+            raise ValueError("order q >= 2, k >= 0 and fixed_level >= 0 required")
         self.s = sysm
         self.q, self.k = q, k
         self.variant = variant
         self.schedule = schedule
+        self.fixed_level = fixed_level
         self.P0 = BasePreconditioner(sysm) if base is None else base
+        self._A_lu = None
 
     # -- V block, eq. Pcv ---------------------------------------------------
     def apply_V(self, level, x):
@@ -124,18 +131,26 @@ class HyperPower:
         """S~_l x = B^T P_{V,l}^{-1} B x."""
         return self.P0.Bt(self.apply_V(level_v, self.P0.B(x)))
 
+    def S_exact(self, x):
+        """S x = B^T A^{-1} B x (eq. Pcq_exact), A^{-1} by sparse LU."""
+        if self._A_lu is None:
+            self._A_lu = spla.splu(self.s.A.tocsc())
+        return self.P0.Bt(self._A_lu.solve(self.P0.B(x)))
+
     def apply_Q(self, level, x):
         """P_{Q,level}^{-1} x for the chosen variant."""
         if level == 0:
             return self.P0.apply_Q0(x)
         if self.variant == "Pcq1":
             lv = self.l_of(level)
+            Sop = lambda y: self.S_tilde(lv, y)        # noqa: E731
         elif self.variant == "Pcq2":
-            lv = 0
+            Sop = lambda y: self.S_tilde(self.fixed_level, y)   # noqa: E731
+        elif self.variant == "Pcq_exact":
+            Sop = self.S_exact
         else:
             raise ValueError(self.variant)
-        return hyperpower_apply(lambda y: self.apply_Q(level - 1, y),
-                                lambda y: self.S_tilde(lv, y), self.q, x)
+        return hyperpower_apply(lambda y: self.apply_Q(level - 1, y), Sop, self.q, x)
 
     def apply(self, x):
         nV = self.s.nV

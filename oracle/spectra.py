@@ -64,11 +64,10 @@ def ritz_extremes(alpha, beta):
     return float(w[0]), float(w[-1])
 
 
-def velocity_block_extremes(pre, steps, seed=0):
-    """Ritz extremes of P_{V,0}^{-1} A (``pre``: a BasePreconditioner)."""
-    r0 = np.random.default_rng(seed).standard_normal(pre.s.nV)
-    al, be = lanczos(pre.A, pre.apply_V0, r0, steps)
-    return ritz_extremes(al, be)
+def velocity_lanczos(H, k, r0, steps):
+    """Lanczos coefficients of the pencil (A, P_{V,k}) (``H``: a HyperPower,
+    whose order q is used), from residual r0."""
+    return lanczos(H.P0.A, lambda r: H.apply_V(k, r), r0, steps)
 
 
 def pressure_null_vector(sysm):
@@ -81,22 +80,59 @@ def pressure_null_vector(sysm):
     return n / np.linalg.norm(n)
 
 
-def schur_block_extremes(pre, steps, seed=0):
-    """Ritz extremes (non-zero part) of P_{Q,0}^{-1} S~_0,
-    S~_0 = B^T P_{V,0}^{-1} B.  Every residual is projected Euclidean-
-    orthogonally to the null vector n of S~_0 (the range of S~_0), which
-    keeps rounding from bringing the zero eigenvalue into the Ritz values."""
-    n = pressure_null_vector(pre.s)
-
-    def S(x):
-        return pre.Bt(pre.apply_V0(pre.B(x)))
+def schur_lanczos(H, k, s_level, x0, steps):
+    """Lanczos coefficients of the pencil (S~_l, P_{Q,k}), S~_l =
+    B^T P_{V,l}^{-1} B with l = s_level (``s_level=None``: the exact
+    S = B^T A^{-1} B of eq. Pcq_exact), P_{Q,k} per H's variant, from the
+    residual r_0 = S~_l x0.  Every residual is projected Euclidean-
+    orthogonally to the null vector n of S~_l (onto the range of S~_l),
+    which keeps rounding from bringing the zero eigenvalue into the Ritz
+    values."""
+    n = pressure_null_vector(H.s)
+    if s_level is None:
+        S = H.S_exact
+    else:
+        def S(x):
+            return H.S_tilde(s_level, x)
 
     def project(r):
         return r - n * (n @ r)
 
-    r0 = S(np.random.default_rng(seed).standard_normal(pre.s.nQ))
-    al, be = lanczos(S, pre.apply_Q0, r0, steps, project)
-    return ritz_extremes(al, be)
+    return lanczos(S, lambda r: H.apply_Q(k, r), S(x0), steps, project)
+
+
+def velocity_block_extremes(pre, steps, seed=0):
+    """Ritz extremes of P_{V,0}^{-1} A (``pre``: a BasePreconditioner)."""
+    from .precond import HyperPower
+    r0 = np.random.default_rng(seed).standard_normal(pre.s.nV)
+    return ritz_extremes(*velocity_lanczos(HyperPower(pre.s, 2, 0, base=pre), 0, r0, steps))
+
+
+def schur_block_extremes(pre, steps, seed=0):
+    """Ritz extremes (non-zero part) of P_{Q,0}^{-1} S~_0,
+    S~_0 = B^T P_{V,0}^{-1} B."""
+    from .precond import HyperPower
+    x0 = np.random.default_rng(seed).standard_normal(pre.s.nQ)
+    return ritz_extremes(*schur_lanczos(HyperPower(pre.s, 2, 0, base=pre), 0, 0, x0, steps))
+
+
+def dense_sequence_spectrum(H, block, k, s_level=None):
+    """All eigenvalues (ascending) of P_{V,k}^{-1} A (block 'V') or of
+    P_{Q,k}^{-1} S~_l (block 'Q'; l = s_level, None for the exact Schur
+    complement; the zero of the constant pressure removed), from the
+    preconditioners' columns; tiny sizes only (the spectra of Sec. 5.2)."""
+    s = H.s
+    if block == "V":
+        X = np.column_stack([H.apply_V(k, e) for e in np.eye(s.nV)])
+        M = s.A.toarray()
+    else:
+        X = np.column_stack([H.apply_Q(k, e) for e in np.eye(s.nQ)])
+        M = np.column_stack([H.S_exact(e) if s_level is None else H.S_tilde(s_level, e)
+                             for e in np.eye(s.nQ)])
+    ev = np.sort(np.linalg.eigvals(X @ M).real)
+    if block == "Q":
+        ev = ev[1:]                       # the constant-pressure zero
+    return ev
 
 
 def hyperpower_interval(lmin, lmax, q, k):

@@ -160,6 +160,28 @@ def test_operator_recursion_matches_closed_forms(q, k):
         assert np.linalg.eigvalsh(0.5 * (Xq + Xq.T)).min() > -1e-12
 
 
+@pytest.mark.parametrize("q,k,l0", [(2, 1, 1), (2, 2, 2), (3, 1, 1)])
+def test_fixed_level_and_exact_schur_closed_forms(q, k, l0):
+    """Eq. Pcq2 with a fixed P_{V,l0} (option (2) of Sec. 4.1) and eq.
+    Pcq_exact are plain hyper-power sequences on S~_{l0} and on
+    S = B^T A^{-1} B: I - S P_k^{-1} = (I - S P_0^{-1})^{q^k}."""
+    S = KronSystem(2, 2, 0.9)
+    A, Dv = _dense_ops(S)
+    B = S.B.toarray()
+    nV, nQ = S.nV, S.nQ
+    P0 = BasePreconditioner(S)
+    X0q = np.column_stack([P0.apply_Q0(e) for e in np.eye(nQ)])
+    Xv = np.linalg.inv(Dv)
+    for _ in range(l0):                                      # dense eq. Pcv, order q
+        Xv = dense_hyperpower(A, Xv, q, 1)[-1]
+    for variant, Sd in (("Pcq2", B.T @ Xv @ B), ("Pcq_exact", B.T @ np.linalg.solve(A, B))):
+        H = HyperPower(S, q, k, variant=variant, base=P0, fixed_level=l0)
+        Xq = np.column_stack([H.apply_Q(k, e) for e in np.eye(nQ)])
+        rhs = np.linalg.matrix_power(np.eye(nQ) - Sd @ X0q, q ** k)
+        assert np.abs((np.eye(nQ) - Sd @ Xq) - rhs).max() < 1e-10, variant
+        assert np.abs(Xq - Xq.T).max() < 1e-10 * np.abs(Xq).max()
+
+
 def test_schur_spectrum_in_unit_interval():
     """sigma(P_{Q,0}^{-1} B^T A^{-1} B) in [0, 1] (a(v,v) >= 2 nu ||div v||^2)."""
     S = KronSystem(3, 2, 0.8)

@@ -17,7 +17,8 @@ import scipy.linalg as sla
 
 from oracle.assemble import KronSystem
 from oracle.precond import BasePreconditioner, dense_hyperpower
-from oracle.spectra import (hyperpower_interval, lanczos, pressure_null_vector, ritz_extremes,
+from oracle.spectra import (dense_sequence_spectrum, hyperpower_interval, lanczos,
+                            pressure_null_vector, ritz_extremes,
                             schur_block_extremes, velocity_block_extremes)
 
 
@@ -113,3 +114,60 @@ def test_pressure_null_vector_is_the_constant_pressure(E, p):
     assert np.abs(B @ n).max() < 1e-12 * np.abs(B).max()
     sv = np.linalg.svd(B, compute_uv=False)
     assert sv[-2] > 1e-3 * sv[0]
+
+
+def test_schur_sequences_at_the_worked_example():
+    """2^3 elements, degree 4 (the spectra of Sec. 5.2), the preconditioned
+    Schur complement P_{Q,k}^{-1} B^T A^{-1} B for the three sequences:
+    * eq. Pcq_exact is a hyper-power sequence on S itself, so its spectrum
+      is the image of the k = 0 spectrum under t -> 2t - t^2 (Corollary
+      cor:Skform), inside (0, 1] for k >= 1;
+    * with inner updates (eq. Pcq1) the spectra are close to those of
+      Pcq_exact (within 10 % in the condition number) and decrease with k;
+    * without inner updates (eq. Pcq2) the sequence converges to
+      S~_0^{-1}, so the condition number tends to that of (S, S~_0), and
+      only its first three updates lower it (as the paper observes)."""
+    from oracle.precond import HyperPower
+    S = KronSystem(2, 4, 1.0)
+    P0 = BasePreconditioner(S)
+    ev = {}
+    for var in ("Pcq_exact", "Pcq1", "Pcq2"):
+        H = HyperPower(S, 2, 0, variant=var, base=P0)
+        ev[var] = [dense_sequence_spectrum(H, "Q", k) for k in range(7 if var == "Pcq2" else 5)]
+    e0 = ev["Pcq_exact"][0]
+    assert e0[0] > 0 and e0[-1] <= 1 + 1e-12
+    for k in range(1, 5):
+        pred = np.sort(e0.copy())
+        for _ in range(k):
+            pred = 2 * pred - pred * pred
+        assert np.allclose(ev["Pcq_exact"][k], np.sort(pred), atol=1e-9)
+    kap = {v: [e[-1] / e[0] for e in ev[v]] for v in ev}
+    for k in range(1, 4):
+        assert kap["Pcq1"][k] < kap["Pcq1"][k - 1]
+        assert abs(kap["Pcq1"][k] / kap["Pcq_exact"][k] - 1) < 0.10
+    # limit of eq. Pcq2: the pencil (S, S~_0)
+    A = S.A.toarray()
+    B = S.B.toarray()
+    o = S.offsets
+    Dv = np.zeros_like(A)
+    for c in range(3):
+        Dv[o[c]:o[c + 1], o[c]:o[c + 1]] = A[o[c]:o[c + 1], o[c]:o[c + 1]]
+    St0 = B.T @ np.linalg.solve(Dv, B)
+    Sx = B.T @ np.linalg.solve(A, B)
+    lim = np.sort(np.linalg.eigvals(np.linalg.pinv(St0) @ Sx).real)[1:]
+    assert abs(kap["Pcq2"][6] / (lim[-1] / lim[0]) - 1) < 1e-3
+    # only the first three updates of eq. Pcq2 lower the condition number
+    assert kap["Pcq2"][3] < kap["Pcq2"][2] < kap["Pcq2"][1] < kap["Pcq2"][0]
+    assert kap["Pcq2"][4] > kap["Pcq2"][3]
+
+
+@pytest.mark.parametrize("var,k,s_level", [("Pcq1", 1, None), ("Pcq1", 2, 1), ("Pcq2", 2, None)])
+def test_schur_lanczos_with_updates_equals_dense(var, k, s_level):
+    from oracle.precond import HyperPower
+    from oracle.spectra import schur_lanczos
+    S = KronSystem(2, 2, 0.8)
+    H = HyperPower(S, 2, 0, variant=var, fixed_level=1)
+    ev = dense_sequence_spectrum(H, "Q", k, s_level)
+    x0 = np.random.default_rng(4).standard_normal(S.nQ)
+    lo, hi = ritz_extremes(*schur_lanczos(H, k, s_level, x0, S.nQ))
+    assert abs(lo - ev[0]) < 1e-8 * ev[-1] and abs(hi - ev[-1]) < 1e-8 * ev[-1]
