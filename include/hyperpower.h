@@ -98,6 +98,10 @@ typedef struct hp_opts {
                            kernels, bit 1 = 1D matrices staged in LDS (if they fit) */
     int op_slabs;       /* operator: i3-slabs run one after the other (pressure chain
                            then velocity per slab), 0 = tuned/model */
+    int schur_level;    /* eq. Pcq2 only: the fixed P_{V,l} inside B' P_{V,l}^{-1} B,
+                           l = schur_level in [0, 6] (default 0 = P_{V,0}, option (1)
+                           of Sec. 4.1; l > 0 is option (2), a fixed P_{V,k}, which for
+                           large l approaches eq. Pcq_exact) */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -173,6 +177,33 @@ hp_status hp_apply_P0(hp_ctx* ctx, const double* x, double* y, int nrhs);
  * opts.schur_variant and opts.l_schedule).  order >= 2, 0 <= iters <= 6. */
 hp_status hp_apply_hyperpower(hp_ctx* ctx, int order, int iters, const double* x,
                               double* y, int nrhs);
+
+/* Blocks whose preconditioned spectrum hp_spectrum estimates. */
+enum { HP_SPEC_VELOCITY = 0, HP_SPEC_SCHUR = 1 };
+
+/* Lanczos estimate of the extreme eigenvalues of a preconditioned block
+ * (Sec. 2, Lemma Sk_posdef and Corollary cor:Skform, which predict the
+ * spectrum after k updates from that of P_0; the spectra of Sec. 5.2):
+ *   HP_SPEC_VELOCITY: P_{V,k}^{-1} A,
+ *   HP_SPEC_SCHUR:    P_{Q,k}^{-1} S~_l, S~_l = B' P_{V,l}^{-1} B with
+ *                     l = s_level (large l approaches B' A^{-1} B),
+ * with k = iters updates of order q = order (eqs. Pcv, Pcq1/Pcq2 per
+ * opts.schur_variant, opts.l_schedule, opts.schur_level) in the context's
+ * precision.  The Lanczos process runs in the inner product of P_{.,k}
+ * from the residual r_0 = start (velocity) or r_0 = S~_l start (Schur;
+ * every residual is projected orthogonally to the constant-pressure null
+ * vector of B, so the smallest non-zero eigenvalue is estimated).
+ * start: device vector of n_V (velocity) or n_Q (Schur) doubles, read only.
+ * steps: 1 <= steps <= block dimension; the process stops early at an
+ * invariant subspace.  alpha, beta: host arrays of `steps` doubles
+ * receiving the tridiagonal matrix (beta[j] couples steps j and j+1), or
+ * NULL.  *done: steps taken; *lmin, *lmax: extreme eigenvalues of the
+ * tridiagonal matrix (Sturm bisection), inner estimates of the block's.
+ * Synchronous; allocates and frees 5-6 block vectors of device memory.
+ * Returns HP_ENOTSPD if r' P^{-1} r < 0 (the preconditioner is indefinite). */
+hp_status hp_spectrum(hp_ctx* ctx, int block, int order, int iters, int s_level, int steps,
+                      const double* start, double* alpha, double* beta, int* done,
+                      double* lmin, double* lmax);
 
 /* Solve K x = b to relative tolerance tol with x_0 = 0 (Sec. 5: MINRES to
  * 1e-8), preconditioned by P_k (opts.order, opts.iters).  MINRES monitors

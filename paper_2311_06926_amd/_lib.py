@@ -19,6 +19,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KRYLOV = {"minres": 0, "fgmres": 1}
 SCHUR = {"Pcq1": 1, "Pcq2": 2}
 SCHEDULE = {"literal": 0, "prev": 1}
+SPEC_VELOCITY, SPEC_SCHUR = 0, 1
 
 
 class HPError(RuntimeError):
@@ -46,6 +47,7 @@ class hp_opts(ctypes.Structure):
         ("op_order", ctypes.c_int),
         ("fd_plan", ctypes.c_int),
         ("op_slabs", ctypes.c_int),
+        ("schur_level", ctypes.c_int),
     ]
 
 
@@ -94,6 +96,8 @@ SIGNATURES = {
     "hp_apply_MV": (I, [P, P, P, I]),
     "hp_grad": (I, [P, P, P, P, P, P, I]),
     "hp_get_tuning": (I, [P, I, ctypes.POINTER(hp_tuning)]),
+    "hp_spectrum": (I, [P, I, I, I, I, I, P, P, P, ctypes.POINTER(I), ctypes.POINTER(D),
+                        ctypes.POINTER(D)]),
     "hp_destroy": (None, [P]),
     "hp_status_string": (ctypes.c_char_p, [I]),
 }

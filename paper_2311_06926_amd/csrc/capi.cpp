@@ -218,7 +218,9 @@ hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields&
     return apply_PQ1(c, q, level - 1, *s, y, nrhs, prec);
 }
 
-// y = P_{Q,level}^{-1} x for eq. Pcq2 (fixed S~_0): q^level Richardson steps.
+// y = P_{Q,level}^{-1} x for eq. Pcq2 with the fixed S~_l, l = opts.schur_level
+// (option (1) of Sec. 4.1 for l = 0, option (2) for l > 0): q^level
+// Richardson steps.
 hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
                      int prec) {
     hipError_t e = launch_P0(c, x, y, false, true, false, prec, nrhs);
@@ -227,7 +229,7 @@ hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields&
     for (int i = 0; i < level; ++i) steps *= q;
     Fields t = hq_slot(c, 0, 0);
     for (long long j = 1; j < steps; ++j) {
-        e = apply_Stilde(c, q, 0, y, t, nrhs, prec);                 // t = S~_0 y
+        e = apply_Stilde(c, q, c->opts.schur_level, y, t, nrhs, prec);  // t = S~_l y
         if (e != hipSuccess) return e;
         e = fields_axpby(c, x, t, 1.0, -1.0, false, true, nrhs);    // t = x - t
         if (e != hipSuccess) return e;
@@ -832,6 +834,144 @@ hp_status autotune(hp_ctx* c) {
     return st;
 }
 
+// ---- spectra of the preconditioned blocks (Sec. 2, Sec. 5.2) ------------------------
+// Number of eigenvalues below x of the symmetric tridiagonal matrix
+// tridiag(b; a; b) (Sturm sequence of the LDL' pivots).
+int sturm_below(const std::vector<double>& a, const std::vector<double>& b, double x) {
+    int cnt = 0;
+    double d = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        d = (a[i] - x) - (i ? b[i - 1] * b[i - 1] / d : 0.0);
+        if (d == 0.0) d = -1e-300;
+        if (d < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Smallest (which = 1) or largest (which = m) eigenvalue by bisection inside
+// the Gershgorin interval.
+double tridiag_eig(const std::vector<double>& a, const std::vector<double>& b, int which) {
+    const int m = (int)a.size();
+    double lo = a[0], hi = a[0];
+    for (int i = 0; i < m; ++i) {
+        double r = (i ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(a, b, mid) >= which) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// The constant pressure n = n1 (x) n1 (x) n1 (null vector of B; n1 = M^^{-1} 1
+// since B = D' M_q and D' annihilates constants), unit Euclidean norm.
+std::vector<double> pressure_null(const hp_ctx* c) {
+    const int nM = c->nM;
+    std::vector<double> n1(nM, 0.0);
+    for (int i = 0; i < nM; ++i)
+        for (int j = 0; j < nM; ++j) n1[i] += c->tab.Mcinv[(size_t)i * nM + j];
+    double s = 0.0;
+    for (double v : n1) s += v * v;
+    const double inv = 1.0 / std::pow(s, 1.5);
+    std::vector<double> n((size_t)nM * nM * nM);
+    size_t t = 0;
+    for (int i3 = 0; i3 < nM; ++i3)
+        for (int i2 = 0; i2 < nM; ++i2)
+            for (int i1 = 0; i1 < nM; ++i1) n[t++] = n1[i1] * n1[i2] * n1[i3] * inv;
+    return n;
+}
+
+struct DevBuf {
+    double* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+// Lanczos in the inner product of the preconditioner (see hp_spectrum).
+hp_status spectrum(hp_ctx* c, int block, int q, int k, int sl, int steps, const double* start,
+                   std::vector<double>& al, std::vector<double>& be) {
+    const bool vel = block == HP_SPEC_VELOCITY;
+    const long long n = vel ? c->nV : c->nQ;
+    const int prec = c->opts.precision;
+    DevBuf mem;
+    if (alloc_device(&mem.p, (size_t)6 * n) != HP_OK) return HP_ENOMEM;
+    double* v = mem.p;
+    double* pv = v + n;       // P v_j = r_j / beta_j
+    double* pvp = v + 2 * n;  // P v_{j-1}
+    double* r = v + 3 * n;
+    double* z = v + 4 * n;
+    double* nul = v + 5 * n;
+    auto F = [&](double* b) { return vel ? vel_fields(c, b, n) : pres_fields(c, b, n); };
+    auto applyM = [&](double* x, double* y) {  // y = A x or S~_l x
+        return vel ? launch_operator(c, OP_A, F(x), F(y), 1.0, 0.0, nullptr, 1)
+                   : apply_Stilde(c, q, sl, F(x), F(y), 1, prec);
+    };
+    auto applyPinv = [&](double* x, double* y) {
+        if (vel) return apply_PV(c, q, k, F(x), F(y), 1, prec);
+        if (c->opts.schur_variant == HP_SCHUR_PCQ2) return apply_PQ2(c, q, k, F(x), F(y), 1, prec);
+        return apply_PQ1(c, q, k, F(x), F(y), 1, prec);
+    };
+    auto dot = [&](const double* x, const double* y, double& out) {
+        return vec_dots(c, n, n, x, y, 1, &out) == hipSuccess ? HP_OK : HP_EHIP;
+    };
+    auto project = [&](double* x) -> hp_status {  // x -= nul (nul' x) (Schur block)
+        if (vel) return HP_OK;
+        double d = 0.0;
+        if (dot(nul, x, d) != HP_OK) return HP_EHIP;
+        HIPCHK(vec_axpbypcz(c->stream, n, 1, -d, nul, n, 1.0, x, n, 0.0, nullptr, 0, x, n));
+        return HP_OK;
+    };
+    if (vel) {
+        HIPCHK(hipMemcpyAsync(r, start, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+        std::vector<double> h = pressure_null(c);
+        HIPCHK(hipMemcpyAsync(nul, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        HIPCHK(hipMemcpyAsync(z, start, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(applyM(z, r));
+        hp_status st = project(r);
+        if (st != HP_OK) return st;
+    }
+    HIPCHK(vec_zero(c->stream, n, pvp));
+    HIPCHK(applyPinv(r, z));
+    double b2 = 0.0;
+    if (dot(r, z, b2) != HP_OK) return HP_EHIP;
+    if (!std::isfinite(b2)) return HP_ENAN;
+    if (b2 < 0.0) return HP_ENOTSPD;
+    if (b2 == 0.0) return HP_EINVAL;  // start vector in the null space
+    double b = std::sqrt(b2), amax = 0.0;
+    for (int j = 0; j < steps; ++j) {
+        HIPCHK(vec_axpbypcz(c->stream, n, 1, 1.0 / b, z, n, 0.0, nullptr, 0, 0.0, nullptr, 0, v, n));
+        HIPCHK(vec_axpbypcz(c->stream, n, 1, 1.0 / b, r, n, 0.0, nullptr, 0, 0.0, nullptr, 0, pv, n));
+        HIPCHK(applyM(v, r));  // r = M v_j
+        double a = 0.0;
+        if (dot(v, r, a) != HP_OK) return HP_EHIP;
+        // r = M v_j - alpha_j P v_j - beta_j P v_{j-1}
+        HIPCHK(vec_axpbypcz(c->stream, n, 1, 1.0, r, n, -a, pv, n, -b, pvp, n, r, n));
+        hp_status st = project(r);
+        if (st != HP_OK) return st;
+        HIPCHK(applyPinv(r, z));
+        double bn2 = 0.0;
+        if (dot(r, z, bn2) != HP_OK) return HP_EHIP;
+        if (!std::isfinite(a) || !std::isfinite(bn2)) return HP_ENAN;
+        al.push_back(a);
+        amax = std::max(amax, std::fabs(a));
+        if (bn2 < -1e-12 * amax * amax) return HP_ENOTSPD;
+        const double bn = std::sqrt(std::max(bn2, 0.0));
+        be.push_back(bn);
+        if (bn <= 1e-10 * amax) break;  // invariant subspace
+        std::swap(pv, pvp);
+        b = bn;
+    }
+    return HP_OK;
+}
+
+
 }  // namespace
 
 // =====================================================================================
@@ -856,6 +996,7 @@ void hp_default_opts(hp_opts* o) {
     o->op_order = -1;
     o->fd_plan = -1;
     o->op_slabs = 0;
+    o->schur_level = 0;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -883,7 +1024,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen > 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
-        o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0)
+        o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0 || o.schur_level < 0 ||
+        o.schur_level > KMAX)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1125,6 +1267,31 @@ hp_status hp_apply_hyperpower(hp_ctx* c, int order, int iters, const double* x, 
         iters > KMAX || !c->fd_ok)
         return HP_EINVAL;
     HIPCHK(apply_Pk(c, order, iters, x, y, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_spectrum(hp_ctx* c, int block, int order, int iters, int s_level, int steps,
+                      const double* start, double* alpha, double* beta, int* done,
+                      double* lmin, double* lmax) {
+    if (!c || !start || !done || !lmin || !lmax || !c->fd_ok || order < 2 || iters < 0 ||
+        iters > KMAX || s_level < 0 || s_level > KMAX ||
+        (block != HP_SPEC_VELOCITY && block != HP_SPEC_SCHUR) || steps < 1 ||
+        steps > (block == HP_SPEC_VELOCITY ? c->nV : c->nQ))
+        return HP_EINVAL;
+    std::vector<double> al, be;
+    al.reserve(steps);
+    be.reserve(steps);
+    hp_status st = spectrum(c, block, order, iters, s_level, steps, start, al, be);
+    if (st != HP_OK) return st;
+    const int m = (int)al.size();
+    *done = m;
+    for (int j = 0; j < m; ++j) {
+        if (alpha) alpha[j] = al[j];
+        if (beta) beta[j] = be[j];
+    }
+    std::vector<double> off(be.begin(), be.begin() + (m - 1));
+    *lmin = tridiag_eig(al, off, 1);
+    *lmax = tridiag_eig(al, off, m);
     return HP_OK;
 }
 

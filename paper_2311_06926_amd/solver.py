@@ -27,13 +27,15 @@ class Solver:
 
     Options (see include/hyperpower.h): c_pen, schur ('Pcq1'|'Pcq2'),
     schedule ('literal'|'prev'), precision ('fp64'|'fp32'|'bf16x3'),
-    krylov ('minres'|'fgmres'), restart, maxit, order, iters, max_rhs.
+    krylov ('minres'|'fgmres'), restart, maxit, order, iters, max_rhs,
+    schur_level (eq. Pcq2: the fixed P_{V,l} in B' P_{V,l}^{-1} B).
     """
 
     def __init__(self, E, p, nu=1.0, *, c_pen=12.5, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
-                 op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, device=None):
+                 op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -57,6 +59,7 @@ class Solver:
         o.op_order = op_order
         o.fd_plan = fd_plan
         o.op_slabs = op_slabs
+        o.schur_level = schur_level
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -143,6 +146,33 @@ class Solver:
         check(self.lib.hp_apply_hyperpower(self.ctx, order, iters, _ptr(x), _ptr(y), nr),
               "hp_apply_hyperpower")
         return y
+
+    def spectrum(self, block="velocity", order=2, iters=0, s_level=0, steps=60, start=None,
+                 seed=0):
+        """Lanczos estimate of the extreme eigenvalues of P_{V,k}^{-1} A
+        (block 'velocity') or of P_{Q,k}^{-1} B' P_{V,l}^{-1} B (block
+        'schur', l = s_level, constant pressure excluded), k = iters updates
+        of order q = order (see hp_spectrum).  start: device vector of the
+        block's size (default: seeded standard normal).  Returns a dict with
+        lmin, lmax, steps, alpha, beta."""
+        from . import synth
+        blk = {"velocity": _lib.SPEC_VELOCITY, "schur": _lib.SPEC_SCHUR}[block]
+        n = self.nV if blk == _lib.SPEC_VELOCITY else self.nQ
+        steps = min(steps, n)
+        if start is None:
+            start = torch.from_numpy(synth.random_vector(n, seed=seed)).to(self.device)
+        if start.numel() != n or start.dtype != torch.float64 or not start.is_contiguous():
+            raise ValueError(f"start must be a contiguous float64 vector of {n} entries")
+        al = (ctypes.c_double * steps)()
+        be = (ctypes.c_double * steps)()
+        done = ctypes.c_int()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        check(self.lib.hp_spectrum(self.ctx, blk, order, iters, s_level, steps, _ptr(start),
+                                   al, be, ctypes.byref(done), ctypes.byref(lo),
+                                   ctypes.byref(hi)), "hp_spectrum")
+        m = done.value
+        return {"lmin": lo.value, "lmax": hi.value, "steps": m,
+                "alpha": np.array(al[:m]), "beta": np.array(be[:m])}
 
     def solve(self, b, tol=1e-8, x=None, raise_on_noconv=True):
         nr = self._nrhs(b, self.N)

@@ -40,7 +40,7 @@ def test_binding_signatures_cover_the_header():
     lib.hp_default_opts(ctypes.byref(opts))
     assert opts.c_pen == 12.5 and opts.order == 2 and opts.max_rhs == 1
     assert opts.autotune == 1 and opts.op_kchunk == 0 and opts.op_order == -1 and opts.fd_plan == -1
-    assert opts.op_slabs == 0
+    assert opts.op_slabs == 0 and opts.schur_level == 0
     assert lib.hp_status_string(-6) == b"not converged within maxit"
 
 
@@ -56,9 +56,12 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.hp_setup(8, 2, 1.0, None, None, None) == -1
     assert lib.hp_apply_K(None, None, None, 1) == -1
     assert lib.hp_get_tuning(None, 1, ctypes.byref(_lib.hp_tuning())) == -1
+    d, lo, hi = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    assert lib.hp_spectrum(None, 0, 2, 0, 0, 10, None, None, None, ctypes.byref(d),
+                           ctypes.byref(lo), ctypes.byref(hi)) == -1
     # out-of-range launch-shape options are rejected before any HIP call
     for field, bad in (("op_kchunk", -1), ("op_order", 2), ("fd_plan", 4), ("fd_plan", -2),
-                       ("op_slabs", -1)):
+                       ("op_slabs", -1), ("schur_level", -1), ("schur_level", 7)):
         opts = _lib.hp_opts()
         lib.hp_default_opts(ctypes.byref(opts))
         setattr(opts, field, bad)
