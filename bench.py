@@ -11,6 +11,9 @@ capture) is excluded.  value = solved degrees of freedom per second
 The JSON line also carries
   operators   DOF/s of apply_K, apply_P0 and apply_hyperpower(q, k)
   sweep       iterations and time-to-solution for q in {2,3} x k in {0..3}
+  spectra     Lanczos spectra of P_0 (GPU), the predicted condition numbers and
+              MINRES bound per k (Corollary cor:Skform), and the (q, k) they
+              choose a priori against the sweep's fastest
   mixed       64^3, degree 3 FGMRES: FP64 vs FP32 vs split-BF16 preconditioner
   batched     48^3, degree 2: 32 right-hand sides in one FGMRES vs one at a time
   hbm         apply_K on an HBM-sized mesh (working set > Infinity Cache)
@@ -333,6 +336,42 @@ def main():
             log(f"[bench] sweep q={qq} k={kk}: {sweep[f'q{qq}_k{kk}']}")
             s2.close()
 
+    # ---- a-priori depth from the P_0 spectra (Lanczos on the GPU): predicted
+    # condition numbers and MINRES bound per k, times the measured cost of
+    # one iteration (apply_K + apply_hyperpower), against the sweep
+    spectra = {}
+    if not args.no_sweep:
+        from paper_2311_06926_amd import spectra as spm
+        cost = {}
+        for qq in (2, 3):
+            s2 = Solver(E, p, 1.0, order=qq, iters=1, schur=args.schur)
+            torch.cuda.synchronize()
+            t0s = time.perf_counter()
+            pred = spm.predict(s2, qq, 3)
+            t_lanczos = time.perf_counter() - t0s
+            per_it = {}
+            for kk in range(0 if qq == 2 else 1, 4):
+                t_pk = timed_loop(lambda: s2.apply_hyperpower(qq, kk, xr, yk), 5, s2.stream)
+                per_it[kk] = t_K + t_pk
+                cost[f"q{qq}_k{kk}"] = pred["k"][kk]["minres_bound"] * per_it[kk]
+            spectra[f"q{qq}"] = {
+                "lanczos_s": t_lanczos, "velocity_0": pred["velocity_0"],
+                "schur_0": pred["schur_0"], "schur_level": pred["schur_level"],
+                "predicted": [{key: r[key] for key in ("k", "kappa_v", "kappa_s", "minres_bound")}
+                              for r in pred["k"]],
+                "us_per_iteration": {kk: 1e6 * v for kk, v in per_it.items()},
+                "chosen_k": spm.choose_iters(pred, per_it),
+            }
+            log(f"[bench] spectra q={qq}: {spectra[f'q{qq}']}")
+            s2.close()
+        choice = min(cost, key=cost.get)
+        spectra["chosen"] = choice
+        if sweep:
+            best = min(sweep, key=lambda key: sweep[key]["ms"])
+            spectra["measured_best"] = best
+            spectra["chosen_ms_over_best_ms"] = sweep[choice]["ms"] / sweep[best]["ms"]
+        log(f"[bench] a-priori choice {choice}; measured best {spectra.get('measured_best')}")
+
     mixed, batched, hbm, diff, large = {}, {}, {}, {}, {}
     if not args.no_extra:
         # ---- mixed precision, 64^3 degree 3, FGMRES(50), q = 2, k = 1
@@ -456,6 +495,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "spectra": spectra,
         "mixed": mixed,
         "batched": batched,
         "hbm": hbm,
