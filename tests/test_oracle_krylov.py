@@ -123,3 +123,32 @@ def test_iteration_counts_table1_8cube(k):
     assert r.converged
     assert abs(r.iters - table[2][k]) <= 3
     assert r.true_relres < 1e-7
+
+
+def test_default_penalty_reading():
+    """C_pen = max(12.5, 2.5 (p+1)) (the paper is silent): 12.5 up to degree
+    4; at degree 8 it keeps T^ positive definite from 6 elements on, where
+    12.5 does not, and keeps sigma(P_{V,0}^{-1} A) at 8^3 inside (0, 2)."""
+    import scipy.linalg as sla
+    from oracle.assemble import default_c_pen
+    from oracle.matrices1d import Matrices1D
+    assert [default_c_pen(p) for p in (2, 3, 4, 6, 8)] == [12.5, 12.5, 12.5, 17.5, 22.5]
+    m = Matrices1D(6, 8, default_c_pen(8))
+    assert sla.eigh(m.Tc, m.Mc, eigvals_only=True)[0] > 0
+    m = Matrices1D(5, 8, 12.5)
+    assert sla.eigh(m.Tc, m.Mc, eigvals_only=True)[0] < 0
+
+
+@pytest.mark.parametrize("p,k", [(6, 1), (8, 1)])
+def test_iteration_counts_table1_high_degree(p, k):
+    """MINRES counts at 8^3 for degrees 6 and 8 reproduce Table 1 within +-2
+    under the default penalty."""
+    table = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_liddriven_all.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            v = line.split()
+            table[(int(v[0]), int(v[1]))] = [int(t) for t in v[2:7]]
+    S, b = cavity(8, p)
+    r = minres(lambda x: S.K @ x, HyperPower(S, 2, k).apply, b, tol=1e-8, maxit=300)
+    assert r.converged and abs(r.iters - table[(8, p)][k]) <= 2
