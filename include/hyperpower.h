@@ -77,7 +77,8 @@ enum { HP_SCHUR_PCQ1 = 1, HP_SCHUR_PCQ2 = 2 };
 enum { HP_L_LITERAL = 0, HP_L_PREV = 1 };
 
 typedef struct hp_opts {
-    double c_pen;       /* Nitsche penalty constant, alpha = c_pen / h (default 12.5) */
+    double c_pen;       /* Nitsche penalty constant, alpha = c_pen / h; 0 (default) =
+                           max(12.5, 2.5 (degree + 1)) */
     int schur_variant;  /* HP_SCHUR_PCQ1 (default) or HP_SCHUR_PCQ2 */
     int l_schedule;     /* HP_L_LITERAL (default) or HP_L_PREV */
     int precision;      /* HP_PREC_* for P_k (default FP64) */
@@ -138,7 +139,10 @@ hp_status hp_get_tuning(const hp_ctx* ctx, int nrhs, hp_tuning* out);
 
 /* Build the univariate tables (App. B.3, Sec. 3.3), the generalised
  * eigen-decompositions for fast diagonalisation (App. A.3-A.4) and the
- * workspace.  elements >= 1, 2 <= degree <= 4, nu > 0.  opts may be NULL
+ * workspace.  elements >= 1, 2 <= degree <= 8, nu > 0.  Returns HP_ENOTSPD
+ * when the Nitsche penalty opts.c_pen is too small for the degree and mesh
+ * (the augmented T^ of Sec. 3.3 is then indefinite, e.g. degree 8 with
+ * fewer than 6 elements at the default 12.5).  opts may be NULL
  * (defaults).  stream: a hipStream_t or NULL.  *out receives the context.
  * Fast diagonalisation holds a whole direction in MFMA tiles, so P_0,
  * P_k and the solve need E + degree - 1 <= 128; above that the context

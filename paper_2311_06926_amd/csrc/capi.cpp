@@ -979,7 +979,7 @@ extern "C" {
 
 void hp_default_opts(hp_opts* o) {
     if (!o) return;
-    o->c_pen = 12.5;
+    o->c_pen = 0.0;
     o->schur_variant = HP_SCHUR_PCQ1;
     o->l_schedule = HP_L_LITERAL;
     o->precision = HP_PREC_FP64;
@@ -1017,11 +1017,11 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
                    hp_ctx** out) {
     if (!out) return HP_EINVAL;
     *out = nullptr;
-    if (elements < 1 || degree < 2 || degree > 4 || !(nu > 0.0)) return HP_EINVAL;
+    if (elements < 1 || degree < 2 || degree > 8 || !(nu > 0.0)) return HP_EINVAL;
     hp_opts o;
     hp_default_opts(&o);
     if (opts) o = *opts;
-    if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen > 0.0) ||
+    if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen >= 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
         o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0 || o.schur_level < 0 ||
@@ -1033,6 +1033,9 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     CtxExtra* ce = new (std::nothrow) CtxExtra();
     if (!ce) return HP_ENOMEM;
     hp_ctx* c = &ce->ctx;
+    // the default penalty grows with the degree like the inverse-inequality
+    // constant it must dominate (12.5 up to degree 4)
+    if (o.c_pen == 0.0) o.c_pen = std::max(12.5, 2.5 * (degree + 1));
     c->opts = o;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) { delete ce; return HP_EHIP; }
@@ -1044,6 +1047,14 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     } catch (...) {
         delete ce;
         return HP_EINVAL;
+    }
+    // A is SPD only if the Nitsche-augmented T^ is (Sec. 3.1: the penalty
+    // alpha = c_pen / h must dominate the inverse inequality, whose constant
+    // grows with the degree); refuse a penalty too small for this mesh
+    if (*std::min_element(c->tab.lamT.begin(), c->tab.lamT.end()) <= 0.0 ||
+        *std::min_element(c->tab.lamK.begin(), c->tab.lamK.end()) <= 0.0) {
+        delete ce;
+        return HP_ENOTSPD;
     }
     const int nN = c->tab.nN;
     c->nN = nN;

@@ -132,8 +132,15 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t off, d
 // Staged per plane kk: g = D u and z = nu g + p (z = p for B) on the tile and
 // a halo of W = p-1.  u3 at plane kk-1 is the previous plane's u3 value of the
 // same staging slot, so each plane reads u3 once.
+// waves per SIMD the register budget allows: the band rows and the windows
+// grow with the degree
 template <int P>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 3))) void k_pres(OpArgs a, double* yp, long long syp) {
+constexpr int waves_for() {
+    return P < 4 ? 4 : (P == 4 ? 3 : 2);
+}
+
+template <int P>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>()))) void k_pres(OpArgs a, double* yp, long long syp) {
     constexpr int W = P - 1;
     constexpr int SW = T1 + 2 * W, SR = T2 + 2 * W;
     constexpr int NS = (SR * SW + NT - 1) / NT;  // staging slots per thread
@@ -464,7 +471,7 @@ constexpr int vel_lds_doubles() {
 }
 
 template <int P>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 3))) void k_vel(OpArgs a, Fields out, Fields src, double alpha,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>()))) void k_vel(OpArgs a, Fields out, Fields src, double alpha,
                                             double beta) {
     __shared__ double lds[vel_lds_doubles<P>()];
     int id = xcd_block(blockIdx.x, a.nblocks);
@@ -493,6 +500,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(P < 4 ? 4 : 
     else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
 }
 
+template <int P>
+void launch_pres(dim3 grid, hipStream_t st, const OpArgs& a, double* yp, long long syp) {
+    hipLaunchKernelGGL(k_pres<P>, grid, dim3(NT), 0, st, a, yp, syp);
+}
+
+template <int P>
+void launch_vel(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
+                double alpha, double beta) {
+    hipLaunchKernelGGL(k_vel<P>, grid, dim3(NT), 0, st, a, out, s, alpha, beta);
+}
+
+// instantiations per degree 2..8 (index = degree)
+using PresLaunch = void (*)(dim3, hipStream_t, const OpArgs&, double*, long long);
+using VelLaunch = void (*)(dim3, hipStream_t, const OpArgs&, const Fields&, const Fields&, double,
+                           double);
+constexpr int PMAX = 8;
+const PresLaunch pres_launch[PMAX + 1] = {nullptr,        nullptr,        launch_pres<2>,
+                                          launch_pres<3>, launch_pres<4>, launch_pres<5>,
+                                          launch_pres<6>, launch_pres<7>, launch_pres<8>};
+const VelLaunch vel_launch[PMAX + 1] = {nullptr,       nullptr,       launch_vel<2>,
+                                        launch_vel<3>, launch_vel<4>, launch_vel<5>,
+                                        launch_vel<6>, launch_vel<7>, launch_vel<8>};
+
 }  // namespace
 
 hipError_t ops_init_attributes() { return hipSuccess; }
@@ -502,7 +532,7 @@ long long ops_ws_stride(const hp_ctx* c) { return c->nQ; }
 OpShape op_model_shape(const hp_ctx* c, int nrhs) {
     // planes per workgroup: a workgroup takes kchunk + 2p steps, and the
     // velocity launch runs in ceil(blocks / resident) rounds (two 512-thread
-    // workgroups per CU, one for degree 4); minimise rounds x steps
+    // workgroups per CU, one from degree 4 on); minimise rounds x steps
     const int nM = c->nM, P = c->p;
     const long long per_chunk =
         (long long)((nM + T1 - 1) / T1) * ((nM + T2 - 1) / T2) * 3 * nrhs;
@@ -533,7 +563,7 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
 
 hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Fields& out,
                            double alpha, double beta, const Fields* src, int nrhs) {
-    if (c->p < 2 || c->p > 4 || nrhs < 1) return hipErrorInvalidValue;
+    if (c->p < 2 || c->p > PMAX || nrhs < 1) return hipErrorInvalidValue;
     OpArgs a{};
     a.bt = c->band;
     for (int i = 0; i < 3; ++i) a.u[i] = in.f[i];
@@ -565,9 +595,7 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
         dim3 grid(a.nblocks);
-        if (P == 2) hipLaunchKernelGGL(k_pres<2>, grid, dim3(NT), 0, c->stream, a, yp, syp);
-        else if (P == 3) hipLaunchKernelGGL(k_pres<3>, grid, dim3(NT), 0, c->stream, a, yp, syp);
-        else hipLaunchKernelGGL(k_pres<4>, grid, dim3(NT), 0, c->stream, a, yp, syp);
+        pres_launch[P](grid, c->stream, a, yp, syp);
     };
     auto vel = [&](int lo, int hi) {
         a.kbase = lo;
@@ -575,9 +603,7 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * 3 * nrhs;
         dim3 grid(a.nblocks);
-        if (P == 2) hipLaunchKernelGGL(k_vel<2>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
-        else if (P == 3) hipLaunchKernelGGL(k_vel<3>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
-        else hipLaunchKernelGGL(k_vel<4>, grid, dim3(NT), 0, c->stream, a, out, s, alpha, beta);
+        vel_launch[P](grid, c->stream, a, out, s, alpha, beta);
     };
     if (mode == OP_BT) {
         pres(0, nM);

@@ -31,7 +31,7 @@ class Solver:
     schur_level (eq. Pcq2: the fixed P_{V,l} in B' P_{V,l}^{-1} B).
     """
 
-    def __init__(self, E, p, nu=1.0, *, c_pen=12.5, schur="Pcq1", schedule="literal",
+    def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,

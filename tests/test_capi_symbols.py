@@ -38,7 +38,7 @@ def test_binding_signatures_cover_the_header():
     lib = _lib.load()
     opts = _lib.hp_opts()
     lib.hp_default_opts(ctypes.byref(opts))
-    assert opts.c_pen == 12.5 and opts.order == 2 and opts.max_rhs == 1
+    assert opts.c_pen == 0.0 and opts.order == 2 and opts.max_rhs == 1
     assert opts.autotune == 1 and opts.op_kchunk == 0 and opts.op_order == -1 and opts.fd_plan == -1
     assert opts.op_slabs == 0 and opts.schur_level == 0
     assert lib.hp_status_string(-6) == b"not converged within maxit"

@@ -10,7 +10,7 @@ Tolerances (FP64 everywhere on the GPU path):
 * MINRES/FGMRES: iteration counts within +-1 of the oracle's, solutions
   agree to 1e-6 (tolerance 1e-8 on the residual).
 Sizes span several 8-row strips, 16-wide MFMA tiles and 64-row blocks, with
-ragged tails (n = 9, 10, 11, 13, 14, 17, 18).
+ragged tails (n = 9, 10, 11, 13, 14, 17, 18), and degrees 2 to 8.
 """
 import sys
 
@@ -23,7 +23,8 @@ from paper_2311_06926_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(3, 2), (8, 2), (5, 3), (8, 3), (12, 2), (15, 3), (4, 4)]
+CASES = [(3, 2), (8, 2), (5, 3), (8, 3), (12, 2), (15, 3), (4, 4), (5, 5), (4, 6), (3, 7),
+         (6, 8)]
 
 
 def say(*a):
@@ -79,6 +80,11 @@ def test_operators(dev, E, p):
 
 @pytest.mark.parametrize("E,p", CASES)
 def test_base_preconditioner(dev, E, p):
+    """P_0 against sparse LU.  Both are backward stable, so each velocity
+    block is checked by its normwise backward error
+    |A_cc y - x| / (|A_cc| |y| + |x|) (max norms) <= 1e-14, and the forward
+    gap by max(1e-11, 1e-14 kappa), kappa >= |A_cc| |y| / |x| (the blocks'
+    condition grows fast with the degree: ~1e11 at degree 8)."""
     from oracle.precond import BasePreconditioner
     from paper_2311_06926_amd.solver import Solver
     nu = 0.8
@@ -88,12 +94,17 @@ def test_base_preconditioner(dev, E, p):
     sol = Solver(E, p, nu)
     x = synth.random_vector(S.N, seed=100 + E * 10 + p)
     y = sol.apply_P0(to_gpu(x, dev)).cpu().numpy()
-    assert rel_err(y, P0.apply(x)) < 1e-11
-    # backward error of the velocity blocks: A_cc y_c = x_c
+    ref = P0.apply(x)
     o = S.offsets
+    kappa = 1.0
     for c, blk in enumerate([S.A11, S.A22, S.A33]):
-        r = blk @ y[o[c]:o[c + 1]] - x[o[c]:o[c + 1]]
-        assert np.abs(r).max() <= 1e-12 * np.abs(x).max() * 10
+        yc, xc = y[o[c]:o[c + 1]], x[o[c]:o[c + 1]]
+        norm_a = abs(blk).sum(axis=1).max()
+        r = blk @ yc - xc
+        eta = np.abs(r).max() / (norm_a * np.abs(yc).max() + np.abs(xc).max())
+        assert eta <= 1e-14, (c, eta)
+        kappa = max(kappa, norm_a * np.abs(yc).max() / np.abs(xc).max())
+    assert rel_err(y, ref) < max(1e-11, 1e-14 * kappa)
     sol.close()
 
 
@@ -113,6 +124,29 @@ def test_hyperpower(dev, E, p, q, k, variant):
     y = sol.apply_hyperpower(q, k, to_gpu(x, dev)).cpu().numpy()
     assert rel_err(y, H.apply(x)) < 1e-11
     sol.close()
+
+
+@pytest.mark.parametrize("E,p", [(5, 5), (4, 6)])
+def test_hyperpower_high_degree(dev, E, p):
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] hyperpower E={E} p={p} q=2 k=2 Pcq1")
+    S = oracle_sys(E, p)
+    sol = Solver(E, p, 1.0)
+    x = synth.random_vector(S.N, seed=300 + p)
+    y = sol.apply_hyperpower(2, 2, to_gpu(x, dev)).cpu().numpy()
+    assert rel_err(y, HyperPower(S, 2, 2).apply(x)) < 1e-10
+    sol.close()
+
+
+def test_penalty_too_small_is_rejected(dev):
+    """Degree 8 on 5 elements with C_pen = 12.5: T^ is indefinite."""
+    from paper_2311_06926_amd._lib import HPError
+    from paper_2311_06926_amd.solver import Solver
+    with pytest.raises(HPError) as e:
+        Solver(5, 8, 1.0, c_pen=12.5)
+    assert e.value.code == -4
+    Solver(6, 8, 1.0).close()
 
 
 def test_hyperpower_prev_schedule(dev):

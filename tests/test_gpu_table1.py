@@ -1,0 +1,75 @@
+"""Table 1 of Sec. 5.3 on the GPU: MINRES iteration counts of the
+lid-driven cavity with P^_k (order 2, eq. Pcq1), k = 0..4.
+
+* 8^3, degrees 6 and 8: the GPU counts equal the oracle's MINRES within +-1
+  (the oracle is slow at these degrees, so k = 0, 1 for degree 6 and k = 1
+  for degree 8).
+* 8^3 and 16^3, degrees 2, 4, 6, 8: the GPU counts against the printed ones
+  within +-3.  The penalty constant (never printed) and the paper's
+  quadrature-based forward operator are readings, so the printed counts are
+  a soft target; the counts measured here are listed in the test output.
+"""
+import os
+import sys
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda", 0)
+
+
+def table1():
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_liddriven_all.txt")
+    rows = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            v = line.split()
+            rows[(int(v[0]), int(v[1]))] = [int(t) for t in v[2:7]]
+    return rows
+
+
+def gpu_counts(E, p, ks):
+    from paper_2311_06926_amd.solver import Solver
+    out = []
+    for k in ks:
+        sol = Solver(E, p, 1.0, iters=k, autotune=False)
+        _, info = sol.solve(sol.build_rhs([1.0]), 1e-8)
+        assert info.converged and info.true_relres < 1e-6
+        out.append(info.iterations)
+        sol.close()
+    return out
+
+
+@pytest.mark.parametrize("p,ks", [(6, (0, 1)), (8, (1,))])
+def test_high_degree_counts_match_oracle(dev, p, ks):
+    from oracle.cases import cavity
+    from oracle.krylov import minres
+    from oracle.precond import HyperPower
+    say(f"[table1] 8^3 degree {p} vs oracle, k in {ks}")
+    S, b = cavity(8, p)
+    got = gpu_counts(8, p, ks)
+    for k, g in zip(ks, got):
+        ref = minres(lambda x: S.K @ x, HyperPower(S, 2, k).apply, b, tol=1e-8, maxit=300)
+        say(f"[table1]   k={k}: GPU {g}, oracle {ref.iters}")
+        assert abs(g - ref.iters) <= 1
+
+
+@pytest.mark.parametrize("E", [8, 16])
+@pytest.mark.parametrize("p", [2, 4, 6, 8])
+def test_counts_against_table1(dev, E, p):
+    paper = table1()[(E, p)]
+    got = gpu_counts(E, p, range(5))
+    say(f"[table1] {E}^3 degree {p}: GPU {got}, paper {paper}")
+    assert all(abs(g - t) <= 3 for g, t in zip(got, paper)), (got, paper)
