@@ -23,6 +23,7 @@ The JSON line also carries
 
     python bench.py [--steps K] [--warmup W] [--order q] [--iters k]
     python bench.py --only {solve,apply_K,apply_P0,copy} ...   (profiling runs)
+    python bench.py --only table1     (Table 1: 8^3..64^3, degrees 2..8, k = 0..4)
 """
 import argparse
 import hashlib
@@ -235,7 +236,8 @@ def main():
     ap.add_argument("--order", type=int, default=2)
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--schur", default="Pcq1")
-    ap.add_argument("--only", default=None, choices=["solve", "apply_K", "apply_P0", "copy"])
+    ap.add_argument("--only", default=None,
+                    choices=["solve", "apply_K", "apply_P0", "copy", "table1"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="preconditioner precision for --only apply_P0")
@@ -267,6 +269,25 @@ def main():
             ya.copy_(xa)
         torch.cuda.synchronize()
         log(f"[bench] copied {args.reps} x {8 * n} bytes")
+        return
+    if args.only == "table1":
+        # Table 1 of Sec. 5.3: MINRES iterations and solution time normalised
+        # by that of P^_0, meshes 8^3..64^3, degrees 2..8, k = 0..4
+        rows = []
+        for Et in (8, 16, 32, 64):
+            for pt in (2, 4, 6, 8):
+                its, ms = [], []
+                for kk in range(5):
+                    s2 = Solver(Et, pt, 1.0, order=2, iters=kk)
+                    b2 = s2.build_rhs([1.0])
+                    _, inf2, t2 = timed_solve(s2, b2, 3)
+                    its.append(inf2.iterations)
+                    ms.append(1e3 * t2)
+                    s2.close()
+                rows.append({"E": Et, "p": pt, "iterations": its, "ms": ms,
+                             "T_sol": [m / ms[0] for m in ms]})
+                log(f"[bench] table1 {Et}^3 p={pt}: {its} ms {[round(m, 2) for m in ms]}")
+        print(json.dumps({"table1": rows}), flush=True)
         return
     if args.only in ("apply_K", "apply_P0"):
         sol = Solver(E, p, 1.0, precision=args.prec,
