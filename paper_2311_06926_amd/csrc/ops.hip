@@ -36,8 +36,14 @@ namespace hp {
 
 namespace {
 
-constexpr int T1 = 32;         // direction-1 points per tile
-constexpr int T2 = 16;         // direction-2 points per tile
+// Tile shape: two-wave workgroups.  Small tiles keep the per-plane chain of
+// a workgroup (stage, barrier, band, barrier, band) short and give more
+// workgroups per CU to overlap it; the larger halo they re-read comes from L2.
+// Measured on apply_K, degree 3 (16x8 against 32x16): 16.0 vs 23.4 us at
+// 16^3, 17.7 vs 26.3 us at 32^3, 32.3 vs 40.7 us at 64^3, 329 vs 360 us at
+// 192^3; 8x8, 16x4, 8x16 and 32x4 were no faster.
+constexpr int T1 = 16;         // direction-1 points per tile
+constexpr int T2 = 8;          // direction-2 points per tile
 constexpr int NT = T1 * T2;    // threads per workgroup, one tile point each
 constexpr int PF = 1;          // planes in flight ahead of the one processed
 
@@ -531,12 +537,14 @@ long long ops_ws_stride(const hp_ctx* c) { return c->nQ; }
 
 OpShape op_model_shape(const hp_ctx* c, int nrhs) {
     // planes per workgroup: a workgroup takes kchunk + 2p steps, and the
-    // velocity launch runs in ceil(blocks / resident) rounds (two 512-thread
-    // workgroups per CU, one from degree 4 on); minimise rounds x steps
+    // velocity launch runs in ceil(blocks / resident) rounds (waves per SIMD
+    // as the kernels' register budget allows, four SIMDs per CU); minimise
+    // rounds x steps
     const int nM = c->nM, P = c->p;
     const long long per_chunk =
         (long long)((nM + T1 - 1) / T1) * ((nM + T2 - 1) / T2) * 3 * nrhs;
-    const long long resident = 256LL * (P < 4 ? 2 : 1);
+    const int waves = P < 4 ? 4 : (P == 4 ? 3 : 2);
+    const long long resident = 256LL * (4 * waves / (NT / 64));
     long long best = -1, best_kc = 1;
     for (int kc = 2; kc <= 64; ++kc) {
         const long long nch = (nM + kc - 1) / kc;
