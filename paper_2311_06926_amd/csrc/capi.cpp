@@ -169,14 +169,17 @@ hipError_t apply_PV(hp_ctx* c, int q, int level, const Fields& x, const Fields& 
     return hipSuccess;
 }
 
-// out = S~_l t = B^T P_{V,l}^{-1} B t  (pressure views)
+// out = S~_l t = B^T P_{V,l}^{-1} B t  (pressure views).  With
+// after_q0 the argument is s and t = P_{Q,0}^{-1} s is implied: B t = 2 nu D^T s
+// (B = D^T M_q, P_{Q,0}^{-1} = 2 nu M_q^{-1}), which skips P_{Q,0} and M_q.
 hipError_t apply_Stilde(hp_ctx* c, int q, int l, const Fields& t, const Fields& out, int nrhs,
-                        int prec) {
+                        int prec, bool after_q0 = false) {
     Extra* ex = extra_of(c);
     const long long nV = c->nV;
     Fields b1 = vel_fields(c, ex->hv + nV * c->opts.max_rhs, nV);       // slot 1
     Fields b2 = vel_fields(c, ex->hv + 2 * nV * c->opts.max_rhs, nV);   // slot 2
-    hipError_t e = launch_operator(c, OP_B, t, b1, 1.0, 0.0, nullptr, nrhs);
+    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, b1, 2.0 * c->nu, 0.0, nullptr, nrhs)
+                            : launch_operator(c, OP_B, t, b1, 1.0, 0.0, nullptr, nrhs);
     if (e != hipSuccess) return e;
     e = apply_PV(c, q, l, b1, b2, nrhs, prec);
     if (e != hipSuccess) return e;
@@ -206,9 +209,14 @@ hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields&
     const Fields* s = &x;  // s_1 = x
     hipError_t e = hipSuccess;
     for (int i = 1; i < q; ++i) {
-        e = apply_PQ1(c, q, level - 1, *s, t, nrhs, prec);     // t = X_{k-1} s_i
-        if (e != hipSuccess) return e;
-        e = apply_Stilde(c, q, lv, t, t, nrhs, prec);          // t = S~ t (B reads t first)
+        if (level == 1) {
+            // X_0 = P_{Q,0}^{-1}: t = S~ X_0 s_i = B' P_{V,l}^{-1} (2 nu D' s_i)
+            e = apply_Stilde(c, q, lv, *s, t, nrhs, prec, true);
+        } else {
+            e = apply_PQ1(c, q, level - 1, *s, t, nrhs, prec);  // t = X_{k-1} s_i
+            if (e != hipSuccess) return e;
+            e = apply_Stilde(c, q, lv, t, t, nrhs, prec);       // t = S~ t (B reads t first)
+        }
         if (e != hipSuccess) return e;
         const Fields* sn = (s == &sa) ? &sb : &sa;
         e = pres_axpbypcz(c, 1.0, x, 1.0, *s, -1.0, t, *sn, nrhs);  // s_{i+1} = x + s_i - t

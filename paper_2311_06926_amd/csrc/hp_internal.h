@@ -103,7 +103,9 @@ namespace hp {
 //  OP_B  : y_u = D^T M_q p
 //  OP_BT : y_p = M_q D u
 //  OP_MV : y_u = M_V u (velocity mass matrix)
-enum OpMode { OP_K = 0, OP_A = 1, OP_B = 2, OP_BT = 3, OP_MV = 4 };
+//  OP_DT : y_u = D^T p (the pressure input in the place of w; with
+//          P_{Q,0}^{-1} = 2 nu M_q^{-1}, B P_{Q,0}^{-1} p = 2 nu D^T p)
+enum OpMode { OP_K = 0, OP_A = 1, OP_B = 2, OP_BT = 3, OP_MV = 4, OP_DT = 5 };
 
 // y_u := alpha * (op result) + beta * src_u  (src_u may alias y_u);
 // y_p := op result.

@@ -617,6 +617,12 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         pres(0, nM);
     } else if (mode == OP_MV) {
         vel(0, nM);
+    } else if (mode == OP_DT) {
+        // the coupling-only velocity kernel reading the pressure input as w
+        a.mode = OP_B;
+        a.ws = in.f[3];
+        a.ws_stride = in.stride[3];
+        vel(0, nM);
     } else {
         // slabs of i3-planes, each pressure chain then velocity, so that the
         // second read of u and the round trip of w can stay in the Infinity
