@@ -26,6 +26,12 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   (option (2)).
 * Q block with the exact Schur complement: eq. ``Pcq_exact``,
   S = B^T A^{-1} B with A^{-1} applied by sparse LU (``variant='Pcq_exact'``).
+* Q block with an inner iterative solve (options (3) and (4) of Sec. 4.1):
+  the sequence of eq. ``Pcq2`` on S_pcg = B^T PCG(A, P_{V,l}) B, where
+  PCG(A, P) b is the preconditioned conjugate gradient iterate for A y = b
+  from y = 0 after at most ``pcg_iters`` steps, stopped early once
+  sqrt(r.z) <= pcg_tol sqrt(r_0.z_0) (``variant='Pcq_pcg'``, l =
+  ``fixed_level``: 0 for option (3), > 0 for option (4)).
 """
 import numpy as np
 import scipy.linalg as sla
@@ -102,7 +108,7 @@ class HyperPower:
     """P_k^{-1} = diag(P_{V,k}^{-1}, P_{Q,k}^{-1}) for order q and k updates."""
 
     def __init__(self, sysm, q=2, k=1, variant="Pcq1", schedule="literal", base=None,
-                 fixed_level=0):
+                 fixed_level=0, pcg_iters=5, pcg_tol=0.0):
         if q < 2 or k < 0 or fixed_level < 0:
             raise ValueError("order q >= 2, k >= 0 and fixed_level >= 0 required")
         self.s = sysm
@@ -110,6 +116,7 @@ class HyperPower:
         self.variant = variant
         self.schedule = schedule
         self.fixed_level = fixed_level
+        self.pcg_iters, self.pcg_tol = pcg_iters, pcg_tol
         self.P0 = BasePreconditioner(sysm) if base is None else base
         self._A_lu = None
 
@@ -137,6 +144,33 @@ class HyperPower:
             self._A_lu = spla.splu(self.s.A.tocsc())
         return self.P0.Bt(self._A_lu.solve(self.P0.B(x)))
 
+    def pcg(self, b):
+        """Preconditioned conjugate gradients for A y = b from y = 0 with
+        P_{V,l}, l = fixed_level (Hestenes-Stiefel), at most pcg_iters steps;
+        stops once sqrt(r.z) <= pcg_tol sqrt(r_0.z_0)."""
+        y = np.zeros_like(b)
+        r = b.copy()
+        z = self.apply_V(self.fixed_level, r)
+        p = z.copy()
+        rz = r @ z
+        rz0 = rz
+        for _ in range(self.pcg_iters):
+            if not rz > 0.0 or np.sqrt(rz) <= self.pcg_tol * np.sqrt(rz0):
+                break
+            Ap = self.P0.A(p)
+            alpha = rz / (p @ Ap)
+            y = y + alpha * p
+            r = r - alpha * Ap
+            z = self.apply_V(self.fixed_level, r)
+            rz_new = r @ z
+            p = z + (rz_new / rz) * p
+            rz = rz_new
+        return y
+
+    def S_pcg(self, x):
+        """S_pcg x = B^T PCG(A, P_{V,l}) B x (options (3), (4) of Sec. 4.1)."""
+        return self.P0.Bt(self.pcg(self.P0.B(x)))
+
     def apply_Q(self, level, x):
         """P_{Q,level}^{-1} x for the chosen variant."""
         if level == 0:
@@ -148,6 +182,8 @@ class HyperPower:
             Sop = lambda y: self.S_tilde(self.fixed_level, y)   # noqa: E731
         elif self.variant == "Pcq_exact":
             Sop = self.S_exact
+        elif self.variant == "Pcq_pcg":
+            Sop = self.S_pcg
         else:
             raise ValueError(self.variant)
         return hyperpower_apply(lambda y: self.apply_Q(level - 1, y), Sop, self.q, x)

@@ -237,3 +237,36 @@ def test_cost_model_ratios():
     t0, t1, t2 = g["timing_384"]
     assert t1 / t0 == pytest.approx(C(1) / C(0), rel=0.01)
     assert t2 / t0 == pytest.approx(C(2) / C(0), rel=0.01)
+
+
+@pytest.mark.parametrize("level,m", [(0, 3), (1, 6)])
+def test_inner_pcg_matches_scipy_cg(level, m):
+    """Options (3)/(4) of Sec. 4.1: the oracle's PCG iterate after m steps
+    from zero equals scipy's preconditioned CG with the same P_{V,l}."""
+    import scipy.sparse.linalg as spla
+    S = KronSystem(3, 2, 0.7)
+    H = HyperPower(S, 2, 0, variant="Pcq_pcg", fixed_level=level, pcg_iters=m)
+    b = np.random.default_rng(3).standard_normal(S.nV)
+    M = spla.LinearOperator((S.nV, S.nV), matvec=lambda r: H.apply_V(level, r))
+    ref, _ = spla.cg(S.A, b, x0=np.zeros(S.nV), rtol=1e-300, atol=0.0, maxiter=m, M=M)
+    got = H.pcg(b)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_inner_pcg_limits():
+    """Run to convergence the inner PCG makes S_pcg the exact Schur
+    complement (so the sequence is eq. Pcq_exact); with a tolerance it stops
+    once the preconditioned residual has dropped by that factor."""
+    S = KronSystem(2, 2, 1.0)
+    P0 = BasePreconditioner(S)
+    Hx = HyperPower(S, 2, 2, variant="Pcq_exact", base=P0)
+    Hp = HyperPower(S, 2, 2, variant="Pcq_pcg", base=P0, pcg_iters=S.nV, pcg_tol=1e-14)
+    x = np.random.default_rng(4).standard_normal(S.nQ)
+    ref = Hx.apply_Q(2, x)
+    assert np.abs(Hp.apply_Q(2, x) - ref).max() <= 1e-8 * np.abs(ref).max()
+    Ht = HyperPower(S, 2, 1, variant="Pcq_pcg", base=P0, pcg_iters=100, pcg_tol=1e-3)
+    b = np.random.default_rng(5).standard_normal(S.nV)
+    y = Ht.pcg(b)
+    r = b - S.A @ y
+    z = P0.apply_V0(r)
+    assert np.sqrt(r @ z) <= 1e-3 * np.sqrt(b @ P0.apply_V0(b)) * (1 + 1e-12)
