@@ -11,6 +11,8 @@ capture) is excluded.  value = solved degrees of freedom per second
 The JSON line also carries
   operators   DOF/s of apply_K, apply_P0 and apply_hyperpower(q, k)
   sweep       iterations and time-to-solution for q in {2,3} x k in {0..3}
+  schur_options  FGMRES iterations and time for the Schur options (1)-(5) of
+              Sec. 4.1 at k = 1, 2
   spectra     Lanczos spectra of P_0 (GPU), the predicted condition numbers and
               MINRES bound per k (Corollary cor:Skform), and the (q, k) they
               choose a priori against the sweep's fastest
@@ -357,6 +359,27 @@ def main():
             log(f"[bench] sweep q={qq} k={kk}: {sweep[f'q{qq}_k{kk}']}")
             s2.close()
 
+    # ---- Schur options of Sec. 4.1 at this mesh (FGMRES, q = 2, k = 1, 2):
+    # (1) eq. Pcq2 with P_{V,0}, (2) eq. Pcq2 with a fixed P_{V,2}, (3)/(4)
+    # eq. Pcq2 on an inner CG solve (tol 1e-2, at most 20 steps) with P_{V,0}
+    # or P_{V,1}, (5) eq. Pcq1 (the default)
+    schur_opts = {}
+    if not args.no_sweep:
+        variants = [("opt1_Pcq2_l0", dict(schur="Pcq2", schur_level=0)),
+                    ("opt2_Pcq2_l2", dict(schur="Pcq2", schur_level=2)),
+                    ("opt3_pcg_l0", dict(schur="Pcq_pcg", schur_level=0)),
+                    ("opt4_pcg_l1", dict(schur="Pcq_pcg", schur_level=1)),
+                    ("opt5_Pcq1", dict(schur="Pcq1"))]
+        for kk in (1, 2):
+            for name, kw in variants:
+                s2 = Solver(E, p, 1.0, order=2, iters=kk, krylov="fgmres", **kw)
+                b2 = s2.build_rhs([1.0])
+                _, inf2, t2 = timed_solve(s2, b2, 3)
+                schur_opts[f"{name}_k{kk}"] = {"iterations": inf2.iterations, "ms": 1e3 * t2,
+                                               "true_relres": inf2.true_relres}
+                log(f"[bench] schur option {name} k={kk}: {schur_opts[f'{name}_k{kk}']}")
+                s2.close()
+
     # ---- a-priori depth from the P_0 spectra (Lanczos on the GPU): predicted
     # condition numbers and MINRES bound per k, times the measured cost of
     # one iteration (apply_K + apply_hyperpower), against the sweep
@@ -517,6 +540,7 @@ def main():
         "cpu_baseline": cpu,
         "sweep": sweep,
         "spectra": spectra,
+        "schur_options": schur_opts,
         "mixed": mixed,
         "batched": batched,
         "hbm": hbm,

@@ -68,9 +68,12 @@ typedef enum {
 enum { HP_PREC_FP64 = 0, HP_PREC_FP32 = 1, HP_PREC_BF16X3 = 2 };
 /* Krylov method. MINRES needs an exactly symmetric preconditioner (FP64). */
 enum { HP_MINRES = 0, HP_FGMRES = 1 };
-/* Schur-complement sequence of Sec. 4.1: eq. Pcq1 (with inner updates) or
- * eq. Pcq2 (without). */
-enum { HP_SCHUR_PCQ1 = 1, HP_SCHUR_PCQ2 = 2 };
+/* Schur-complement sequence of Sec. 4.1: eq. Pcq1 (with inner updates),
+ * eq. Pcq2 (without; B' P_{V,l}^{-1} B with l = schur_level), or eq. Pcq2 on
+ * B' PCG(A, P_{V,l}) B, an inner preconditioned conjugate-gradient solve
+ * (options (3), l = 0, and (4), l > 0; the operator is not linear, so the
+ * solve needs HP_FGMRES). */
+enum { HP_SCHUR_PCQ1 = 1, HP_SCHUR_PCQ2 = 2, HP_SCHUR_PCG = 3 };
 /* Index l of P_{V,l} used by the k-th update of eq. Pcq1: LITERAL is the
  * schedule of Sec. 4.1 option (5), l = 0 for k = 1 and l = k for k > 1;
  * PREV uses l = k - 1. */
@@ -102,7 +105,11 @@ typedef struct hp_opts {
     int schur_level;    /* eq. Pcq2 only: the fixed P_{V,l} inside B' P_{V,l}^{-1} B,
                            l = schur_level in [0, 6] (default 0 = P_{V,0}, option (1)
                            of Sec. 4.1; l > 0 is option (2), a fixed P_{V,k}, which for
-                           large l approaches eq. Pcq_exact) */
+                           large l approaches eq. Pcq_exact); for HP_SCHUR_PCG the
+                           preconditioner P_{V,l} of the inner conjugate gradients */
+    int schur_pcg_iters;   /* HP_SCHUR_PCG: inner CG steps, 1..1000 (default 20) */
+    double schur_pcg_tol;  /* HP_SCHUR_PCG: a right-hand side stops once its
+                              sqrt(r.P^{-1}r) has dropped by this factor (default 1e-2) */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */

@@ -17,7 +17,7 @@ HP_STATUS = {
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KRYLOV = {"minres": 0, "fgmres": 1}
-SCHUR = {"Pcq1": 1, "Pcq2": 2}
+SCHUR = {"Pcq1": 1, "Pcq2": 2, "Pcq_pcg": 3}
 SCHEDULE = {"literal": 0, "prev": 1}
 SPEC_VELOCITY, SPEC_SCHUR = 0, 1
 
@@ -48,6 +48,8 @@ class hp_opts(ctypes.Structure):
         ("fd_plan", ctypes.c_int),
         ("op_slabs", ctypes.c_int),
         ("schur_level", ctypes.c_int),
+        ("schur_pcg_iters", ctypes.c_int),
+        ("schur_pcg_tol", ctypes.c_double),
     ]
 
 

@@ -42,6 +42,12 @@ struct Extra {
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     double* ws2 = nullptr;
     double* hq = nullptr;  // 3 pressure vectors per level x (KMAX+1) x max_rhs
+    // inner PCG of the Schur variant HP_SCHUR_PCG: r, z, p, A p (velocity x
+    // max_rhs each), per-rhs scalars, step coefficients and dot partials
+    double* cgv = nullptr;
+    CgScalars* cgsc = nullptr;
+    double* cgcoef = nullptr;
+    double* cgpart = nullptr;
     // Krylov vectors
     double* kv = nullptr;
     size_t kv_doubles = 0;
@@ -186,6 +192,57 @@ hipError_t apply_Stilde(hp_ctx* c, int q, int l, const Fields& t, const Fields& 
     return launch_operator(c, OP_BT, b2, out, 1.0, 0.0, nullptr, nrhs);
 }
 
+// out = S_pcg t = B' Y, Y the preconditioned conjugate-gradient iterate for
+// A Y = B t from Y = 0 with P_{V,l}, l = opts.schur_level, after
+// opts.schur_pcg_iters steps (a right-hand side stops early once
+// sqrt(r.z) <= opts.schur_pcg_tol sqrt(r_0.z_0)): options (3) (l = 0) and
+// (4) (l > 0) of Sec. 4.1.  after_q0 as for apply_Stilde.  Every step is a
+// fixed launch sequence with device-side scalars (capturable in a graph).
+hipError_t apply_Spcg(hp_ctx* c, int q, const Fields& t, const Fields& out, int nrhs, int prec,
+                      bool after_q0 = false) {
+    Extra* ex = extra_of(c);
+    const long long nV = c->nV, R = c->opts.max_rhs;
+    const int lv = c->opts.schur_level;
+    hipStream_t st = c->stream;
+    double* bv = ex->hv + nV * R;       // slot 1: B t
+    double* y = ex->hv + 2 * nV * R;    // slot 2: the iterate
+    double* r = ex->cgv;
+    double* z = r + nV * R;
+    double* pv = z + nV * R;
+    double* qv = pv + nV * R;
+    double* cx = ex->cgcoef;
+    double* cr = cx + 2 * R;
+    double* cp = cr + 2 * R;
+    auto F = [&](double* b) { return vel_fields(c, b, nV); };
+    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, F(bv), 2.0 * c->nu, 0.0, nullptr, nrhs)
+                            : launch_operator(c, OP_B, t, F(bv), 1.0, 0.0, nullptr, nrhs);
+    if (e != hipSuccess) return e;
+    const long long n = nV * nrhs;  // velocity vectors are contiguous per rhs
+    if ((e = vec_copy(st, n, bv, r)) != hipSuccess) return e;
+    if ((e = vec_zero(st, n, y)) != hipSuccess) return e;
+    if ((e = apply_PV(c, q, lv, F(r), F(z), nrhs, prec)) != hipSuccess) return e;
+    if ((e = vec_copy(st, n, z, pv)) != hipSuccess) return e;
+    if ((e = vec_dot_partials(st, nV, nV, r, z, nrhs, ex->cgpart)) != hipSuccess) return e;
+    if ((e = cg_init(st, ex->cgsc, ex->cgpart, nrhs)) != hipSuccess) return e;
+    for (int j = 0; j < c->opts.schur_pcg_iters; ++j) {
+        if ((e = launch_operator(c, OP_A, F(pv), F(qv), 1.0, 0.0, nullptr, nrhs)) != hipSuccess)
+            return e;
+        if ((e = vec_dot_partials(st, nV, nV, pv, qv, nrhs, ex->cgpart)) != hipSuccess) return e;
+        if ((e = cg_alpha(st, ex->cgsc, ex->cgpart, cx, cr, nrhs)) != hipSuccess) return e;
+        const double* xy[2] = {y, pv};
+        if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xy, cx, y)) != hipSuccess) return e;
+        const double* xr[2] = {r, qv};
+        if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xr, cr, r)) != hipSuccess) return e;
+        if ((e = apply_PV(c, q, lv, F(r), F(z), nrhs, prec)) != hipSuccess) return e;
+        if ((e = vec_dot_partials(st, nV, nV, r, z, nrhs, ex->cgpart)) != hipSuccess) return e;
+        if ((e = cg_beta(st, ex->cgsc, ex->cgpart, cp, c->opts.schur_pcg_tol, nrhs)) != hipSuccess)
+            return e;
+        const double* xp[2] = {z, pv};
+        if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xp, cp, pv)) != hipSuccess) return e;
+    }
+    return launch_operator(c, OP_BT, F(y), out, 1.0, 0.0, nullptr, nrhs);
+}
+
 int l_of(const hp_ctx* c, int k) {
     if (c->opts.l_schedule == HP_L_LITERAL) return k == 1 ? 0 : k;
     return k - 1;
@@ -198,7 +255,9 @@ Fields hq_slot(hp_ctx* c, int level, int slot) {
 }
 
 // y = P^_{Q,level}^{-1} x by the recursion of eq. Pcq1:
-//   X_k = X_{k-1} sum_{i<q} (I - S~_{l(k)} X_{k-1})^i,
+//   X_k = X_{k-1} sum_{i<q} (I - S~_{l(k)} X_{k-1})^i
+// (for HP_SCHUR_PCG the same recursion with the fixed S_pcg in place of
+// S~_{l(k)}: eq. Pcq2 taken literally, as S_pcg is not linear),
 // with the sum evaluated in Horner form, s_1 = x, s_{i+1} = x + (I - S X) s_i,
 // so that y = X_{k-1} s_q (one fused update per term instead of two).
 hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
@@ -206,16 +265,19 @@ hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields&
     if (level == 0) return launch_P0(c, x, y, false, true, false, prec, nrhs);
     Fields sa = hq_slot(c, level, 0), sb = hq_slot(c, level, 1), t = hq_slot(c, level, 2);
     const int lv = l_of(c, level);
+    const bool pcg = c->opts.schur_variant == HP_SCHUR_PCG;  // fixed S_pcg (eq. Pcq2 form)
     const Fields* s = &x;  // s_1 = x
     hipError_t e = hipSuccess;
     for (int i = 1; i < q; ++i) {
         if (level == 1) {
             // X_0 = P_{Q,0}^{-1}: t = S~ X_0 s_i = B' P_{V,l}^{-1} (2 nu D' s_i)
-            e = apply_Stilde(c, q, lv, *s, t, nrhs, prec, true);
+            e = pcg ? apply_Spcg(c, q, *s, t, nrhs, prec, true)
+                    : apply_Stilde(c, q, lv, *s, t, nrhs, prec, true);
         } else {
             e = apply_PQ1(c, q, level - 1, *s, t, nrhs, prec);  // t = X_{k-1} s_i
             if (e != hipSuccess) return e;
-            e = apply_Stilde(c, q, lv, t, t, nrhs, prec);       // t = S~ t (B reads t first)
+            // t = S~ t (B reads t first)
+            e = pcg ? apply_Spcg(c, q, t, t, nrhs, prec) : apply_Stilde(c, q, lv, t, t, nrhs, prec);
         }
         if (e != hipSuccess) return e;
         const Fields* sn = (s == &sa) ? &sb : &sa;
@@ -1005,6 +1067,8 @@ void hp_default_opts(hp_opts* o) {
     o->fd_plan = -1;
     o->op_slabs = 0;
     o->schur_level = 0;
+    o->schur_pcg_iters = 20;
+    o->schur_pcg_tol = 1e-2;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -1033,7 +1097,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
         o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0 || o.schur_level < 0 ||
-        o.schur_level > KMAX)
+        o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
+        o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0))
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1146,6 +1211,14 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         }
     }
     if (alloc_device(&ex->hq, (size_t)3 * c->nQ * R * (KMAX + 1)) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
+    if (o.schur_variant == HP_SCHUR_PCG &&
+        (alloc_device(&ex->cgv, (size_t)4 * c->nV * R) != HP_OK ||
+         alloc_device(&ex->cgcoef, (size_t)6 * R) != HP_OK ||
+         alloc_device(&ex->cgpart, vec_partial_doubles(1, (int)R)) != HP_OK ||
+         hipMalloc(reinterpret_cast<void**>(&ex->cgsc), sizeof(CgScalars) * R) != hipSuccess)) {
+        hp_destroy(c);
+        return HP_ENOMEM;
+    }
     ex->coef_doubles = (size_t)std::max(4, 132) * R;
     if (alloc_device(&ex->dcoef, ex->coef_doubles) != HP_OK) { hp_destroy(c); return HP_ENOMEM; }
     if (hipHostMalloc(reinterpret_cast<void**>(&ex->hcoef), ex->coef_doubles * sizeof(double)) != hipSuccess) {
@@ -1318,7 +1391,9 @@ hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
                    hp_solve_info* info) {
     if (check_rhs(c, nrhs) != HP_OK || !b || !x || b == x || !(tol > 0.0) || !c->fd_ok)
         return HP_EINVAL;
-    if (c->opts.krylov == HP_MINRES && c->opts.precision != HP_PREC_FP64) return HP_EINVAL;
+    if (c->opts.krylov == HP_MINRES &&
+        (c->opts.precision != HP_PREC_FP64 || c->opts.schur_variant == HP_SCHUR_PCG))
+        return HP_EINVAL;  // MINRES needs a fixed symmetric preconditioner
     auto t0 = std::chrono::steady_clock::now();
     hp_solve_info loc{};
     hp_status s = c->opts.krylov == HP_MINRES ? minres(c, b, x, nrhs, tol, &loc)
@@ -1399,6 +1474,10 @@ void hp_destroy(hp_ctx* c) {
     if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);
     if (ex->mcoef) (void)hipFree(ex->mcoef);
     if (ex->mpart) (void)hipFree(ex->mpart);
+    if (ex->cgv) (void)hipFree(ex->cgv);
+    if (ex->cgcoef) (void)hipFree(ex->cgcoef);
+    if (ex->cgpart) (void)hipFree(ex->cgpart);
+    if (ex->cgsc) (void)hipFree(ex->cgsc);
     if (ex->mev[0]) (void)hipEventDestroy(ex->mev[0]);
     if (ex->mev[1]) (void)hipEventDestroy(ex->mev[1]);
     if (ex->cap) (void)hipStreamDestroy(ex->cap);

@@ -387,6 +387,51 @@ __global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coe
     if (mirror) mirror[r] = sc[r];
 }
 
+// ---- inner PCG for A y = b (Schur options (3)/(4) of Sec. 4.1) ------------------------
+// Per rhs: rz = r.z; the step coefficients are written for vec_lincomb:
+// cx = (1, alpha) for y += alpha p, cr = (1, -alpha) for r -= alpha A p,
+// cp = (1, beta) for p = z + beta p.  A right-hand side whose preconditioned
+// residual has dropped to tol of its start (or whose r.z is not positive)
+// is frozen: alpha = 0 from then on.
+__global__ void k_cg_init(CgScalars* sc, const double* part_rz, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double rz = sum_partials(part_rz, r);
+    sc[r].rz = rz;
+    sc[r].rz0 = rz;
+    sc[r].done = (rz > 0.0 && isfinite(rz)) ? 0 : 1;
+}
+
+__global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, double* cx, double* cr,
+                           int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    const double pq = sum_partials(part_pq, r);
+    double a = 0.0;
+    if (!sc[r].done && pq > 0.0 && isfinite(pq)) a = sc[r].rz / pq;
+    else sc[r].done = 1;
+    cx[2 * r] = 1.0;
+    cx[2 * r + 1] = a;
+    cr[2 * r] = 1.0;
+    cr[2 * r + 1] = -a;
+}
+
+__global__ void k_cg_beta(CgScalars* sc, const double* part_rz, double* cp, double tol, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    cp[2 * r] = 1.0;
+    cp[2 * r + 1] = 0.0;
+    if (sc[r].done) return;
+    const double rzn = sum_partials(part_rz, r);
+    if (!(rzn > 0.0) || !isfinite(rzn)) {
+        sc[r].done = 1;
+        return;
+    }
+    cp[2 * r + 1] = rzn / sc[r].rz;
+    sc[r].rz = rzn;
+    if (sqrt(rzn) <= tol * sqrt(sc[r].rz0)) sc[r].done = 1;
+}
+
 // MINRES tail: w_new = cw0 z + cw1 w_old + cw2 w and x = cx0 x + cx1 w_new in one pass
 __global__ void k_minres_update(long long n, long long ld, const double* z, const double* wo,
                                 const double* w, const double* cw, double* wn, double* x,
@@ -427,6 +472,22 @@ hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, con
                          double* x, const double* cx) {
     hipLaunchKernelGGL(k_minres_update, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, z, wo, w,
                        cw, wn, x, cx);
+    return hipGetLastError();
+}
+hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
+    return hipGetLastError();
+}
+hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, double* cx, double* cr,
+                    int nrhs) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, cx, cr,
+                       nrhs);
+    return hipGetLastError();
+}
+hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, double* cp, double tol,
+                   int nrhs) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, cp, tol,
+                       nrhs);
     return hipGetLastError();
 }
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,

@@ -49,6 +49,19 @@ hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, con
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
 
+// Per-right-hand-side state of the inner preconditioned CG.
+struct CgScalars {
+    double rz, rz0;
+    int done, pad;
+};
+hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs);
+// cx = (1, alpha), cr = (1, -alpha) per rhs (2 doubles each)
+hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, double* cx, double* cr,
+                    int nrhs);
+// cp = (1, beta) per rhs; freezes a rhs once sqrt(r.z) <= tol sqrt(r0.z0)
+hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, double* cp, double tol,
+                   int nrhs);
+
 // Per-right-hand-side state of device-side FGMRES.
 struct FgScalars {
     double bnorm, rel;

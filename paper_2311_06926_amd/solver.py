@@ -25,17 +25,18 @@ def _ptr(t):
 class Solver:
     """Context for E^3 elements, velocity degree p, viscosity nu.
 
-    Options (see include/hyperpower.h): c_pen, schur ('Pcq1'|'Pcq2'),
+    Options (see include/hyperpower.h): c_pen, schur ('Pcq1'|'Pcq2'|'Pcq_pcg'),
     schedule ('literal'|'prev'), precision ('fp64'|'fp32'|'bf16x3'),
     krylov ('minres'|'fgmres'), restart, maxit, order, iters, max_rhs,
-    schur_level (eq. Pcq2: the fixed P_{V,l} in B' P_{V,l}^{-1} B).
+    schur_level (eq. Pcq2: the fixed P_{V,l} in B' P_{V,l}^{-1} B; Pcq_pcg: the
+    inner CG preconditioner P_{V,l}), schur_pcg_iters, schur_pcg_tol.
     """
 
     def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
-                 device=None):
+                 schur_pcg_iters=20, schur_pcg_tol=1e-2, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -60,6 +61,8 @@ class Solver:
         o.fd_plan = fd_plan
         o.op_slabs = op_slabs
         o.schur_level = schur_level
+        o.schur_pcg_iters = schur_pcg_iters
+        o.schur_pcg_tol = schur_pcg_tol
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):

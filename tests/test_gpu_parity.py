@@ -241,6 +241,56 @@ def test_fgmres_matches_oracle(dev):
     sol.close()
 
 
+@pytest.mark.parametrize("level,k,m", [(0, 1, 4), (1, 1, 3), (0, 2, 3)])
+def test_inner_pcg_schur_variant(dev, level, k, m):
+    """Options (3)/(4) of Sec. 4.1: eq. Pcq2 on B' PCG(A, P_{V,l}) B with a
+    fixed number of inner steps (tolerance 0), single and batched, against
+    the oracle's PCG variant."""
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 5, 3
+    say(f"[parity] inner-PCG Schur E={E} p={p} l={level} k={k} m={m}")
+    S = oracle_sys(E, p)
+    H = HyperPower(S, 2, k, variant="Pcq_pcg", fixed_level=level, pcg_iters=m, pcg_tol=0.0)
+    sol = Solver(E, p, 1.0, schur="Pcq_pcg", schur_level=level, schur_pcg_iters=m,
+                 schur_pcg_tol=0.0, max_rhs=2, krylov="fgmres")
+    x = synth.random_vector(2 * S.N, seed=400 + 10 * level + k)
+    y = sol.apply_hyperpower(2, k, to_gpu(x, dev)).cpu().numpy()
+    for r in range(2):
+        xr = x[r * S.N:(r + 1) * S.N]
+        assert rel_err(y[r * S.N:(r + 1) * S.N], H.apply(xr)) < 1e-10, r
+    y1 = sol.apply_hyperpower(2, k, to_gpu(x[:S.N], dev)).cpu().numpy()
+    assert np.array_equal(y1, y[:S.N])
+    sol.close()
+
+
+def test_inner_pcg_fgmres_solve(dev):
+    from oracle.cases import cavity
+    from oracle.krylov import fgmres
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd._lib import HPError
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] FGMRES with the inner-PCG Schur variant, 6^3 p=2 k=1")
+    S, b = cavity(6, 2)
+    H = HyperPower(S, 2, 1, variant="Pcq_pcg", pcg_iters=5, pcg_tol=0.0)
+    ref = fgmres(lambda v: S.K @ v, lambda v, j: H.apply(v), b, tol=1e-8, restart=50)
+    sol = Solver(6, 2, 1.0, iters=1, krylov="fgmres", schur="Pcq_pcg", schur_pcg_iters=5,
+                 schur_pcg_tol=0.0)
+    x, info = sol.solve(sol.build_rhs([1.0]), tol=1e-8)
+    assert abs(info.iterations - ref.iters) <= 1
+    assert info.true_relres <= 1e-8 * 1.01
+    sol.close()
+    tolsol = Solver(6, 2, 1.0, iters=2, krylov="fgmres", schur="Pcq_pcg", schur_level=1)
+    _, info = tolsol.solve(tolsol.build_rhs([1.0]), tol=1e-8)
+    say(f"[parity]   tol 1e-2 inner CG, l=1, k=2: {info.iterations} iterations")
+    assert info.converged and info.true_relres <= 1e-8 * 1.01
+    tolsol.close()
+    mr = Solver(6, 2, 1.0, iters=1, schur="Pcq_pcg")
+    with pytest.raises(HPError):
+        mr.solve(mr.build_rhs([1.0]), tol=1e-8)
+    mr.close()
+
+
 def test_fp32_preconditioner_error_is_small(dev):
     from paper_2311_06926_amd.solver import Solver
     say("[parity] FP32 P0 vs FP64 P0")
