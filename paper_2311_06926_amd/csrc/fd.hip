@@ -217,7 +217,7 @@ struct ZArgs {
     long long sin[4], sout[4];
     int dims[4][3];
     int fields_lo, fields_hi;
-    int accumulate;
+    int accumulate;   // bit f set: field f is added to its output
     double two_nu;
 };
 
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
         if (r0 + row >= plane) continue;
         TO v = (TO)S[row * ld + kk];
         long long o = r0 + row + (long long)kk * plane;
-        if (a.accumulate) y[o] += v;
+        if ((a.accumulate >> f) & 1) y[o] += v;
         else y[o] = v;
     }
 }
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
         if (r0 + row >= plane) continue;
         TO v = (TO)Out[row * ld + kk];
         long long o = r0 + row + (long long)kk * plane;
-        if (a.accumulate) y[o] += v;
+        if ((a.accumulate >> f) & 1) y[o] += v;
         else y[o] = v;
     }
 }
@@ -751,21 +751,30 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         za.sout[f] = N;
     }
     za.two_nu = 2.0 * c->nu;
-    if (vel) {
-        ZArgs zv = za;
-        zv.fields_lo = 0;
-        zv.fields_hi = 3;
-        zv.accumulate = 0;
-        launch_z(zv, false, 3);
-    }
-    if (pres) {
-        ZArgs zp = za;
-        zp.fields_lo = 3;
-        zp.fields_hi = 4;
-        zp.out[3] = out.f[3];
-        zp.sout[3] = out.stride[3];
-        zp.accumulate = accumulate ? 1 : 0;
-        launch_z(zp, true, 1);
+    // the pressure's mode-3 step writes the final output; the velocity's
+    // feeds the inverse xy step.  In FP64 both output types agree, so the
+    // four fields share one launch.
+    za.out[3] = out.f[3];
+    za.sout[3] = out.stride[3];
+    za.accumulate = accumulate ? (1 << 3) : 0;
+    if (vel && pres && std::is_same<T, double>::value) {
+        ZArgs zb = za;
+        zb.fields_lo = 0;
+        zb.fields_hi = 4;
+        launch_z(zb, true, 4);
+    } else {
+        if (vel) {
+            ZArgs zv = za;
+            zv.fields_lo = 0;
+            zv.fields_hi = 3;
+            launch_z(zv, false, 3);
+        }
+        if (pres) {
+            ZArgs zp = za;
+            zp.fields_lo = 3;
+            zp.fields_hi = 4;
+            launch_z(zp, true, 1);
+        }
     }
     if (vel) {
         XYArgs xi = xa;
