@@ -54,11 +54,11 @@ struct Extra {
     double* dcoef = nullptr;  // device coefficient staging
     double* hcoef = nullptr;  // pinned host coefficients
     size_t coef_doubles = 0;
-    // device-side MINRES state: scalars, coefficient slots, dot partials
+    // device-side MINRES state (two buffers, read and written alternately),
+    // coefficient slots, dot partials
     MinresScalars* msc = nullptr;
     MinresScalars* hmsc[2] = {nullptr, nullptr};  // pinned host mirrors
     MinresScalars* dmsc[2] = {nullptr, nullptr};  // their device addresses
-    double* mcoef = nullptr;   // 8 per rhs: v (3), w (3), x (2)
     double* mpart = nullptr;   // 2 x DOT partials per rhs
     hipEvent_t mev[2] = {nullptr, nullptr};
     hipStream_t cap = nullptr;  // non-blocking stream used only for graph capture
@@ -415,31 +415,27 @@ MinresBufs minres_bufs(hp_ctx* c, int phase, int nrhs) {
     return b;
 }
 
-// One MINRES iteration; the updated scalars are also written to the host
-// mirror `mirror` (device address of pinned host memory).
+// One MINRES iteration; it reads the scalar state msc[cur] and writes the
+// next one to msc[cur ^ 1] and to the host mirror `mirror` (device address
+// of pinned host memory).
 hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
-                            MinresScalars* mirror) {
+                            MinresScalars* mirror, int cur) {
     Extra* ex = extra_of(c);
     const long long N = c->N;
     const int R = c->opts.max_rhs;
-    double* cv = ex->mcoef;
-    double* cw = ex->mcoef + 3 * R;
-    double* cx = ex->mcoef + 6 * R;
+    MinresScalars* s_cur = ex->msc + cur * R;
+    MinresScalars* s_next = ex->msc + (cur ^ 1) * R;
     double* p0 = ex->mpart;
     double* p1 = ex->mpart + vec_partial_doubles(1, R);
     hipError_t e;
     if ((e = launch_operator(c, OP_K, full_fields(c, b.z), full_fields(c, b.Kz), 1.0, 0.0, nullptr,
                              nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
-    if ((e = minres_a(c->stream, ex->msc, p0, cv, nrhs)) != hipSuccess) return e;
-    {
-        const double* xs[3] = {b.Kz, b.v, b.vo};
-        if ((e = vec_lincomb(c->stream, N, N, nrhs, 3, xs, cv, b.vn)) != hipSuccess) return e;
-    }
+    if ((e = minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur, p0)) != hipSuccess)
+        return e;
     if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.zn, b.vn, nrhs, p1)) != hipSuccess) return e;
-    if ((e = minres_b(c->stream, ex->msc, p1, cw, cx, tol, nrhs, mirror)) != hipSuccess) return e;
-    return minres_update(c->stream, N, N, nrhs, b.z, b.wo, b.w, cw, b.wn, b.x, cx);
+    return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, s_cur, s_next, p1, tol, mirror);
 }
 
 void drop_graphs(Extra* ex) {
@@ -468,8 +464,10 @@ hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
             st = HP_EHIP;
             break;
         }
-        // iteration it (phase (it-1) % 6) is polled through mirror it & 1
-        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[(ph + 1) & 1]);
+        // iteration it (phase (it-1) % 6) reads state it & 1 and is polled
+        // through mirror it & 1
+        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol,
+                                        ex->dmsc[(ph + 1) & 1], (ph + 1) & 1);
         hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
         if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
         if (st == HP_OK && hipGraphInstantiate(&ex->g_exec[ph], g, nullptr, nullptr, 0) != hipSuccess)
@@ -509,14 +507,16 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     HIPCHK(vec_copy(c->stream, V, b, b0.v));
     HIPCHK(apply_Pk(c, c->opts.order, c->opts.iters, b0.v, b0.z, nrhs));
     HIPCHK(vec_dot_partials(c->stream, N, N, b0.z, b0.v, nrhs, ex->mpart));
-    HIPCHK(minres_init(c->stream, ex->msc, ex->mpart, nrhs));
+    // iteration it reads the state msc[it & 1]: the first reads msc[1]
+    MinresScalars* s1 = ex->msc + c->opts.max_rhs;
+    HIPCHK(minres_init(c->stream, s1, ex->mpart, nrhs));
     const size_t sbytes = sizeof(MinresScalars) * nrhs;
     auto all_done = [&](const MinresScalars* h) {
         for (int r = 0; r < nrhs; ++r)
             if (!h[r].done) return false;
         return true;
     };
-    HIPCHK(hipMemcpyAsync(ex->hmsc[0], ex->msc, sbytes, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(ex->hmsc[0], s1, sbytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     int it = 0;
     bool finished = all_done(ex->hmsc[0]);
@@ -526,7 +526,8 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         if (graphs) {
             HIPCHK(hipGraphLaunch(ex->g_exec[ph], c->stream));
         } else {
-            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1]));
+            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1],
+                                    it & 1));
         }
         HIPCHK(hipEventRecord(ex->mev[it & 1], c->stream));
         if (it >= 2) {
@@ -535,8 +536,10 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         }
     }
     HIPCHK(hipStreamSynchronize(c->stream));
+    // after `it` iterations the state is msc[(it + 1) & 1]
     const MinresScalars* h = ex->hmsc[it & 1];
-    HIPCHK(hipMemcpy(ex->hmsc[it & 1], ex->msc, sbytes, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ex->hmsc[it & 1], ex->msc + ((it + 1) & 1) * c->opts.max_rhs, sbytes,
+                     hipMemcpyDeviceToHost));
     HIPCHK(vec_copy(c->stream, V, b0.x, x));
     hp_status status = HP_OK;
     bool conv = true;
@@ -1225,14 +1228,13 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hp_destroy(c);
         return HP_ENOMEM;
     }
-    if (hipMalloc(reinterpret_cast<void**>(&ex->msc), sizeof(MinresScalars) * R) != hipSuccess ||
+    if (hipMalloc(reinterpret_cast<void**>(&ex->msc), 2 * sizeof(MinresScalars) * R) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[0]), sizeof(MinresScalars) * R,
                       hipHostMallocMapped) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&ex->hmsc[1]), sizeof(MinresScalars) * R,
                       hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[0]), ex->hmsc[0], 0) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[1]), ex->hmsc[1], 0) != hipSuccess ||
-        alloc_device(&ex->mcoef, 8 * R) != HP_OK ||
         alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
@@ -1472,7 +1474,6 @@ void hp_destroy(hp_ctx* c) {
     if (ex->msc) (void)hipFree(ex->msc);
     if (ex->hmsc[0]) (void)hipHostFree(ex->hmsc[0]);
     if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);
-    if (ex->mcoef) (void)hipFree(ex->mcoef);
     if (ex->mpart) (void)hipFree(ex->mpart);
     if (ex->cgv) (void)hipFree(ex->cgv);
     if (ex->cgcoef) (void)hipFree(ex->cgcoef);

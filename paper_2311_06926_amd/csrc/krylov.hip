@@ -304,15 +304,13 @@ __global__ void k_minres_init(MinresScalars* sc, const double* part_zv, int nrhs
 }
 
 // after Kz = K z:  delta = (Kz.z)/gamma^2; coefficients of v_new = Kz/gamma - (delta/gamma) v - (gamma/gamma_old) v_old
-__device__ void minres_a_one(MinresScalars* sc, const double* part_kz, double* coef_v, int r) {
-    MinresScalars& m = sc[r];
-    double* cv = coef_v + 3 * r;
+__device__ void minres_a_core(MinresScalars& m, double kz, double* cv) {
     if (m.done) {
         cv[0] = cv[1] = cv[2] = 0.0;
         return;
     }
     const double g = m.gamma;
-    m.delta = sum_partials(part_kz, r) / (g * g);
+    m.delta = kz / (g * g);
     cv[0] = 1.0 / g;
     cv[1] = -m.delta / g;
     cv[2] = -g / m.gamma_old;
@@ -320,18 +318,13 @@ __device__ void minres_a_one(MinresScalars* sc, const double* part_kz, double* c
 
 // after z_new = P^{-1} v_new: gamma_new, the Givens rotation, coefficients of
 // w_new = (z/gamma - a3 w_old - a2 w)/a1 and x += c_new eta w_new, then shift.
-__device__ void minres_b_one(MinresScalars* sc, const double* part_zv, double* coef_w,
-                             double* coef_x, double tol, int r) {
-    MinresScalars& m = sc[r];
-    double* cw = coef_w + 3 * r;
-    double* cx = coef_x + 2 * r;
+__device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* cx, double tol) {
     cx[0] = 1.0;
     if (m.done) {
         cw[0] = cw[1] = cw[2] = 0.0;
         cx[1] = 0.0;
         return;
     }
-    double zv = sum_partials(part_zv, r);
     if (!isfinite(zv)) {
         m.status = -7;
         m.done = 1;
@@ -370,21 +363,6 @@ __device__ void minres_b_one(MinresScalars* sc, const double* part_zv, double* c
     m.rel = fabs(m.eta) / m.beta0;
     m.iters += 1;
     if (m.rel <= tol || gn == 0.0 || m.status != 0) m.done = 1;
-}
-
-__global__ void k_minres_a(MinresScalars* sc, const double* part_kz, double* coef_v, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < nrhs) minres_a_one(sc, part_kz, coef_v, r);
-}
-
-// mirror: host-mapped copy of the scalars (may be null), written after the
-// update so that the host can poll convergence without a copy launch
-__global__ void k_minres_b(MinresScalars* sc, const double* part_zv, double* coef_w,
-                           double* coef_x, double tol, int nrhs, MinresScalars* mirror) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    minres_b_one(sc, part_zv, coef_w, coef_x, tol, r);
-    if (mirror) mirror[r] = sc[r];
 }
 
 // ---- inner PCG for A y = b (Schur options (3)/(4) of Sec. 4.1) ------------------------
@@ -432,20 +410,64 @@ __global__ void k_cg_beta(CgScalars* sc, const double* part_rz, double* cp, doub
     if (sqrt(rzn) <= tol * sqrt(sc[r].rz0)) sc[r].done = 1;
 }
 
-// MINRES tail: w_new = cw0 z + cw1 w_old + cw2 w and x = cx0 x + cx1 w_new in one pass
-__global__ void k_minres_update(long long n, long long ld, const double* z, const double* wo,
-                                const double* w, const double* cw, double* wn, double* x,
-                                const double* cx) {
+// The two MINRES vector updates, each fused with the scalar step that gives
+// its coefficients: every workgroup finishes the dot product from the
+// per-block partials (the same fixed-order sum in each) and forms the
+// coefficients itself, so no separate scalar launch is needed.
+//   k_minres_v: delta from (Kz.z); v_new = cv . (Kz, v, v_old); workgroup 0
+//               records delta in the state.
+//   k_minres_w: gamma_new, the Givens rotation and the shift from (z_new.v_new)
+//               applied to a copy of the state; w_new = cw . (z, w_old, w) and
+//               x += cx1 w_new; workgroup 0 writes the new state to sc_out
+//               (a second buffer, so no workgroup reads a half-updated state)
+//               and to the host mirror.
+__device__ __forceinline__ double sum_block_partials(const double* part, int r, double* sh) {
+    const double p = threadIdx.x < DOT_BLOCKS ? part[(long long)r * DOT_BLOCKS + threadIdx.x] : 0.0;
+    return block_sum(p, sh);  // valid in thread 0
+}
+
+__global__ void k_minres_v(long long n, long long ld, const double* kz, const double* v,
+                           const double* vo, double* vn, MinresScalars* sc, const double* part) {
+    __shared__ double sh[VT / 64];
+    __shared__ double cv[3];
     const int r = blockIdx.y;
-    const double c0 = cw[3 * r], c1 = cw[3 * r + 1], c2 = cw[3 * r + 2];
-    const double d0 = cx[2 * r], d1 = cx[2 * r + 1];
+    const double d = sum_block_partials(part, r, sh);
+    if (threadIdx.x == 0) {
+        MinresScalars m = sc[r];
+        minres_a_core(m, d, cv);
+        if (blockIdx.x == 0) sc[r].delta = m.delta;
+    }
+    __syncthreads();
+    const double c0 = cv[0], c1 = cv[1], c2 = cv[2];
+    const long long off = (long long)r * ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += st) vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
+}
+
+__global__ void k_minres_w(long long n, long long ld, const double* z, const double* wo,
+                           const double* w, double* wn, double* x, const MinresScalars* sc_in,
+                           MinresScalars* sc_out, const double* part, double tol,
+                           MinresScalars* mirror) {
+    __shared__ double sh[VT / 64];
+    __shared__ double cw[3], cx[2];
+    const int r = blockIdx.y;
+    const double d = sum_block_partials(part, r, sh);
+    if (threadIdx.x == 0) {
+        MinresScalars m = sc_in[r];
+        minres_b_core(m, d, cw, cx, tol);
+        if (blockIdx.x == 0) {
+            sc_out[r] = m;
+            if (mirror) mirror[r] = m;
+        }
+    }
+    __syncthreads();
+    const double c0 = cw[0], c1 = cw[1], c2 = cw[2], d0 = cx[0], d1 = cx[1];
     const long long off = (long long)r * ld;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long st = (long long)gridDim.x * blockDim.x;
     for (; i < n; i += st) {
-        double v = c0 * z[off + i];
-        v += c1 * wo[off + i];
-        v += c2 * w[off + i];
+        const double v = c0 * z[off + i] + c1 * wo[off + i] + c2 * w[off + i];
         wn[off + i] = v;
         x[off + i] = d0 * x[off + i] + d1 * v;
     }
@@ -457,21 +479,19 @@ hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int
     hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
     return hipGetLastError();
 }
-hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double* coef_v, int nrhs) {
-    hipLaunchKernelGGL(k_minres_a, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, coef_v, nrhs);
+hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
+                    const double* v, const double* vo, double* vn, MinresScalars* sc,
+                    const double* part) {
+    hipLaunchKernelGGL(k_minres_v, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, kz, v, vo, vn, sc,
+                       part);
     return hipGetLastError();
 }
-hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
-                    double* coef_x, double tol, int nrhs, MinresScalars* mirror) {
-    hipLaunchKernelGGL(k_minres_b, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, coef_w,
-                       coef_x, tol, nrhs, mirror);
-    return hipGetLastError();
-}
-hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
-                         const double* wo, const double* w, const double* cw, double* wn,
-                         double* x, const double* cx) {
-    hipLaunchKernelGGL(k_minres_update, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, z, wo, w,
-                       cw, wn, x, cx);
+hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
+                    const double* wo, const double* w, double* wn, double* x,
+                    const MinresScalars* sc_in, MinresScalars* sc_out, const double* part,
+                    double tol, MinresScalars* mirror) {
+    hipLaunchKernelGGL(k_minres_w, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, z, wo, w, wn, x,
+                       sc_in, sc_out, part, tol, mirror);
     return hipGetLastError();
 }
 hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs) {

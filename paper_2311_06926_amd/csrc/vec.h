@@ -37,14 +37,18 @@ struct MinresScalars {
     int iters, done, status, pad;
 };
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs);
-hipError_t minres_a(hipStream_t s, MinresScalars* sc, const double* part, double* coef_v, int nrhs);
-// mirror: device pointer of a host-mapped copy of sc (or null), refreshed by the kernel
-hipError_t minres_b(hipStream_t s, MinresScalars* sc, const double* part, double* coef_w,
-                    double* coef_x, double tol, int nrhs, MinresScalars* mirror);
-// w_new = cw . (z, w_old, w) and x = cx . (x, w_new), per rhs, in one pass
-hipError_t minres_update(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
-                         const double* wo, const double* w, const double* cw, double* wn,
-                         double* x, const double* cx);
+// v_new = cv . (Kz, v, v_old) with delta and cv formed from the partials of
+// (Kz.z) in every workgroup; records delta in sc
+hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
+                    const double* v, const double* vo, double* vn, MinresScalars* sc,
+                    const double* part);
+// from the partials of (z_new.v_new): the rotation of sc_in, w_new = cw . (z, w_old, w),
+// x += cx1 w_new; the new state goes to sc_out (not sc_in) and to mirror
+// (device pointer of a host-mapped copy, or null)
+hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
+                    const double* wo, const double* w, double* wn, double* x,
+                    const MinresScalars* sc_in, MinresScalars* sc_out, const double* part,
+                    double tol, MinresScalars* mirror);
 // partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
