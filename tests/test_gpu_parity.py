@@ -223,6 +223,27 @@ def test_minres_config1(dev, k):
     sol.close()
 
 
+@pytest.mark.parametrize("m", [1, 2, 3, 7])
+@pytest.mark.parametrize("graph", [True, False])
+def test_minres_iteration_limit_matches_oracle_iterates(dev, m, graph):
+    """MINRES stopped by the iteration limit (tol 0): the GPU iterate after m
+    steps equals the oracle's m-th iterate (the same recurrences), and the
+    solve reports m iterations and HP_ENOCONV."""
+    from oracle.cases import cavity
+    from oracle.krylov import minres
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] MINRES iteration limit m={m} graph={graph}")
+    S, b = cavity(5, 2)
+    ref = minres(lambda v: S.K @ v, HyperPower(S, 2, 1).apply, b, tol=0.0, maxit=m)
+    sol = Solver(5, 2, 1.0, iters=1, maxit=m, use_graph=graph)
+    x, info = sol.solve(sol.build_rhs([1.0]), tol=1e-300, raise_on_noconv=False)
+    assert info.iterations == m and info.converged == 0
+    xs = x.cpu().numpy()
+    assert np.abs(xs[:S.nV] - ref.x[:S.nV]).max() <= 1e-10 * np.abs(ref.x[:S.nV]).max()
+    sol.close()
+
+
 def test_fgmres_matches_oracle(dev):
     from oracle.cases import cavity
     from oracle.krylov import fgmres
