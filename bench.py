@@ -243,6 +243,10 @@ def main():
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="preconditioner precision for --only apply_P0")
+    ap.add_argument("--op-kchunk", type=int, default=0,
+                    help="--only apply_K/apply_P0: force the operator i3-chunk (no autotuning)")
+    ap.add_argument("--op-order", type=int, default=-1,
+                    help="--only apply_K/apply_P0: force the velocity workgroup order")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip mixed/batched/hbm legs")
     ap.add_argument("--no-cpu", action="store_true")
@@ -292,8 +296,11 @@ def main():
         print(json.dumps({"table1": rows}), flush=True)
         return
     if args.only in ("apply_K", "apply_P0"):
+        forced = args.op_kchunk > 0
         sol = Solver(E, p, 1.0, precision=args.prec,
-                     krylov="minres" if args.prec == "fp64" else "fgmres")
+                     krylov="minres" if args.prec == "fp64" else "fgmres",
+                     autotune=not forced, op_kchunk=args.op_kchunk, op_order=args.op_order,
+                     op_slabs=1 if forced else 0)
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
         fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
