@@ -110,6 +110,8 @@ typedef struct hp_opts {
     int schur_pcg_iters;   /* HP_SCHUR_PCG: inner CG steps, 1..1000 (default 20) */
     double schur_pcg_tol;  /* HP_SCHUR_PCG: a right-hand side stops once its
                               sqrt(r.P^{-1}r) has dropped by this factor (default 1e-2) */
+    int op_fused;       /* operator K and A: -1 = tuned/model (default), 0 = the pressure
+                           and velocity kernels, 1 = one single-pass kernel (degree <= 4) */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */

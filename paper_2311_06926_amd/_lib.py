@@ -50,6 +50,7 @@ class hp_opts(ctypes.Structure):
         ("schur_level", ctypes.c_int),
         ("schur_pcg_iters", ctypes.c_int),
         ("schur_pcg_tol", ctypes.c_double),
+        ("op_fused", ctypes.c_int),
     ]
 
 

@@ -1070,6 +1070,7 @@ void hp_default_opts(hp_opts* o) {
     o->fd_plan = -1;
     o->op_slabs = 0;
     o->schur_level = 0;
+    o->op_fused = -1;
     o->schur_pcg_iters = 20;
     o->schur_pcg_tol = 1e-2;
 }
@@ -1101,7 +1102,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
         o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0 || o.schur_level < 0 ||
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
-        o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0))
+        o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
+        o.op_fused < -1 || o.op_fused > 1)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1145,7 +1147,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     // ---- tables
     const int p = degree, wN = p, wM = p - 1;
     const int NNp = pad16(nN), NMp = pad16(nM);
-    size_t nb = (size_t)2 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
+    size_t nb = (size_t)3 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
     // (+32: the dense tables start on a 256-byte boundary, for vector loads)
     size_t nfd = NMp <= 128 ? (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM + 32 : 0;
     if (alloc_device(&c->d_tables, nb + nfd) != HP_OK) { delete ce; return HP_ENOMEM; }
@@ -1154,9 +1156,26 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->band.ptr[BM_N] = tp; upload_band(c->tab.M_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
     c->band.ptr[BM_C] = tp; upload_band(c->tab.Mc, nM, wM, tp); tp += (size_t)nM * (2 * wM + 1);
     c->band.ptr[BT_C] = tp; upload_band(c->tab.Tc, nM, wM, tp); tp += (size_t)nM * (2 * wM + 1);
-    c->band.n[BK_N] = c->band.n[BM_N] = nN;
+    {
+        // D^^T M^: row i = M^ row i - M^ row i+1 (D^^T w at i is w_i - w_{i+1}),
+        // columns i-p+1 .. i+p, stored with half-width p
+        const int W = 2 * wN + 1;
+        std::vector<double> dm((size_t)nN * W, 0.0);
+        auto mc = [&](int rr, int cc) {
+            return (rr >= 0 && rr < nM && cc >= 0 && cc < nM) ? c->tab.Mc[(size_t)rr * nM + cc] : 0.0;
+        };
+        for (int i = 0; i < nN; ++i)
+            for (int t = 0; t < W; ++t) {
+                const int col = i - wN + t;
+                dm[(size_t)i * W + t] = mc(i, col) - mc(i + 1, col);
+            }
+        (void)hipMemcpy(tp, dm.data(), dm.size() * sizeof(double), hipMemcpyHostToDevice);
+        c->band.ptr[BD_M] = tp;
+        tp += (size_t)nN * W;
+    }
+    c->band.n[BK_N] = c->band.n[BM_N] = c->band.n[BD_M] = nN;
     c->band.n[BM_C] = c->band.n[BT_C] = nM;
-    c->band.w[BK_N] = c->band.w[BM_N] = wN;
+    c->band.w[BK_N] = c->band.w[BM_N] = c->band.w[BD_M] = wN;
     c->band.w[BM_C] = c->band.w[BT_C] = wM;
     auto up64 = [&](const std::vector<double>& v) {
         (void)hipMemcpy(tp, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice);

@@ -12,7 +12,9 @@ namespace hp {
 
 // Banded symmetric 1D matrices used by the sum-factorised operators.
 // Row i of band matrix `id` holds A[i][i-w .. i+w] (zeros outside range).
-enum BandId { BK_N = 0, BM_N = 1, BM_C = 2, BT_C = 3, NBAND = 4 };
+// BD_M is D^^T M^ (interior degree-p rows, half-width p): the coupling of a
+// velocity component with z in its own direction.
+enum BandId { BK_N = 0, BM_N = 1, BM_C = 2, BT_C = 3, BD_M = 4, NBAND = 5 };
 
 struct BandTables {
     const double* ptr[NBAND];  // device pointers, row-major n x (2w+1)
@@ -50,6 +52,7 @@ struct OpShape {
     int kchunk = 0;
     int comp_fast = 1;
     int slabs = 1;  // i3-slabs, each running the pressure then the velocity kernel
+    int fused = 0;  // K and A in one single-pass kernel (k_fused)
 };
 struct OpTuned {
     int nrhs = 0;

@@ -12,7 +12,8 @@
 // the degree p-1 ones), so one application costs O(N p) flops and is bound
 // by HBM traffic at large sizes.
 //
-// Two streaming kernels; each reads its inputs and writes its outputs once:
+// Two streaming kernels (the default; a single-pass alternative, k_fused,
+// follows them); each reads its inputs and writes its outputs once:
 //   k_pres : the pressure chain.  g = D u and z = nu g + p are formed while
 //            staging; y_p = M_q g and w = M_q z.
 //   k_vel  : per velocity component, y_c = nu L_c u_c + D_c^T w (with an
@@ -506,6 +507,260 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
 }
 
+// ---- single pass (K and A) ---------------------------------------------------------------
+// With B = D^T M_q the coupling of component c is D_c^T M_q z, z = nu D u + p
+// (z = nu D u for A), which is the Kronecker product of M^ in the two other
+// directions and of D^^T M^ (banded, half-width p) in direction c.  So no w is
+// needed: per i3-plane the kernel stages u1, u2, u3 and p on the tile and a
+// halo of p, forms g = D u and z in LDS, and runs all four outputs through the
+// same scheme as k_vel -- a direction-1 band pass over the tile rows and halo
+// rows, a direction-2 band pass at the thread's point, and direction-3 register
+// windows:
+//   y_1 = alpha ((nu [M^ M^ K + 2 M^ T^ M + 2 T^ M^ M] u_1) + (M^ M^ D^^T M^) z) + beta s_1
+//   (y_2 likewise), y_3 with the own-direction factors in direction 3, and
+//   y_p = M_q g (K only).
+// u is read once and nothing intermediate is written.  The band rows of the
+// tile's columns and rows sit in LDS (registers hold the direction-3 windows).
+template <int P>
+constexpr int fused_lds_doubles() {
+    return 5 * (T2 + 2 * P) * (T1 + 2 * P) + 9 * (T2 + 2 * P) * T1 + 5 * (T1 + T2) * (2 * P + 1);
+}
+
+template <int P>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_fused(
+    OpArgs a, Fields out, Fields src, double alpha, double beta) {
+    constexpr int W = P;                   // staging halo and the widest band
+    constexpr int B = 2 * P + 1;           // band row length (all rows padded to it)
+    constexpr int SW = T1 + 2 * W, SR = T2 + 2 * W;
+    constexpr int NS = (SR * SW + NT - 1) / NT;
+    constexpr int RA = SR * SW;            // a staged array
+    constexpr int RB = SR * T1;            // a direction-1 result
+    __shared__ double lds[fused_lds_doubles<P>()];
+    double* X1 = lds;
+    double* X2 = X1 + RA;
+    double* X3 = X2 + RA;
+    double* ZS = X3 + RA;
+    double* GS = ZS + RA;
+    double* A1 = GS + RA;   // K u1, M u1 (direction 1)
+    double* B1 = A1 + RB;
+    double* Z1 = B1 + RB;   // D^^T M^ z
+    double* A2 = Z1 + RB;   // M^ u2, T^ u2
+    double* B2 = A2 + RB;
+    double* A3 = B2 + RB;   // M^ u3, T^ u3
+    double* B3 = A3 + RB;
+    double* ZM = B3 + RB;   // M^ z (shared by components 2 and 3)
+    double* GM = ZM + RB;   // M^ g
+    double* R1 = GM + RB;   // band rows of the tile's columns: K, M, D^T M^, M^, T^ (x T1)
+    double* R2 = R1 + 5 * T1 * B;  // band rows of the tile's rows (x T2)
+    const int nM = a.nM, nN = a.nN;
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    const int r = id / a.nchunk;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    const int kend = min(min(k0 + a.kchunk, a.klim), nM);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const bool use_p = (a.mode == OP_K);
+    const double nu = a.nu;
+    const double* u1 = a.u[0] + (long long)r * a.su;
+    const double* u2 = a.u[1] + (long long)r * a.su;
+    const double* u3 = a.u[2] + (long long)r * a.su;
+    const double* pp = use_p ? a.p + (long long)r * a.sp : u1;
+    const long long P1 = (long long)nN * nM, P3 = (long long)nM * nM;
+    const uint32_t B1b = 8u * (uint32_t)P1, B3b = 8u * (uint32_t)P3;
+    const uint32_t BPb = use_p ? B3b : 0u;
+    // band rows into LDS: R1[b][c][t] for the column index i0 + c, R2[b][g][t]
+    // for the row index j0 + g; b = K, M (interior, n_N), D^T M^ (n_N), M^, T^ (n_M,
+    // half-width p-1, stored shifted by one)
+    for (int e = threadIdx.x; e < 5 * (T1 + T2) * B; e += NT) {
+        const int t = e % B, q = e / B;
+        const bool col = q < 5 * T1;
+        const int qq = col ? q : q - 5 * T1;
+        const int b = col ? qq / T1 : qq / T2;
+        const int idx = (col ? i0 + qq % T1 : j0 + qq % T2);
+        double v = 0.0;
+        if (b <= 2) {
+            const int tab = b == 0 ? BK_N : (b == 1 ? BM_N : BD_M);
+            if (idx < nN) v = a.bt.ptr[tab][(long long)idx * B + t];
+        } else {
+            const int tab = b == 3 ? BM_C : BT_C;
+            if (idx < nM && t >= 1 && t <= 2 * P - 1) v = a.bt.ptr[tab][(long long)idx * (B - 2) + t - 1];
+        }
+        if (col) R1[q * B + t] = v;
+        else R2[qq * B + t] = v;
+    }
+    // staging offsets (as k_pres): u1[ii], u1[ii-1], u2[jj], u2[jj-1], u3 / p at (ii, jj)
+    uint32_t oa[NS], ob[NS], oc[NS], od[NS], oe[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int idx = threadIdx.x + s * NT;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W + rr, ii = i0 - W + cc;
+        const bool ok = idx < RA && jj >= 0 && jj < nM && ii >= 0 && ii < nM;
+        oa[s] = (ok && ii < nN) ? 8u * (nN * jj + ii) : OOB;
+        ob[s] = (ok && ii >= 1) ? 8u * (nN * jj + ii - 1) : OOB;
+        oc[s] = (ok && jj < nN) ? 8u * (ii + nM * jj) : OOB;
+        od[s] = (ok && jj >= 1) ? 8u * (ii + nM * (jj - 1)) : OOB;
+        oe[s] = ok ? 8u * (ii + nM * jj) : OOB;
+    }
+    auto fetch = [&](int kk, double (&v)[NS][6]) {
+        const bool kin = kk >= 0 && kk < nM;
+        const bool k3in = kk >= 0 && kk < nN;
+        const int kc = kin ? kk : 0, k3 = k3in ? kk : 0;
+        const auto r1 = make_rsrc(u1 + P1 * kc, kin ? B1b : 0u);
+        const auto r2 = make_rsrc(u2 + P1 * kc, kin ? B1b : 0u);
+        const auto r3 = make_rsrc(u3 + P3 * k3, k3in ? B3b : 0u);
+        const auto rp = make_rsrc(pp + P3 * kc, kin ? BPb : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v[s][0] = bload(r1, oa[s]);
+            v[s][1] = bload(r1, ob[s]);
+            v[s][2] = bload(r2, oc[s]);
+            v[s][3] = bload(r2, od[s]);
+            v[s][4] = bload(r3, oe[s]);
+            v[s][5] = bload(rp, oe[s]);
+        }
+    };
+    // outputs: component planes and this thread's offsets (OOB where no output)
+    const uint32_t o1 = (i < nN && j < nM) ? 8u * (i + nN * j) : OOB;
+    const uint32_t o2 = (i < nM && j < nN) ? 8u * (i + nM * j) : OOB;
+    const uint32_t o3 = (i < nM && j < nM) ? 8u * (i + nM * j) : OOB;
+    double* y1 = out.f[0] + (long long)r * out.stride[0];
+    double* y2 = out.f[1] + (long long)r * out.stride[1];
+    double* y3 = out.f[2] + (long long)r * out.stride[2];
+    double* yp = use_p ? out.f[3] + (long long)r * out.stride[3] : y3;
+    const bool has_src = beta != 0.0;
+    const double* s1 = has_src ? src.f[0] + (long long)r * src.stride[0] : y1;
+    const double* s2 = has_src ? src.f[1] + (long long)r * src.stride[1] : y2;
+    const double* s3 = has_src ? src.f[2] + (long long)r * src.stride[2] : y3;
+    const uint32_t SB1 = has_src ? B1b : 0u, SB3 = has_src ? B3b : 0u;
+    const uint32_t YPB = use_p ? B3b : 0u;
+    Window<P - 1> wa1, wb1, wa2, wb2, wp;
+    Window<P> wa3, wb3, wz3;
+    wa1.clear(); wb1.clear(); wa2.clear(); wb2.clear(); wp.clear();
+    wa3.clear(); wb3.clear(); wz3.clear();
+    double buf[NS][6], a3prev[NS];
+    {
+        double t[NS][6];
+        fetch(k0 - W - 1, t);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) a3prev[s] = t[s][4];
+    }
+    fetch(k0 - W, buf);
+    for (int kk = k0 - W; kk < kend + W; ++kk) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int idx = threadIdx.x + s * NT;
+            if (idx < RA) {
+                const double gv = (buf[s][0] - buf[s][1]) + (buf[s][2] - buf[s][3]) + (buf[s][4] - a3prev[s]);
+                X1[idx] = buf[s][0];
+                X2[idx] = buf[s][2];
+                X3[idx] = buf[s][4];
+                GS[idx] = gv;
+                ZS[idx] = nu * gv + buf[s][5];
+            }
+            a3prev[s] = buf[s][4];
+        }
+        fetch(kk + 1, buf);
+        __syncthreads();
+        // direction 1 over the tile rows and halo rows
+        {
+            const double* rk = R1 + (0 * T1 + c) * B;
+            const double* rm = R1 + (1 * T1 + c) * B;
+            const double* rd = R1 + (2 * T1 + c) * B;
+            const double* rc = R1 + (3 * T1 + c) * B;
+            const double* rt = R1 + (4 * T1 + c) * B;
+            for (int rr = g; rr < SR; rr += T2) {
+                double sk = 0.0, sm = 0.0, sd = 0.0, sz = 0.0, s2m = 0.0, s2t = 0.0, s3m = 0.0,
+                       s3t = 0.0, sg = 0.0;
+#pragma unroll
+                for (int t = 0; t < B; ++t) {
+                    const int o = rr * SW + c + t;
+                    const double x1 = X1[o], x2 = X2[o], x3 = X3[o], zv = ZS[o], gv = GS[o];
+                    const double ck = rk[t], cm = rm[t], cd = rd[t], cc = rc[t], ct = rt[t];
+                    sk += ck * x1;
+                    sm += cm * x1;
+                    sd += cd * zv;
+                    sz += cc * zv;
+                    s2m += cc * x2;
+                    s2t += ct * x2;
+                    s3m += cc * x3;
+                    s3t += ct * x3;
+                    sg += cc * gv;
+                }
+                const int o = rr * T1 + c;
+                A1[o] = sk;
+                B1[o] = sm;
+                Z1[o] = sd;
+                ZM[o] = sz;
+                A2[o] = s2m;
+                B2[o] = s2t;
+                A3[o] = s3m;
+                B3[o] = s3t;
+                GM[o] = sg;
+            }
+        }
+        __syncthreads();
+        // direction 2 at this thread's point; push into the direction-3 windows
+        {
+            const double* qk = R2 + (0 * T2 + g) * B;
+            const double* qm = R2 + (1 * T2 + g) * B;
+            const double* qd = R2 + (2 * T2 + g) * B;
+            const double* qc = R2 + (3 * T2 + g) * B;
+            const double* qt = R2 + (4 * T2 + g) * B;
+            double am1 = 0, ak1 = 0, bm1 = 0, bk1 = 0, zz1 = 0;
+            double am2 = 0, ak2 = 0, bm2 = 0, zz2 = 0;
+            double am3 = 0, ak3 = 0, bm3 = 0, zz3 = 0, gp = 0;
+#pragma unroll
+            for (int t = 0; t < B; ++t) {
+                const int o = (g + t) * T1 + c;
+                const double cc = qc[t], ct = qt[t], ck = qk[t], cm = qm[t], cd = qd[t];
+                const double va1 = A1[o], vb1 = B1[o], vz1 = Z1[o];
+                const double va2 = A2[o], vb2 = B2[o], vzm = ZM[o];
+                const double va3 = A3[o], vb3 = B3[o], vg = GM[o];
+                am1 += cc * va1; ak1 += ct * va1; bm1 += cc * vb1; bk1 += ct * vb1; zz1 += cc * vz1;
+                am2 += cm * va2; ak2 += ck * va2; bm2 += cm * vb2; zz2 += cd * vzm;
+                am3 += cc * va3; ak3 += ct * va3; bm3 += cc * vb3; zz3 += cc * vzm;
+                gp += cc * vg;
+            }
+            wa1.push(nu * (am1 + 2.0 * bk1) + zz1);
+            wb1.push(2.0 * bm1);
+            wa2.push(nu * (ak2 + 2.0 * bm2) + zz2);
+            wb2.push(2.0 * am2);
+            wa3.push(am3);
+            wb3.push(2.0 * (ak3 + bm3));
+            wz3.push(zz3);
+            wp.push(gp);
+        }
+        // outputs: components 1, 2 and the pressure p-1 planes behind, component 3 p behind
+        {
+            const int k = kk - (P - 1);
+            if (k >= k0 && k < kend) {
+                const double* rmc = a.bt.ptr[BM_C] + k * (2 * P - 1);
+                const double* rtc = a.bt.ptr[BT_C] + k * (2 * P - 1);
+                const double v1 = wa1.dot(rmc) + nu * wb1.dot(rtc);
+                const double v2 = wa2.dot(rmc) + nu * wb2.dot(rtc);
+                const double e1 = bload(make_rsrc(s1 + P1 * k, SB1), o1);
+                const double e2 = bload(make_rsrc(s2 + P1 * k, SB1), o2);
+                bstore(make_rsrc(y1 + P1 * k, B1b), o1, alpha * v1 + beta * e1);
+                bstore(make_rsrc(y2 + P1 * k, B1b), o2, alpha * v2 + beta * e2);
+                bstore(make_rsrc(yp + P3 * k, YPB), o3, wp.dot(rmc));
+            }
+            const int k3 = kk - P;
+            if (k3 >= k0 && k3 < kend && k3 < nN) {
+                const double v3 = nu * (wa3.dot(a.bt.ptr[BK_N] + k3 * B) + wb3.dot(a.bt.ptr[BM_N] + k3 * B)) +
+                                  wz3.dot(a.bt.ptr[BD_M] + k3 * B);
+                const double e3 = bload(make_rsrc(s3 + P3 * k3, SB3), o3);
+                bstore(make_rsrc(y3 + P3 * k3, B3b), o3, alpha * v3 + beta * e3);
+            }
+        }
+    }
+}
+
 template <int P>
 void launch_pres(dim3 grid, hipStream_t st, const OpArgs& a, double* yp, long long syp) {
     hipLaunchKernelGGL(k_pres<P>, grid, dim3(NT), 0, st, a, yp, syp);
@@ -516,6 +771,19 @@ void launch_vel(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, c
                 double alpha, double beta) {
     hipLaunchKernelGGL(k_vel<P>, grid, dim3(NT), 0, st, a, out, s, alpha, beta);
 }
+
+template <int P>
+void launch_fused(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
+                  double alpha, double beta) {
+    hipLaunchKernelGGL(k_fused<P>, grid, dim3(NT), 0, st, a, out, s, alpha, beta);
+}
+using FusedLaunch = void (*)(dim3, hipStream_t, const OpArgs&, const Fields&, const Fields&, double,
+                             double);
+// the single-pass kernel for degrees 2..4 (its windows and staging fill the
+// register file beyond)
+constexpr int FUSED_PMAX = 4;
+const FusedLaunch fused_launch[FUSED_PMAX + 1] = {nullptr, nullptr, launch_fused<2>,
+                                                  launch_fused<3>, launch_fused<4>};
 
 // instantiations per degree 2..8 (index = degree)
 using PresLaunch = void (*)(dim3, hipStream_t, const OpArgs&, double*, long long);
@@ -565,7 +833,9 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
     if (c->opts.op_kchunk > 0) sh.kchunk = c->opts.op_kchunk;
     if (c->opts.op_slabs > 0) sh.slabs = c->opts.op_slabs;
     if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
+    if (c->opts.op_fused >= 0) sh.fused = c->opts.op_fused;
     if (c->op_force.kchunk > 0) sh = c->op_force;
+    if (c->p > FUSED_PMAX) sh.fused = 0;
     return sh;
 }
 
@@ -613,6 +883,14 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         dim3 grid(a.nblocks);
         vel_launch[P](grid, c->stream, a, out, s, alpha, beta);
     };
+    if (sh.fused && (mode == OP_K || mode == OP_A)) {
+        a.kbase = 0;
+        a.klim = nM;
+        a.nchunk = (nM + a.kchunk - 1) / a.kchunk;
+        a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
+        fused_launch[P](dim3(a.nblocks), c->stream, a, out, s, alpha, beta);
+        return hipGetLastError();
+    }
     if (mode == OP_BT) {
         pres(0, nM);
     } else if (mode == OP_MV) {

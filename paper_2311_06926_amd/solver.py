@@ -36,7 +36,7 @@ class Solver:
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
-                 schur_pcg_iters=20, schur_pcg_tol=1e-2, device=None):
+                 schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -63,6 +63,7 @@ class Solver:
         o.schur_level = schur_level
         o.schur_pcg_iters = schur_pcg_iters
         o.schur_pcg_tol = schur_pcg_tol
+        o.op_fused = op_fused
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):

@@ -10,6 +10,7 @@
   and of the pressure block, M_q y_p = 2 nu x_p, on sampled rows.
 * The solve at 32^3 (q = 2, k = 1, MINRES): the oracle's lid right-hand side
   in, and on sampled rows |b - K x|_i <= ||b - K x||_2 <= tol ||b||_2.
+* The single-pass operator kernel against the two-kernel path and the oracle.
 * Launch shapes: every i3-chunk length and workgroup order, and every P_0
   plan that fits, gives the same result (bit for bit for the operators,
   whose per-point arithmetic does not depend on the shape; within the P_0
@@ -139,6 +140,33 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
                     assert torch.equal(a, b), (kc, order, slabs)
                 s.close()
     base.close()
+
+
+@pytest.mark.parametrize("E,p", [(3, 2), (8, 3), (13, 2), (4, 4), (33, 3)])
+def test_single_pass_operator_matches(dev, E, p):
+    """The single-pass kernel (op_fused=1: D_c^T M_q z applied as a Kronecker
+    product, no w) against the two-kernel path and, at the small meshes, the
+    oracle: K, A, the A-residual of P_1, single and batched."""
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[shapes] single-pass operator E={E} p={p}")
+    nu = 0.7
+    two = Solver(E, p, nu, autotune=False, op_fused=0, max_rhs=2)
+    one = Solver(E, p, nu, autotune=False, op_fused=1, max_rhs=2)
+    for nr in (1, 2):
+        x = torch.from_numpy(synth.random_vector(nr * two.N, seed=E + p + nr)).to(dev)
+        u = torch.from_numpy(synth.random_vector(nr * two.nV, seed=5 + E)).to(dev)
+        for a, b in ((two.apply_K(x), one.apply_K(x)), (two.apply_A(u), one.apply_A(u)),
+                     (two.apply_hyperpower(2, 1, x), one.apply_hyperpower(2, 1, x))):
+            assert float((a - b).abs().max() / a.abs().max()) < 1e-14
+    if E <= 13:
+        from oracle.assemble import KronSystem
+        S = KronSystem(E, p, nu)
+        xh = synth.random_vector(S.N, seed=7)
+        y = one.apply_K(torch.from_numpy(xh).to(dev)).cpu().numpy()
+        ref = S.K @ xh
+        assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-12
+    two.close()
+    one.close()
 
 
 @pytest.mark.parametrize("E,p", [(8, 3), (13, 2), (4, 4)])
