@@ -8,6 +8,7 @@
   relative to max |K x|, as for the small meshes.
 * P_0 at 32^3: the backward error of each velocity block, A_cc y_c = x_c,
   and of the pressure block, M_q y_p = 2 nu x_p, on sampled rows.
+* P_1 at 32^3 through its definition with the separately checked operators.
 * The solve at 32^3 (q = 2, k = 1, MINRES): the oracle's lid right-hand side
   in, and on sampled rows |b - K x|_i <= ||b - K x||_2 <= tol ||b||_2.
 * The single-pass operator kernel against the two-kernel path and the oracle.
@@ -92,6 +93,45 @@ def test_P0_full_size_backward_error(dev):
     loc = np.unique(np.concatenate([rng.integers(0, nq, 800), [0, nq - 1]]))
     r = R.mass_q_entries(y[o[3]:], loc) - 2.0 * nu * x[o[3] + loc]
     assert np.abs(r).max() <= 1e-10 * 2.0 * nu * np.abs(x[o[3]:]).max()
+    sol.close()
+
+
+def test_hyperpower_full_size_composition(dev):
+    """P_1 (q = 2, eq. Pcq1) at 32^3, degree 3, in the benchmark's launch
+    configuration, checked through its definition with the separately
+    verified operators (apply_A/B/Bt against the oracle's rows, P_0 by its
+    backward error): velocity y = X0 (2x - A X0 x), pressure
+    y = Q0 (2x - B' X0 B Q0 x) with X0 = P_{V,0}^{-1}, Q0 = P_{Q,0}^{-1}."""
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 32, 3
+    say(f"[fullsize] P_1 composition E={E} p={p}")
+    sol = Solver(E, p, 1.0)
+    nV, N = sol.nV, sol.N
+    x = torch.from_numpy(synth.random_vector(N, seed=17)).to(dev)
+    y = sol.apply_hyperpower(2, 1, x)
+
+    def P0(v):
+        return sol.apply_P0(v)
+
+    def vel(v):
+        full = torch.zeros(N, dtype=torch.float64, device=dev)
+        full[:nV] = v
+        return P0(full)[:nV]
+
+    def pres(q):
+        full = torch.zeros(N, dtype=torch.float64, device=dev)
+        full[nV:] = q
+        return P0(full)[nV:]
+
+    xv, xq = x[:nV].contiguous(), x[nV:].contiguous()
+    y0 = vel(xv)
+    yv = vel(2 * xv - sol.apply_A(y0))
+    t = pres(xq)
+    yq = pres(2 * xq - sol.apply_Bt(vel(sol.apply_B(t))))
+    ev = float((y[:nV] - yv).abs().max() / yv.abs().max())
+    eq = float((y[nV:] - yq).abs().max() / yq.abs().max())
+    say(f"[fullsize]   velocity {ev:.2e}, pressure {eq:.2e}")
+    assert ev < 1e-12 and eq < 1e-12
     sol.close()
 
 
