@@ -16,6 +16,8 @@
   plan that fits, gives the same result (bit for bit for the operators,
   whose per-point arithmetic does not depend on the shape; within the P_0
   tolerance for the plans); the autotuner reports shapes in range.
+* The mixed-precision solve at 64^3 and the batched solve at 48^3 x 32: residual
+  rows against the oracle's rows of K.
 * The differentiable solve at 96^3 (FP32 P_k in FP64 FGMRES): adjoint
   gradients against central differences with step 1e-6.
 """
@@ -150,6 +152,58 @@ def test_solve_full_size_residual_on_samples(dev):
     idx = samples(R.offsets, 3000, seed=9)
     r = b[idx] - R.rows(x, idx)
     assert np.abs(r).max() <= 1.01 * tol * np.linalg.norm(b)
+    sol.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_solve_full_size(dev, prec):
+    """The mixed-precision workload (64^3, degree 3, FGMRES(50) in FP64 with
+    P_1 in FP32 or split BF16): the oracle's lid right-hand side in, and on
+    sampled rows |b - K x|_i <= tol ||b||_2 with the oracle's rows of K."""
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, tol = 64, 3, 1e-8
+    say(f"[fullsize] mixed-precision solve E={E} p={p} {prec}")
+    R = KronRows(E, p, 1.0)
+    b = R.lid_rhs(1.0)
+    sol = Solver(E, p, 1.0, krylov="fgmres", precision=prec, iters=1)
+    xg, info = sol.solve(torch.from_numpy(b).to(dev), tol)
+    x = xg.cpu().numpy()
+    say(f"[fullsize]   {info.iterations} iterations, true relres {info.true_relres:.2e}")
+    assert info.converged and info.true_relres <= 1.01 * tol
+    idx = samples(R.offsets, 2000, seed=64)
+    r = b[idx] - R.rows(x, idx)
+    assert np.abs(r).max() <= 1.01 * tol * np.linalg.norm(b)
+    sol.close()
+
+
+def test_batched_solve_full_size(dev):
+    """The batched workload (48^3, degree 2, 32 seeded right-hand sides, one
+    FGMRES with P_1 in FP32): for four of the systems, sampled rows of
+    b_r - K x_r against the oracle's rows of K."""
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, nr, tol = 48, 2, 32, 1e-8
+    say(f"[fullsize] batched solve E={E} p={p} nrhs={nr}")
+    lids, amps, wavs = [], [], []
+    for r in range(nr):
+        modes, U = synth.body_force_modes(r)
+        a, w = synth.modes_to_arrays(modes)
+        lids.append(U)
+        amps.append(a)
+        wavs.append(w)
+    sol = Solver(E, p, 1.0, krylov="fgmres", precision="fp32", iters=1, max_rhs=nr)
+    bg = sol.build_rhs(np.array(lids), (np.stack(amps), np.stack(wavs)))
+    xg, info = sol.solve(bg, tol)
+    say(f"[fullsize]   {info.iterations} iterations, true relres {info.true_relres:.2e}")
+    assert info.converged and info.true_relres <= 1.01 * tol
+    R = KronRows(E, p, 1.0)
+    b = bg.cpu().numpy().reshape(nr, sol.N)
+    x = xg.cpu().numpy().reshape(nr, sol.N)
+    for r in (0, 7, 19, 31):
+        idx = samples(R.offsets, 800, seed=100 + r)
+        res = b[r, idx] - R.rows(x[r], idx)
+        assert np.abs(res).max() <= 1.01 * tol * np.linalg.norm(b[r]), r
     sol.close()
 
 
