@@ -99,7 +99,9 @@ typedef struct hp_opts {
     int op_order;       /* operator kernels: velocity workgroup order, -1 = tuned/model,
                            0 = tiles fastest, 1 = components fastest */
     int fd_plan;        /* P_0 kernels: -1 = tuned/default, else bit 0 = 16-wave
-                           kernels, bit 1 = 1D matrices staged in LDS (if they fit) */
+                           kernels, bit 1 = 1D matrices staged in LDS (if they fit),
+                           bit 2 = 2x2 blocks of MFMA tiles per wave (16-wave plans,
+                           FP64/FP32) */
     int op_slabs;       /* operator: i3-slabs run one after the other (pressure chain
                            then velocity per slab), 0 = tuned/model */
     int schur_level;    /* eq. Pcq2 only: the fixed P_{V,l} inside B' P_{V,l}^{-1} B,

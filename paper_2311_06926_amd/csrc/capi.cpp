@@ -881,7 +881,7 @@ hp_status autotune(hp_ctx* c) {
     for (int prec = 0; prec < 3 && st == HP_OK && c->fd_ok && c->opts.fd_plan < 0; ++prec) {
         double best = -1.0;
         int best_plan = -1;
-        for (int plan = 0; plan <= 3; ++plan) {
+        for (int plan = 0; plan <= 7; ++plan) {
             if (!fd_plan_valid(c, prec, plan)) continue;
             c->fd_force = plan;
             const double us = time_launches(c, e0, e1, 3, [&]() {
@@ -1100,7 +1100,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen >= 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
-        o.fd_plan < -1 || o.fd_plan > 3 || o.op_slabs < 0 || o.schur_level < 0 ||
+        o.fd_plan < -1 || o.fd_plan > 7 || o.op_slabs < 0 || o.schur_level < 0 ||
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1)

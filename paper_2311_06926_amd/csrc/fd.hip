@@ -374,6 +374,46 @@ __device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* G, int ldg, co
     return acc;
 }
 
+// A 2x2 block of tile products: row tiles G0, G1 (G1 used when g1) and column
+// tiles H0, H1 (when h1), each operand fragment loaded once for two MFMAs.
+template <typename T, bool GA>
+__device__ __forceinline__ void tile_gemm_2x2(const T* G0, const T* G1, int ldg, const T* H0,
+                                              const T* H1, int h_k, int h_i, int K, int lr, int lk,
+                                              bool g1, bool h1,
+                                              typename Mfma<T>::V (&acc)[2][2]) {
+    using M = Mfma<T>;
+    using V4 = typename Vec4T<T>::V;
+    const T* gp0 = G0 + lr * ldg + 4 * lk;
+    const T* gp1 = G1 + lr * ldg + 4 * lk;
+    const T* hp0 = H0 + lr * h_i + 4 * lk * h_k;
+    const T* hp1 = H1 + lr * h_i + 4 * lk * h_k;
+    V4 ga[2], gb[2];
+    ga[0] = *reinterpret_cast<const V4*>(gp0);
+    gb[0] = g1 ? *reinterpret_cast<const V4*>(gp1) : ga[0];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        if (16 * c >= K) break;
+        if (16 * (c + 1) < K) {
+            ga[(c + 1) & 1] = *reinterpret_cast<const V4*>(gp0 + 16 * (c + 1));
+            gb[(c + 1) & 1] = g1 ? *reinterpret_cast<const V4*>(gp1 + 16 * (c + 1)) : ga[(c + 1) & 1];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const T x0 = hp0[(16 * c + s) * h_k];
+            const T x1 = h1 ? hp1[(16 * c + s) * h_k] : x0;
+            const T a0 = ga[c & 1][s], a1 = gb[c & 1][s];
+            acc[0][0] = GA ? M::mma(a0, x0, acc[0][0]) : M::mma(x0, a0, acc[0][0]);
+            acc[0][1] = GA ? M::mma(a0, x1, acc[0][1]) : M::mma(x1, a0, acc[0][1]);
+            acc[1][0] = GA ? M::mma(a1, x0, acc[1][0]) : M::mma(x0, a1, acc[1][0]);
+            acc[1][1] = GA ? M::mma(a1, x1, acc[1][1]) : M::mma(x1, a1, acc[1][1]);
+        }
+    }
+}
+
 // Split-BF16 ("bf16x3") product for FP32 data: each operand is written as
 // hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even), and
 // A B ~= A_hi B_hi + A_hi B_lo + A_lo B_hi, three 16x16x16 BF16 MFMAs per
@@ -438,7 +478,7 @@ __device__ __forceinline__ typename Mfma<T>::V tile_mm(const T* G, int ldg, cons
 // dense 1D matrices, or lets FP64 planes up to 128 x 128 use 16 waves).
 constexpr int XY_MT = 4;        // tiles per wave: 8 x 8 tiles over 16 waves
 
-template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false>
+template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false, bool BLK = false>
 __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     using V = typename M::V;
@@ -478,6 +518,64 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
         Rt = Rs;
     }
     __syncthreads();
+    if constexpr (!SPLIT && BLK) {
+        {
+            // 2x2 blocks of tiles per wave: each operand fragment feeds two MFMAs
+            const int nbb1 = (nb1 + 1) >> 1, nbb2 = (nb2 + 1) >> 1;
+            const int nblk = nbb1 * nbb2;
+            V bacc[2][2];
+            const bool mine = wave < nblk;  // 16 waves cover up to 4 x 4 blocks
+            const int RB = mine ? wave % nbb1 : 0, CB = mine ? wave / nbb1 : 0;
+            const bool g1 = 2 * RB + 1 < nb1, h1 = 2 * CB + 1 < nb2;
+            if (mine)
+                tile_gemm_2x2<T, true>(L + 2 * RB * 16 * ldL, L + (2 * RB + 1) * 16 * ldL, ldL,
+                                       S + 2 * CB * 16 * ld, S + (2 * CB + 1) * 16 * ld, 1, ld, N1,
+                                       lr, lk, g1, h1, bacc);
+            __syncthreads();
+            if (mine)
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        if ((ii && !g1) || (jj && !h1)) continue;
+                        const int rb = 2 * RB + ii, cb = 2 * CB + jj;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = bacc[ii][jj][i];
+                    }
+            __syncthreads();
+            // step 2: Y = T R; block (RB2, CB2): G from R^T rows cb, H from T rows rb
+            const int nbr = (nb1 + 1) >> 1, nbc = (nb2 + 1) >> 1;
+            const bool mine2 = wave < nbr * nbc;
+            const int RB2 = mine2 ? wave % nbr : 0, CB2 = mine2 ? wave / nbr : 0;
+            const bool gc1 = 2 * CB2 + 1 < nb2, hr1 = 2 * RB2 + 1 < nb1;
+            if (mine2)
+                tile_gemm_2x2<T, false>(Rt + 2 * CB2 * 16 * ldR, Rt + (2 * CB2 + 1) * 16 * ldR, ldR,
+                                        S + 2 * RB2 * 16, S + (2 * RB2 + 1) * 16, ld, 1, N2, lr, lk,
+                                        gc1, hr1, bacc);
+            __syncthreads();
+            if (mine2)
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        if ((ii && !gc1) || (jj && !hr1)) continue;
+                        const int cb = 2 * CB2 + ii, rb = 2 * RB2 + jj;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = bacc[ii][jj][i];
+                    }
+            __syncthreads();
+            TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
+            for (int idx = threadIdx.x; idx < n1 * n2; idx += FD_WIDE) {
+                int col = idx / n1, row = idx - col * n1;
+                TO v = (TO)S[col * ld + row];
+                if (a.accumulate) y[idx] += v;
+                else y[idx] = v;
+            }
+            return;
+        }
+    }
     const int ntile = nb1 * nb2;
     V acc[XY_MT];
     // step 1: T = L X  (tile (rb, cb): rows of L, columns of X)
@@ -625,13 +723,14 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
 // LDS plan for a direction of padded size np: wide (two buffers) or in place,
 // and whether the dense 1D matrices are staged in LDS as well.
 struct FDPlan {
-    bool wide, stage_xy, stage_z;
+    bool wide, stage_xy, stage_z, block;
     size_t shm_xy, shm_z;
 };
 
 // The plan of plan code `code` (bit 0: wide kernels, bit 1: stage the 1D
-// matrices in LDS when they fit); code < 0 gives the default plan: wide when
-// two planes fit in LDS, staging when it leaves room for a second workgroup.
+// matrices in LDS when they fit, bit 2: 2x2 blocks of MFMA tiles per wave in
+// the wide xy kernel); code < 0 gives the default plan: wide when two planes
+// fit in LDS, staging when it leaves room for a second workgroup.
 template <typename T>
 FDPlan fd_plan(int np, int code) {
     // wide kernels: the xy kernel transforms one plane in place (one plane of
@@ -654,6 +753,7 @@ FDPlan fd_plan(int np, int code) {
         pl.wide = (code & 1) != 0;
         pl.stage_xy = (code & 2) && plane + mats <= lim;
         pl.stage_z = (code & 2) && (pl.wide ? 2 : 1) * zbuf + mats <= lim;
+        pl.block = (code & 4) && pl.wide;
     }
     pl.shm_xy = plane + (pl.stage_xy ? mats : 0);
     pl.shm_z = (pl.wide ? 2 : 1) * zbuf + (pl.stage_z ? mats : 0);
@@ -663,7 +763,8 @@ FDPlan fd_plan(int np, int code) {
 template <typename T>
 bool fd_plan_fits(int np, int code) {
     if (code < 0) return true;
-    if (code > 3) return false;
+    if (code > 7) return false;
+    if ((code & 4) && !(code & 1)) return false;  // blocking exists in the wide kernel only
     const size_t lim = 160 * 1024, e = sizeof(T);
     const size_t plane = (size_t)np * (np + 1) * e, zbuf = (size_t)ZROWS * (np + 1) * e;
     // a staging plan must actually stage something to differ from its pair
@@ -700,7 +801,15 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     const dim3 bxy(pl.wide ? FD_WIDE : FD_THREADS);
     auto launch_xy = [&](const XYArgs& xa_, bool to_double, int nfields) {
         dim3 g(nM, nfields * nrhs);
-        if (pl.wide) {
+        if (pl.wide && pl.block && !SPLIT) {
+            if (to_double) {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            } else {
+                if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, double, T, true, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+                else hipLaunchKernelGGL((k_fd_xy_w<T, double, T, false, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
+            }
+        } else if (pl.wide) {
             if (to_double) {
                 if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
                 else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false, SPLIT>), g, bxy, pl.shm_xy, c->stream, xa_, t);
@@ -809,6 +918,10 @@ hipError_t set_fd_attrs() {
         reinterpret_cast<const void*>(&k_fd_xy_w<T, double, T, false>),
         reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, true>),
         reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, false>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, double, T, true, false, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, double, T, false, false, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, true, false, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_w<T, T, double, false, false, true>),
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, true>),
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, false>),
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, true>),
@@ -845,6 +958,7 @@ hipError_t fd_init_attributes() {
 
 bool fd_plan_valid(const hp_ctx* c, int precision, int plan) {
     const int NMp = (c->nM + 15) & ~15;
+    if (precision == HP_PREC_BF16X3 && plan >= 0 && (plan & 4)) return false;  // not blocked
     return precision == HP_PREC_FP64 ? fd_plan_fits<double>(NMp, plan) : fd_plan_fits<float>(NMp, plan);
 }
 
