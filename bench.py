@@ -244,9 +244,11 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="preconditioner precision for --only apply_P0")
     ap.add_argument("--op-kchunk", type=int, default=0,
-                    help="--only apply_K/apply_P0: force the operator i3-chunk (no autotuning)")
+                    help="--only solve/apply_K/apply_P0: force the operator i3-chunk (no autotuning)")
     ap.add_argument("--op-order", type=int, default=-1,
-                    help="--only apply_K/apply_P0: force the velocity workgroup order")
+                    help="--only solve/apply_K/apply_P0: force the velocity workgroup order")
+    ap.add_argument("--fd-plan", type=int, default=-1,
+                    help="--only solve/apply_P0: force the fast-diagonalisation plan (-1: tuned)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip mixed/batched/hbm legs")
     ap.add_argument("--no-cpu", action="store_true")
@@ -300,7 +302,7 @@ def main():
         sol = Solver(E, p, 1.0, precision=args.prec,
                      krylov="minres" if args.prec == "fp64" else "fgmres",
                      autotune=not forced, op_kchunk=args.op_kchunk, op_order=args.op_order,
-                     op_slabs=1 if forced else 0)
+                     op_slabs=1 if forced else 0, fd_plan=args.fd_plan)
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
         fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
@@ -310,13 +312,16 @@ def main():
         return
 
     log(f"[bench] setup E={E} p={p} q={q} k={k} N={N}")
-    sol = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur)
+    forced = args.op_kchunk > 0
+    sol = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, fd_plan=args.fd_plan,
+                 op_kchunk=args.op_kchunk, op_order=args.op_order, op_slabs=1 if forced else 0)
     stream = sol.stream
     b = sol.build_rhs([1.0])
     x, info = sol.solve(b, 1e-8)
     for _ in range(args.warmup):
         x, info = sol.solve(b, 1e-8, x=x)
-    log(f"[bench] warmup done: {info.iterations} iterations, true relres {info.true_relres:.2e}")
+    log(f"[bench] warmup done: {info.iterations} iterations, true relres {info.true_relres:.2e}, "
+        f"tuning {sol.tuning(1)}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -353,6 +358,18 @@ def main():
         "traffic": pmc_traffic(f"apply_P0_E{E}p{p}_pmc.txt", ["fd.hip"]),
         "algorithmic_flops_per_launch": flops, "avg_launch_us": t_P0 * 1e6,
     }
+
+    # ---- the same solve with each iteration replayed as a captured HIP graph
+    # against direct launches (the default; identical results)
+    modes = {}
+    if not args.no_sweep:
+        for g in (True, False):
+            s2 = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, use_graph=g)
+            b2 = s2.build_rhs([1.0])
+            _, inf2, t2 = timed_solve(s2, b2, 5)
+            modes["graph" if g else "direct"] = {"iterations": inf2.iterations, "ms": 1e3 * t2}
+            s2.close()
+        log(f"[bench] launch modes: {modes}")
 
     # ---- sweep q x k
     sweep = {}
@@ -545,6 +562,7 @@ def main():
         "operators": ops,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "launch_modes": modes,
         "sweep": sweep,
         "spectra": spectra,
         "schur_options": schur_opts,

@@ -60,6 +60,10 @@ struct Extra {
     MinresScalars* hmsc[2] = {nullptr, nullptr};  // pinned host mirrors
     MinresScalars* dmsc[2] = {nullptr, nullptr};  // their device addresses
     double* mpart = nullptr;   // 2 x DOT partials per rhs
+    // partials of the velocity part of the MINRES (z_new . v_new), written by
+    // the last fast-diagonalisation launch of P_V (3 nM per rhs); zeroed
+    // once, the slots of planes a field lacks stay zero
+    double* mfg = nullptr;
     hipEvent_t mev[2] = {nullptr, nullptr};
     hipStream_t cap = nullptr;  // non-blocking stream used only for graph capture
     // cached iteration graphs (one per buffer-rotation phase)
@@ -159,17 +163,19 @@ hipError_t pres_axpbypcz(hp_ctx* c, double a, const Fields& x, double b, const F
 // from y = 0, which equals the hyper-power recursion of eq. Pcv (its Neumann
 // form, eq. neumann).  x, y: velocity views; must not alias each other.
 hipError_t apply_PV(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
-                    int prec) {
+                    int prec, const FdDot* dot = nullptr) {
     Extra* ex = extra_of(c);
-    hipError_t e = launch_P0(c, x, y, true, false, false, prec, nrhs);
-    if (e != hipSuccess) return e;
     long long steps = 1;
     for (int i = 0; i < level; ++i) steps *= q;
+    // the dot partials come from the last fast-diagonalisation launch
+    hipError_t e = launch_P0(c, x, y, true, false, false, prec, nrhs, steps == 1 ? dot : nullptr);
+    if (e != hipSuccess) return e;
     Fields r = vel_fields(c, ex->hv + (size_t)ex->pv_slot * c->nV * c->opts.max_rhs, c->nV);
     for (long long j = 1; j < steps; ++j) {
         e = launch_operator(c, OP_A, y, r, -1.0, 1.0, &x, nrhs);  // r = x - A y
         if (e != hipSuccess) return e;
-        e = launch_P0(c, r, y, true, false, true, prec, nrhs);  // y += P0^{-1} r
+        e = launch_P0(c, r, y, true, false, true, prec, nrhs,    // y += P0^{-1} r
+                      j + 1 == steps ? dot : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -313,16 +319,35 @@ hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields&
 // independent, so the Q block is issued on a second stream with its own
 // workspace and residual slot (fork/join through events, which also holds
 // under stream capture) while the V block runs on the context stream.
-hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs) {
+// Optional dot product of the result with `with` (a full vector), as
+// partials: the velocity part from the V block's last launch (3 nM per rhs,
+// into vpart), the pressure part by a dot kernel behind the Q block (into
+// qpart, vec_dot_partial_count() per rhs).
+struct PkDot {
+    const double* with;
+    double* vpart;
+    double* qpart;
+};
+
+hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs,
+                    const PkDot* pd = nullptr) {
     const int prec = c->opts.precision;
     Extra* ex = extra_of(c);
+    const long long N = c->N, oq = c->off[3];
+    const FdDot vdot = pd ? FdDot{pd->with, pd->vpart} : FdDot{};
     auto q_block = [&]() {
+        hipError_t e;
         if (c->opts.schur_variant == HP_SCHUR_PCQ2)
-            return apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-        return apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+            e = apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+        else
+            e = apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+        if (e == hipSuccess && pd)
+            e = vec_dot_partials(c->stream, c->nQ, N, y + oq, pd->with + oq, nrhs, pd->qpart);
+        return e;
     };
     if (!ex->side) {
-        hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+        hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec,
+                                pd ? &vdot : nullptr);
         return e != hipSuccess ? e : q_block();
     }
     hipStream_t main = c->stream;
@@ -339,7 +364,8 @@ hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrh
     ex->pv_slot = 0;
     // join even after an error, so that a capture on `main` stays well formed
     e = hipEventRecord(ex->join_ev, ex->side);
-    hipError_t ev = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec);
+    hipError_t ev = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec,
+                             pd ? &vdot : nullptr);
     if (e == hipSuccess) e = hipStreamWaitEvent(main, ex->join_ev, 0);
     if (eq != hipSuccess) return eq;
     if (ev != hipSuccess) return ev;
@@ -427,15 +453,21 @@ hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol
     MinresScalars* s_next = ex->msc + (cur ^ 1) * R;
     double* p0 = ex->mpart;
     double* p1 = ex->mpart + vec_partial_doubles(1, R);
+    const long long nd = vec_dot_partial_count();
     hipError_t e;
     if ((e = launch_operator(c, OP_K, full_fields(c, b.z), full_fields(c, b.Kz), 1.0, 0.0, nullptr,
                              nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
-    if ((e = minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur, p0)) != hipSuccess)
+    if ((e = minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur, Partials{p0, nd})) !=
+        hipSuccess)
         return e;
-    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs)) != hipSuccess) return e;
-    if ((e = vec_dot_partials(c->stream, N, N, b.zn, b.vn, nrhs, p1)) != hipSuccess) return e;
-    return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, s_cur, s_next, p1, tol, mirror);
+    // (z_new . v_new): velocity part from the V block's last launch, pressure
+    // part behind the Q block
+    const PkDot pd{b.vn, ex->mfg, p1};
+    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd)) != hipSuccess)
+        return e;
+    return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, s_cur, s_next,
+                    Partials{ex->mfg, 3LL * c->nM}, Partials{p1, nd}, tol, mirror);
 }
 
 void drop_graphs(Extra* ex) {
@@ -1063,7 +1095,7 @@ void hp_default_opts(hp_opts* o) {
     o->iters = 1;
     o->max_rhs = 1;
     o->check_every = 6;
-    o->use_graph = 1;
+    o->use_graph = 0;
     o->autotune = 1;
     o->op_kchunk = 0;
     o->op_order = -1;
@@ -1255,6 +1287,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[0]), ex->hmsc[0], 0) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[1]), ex->hmsc[1], 0) != hipSuccess ||
         alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
+        alloc_device(&ex->mfg, (size_t)3 * c->nM * R) != HP_OK ||
+        hipMemset(ex->mfg, 0, sizeof(double) * 3 * c->nM * R) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&ex->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -1494,6 +1528,7 @@ void hp_destroy(hp_ctx* c) {
     if (ex->hmsc[0]) (void)hipHostFree(ex->hmsc[0]);
     if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);
     if (ex->mpart) (void)hipFree(ex->mpart);
+    if (ex->mfg) (void)hipFree(ex->mfg);
     if (ex->cgv) (void)hipFree(ex->cgv);
     if (ex->cgcoef) (void)hipFree(ex->cgcoef);
     if (ex->cgpart) (void)hipFree(ex->cgpart);

@@ -105,7 +105,54 @@ struct XYArgs {
     int fields_lo, fields_hi;   // field range [lo, hi)
     int inverse;                // 0: forward (U^T), 1: inverse (U)
     int accumulate;             // final output: y += result
+    // FP64 output only: partial sums of (stored output) . dw per (field,
+    // plane) to dpart[r * dp_stride + f * dp_planes + k] (dpart null: none)
+    const double* dw[4];        // same layout and rhs stride as out
+    double* dpart;
+    long long dp_stride;
+    int dp_planes;
 };
+
+// The final write-out of plane k of field f from the column-major plane S
+// (leading dimension ld): y = S, or y += S.  With a dot the workgroup also
+// sums (stored value) x dw over the plane, a fixed-order reduction whose
+// scratch reuses S once every read of it is done.
+template <typename T, typename TO, int NTH>
+__device__ __forceinline__ void xy_store(const XYArgs& a, T* S, int ld, int f, int r, int k,
+                                         int n1, int n2) {
+    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
+    if constexpr (std::is_same<TO, double>::value) {
+        if (a.dpart) {
+            const double* w = a.dw[f] + (long long)r * a.sout[f] + (long long)k * n1 * n2;
+            double s = 0.0;
+            for (int idx = threadIdx.x; idx < n1 * n2; idx += NTH) {
+                int col = idx / n1, row = idx - col * n1;
+                double v = (double)S[col * ld + row];
+                if (a.accumulate) v += y[idx];
+                y[idx] = v;
+                s += v * w[idx];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            __syncthreads();
+            double* red = reinterpret_cast<double*>(S);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int wv = 0; wv < NTH / 64; ++wv) t += red[wv];
+                a.dpart[(long long)r * a.dp_stride + (long long)f * a.dp_planes + k] = t;
+            }
+            return;
+        }
+    }
+    for (int idx = threadIdx.x; idx < n1 * n2; idx += NTH) {
+        int col = idx / n1, row = idx - col * n1;
+        TO v = (TO)S[col * ld + row];
+        if (a.accumulate) y[idx] += v;
+        else y[idx] = v;
+    }
+}
 
 template <typename T>
 __device__ __forceinline__ const T* xy_left(const FDTables<T>& t, int f, int inverse) {
@@ -202,13 +249,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
             }
     }
     __syncthreads();
-    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
-    for (int idx = threadIdx.x; idx < n1 * n2; idx += FD_THREADS) {
-        int col = idx / n1, row = idx - col * n1;
-        TO v = (TO)S[col * ld + row];
-        if (a.accumulate) y[idx] += v;
-        else y[idx] = v;
-    }
+    xy_store<T, TO, FD_THREADS>(a, S, ld, f, r, k, n1, n2);
 }
 
 struct ZArgs {
@@ -566,13 +607,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
                             S[(cb * 16 + lr) * ld + rb * 16 + M::row(lk, i)] = bacc[ii][jj][i];
                     }
             __syncthreads();
-            TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
-            for (int idx = threadIdx.x; idx < n1 * n2; idx += FD_WIDE) {
-                int col = idx / n1, row = idx - col * n1;
-                TO v = (TO)S[col * ld + row];
-                if (a.accumulate) y[idx] += v;
-                else y[idx] = v;
-            }
+            xy_store<T, TO, FD_WIDE>(a, S, ld, f, r, k, n1, n2);
             return;
         }
     }
@@ -620,13 +655,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
         }
     }
     __syncthreads();
-    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
-    for (int idx = threadIdx.x; idx < n1 * n2; idx += FD_WIDE) {
-        int col = idx / n1, row = idx - col * n1;
-        TO v = (TO)S[col * ld + row];
-        if (a.accumulate) y[idx] += v;
-        else y[idx] = v;
-    }
+    xy_store<T, TO, FD_WIDE>(a, S, ld, f, r, k, n1, n2);
 }
 
 // z: 64 (i1,i2)-rows x n3 per workgroup, tiles of Y = X U3 and Z = Y U3^T
@@ -775,7 +804,7 @@ bool fd_plan_fits(int np, int code) {
 
 template <typename T, bool SPLIT = false>
 hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Fields& out, bool vel,
-                  bool pres, bool accumulate, int nrhs) {
+                  bool pres, bool accumulate, int nrhs, const FdDot* dot) {
     // scratch for the two intermediate tensors (precision T), per rhs N values each
     const long long N = c->N;
     T* tmp1 = reinterpret_cast<T*>(c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs);
@@ -897,6 +926,12 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         xi.fields_hi = 3;
         xi.inverse = 1;
         xi.accumulate = accumulate ? 1 : 0;
+        if (dot) {
+            for (int f = 0; f < 3; ++f) xi.dw[f] = dot->with + c->off[f];
+            xi.dpart = dot->part;
+            xi.dp_stride = 3LL * nM;
+            xi.dp_planes = nM;
+        }
         launch_xy(xi, true, 3);
     }
     return hipGetLastError();
@@ -969,11 +1004,13 @@ int fd_plan_in_use(const hp_ctx* c, int precision) {
 }
 
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
-                     bool accumulate, int precision, int nrhs) {
-    if (precision == HP_PREC_FP64) return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs);
+                     bool accumulate, int precision, int nrhs, const FdDot* dot) {
+    if (dot && (precision != HP_PREC_FP64 || !vel)) return hipErrorInvalidValue;
+    if (precision == HP_PREC_FP64)
+        return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs, dot);
     if (precision == HP_PREC_BF16X3)
-        return run_P0<float, true>(c, c->fd32, in, out, vel, pres, accumulate, nrhs);
-    return run_P0<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs);
+        return run_P0<float, true>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr);
+    return run_P0<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr);
 }
 
 }  // namespace hp

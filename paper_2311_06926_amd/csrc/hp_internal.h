@@ -128,8 +128,16 @@ long long ops_ws_stride(const hp_ctx* c);
 hipError_t fd_init_attributes();
 // y = P_0^{-1} x restricted to the selected blocks (velocity and/or pressure);
 // accumulate: y += result instead of y = result.
+// dot (FP64 velocity blocks only, may be null): the last launch also writes
+// partial sums of (final output) . dot->with, one per (velocity field,
+// i3-plane), to dot->part[r * 3 * nM + f * nM + k] (planes a field lacks are
+// never written: kept zero by the caller).
+struct FdDot {
+    const double* with;  // full vector, same layout and rhs stride as the output's
+    double* part;
+};
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
-                     bool accumulate, int precision, int nrhs);
+                     bool accumulate, int precision, int nrhs, const FdDot* dot = nullptr);
 // fast-diagonalisation plans: bit 0 = one MFMA tile per wave (wide kernels),
 // bit 1 = stage the 1D matrices in LDS.  Whether plan `plan` fits the LDS for
 // `precision`, and the plan launch_P0 uses (forced, option, tuned, default).

@@ -421,17 +421,22 @@ __global__ void k_cg_beta(CgScalars* sc, const double* part_rz, double* cp, doub
 //               x += cx1 w_new; workgroup 0 writes the new state to sc_out
 //               (a second buffer, so no workgroup reads a half-updated state)
 //               and to the host mirror.
-__device__ __forceinline__ double sum_block_partials(const double* part, int r, double* sh) {
-    const double p = threadIdx.x < DOT_BLOCKS ? part[(long long)r * DOT_BLOCKS + threadIdx.x] : 0.0;
-    return block_sum(p, sh);  // valid in thread 0
+// Thread t sums partials t, t + VT, ... of set a, then of set b; the block
+// sum of those is valid in thread 0.  The order depends only on the counts.
+__device__ __forceinline__ double sum_block_partials(Partials a, Partials b, int r, double* sh) {
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < a.count; i += VT) s += a.part[r * a.count + i];
+    if (b.part)
+        for (long long i = threadIdx.x; i < b.count; i += VT) s += b.part[r * b.count + i];
+    return block_sum(s, sh);
 }
 
 __global__ void k_minres_v(long long n, long long ld, const double* kz, const double* v,
-                           const double* vo, double* vn, MinresScalars* sc, const double* part) {
+                           const double* vo, double* vn, MinresScalars* sc, Partials part) {
     __shared__ double sh[VT / 64];
     __shared__ double cv[3];
     const int r = blockIdx.y;
-    const double d = sum_block_partials(part, r, sh);
+    const double d = sum_block_partials(part, Partials{nullptr, 0}, r, sh);
     if (threadIdx.x == 0) {
         MinresScalars m = sc[r];
         minres_a_core(m, d, cv);
@@ -447,12 +452,12 @@ __global__ void k_minres_v(long long n, long long ld, const double* kz, const do
 
 __global__ void k_minres_w(long long n, long long ld, const double* z, const double* wo,
                            const double* w, double* wn, double* x, const MinresScalars* sc_in,
-                           MinresScalars* sc_out, const double* part, double tol,
+                           MinresScalars* sc_out, Partials pa, Partials pb, double tol,
                            MinresScalars* mirror) {
     __shared__ double sh[VT / 64];
     __shared__ double cw[3], cx[2];
     const int r = blockIdx.y;
-    const double d = sum_block_partials(part, r, sh);
+    const double d = sum_block_partials(pa, pb, r, sh);
     if (threadIdx.x == 0) {
         MinresScalars m = sc_in[r];
         minres_b_core(m, d, cw, cx, tol);
@@ -481,19 +486,20 @@ hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int
 }
 hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
                     const double* v, const double* vo, double* vn, MinresScalars* sc,
-                    const double* part) {
-    hipLaunchKernelGGL(k_minres_v, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, kz, v, vo, vn, sc,
-                       part);
+                    Partials part) {
+    hipLaunchKernelGGL(k_minres_v, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n,
+                       ld, kz, v, vo, vn, sc, part);
     return hipGetLastError();
 }
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
                     const double* wo, const double* w, double* wn, double* x,
-                    const MinresScalars* sc_in, MinresScalars* sc_out, const double* part,
+                    const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
                     double tol, MinresScalars* mirror) {
-    hipLaunchKernelGGL(k_minres_w, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, z, wo, w, wn, x,
-                       sc_in, sc_out, part, tol, mirror);
+    hipLaunchKernelGGL(k_minres_w, dim3(grid_for(n), nrhs), dim3(VT), 0,
+                       s, n, ld, z, wo, w, wn, x, sc_in, sc_out, a, b, tol, mirror);
     return hipGetLastError();
 }
+long long vec_dot_partial_count() { return DOT_BLOCKS; }
 hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs) {
     hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
     return hipGetLastError();

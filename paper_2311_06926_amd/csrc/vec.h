@@ -37,21 +37,30 @@ struct MinresScalars {
     int iters, done, status, pad;
 };
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs);
+// A dot product handed over as partial sums: part[r * count + i], i < count,
+// for right-hand side r (summed in a fixed order by the consumer).
+struct Partials {
+    const double* part;
+    long long count;
+};
 // v_new = cv . (Kz, v, v_old) with delta and cv formed from the partials of
 // (Kz.z) in every workgroup; records delta in sc
 hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
                     const double* v, const double* vo, double* vn, MinresScalars* sc,
-                    const double* part);
-// from the partials of (z_new.v_new): the rotation of sc_in, w_new = cw . (z, w_old, w),
-// x += cx1 w_new; the new state goes to sc_out (not sc_in) and to mirror
-// (device pointer of a host-mapped copy, or null)
+                    Partials part);
+// from the partials of (z_new.v_new) (the sum of two sets, b.part may be
+// null): the rotation of sc_in, w_new = cw . (z, w_old, w), x += cx1 w_new;
+// the new state goes to sc_out (not sc_in) and to mirror (device pointer of a
+// host-mapped copy, or null)
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
                     const double* wo, const double* w, double* wn, double* x,
-                    const MinresScalars* sc_in, MinresScalars* sc_out, const double* part,
+                    const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
                     double tol, MinresScalars* mirror);
 // partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
+// partials vec_dot_partials writes per right-hand side
+long long vec_dot_partial_count();
 
 // Per-right-hand-side state of the inner preconditioned CG.
 struct CgScalars {

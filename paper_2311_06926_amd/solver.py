@@ -34,7 +34,7 @@ class Solver:
 
     def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
-                 iters=1, max_rhs=1, check_every=6, use_graph=True, autotune=True,
+                 iters=1, max_rhs=1, check_every=6, use_graph=False, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, device=None):
         if not torch.cuda.is_available():
