@@ -117,6 +117,10 @@ typedef struct hp_opts {
                               sqrt(r.P^{-1}r) has dropped by this factor (default 1e-2) */
     int op_fused;       /* operator K and A: -1 = tuned/model (default), 0 = the pressure
                            and velocity kernels, 1 = one single-pass kernel (degree <= 4) */
+    int op_staged;      /* operator K and A velocity kernel: -1 = tuned/model (default),
+                           0 = streams its i3-planes, 1 = loads all planes of its chunk at
+                           once (degree <= 4, op_kchunk 2, 4 or 8 (8: degree <= 3));
+                           same results bit for bit */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -128,6 +132,7 @@ typedef struct hp_tuning {
     int fd_plan[3];     /* P_0 plan per precision (HP_PREC_*), -1 = default plan */
     double op_us;       /* tuned apply_K time (microseconds), 0 if not tuned */
     double fd_us[3];    /* tuned apply_P0 time per precision, 0 if not tuned */
+    int op_staged;      /* 1 if the operator uses the all-planes velocity kernel */
 } hp_tuning;
 
 /* Per-solve report (host struct, filled by hp_solve / hp_grad). */

@@ -51,6 +51,7 @@ class hp_opts(ctypes.Structure):
         ("schur_pcg_iters", ctypes.c_int),
         ("schur_pcg_tol", ctypes.c_double),
         ("op_fused", ctypes.c_int),
+        ("op_staged", ctypes.c_int),
     ]
 
 
@@ -63,6 +64,7 @@ class hp_tuning(ctypes.Structure):
         ("fd_plan", ctypes.c_int * 3),
         ("op_us", ctypes.c_double),
         ("fd_us", ctypes.c_double * 3),
+        ("op_staged", ctypes.c_int),
     ]
 
 

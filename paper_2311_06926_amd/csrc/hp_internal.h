@@ -53,6 +53,7 @@ struct OpShape {
     int comp_fast = 1;
     int slabs = 1;  // i3-slabs, each running the pressure then the velocity kernel
     int fused = 0;  // K and A in one single-pass kernel (k_fused)
+    int staged = 0;  // K and A velocity: all planes of a chunk at once (k_vel_all)
 };
 struct OpTuned {
     int nrhs = 0;
@@ -120,6 +121,8 @@ hipError_t ops_init_attributes();
 // option, tuned, else the cost model) and the cost model alone
 OpShape op_shape(const hp_ctx* c, int nrhs);
 OpShape op_model_shape(const hp_ctx* c, int nrhs);
+// whether the all-planes velocity kernel exists for this degree and chunk
+bool op_staged_ok(int degree, int kchunk);
 // doubles of workspace per right-hand side used by launch_operator (holds w);
 // the fast-diagonalisation scratch follows at ops_ws_stride(c) * max_rhs
 long long ops_ws_stride(const hp_ctx* c);

@@ -507,6 +507,199 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
 }
 
+// ---- velocity, all planes of a chunk at once (K and A) ------------------------------------
+// For small meshes, where k_vel's per-plane chain (stage, barrier, band,
+// barrier, band) repeated kc + 2w times sets its duration, this variant
+// issues the loads of all kc + 2w planes of its tile and halo (and of every
+// output's coupling and source) at once, applies direction 1 and direction 2
+// as one pass each over all planes, and forms direction 3 from the thread's
+// own column of results in registers.  Each output is the same sequence of
+// floating-point operations as in k_vel, so the results agree bit for bit.
+// KC = kchunk (2, 4 or 8), degrees 2..4.
+template <int P, int C, int KC>
+__device__ void vel_component_all(const OpArgs& a, const Fields& out, const Fields& src,
+                                  double alpha, double beta, int r, int i0, int j0, int k0,
+                                  double* lds) {
+    constexpr int W1 = (C == 0) ? P : P - 1;
+    constexpr int W2 = (C == 1) ? P : P - 1;
+    constexpr int W3 = (C == 2) ? P : P - 1;
+    constexpr int SW = T1 + 2 * W1, SR = T2 + 2 * W2;
+    constexpr int NS = (SR * SW + NT - 1) / NT;
+    constexpr int NP = KC + 2 * W3;  // staged planes k0 - W3 .. k0 + KC + W3 - 1
+    const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
+    if (i0 >= n1 || j0 >= n2 || k0 >= n3) return;
+    const int kend = min(min(k0 + a.kchunk, a.klim), n3);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const bool act = i < n1 && j < n2;
+    const int nM = a.nM;
+    const double* wv = a.ws + (long long)r * a.ws_stride;
+    const long long plane = (long long)n1 * n2;
+    const long long wplane = (long long)nM * nM;
+    const uint32_t YB = 8u * (uint32_t)plane, WB = 8u * (uint32_t)wplane;
+    double* y = out.f[C] + (long long)r * out.stride[C];
+    const bool has_src = beta != 0.0;
+    const double* sv = has_src ? src.f[C] + (long long)r * src.stride[C] : y;
+    const uint32_t SB = has_src ? YB : 0u;
+    const uint32_t wo = act ? 8u * (i + nM * j) : OOB;
+    const uint32_t wo1 = act ? wo + (C == 0 ? 8u : C == 1 ? 8u * nM : 0u) : OOB;
+    const uint32_t yo = act ? 8u * (i + n1 * j) : OOB;
+    const double* x = a.u[C] + (long long)r * a.su;
+    uint32_t so[NS];  // staging byte offsets, OOB outside the component
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int idx = threadIdx.x + s * NT;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W2 + rr, ii = i0 - W1 + cc;
+        const bool ok = idx < SR * SW && jj >= 0 && jj < n2 && ii >= 0 && ii < n1;
+        so[s] = ok ? 8u * (jj * n1 + ii) : OOB;
+    }
+    // every load of the workgroup, issued before the first is used
+    double xr[NP][NS];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int kk = k0 - W3 + q;
+        const bool kin = kk >= 0 && kk < n3;
+        const auto rx = make_rsrc(x + plane * (kin ? kk : 0), kin ? YB : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) xr[q][s] = bload(rx, so[s]);
+    }
+    double w0[KC], w1[KC], sd[KC];
+#pragma unroll
+    for (int o = 0; o < KC; ++o) {
+        const int k = k0 + o;
+        const bool on = k < kend;
+        const int kc = on ? k : k0;
+        w0[o] = bload(make_rsrc(wv + wplane * kc, on ? WB : 0u), wo);
+        w1[o] = bload(make_rsrc(wv + wplane * (C == 2 ? kc + 1 : kc), on ? WB : 0u), wo1);
+        sd[o] = bload(make_rsrc(sv + plane * kc, on ? SB : 0u), yo);
+    }
+    const double* t1a = a.bt.ptr[C == 0 ? BK_N : BM_C];
+    const double* t1b = a.bt.ptr[C == 0 ? BM_N : BT_C];
+    const double* m2t = a.bt.ptr[C == 1 ? BM_N : BM_C];
+    const double* k2t = a.bt.ptr[C == 1 ? BK_N : BT_C];
+    const double* ta = a.bt.ptr[C == 2 ? BK_N : BM_C];
+    const double* tb = a.bt.ptr[C == 2 ? BM_N : BT_C];
+    double ca[2 * W1 + 1], cb[2 * W1 + 1], cm[2 * W2 + 1], ck[2 * W2 + 1];
+    load_band_row<W1>(t1a, i, i < n1, ca);
+    load_band_row<W1>(t1b, i, i < n1, cb);
+    load_band_row<W2>(m2t, j, j < n2, cm);
+    load_band_row<W2>(k2t, j, j < n2, ck);
+    double* xs = lds;                    // NP x SR x SW
+    double* pa = xs + NP * SR * SW;      // NP x SR x T1
+    double* pb = pa + NP * SR * T1;
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int idx = threadIdx.x + s * NT;
+            if (idx < SR * SW) xs[q * SR * SW + idx] = xr[q][s];
+        }
+    __syncthreads();
+    // direction 1 over the tile rows and halo rows of every plane
+    for (int q = 0; q < NP; ++q) {
+        const double* xq = xs + q * SR * SW;
+        for (int rr = g; rr < SR; rr += T2) {
+            double sa = 0.0, sb = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * W1; ++t) {
+                const double xv = xq[rr * SW + c + t];
+                sa += ca[t] * xv;
+                sb += cb[t] * xv;
+            }
+            pa[q * SR * T1 + rr * T1 + c] = sa;
+            pb[q * SR * T1 + rr * T1 + c] = sb;
+        }
+    }
+    __syncthreads();
+    // direction 2 at the thread's point of every plane
+    double gav[NP], gbv[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const double* paq = pa + q * SR * T1;
+        const double* pbq = pb + q * SR * T1;
+        double am = 0.0, ak = 0.0, bm = 0.0, bk = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W2; ++t) {
+            const double va = paq[(g + t) * T1 + c], vb = pbq[(g + t) * T1 + c];
+            am += cm[t] * va;
+            ak += ck[t] * va;
+            bm += cm[t] * vb;
+            bk += ck[t] * vb;
+        }
+        double ga, gb = 0.0;
+        if (C == 0) {
+            ga = am + 2.0 * bk;
+            gb = 2.0 * bm;
+        } else if (C == 1) {
+            ga = ak + 2.0 * bm;
+            gb = 2.0 * am;
+        } else {
+            ga = am;
+            gb = 2.0 * (ak + bm);
+        }
+        gav[q] = ga;
+        gbv[q] = gb;
+    }
+    // direction 3 (band rows uniform over the workgroup, read through the
+    // scalar cache) and the epilogue
+#pragma unroll
+    for (int o = 0; o < KC; ++o) {
+        const int k = k0 + o;
+        const bool on = k < kend;
+        const int kc = on ? k : k0;
+        Window<W3> wa, wb;
+#pragma unroll
+        for (int t = 0; t <= 2 * W3; ++t) {
+            wa.v[t] = gav[o + t];
+            wb.v[t] = gbv[o + t];
+        }
+        const double v = a.nu * (wa.dot(ta + kc * (2 * W3 + 1)) + wb.dot(tb + kc * (2 * W3 + 1))) +
+                         (w0[o] - w1[o]);
+        bstore(make_rsrc(y + plane * kc, on ? YB : 0u), yo, alpha * v + beta * sd[o]);
+    }
+}
+
+template <int P, int KC>
+constexpr int vel_all_lds_doubles() {
+    // the largest component: NP planes of staged values and two band passes
+    int m = 0;
+    for (int C = 0; C < 3; ++C) {
+        const int W1 = (C == 0) ? P : P - 1, W2 = (C == 1) ? P : P - 1, W3 = (C == 2) ? P : P - 1;
+        const int SW = T1 + 2 * W1, SR = T2 + 2 * W2, NP = KC + 2 * W3;
+        const int d = NP * (SR * SW + 2 * SR * T1);
+        m = d > m ? d : m;
+    }
+    return m;
+}
+
+template <int P, int KC>
+__global__ __launch_bounds__(NT) void k_vel_all(OpArgs a, Fields out, Fields src, double alpha,
+                                                double beta) {
+    extern __shared__ double lds_all[];
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    int comp;
+    if (a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    id /= a.nchunk;
+    if (!a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
+    const int r = id;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    if (comp == 0) vel_component_all<P, 0, KC>(a, out, src, alpha, beta, r, i0, j0, k0, lds_all);
+    else if (comp == 1) vel_component_all<P, 1, KC>(a, out, src, alpha, beta, r, i0, j0, k0, lds_all);
+    else vel_component_all<P, 2, KC>(a, out, src, alpha, beta, r, i0, j0, k0, lds_all);
+}
+
 // ---- single pass (K and A) ---------------------------------------------------------------
 // With B = D^T M_q the coupling of component c is D_c^T M_q z, z = nu D u + p
 // (z = nu D u for A), which is the Kronecker product of M^ in the two other
@@ -797,9 +990,45 @@ const VelLaunch vel_launch[PMAX + 1] = {nullptr,       nullptr,       launch_vel
                                         launch_vel<3>, launch_vel<4>, launch_vel<5>,
                                         launch_vel<6>, launch_vel<7>, launch_vel<8>};
 
+template <int P, int KC>
+void launch_vel_all(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
+                    double alpha, double beta) {
+    constexpr size_t shm = sizeof(double) * vel_all_lds_doubles<P, KC>();
+    hipLaunchKernelGGL((k_vel_all<P, KC>), grid, dim3(NT), shm, st, a, out, s, alpha, beta);
+}
+template <int P, int KC>
+hipError_t vel_all_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_vel_all<P, KC>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(double) * vel_all_lds_doubles<P, KC>()));
+}
+// the all-planes velocity kernels: degrees 2..4 x chunks 2, 4, 8 (8: degree <= 3)
+VelLaunch vel_all_launch(int P, int kc) {
+    switch (P * 16 + kc) {
+        case 2 * 16 + 2: return launch_vel_all<2, 2>;
+        case 2 * 16 + 4: return launch_vel_all<2, 4>;
+        case 2 * 16 + 8: return launch_vel_all<2, 8>;
+        case 3 * 16 + 2: return launch_vel_all<3, 2>;
+        case 3 * 16 + 4: return launch_vel_all<3, 4>;
+        case 3 * 16 + 8: return launch_vel_all<3, 8>;
+        case 4 * 16 + 2: return launch_vel_all<4, 2>;
+        case 4 * 16 + 4: return launch_vel_all<4, 4>;
+        default: return nullptr;
+    }
+}
+
 }  // namespace
 
-hipError_t ops_init_attributes() { return hipSuccess; }
+bool op_staged_ok(int degree, int kchunk) { return vel_all_launch(degree, kchunk) != nullptr; }
+
+hipError_t ops_init_attributes() {
+    const hipError_t es[] = {vel_all_attr<2, 2>(), vel_all_attr<2, 4>(), vel_all_attr<2, 8>(),
+                             vel_all_attr<3, 2>(), vel_all_attr<3, 4>(), vel_all_attr<3, 8>(),
+                             vel_all_attr<4, 2>(), vel_all_attr<4, 4>()};
+    for (hipError_t e : es)
+        if (e != hipSuccess) return e;
+    return hipSuccess;
+}
 
 long long ops_ws_stride(const hp_ctx* c) { return c->nQ; }
 
@@ -834,6 +1063,7 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
     if (c->opts.op_slabs > 0) sh.slabs = c->opts.op_slabs;
     if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
     if (c->opts.op_fused >= 0) sh.fused = c->opts.op_fused;
+    if (c->opts.op_staged >= 0) sh.staged = c->opts.op_staged;
     if (c->op_force.kchunk > 0) sh = c->op_force;
     if (c->p > FUSED_PMAX) sh.fused = 0;
     return sh;
@@ -875,13 +1105,15 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         dim3 grid(a.nblocks);
         pres_launch[P](grid, c->stream, a, yp, syp);
     };
+    const VelLaunch vall = (sh.staged && (mode == OP_K || mode == OP_A))
+                               ? vel_all_launch(P, a.kchunk) : nullptr;
     auto vel = [&](int lo, int hi) {
         a.kbase = lo;
         a.klim = hi;
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * 3 * nrhs;
         dim3 grid(a.nblocks);
-        vel_launch[P](grid, c->stream, a, out, s, alpha, beta);
+        (vall ? vall : vel_launch[P])(grid, c->stream, a, out, s, alpha, beta);
     };
     if (sh.fused && (mode == OP_K || mode == OP_A)) {
         a.kbase = 0;

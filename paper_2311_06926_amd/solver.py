@@ -36,7 +36,8 @@ class Solver:
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
                  iters=1, max_rhs=1, check_every=6, use_graph=False, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
-                 schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, device=None):
+                 schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
+                 device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -64,6 +65,7 @@ class Solver:
         o.schur_pcg_iters = schur_pcg_iters
         o.schur_pcg_tol = schur_pcg_tol
         o.op_fused = op_fused
+        o.op_staged = op_staged
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -89,7 +91,8 @@ class Solver:
         check(self.lib.hp_get_tuning(self.ctx, nrhs, ctypes.byref(t)), "hp_get_tuning")
         return {"op_kchunk": t.op_kchunk, "op_order": t.op_order, "op_slabs": t.op_slabs,
                 "op_tuned": bool(t.op_tuned),
-                "op_us": t.op_us, "fd_plan": list(t.fd_plan), "fd_us": list(t.fd_us)}
+                "op_us": t.op_us, "fd_plan": list(t.fd_plan), "fd_us": list(t.fd_us),
+                "op_staged": t.op_staged}
 
     # -- memory helpers ------------------------------------------------------
     def empty(self, n, nrhs=1):

@@ -219,20 +219,24 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
 
     def run(s):
         return [s.apply_K(x), s.apply_K(x[:s.N].contiguous()), s.apply_A(u), s.apply_B(q),
-                s.apply_Bt(u), s.apply_MV(u)]
+                s.apply_Bt(u), s.apply_MV(u), s.apply_hyperpower(2, 1, x[:s.N].contiguous())]
 
     ref = run(base)
     nM = E + p - 1
-    for kc in sorted({1, 2, 5, nM}):
-        for order in (0, 1):
-            for slabs in (1, 3):
-                s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order,
-                           op_slabs=slabs)
-                t = s.tuning(1)
-                assert t["op_kchunk"] == kc and t["op_order"] == order and t["op_slabs"] == slabs
-                for a, b in zip(run(s), ref):
-                    assert torch.equal(a, b), (kc, order, slabs)
-                s.close()
+    shapes = [(kc, order, slabs, 0) for kc in sorted({1, 2, 5, nM}) for order in (0, 1)
+              for slabs in (1, 3)]
+    # the all-planes velocity kernel (K and A; chunks 2, 4, 8, degree <= 4, 8 only to 3)
+    shapes += [(kc, order, slabs, 1) for kc in (2, 4, 8) if p <= 4 and (kc < 8 or p <= 3)
+               for order in (0, 1) for slabs in (1, 3)]
+    for kc, order, slabs, staged in shapes:
+        s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order,
+                   op_slabs=slabs, op_staged=staged)
+        t = s.tuning(1)
+        assert t["op_kchunk"] == min(kc, nM) and t["op_order"] == order
+        assert t["op_slabs"] == slabs and t["op_staged"] == (staged if kc <= nM else 0)
+        for a, b in zip(run(s), ref):
+            assert torch.equal(a, b), (kc, order, slabs, staged)
+        s.close()
     base.close()
 
 
