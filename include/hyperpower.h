@@ -92,10 +92,10 @@ typedef struct hp_opts {
     int iters;          /* hyper-power updates k >= 0 used by hp_solve (default 1) */
     int max_rhs;        /* largest batch accepted (workspace size, default 1) */
     int check_every;    /* solve: host polls convergence every m iterations (default 6) */
-    int use_graph;      /* solve: 1 = replay each iteration (FGMRES: each Arnoldi step)
-                           as a captured HIP graph, 0 = launch its kernels directly
-                           (default 0, the faster of the two at most sizes; results
-                           are identical bit for bit) */
+    int use_graph;      /* solve: 0 = launch the kernels of each iteration directly
+                           (default), 1 = replay each iteration (FGMRES: each Arnoldi
+                           step) as one captured HIP graph; results are identical bit
+                           for bit in both modes */
     int autotune;       /* time the launch shapes below at setup and keep the fastest
                            (default 1); results do not depend on the shapes */
     int op_kchunk;      /* operator kernels: i3-planes per workgroup, 0 = tuned/model */

@@ -329,43 +329,62 @@ struct PkDot {
     double* qpart;
 };
 
+// The Q block of P_k (and the pressure part of the dot) on c->stream.
+hipError_t pk_q_block(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs,
+                      const PkDot* pd) {
+    const int prec = c->opts.precision;
+    hipError_t e;
+    if (c->opts.schur_variant == HP_SCHUR_PCQ2)
+        e = apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+    else
+        e = apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
+    const long long oq = c->off[3];
+    if (e == hipSuccess && pd)
+        e = vec_dot_partials(c->stream, c->nQ, c->N, y + oq, pd->with + oq, nrhs, pd->qpart);
+    return e;
+}
+
+// The V block of P_k (and the velocity part of the dot) on c->stream.
+hipError_t pk_v_block(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs,
+                      const PkDot* pd) {
+    const FdDot vdot = pd ? FdDot{pd->with, pd->vpart} : FdDot{};
+    return apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, c->opts.precision,
+                    pd ? &vdot : nullptr);
+}
+
+// Runs fn() with the Q block's settings: stream s, the second workspace and
+// its own Richardson residual slot; restores the context afterwards.
+template <typename F>
+hipError_t with_q_settings(hp_ctx* c, hipStream_t s, F fn) {
+    Extra* ex = extra_of(c);
+    hipStream_t s0 = c->stream;
+    double* ws0 = c->ws;
+    c->stream = s;
+    c->ws = ex->ws2;
+    ex->pv_slot = 3;
+    const hipError_t e = fn();
+    c->stream = s0;
+    c->ws = ws0;
+    ex->pv_slot = 0;
+    return e;
+}
+
 hipError_t apply_Pk(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs,
                     const PkDot* pd = nullptr) {
-    const int prec = c->opts.precision;
     Extra* ex = extra_of(c);
-    const long long N = c->N, oq = c->off[3];
-    const FdDot vdot = pd ? FdDot{pd->with, pd->vpart} : FdDot{};
-    auto q_block = [&]() {
-        hipError_t e;
-        if (c->opts.schur_variant == HP_SCHUR_PCQ2)
-            e = apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-        else
-            e = apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-        if (e == hipSuccess && pd)
-            e = vec_dot_partials(c->stream, c->nQ, N, y + oq, pd->with + oq, nrhs, pd->qpart);
-        return e;
-    };
     if (!ex->side) {
-        hipError_t e = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec,
-                                pd ? &vdot : nullptr);
-        return e != hipSuccess ? e : q_block();
+        hipError_t e = pk_v_block(c, q, k, x, y, nrhs, pd);
+        return e != hipSuccess ? e : pk_q_block(c, q, k, x, y, nrhs, pd);
     }
     hipStream_t main = c->stream;
-    double* ws_main = c->ws;
     hipError_t e = hipEventRecord(ex->fork_ev, main);
     if (e == hipSuccess) e = hipStreamWaitEvent(ex->side, ex->fork_ev, 0);
     if (e != hipSuccess) return e;
-    c->stream = ex->side;
-    c->ws = ex->ws2;
-    ex->pv_slot = 3;
-    hipError_t eq = q_block();
-    c->stream = main;
-    c->ws = ws_main;
-    ex->pv_slot = 0;
+    const hipError_t eq =
+        with_q_settings(c, ex->side, [&]() { return pk_q_block(c, q, k, x, y, nrhs, pd); });
     // join even after an error, so that a capture on `main` stays well formed
     e = hipEventRecord(ex->join_ev, ex->side);
-    hipError_t ev = apply_PV(c, q, k, vel_of_full(c, x), vel_of_full(c, y), nrhs, prec,
-                             pd ? &vdot : nullptr);
+    const hipError_t ev = pk_v_block(c, q, k, x, y, nrhs, pd);
     if (e == hipSuccess) e = hipStreamWaitEvent(main, ex->join_ev, 0);
     if (eq != hipSuccess) return eq;
     if (ev != hipSuccess) return ev;
@@ -443,31 +462,52 @@ MinresBufs minres_bufs(hp_ctx* c, int phase, int nrhs) {
 
 // One MINRES iteration; it reads the scalar state msc[cur] and writes the
 // next one to msc[cur ^ 1] and to the host mirror `mirror` (device address
-// of pinned host memory).
-hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
-                            MinresScalars* mirror, int cur) {
+// of pinned host memory).  Its pieces: (a) K z, (Kz . z) and the v update;
+// then P_k as the Q block (q) beside the V block (v), whose launches also
+// leave the partials of (z_new . v_new); (w) the rotation and the w/x update.
+hipError_t minres_a(hp_ctx* c, const MinresBufs& b, int nrhs, int cur) {
     Extra* ex = extra_of(c);
     const long long N = c->N;
-    const int R = c->opts.max_rhs;
-    MinresScalars* s_cur = ex->msc + cur * R;
-    MinresScalars* s_next = ex->msc + (cur ^ 1) * R;
+    MinresScalars* s_cur = ex->msc + cur * c->opts.max_rhs;
     double* p0 = ex->mpart;
-    double* p1 = ex->mpart + vec_partial_doubles(1, R);
-    const long long nd = vec_dot_partial_count();
     hipError_t e;
     if ((e = launch_operator(c, OP_K, full_fields(c, b.z), full_fields(c, b.Kz), 1.0, 0.0, nullptr,
                              nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
-    if ((e = minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur, Partials{p0, nd})) !=
-        hipSuccess)
-        return e;
-    // (z_new . v_new): velocity part from the V block's last launch, pressure
-    // part behind the Q block
-    const PkDot pd{b.vn, ex->mfg, p1};
+    return minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur,
+                    Partials{p0, vec_dot_partial_count()});
+}
+PkDot minres_pk_dot(hp_ctx* c, const MinresBufs& b) {
+    Extra* ex = extra_of(c);
+    return PkDot{b.vn, ex->mfg, ex->mpart + vec_partial_doubles(1, c->opts.max_rhs)};
+}
+hipError_t minres_q(hp_ctx* c, const MinresBufs& b, int nrhs) {
+    const PkDot pd = minres_pk_dot(c, b);
+    return pk_q_block(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd);
+}
+hipError_t minres_vb(hp_ctx* c, const MinresBufs& b, int nrhs) {
+    const PkDot pd = minres_pk_dot(c, b);
+    return pk_v_block(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd);
+}
+hipError_t minres_w_step(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
+                         MinresScalars* mirror, int cur) {
+    Extra* ex = extra_of(c);
+    const long long N = c->N;
+    const int R = c->opts.max_rhs;
+    const PkDot pd = minres_pk_dot(c, b);
+    return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, ex->msc + cur * R,
+                    ex->msc + (cur ^ 1) * R, Partials{pd.vpart, 3LL * c->nM},
+                    Partials{pd.qpart, vec_dot_partial_count()}, tol, mirror);
+}
+
+hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
+                            MinresScalars* mirror, int cur) {
+    hipError_t e;
+    if ((e = minres_a(c, b, nrhs, cur)) != hipSuccess) return e;
+    const PkDot pd = minres_pk_dot(c, b);
     if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd)) != hipSuccess)
         return e;
-    return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, s_cur, s_next,
-                    Partials{ex->mfg, 3LL * c->nM}, Partials{p1, nd}, tol, mirror);
+    return minres_w_step(c, b, nrhs, tol, mirror, cur);
 }
 
 void drop_graphs(Extra* ex) {
@@ -479,6 +519,22 @@ void drop_graphs(Extra* ex) {
     ex->g_valid = false;
 }
 
+// Captures fn() on the capture stream and instantiates it into *out.
+template <typename F>
+hp_status capture_graph(hp_ctx* c, hipGraphExec_t* out, F fn) {
+    Extra* ex = extra_of(c);
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(ex->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HP_EHIP;
+    const hipError_t e = fn();
+    const hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
+    hp_status st = (e != hipSuccess || e2 != hipSuccess) ? HP_EHIP : HP_OK;
+    if (st == HP_OK && hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) st = HP_EHIP;
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+}
+
+// Graphs of the MINRES iterations, one per buffer-rotation phase (period 6);
+// the Q block of P_k is a parallel branch of each.
 hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
     Extra* ex = extra_of(c);
     const hp_opts& o = c->opts;
@@ -491,20 +547,13 @@ hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
     c->stream = ex->cap;
     hp_status st = HP_OK;
     for (int ph = 0; ph < 6 && st == HP_OK; ++ph) {
-        hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(ex->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            st = HP_EHIP;
-            break;
-        }
         // iteration it (phase (it-1) % 6) reads state it & 1 and is polled
         // through mirror it & 1
-        hipError_t e = minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol,
-                                        ex->dmsc[(ph + 1) & 1], (ph + 1) & 1);
-        hipError_t e2 = hipStreamEndCapture(ex->cap, &g);
-        if (e != hipSuccess || e2 != hipSuccess) st = HP_EHIP;
-        if (st == HP_OK && hipGraphInstantiate(&ex->g_exec[ph], g, nullptr, nullptr, 0) != hipSuccess)
-            st = HP_EHIP;
-        if (g) (void)hipGraphDestroy(g);
+        const MinresBufs bb = minres_bufs(c, ph, nrhs);
+        const int cur = (ph + 1) & 1;
+        st = capture_graph(c, &ex->g_exec[ph], [&]() {
+            return minres_iteration(c, bb, nrhs, tol, ex->dmsc[cur], cur);
+        });
     }
     c->stream = user;
     if (st != HP_OK) {
@@ -1160,7 +1209,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.fd_plan < -1 || o.fd_plan > 7 || o.op_slabs < 0 || o.schur_level < 0 ||
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
-        o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1)
+        o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
+        o.use_graph < 0 || o.use_graph > 1)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;

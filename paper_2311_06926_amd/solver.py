@@ -55,7 +55,7 @@ class Solver:
         o.iters = iters
         o.max_rhs = max_rhs
         o.check_every = check_every
-        o.use_graph = int(bool(use_graph))
+        o.use_graph = int(use_graph)
         o.autotune = int(bool(autotune))
         o.op_kchunk = op_kchunk
         o.op_order = op_order

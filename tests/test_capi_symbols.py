@@ -66,7 +66,7 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
                        ("op_slabs", -1), ("schur_level", -1), ("schur_level", 7),
                        ("schur_variant", 0), ("schur_variant", 4), ("schur_pcg_iters", 0),
                        ("schur_pcg_tol", -1.0), ("op_fused", -2), ("op_fused", 2),
-                       ("op_staged", -2), ("op_staged", 2)):
+                       ("op_staged", -2), ("op_staged", 2), ("use_graph", -1), ("use_graph", 2)):
         opts = _lib.hp_opts()
         lib.hp_default_opts(ctypes.byref(opts))
         setattr(opts, field, bad)
