@@ -91,7 +91,10 @@ typedef struct hp_opts {
     int order;          /* hyper-power order q >= 2 used by hp_solve (default 2) */
     int iters;          /* hyper-power updates k >= 0 used by hp_solve (default 1) */
     int max_rhs;        /* largest batch accepted (workspace size, default 1) */
-    int check_every;    /* solve: host polls convergence every m iterations (default 6) */
+    int poll_lag;       /* MINRES: the host reads the convergence flags of iteration j
+                           once iteration j + poll_lag is enqueued (1..3, default 1), so
+                           that it stays that far ahead of the device; up to poll_lag
+                           iterations then run past convergence and leave x unchanged */
     int use_graph;      /* solve: 0 = launch the kernels of each iteration directly
                            (default), 1 = replay each iteration (FGMRES: each Arnoldi
                            step) as one captured HIP graph; results are identical bit

@@ -40,7 +40,7 @@ class hp_opts(ctypes.Structure):
         ("order", ctypes.c_int),
         ("iters", ctypes.c_int),
         ("max_rhs", ctypes.c_int),
-        ("check_every", ctypes.c_int),
+        ("poll_lag", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("autotune", ctypes.c_int),
         ("op_kchunk", ctypes.c_int),

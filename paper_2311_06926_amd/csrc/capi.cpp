@@ -64,7 +64,7 @@ struct Extra {
     // the last fast-diagonalisation launch of P_V (3 nM per rhs); zeroed
     // once, the slots of planes a field lacks stay zero
     double* mfg = nullptr;
-    hipEvent_t mev[2] = {nullptr, nullptr};
+    hipEvent_t mev[4] = {nullptr, nullptr, nullptr, nullptr};  // ring of iteration ends
     hipStream_t cap = nullptr;  // non-blocking stream used only for graph capture
     // cached iteration graphs (one per buffer-rotation phase)
     bool g_valid = false;
@@ -600,6 +600,7 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     HIPCHK(hipMemcpyAsync(ex->hmsc[0], s1, sbytes, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     int it = 0;
+    const int lag = c->opts.poll_lag;
     bool finished = all_done(ex->hmsc[0]);
     while (!finished && it < c->opts.maxit) {
         const int ph = it % 6;
@@ -610,10 +611,12 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
             HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1],
                                     it & 1));
         }
-        HIPCHK(hipEventRecord(ex->mev[it & 1], c->stream));
-        if (it >= 2) {
-            HIPCHK(hipEventSynchronize(ex->mev[(it - 1) & 1]));
-            finished = all_done(ex->hmsc[(it - 1) & 1]);
+        // the flags of iteration it - lag, read once iteration it is enqueued
+        // (its mirror slot may already hold a later state: done is monotone)
+        HIPCHK(hipEventRecord(ex->mev[it & 3], c->stream));
+        if (it > lag) {
+            HIPCHK(hipEventSynchronize(ex->mev[(it - lag) & 3]));
+            finished = all_done(ex->hmsc[(it - lag) & 1]);
         }
     }
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1167,7 +1170,7 @@ void hp_default_opts(hp_opts* o) {
     o->order = 2;
     o->iters = 1;
     o->max_rhs = 1;
-    o->check_every = 6;
+    o->poll_lag = 1;
     o->use_graph = 0;
     o->autotune = 1;
     o->op_kchunk = 0;
@@ -1210,7 +1213,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
-        o.use_graph < 0 || o.use_graph > 1)
+        o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1366,6 +1369,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hipMemset(ex->mfg, 0, sizeof(double) * 3 * c->nM * R) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ex->mev[2], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ex->mev[3], hipEventDisableTiming) != hipSuccess ||
         hipStreamCreateWithFlags(&ex->cap, hipStreamNonBlocking) != hipSuccess) {
         hp_destroy(c);
         return HP_ENOMEM;
@@ -1609,8 +1614,8 @@ void hp_destroy(hp_ctx* c) {
     if (ex->cgcoef) (void)hipFree(ex->cgcoef);
     if (ex->cgpart) (void)hipFree(ex->cgpart);
     if (ex->cgsc) (void)hipFree(ex->cgsc);
-    if (ex->mev[0]) (void)hipEventDestroy(ex->mev[0]);
-    if (ex->mev[1]) (void)hipEventDestroy(ex->mev[1]);
+    for (hipEvent_t ev : ex->mev)
+        if (ev) (void)hipEventDestroy(ev);
     if (ex->cap) (void)hipStreamDestroy(ex->cap);
     if (ex->hcoef) (void)hipHostFree(ex->hcoef);
     delete ce;

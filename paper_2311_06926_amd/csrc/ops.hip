@@ -294,6 +294,165 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     }
 }
 
+// ---- pressure chain, all planes of a chunk at once (K and A) -----------------------------
+// The counterpart of k_vel_all for k_pres: the loads of all kc + 2w planes
+// (and the u3 plane before them) are issued at once, g and z are formed into
+// LDS, directions 1 and 2 are one pass each over all planes and direction 3
+// reads the thread's column from registers.  Same operation sequence per
+// output as k_pres (bitwise-identical results).  KC = kchunk (2 or 4),
+// degrees 2 and 3.
+template <int P, int KC>
+__global__ __launch_bounds__(NT) void k_pres_all(OpArgs a, double* yp, long long syp) {
+    constexpr int W = P - 1;
+    constexpr int SW = T1 + 2 * W, SR = T2 + 2 * W;
+    constexpr int NS = (SR * SW + NT - 1) / NT;
+    constexpr int NP = KC + 2 * W;  // planes k0 - W .. k0 + KC + W - 1
+    extern __shared__ double lds_p[];
+    double* gs = lds_p;                  // NP x SR x SW
+    double* zs = gs + NP * SR * SW;
+    double* pg = zs + NP * SR * SW;      // NP x SR x T1
+    double* pz = pg + NP * SR * T1;
+    const int nM = a.nM, nN = a.nN;
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    const int r = id / a.nchunk;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    const int kend = min(min(k0 + a.kchunk, a.klim), nM);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const bool act = i < nM && j < nM;
+    const int mode = a.mode;
+    const bool need_g = (mode == OP_K || mode == OP_BT);
+    const bool need_z = (mode != OP_BT);
+    const bool use_u = (mode != OP_B);
+    const bool use_p = (mode == OP_K || mode == OP_B);
+    const double zg = (mode == OP_B) ? 0.0 : a.nu;   // z = zg g + p
+    double* wv = a.ws + (long long)r * a.ws_stride;
+    const double* pp = use_p ? a.p + (long long)r * a.sp : wv;
+    const double* u1 = use_u ? a.u[0] + (long long)r * a.su : pp;
+    const double* u2 = use_u ? a.u[1] + (long long)r * a.su : pp;
+    const double* u3 = use_u ? a.u[2] + (long long)r * a.su : pp;
+    double* ypr = need_g ? yp + (long long)r * syp : wv;
+    const double* tm = a.bt.ptr[BM_C];
+    const long long P1 = (long long)nN * nM;
+    const long long P2 = (long long)nM * nN;
+    const long long P3 = (long long)nM * nM;
+    const uint32_t B1 = use_u ? 8u * (uint32_t)P1 : 0u, B2 = use_u ? 8u * (uint32_t)P2 : 0u;
+    const uint32_t B3 = use_u ? 8u * (uint32_t)P3 : 0u, BP = use_p ? 8u * (uint32_t)P3 : 0u;
+    uint32_t oa[NS], ob[NS], oc[NS], od[NS], oe[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int idx = threadIdx.x + s * NT;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W + rr, ii = i0 - W + cc;
+        const bool ok = idx < SR * SW && jj >= 0 && jj < nM && ii >= 0 && ii < nM;
+        oa[s] = (ok && ii < nN) ? 8u * (nN * jj + ii) : OOB;
+        ob[s] = (ok && ii >= 1) ? 8u * (nN * jj + ii - 1) : OOB;
+        oc[s] = (ok && jj < nN) ? 8u * (ii + nM * jj) : OOB;
+        od[s] = (ok && jj >= 1) ? 8u * (ii + nM * (jj - 1)) : OOB;
+        oe[s] = ok ? 8u * (ii + nM * jj) : OOB;
+    }
+    // every load of the workgroup first: u3 from plane k0 - W - 1 on, the
+    // other values from plane k0 - W on
+    double v1a[NP][NS], v1b[NP][NS], v2c[NP][NS], v2d[NP][NS], vp[NP][NS], v3[NP + 1][NS];
+#pragma unroll
+    for (int q = 0; q <= NP; ++q) {
+        const int kk = k0 - W - 1 + q;
+        const bool k3in = kk >= 0 && kk < nN;
+        const auto r3 = make_rsrc(u3 + P3 * (k3in ? kk : 0), k3in ? B3 : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v3[q][s] = bload(r3, oe[s]);
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        const int kk = k0 - W + q;
+        const bool kin = kk >= 0 && kk < nM;
+        const int kc = kin ? kk : 0;
+        const auto r1 = make_rsrc(u1 + P1 * kc, kin ? B1 : 0u);
+        const auto r2 = make_rsrc(u2 + P2 * kc, kin ? B2 : 0u);
+        const auto rp = make_rsrc(pp + P3 * kc, kin ? BP : 0u);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v1a[q][s] = bload(r1, oa[s]);
+            v1b[q][s] = bload(r1, ob[s]);
+            v2c[q][s] = bload(r2, oc[s]);
+            v2d[q][s] = bload(r2, od[s]);
+            vp[q][s] = bload(rp, oe[s]);
+        }
+    }
+    double c1[2 * W + 1], c2[2 * W + 1];
+    load_band_row<W>(tm, i, i < nM, c1);
+    load_band_row<W>(tm, j, j < nM, c2);
+    const uint32_t oo = act ? 8u * (i + nM * j) : OOB;
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int idx = threadIdx.x + s * NT;
+            if (idx < SR * SW) {
+                const double gv = (v1a[q][s] - v1b[q][s]) + (v2c[q][s] - v2d[q][s]) +
+                                  (v3[q + 1][s] - v3[q][s]);
+                gs[q * SR * SW + idx] = gv;
+                zs[q * SR * SW + idx] = zg * gv + vp[q][s];
+            }
+        }
+    __syncthreads();
+    for (int q = 0; q < NP; ++q) {
+        const double* gq = gs + q * SR * SW;
+        const double* zq = zs + q * SR * SW;
+        for (int rr = g; rr < SR; rr += T2) {
+            double sg = 0.0, sz = 0.0;
+#pragma unroll
+            for (int t = 0; t <= 2 * W; ++t) {
+                sg += c1[t] * gq[rr * SW + c + t];
+                sz += c1[t] * zq[rr * SW + c + t];
+            }
+            pg[q * SR * T1 + rr * T1 + c] = sg;
+            pz[q * SR * T1 + rr * T1 + c] = sz;
+        }
+    }
+    __syncthreads();
+    double sgv[NP], szv[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+        double sg = 0.0, sz = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            sg += c2[t] * pg[q * SR * T1 + (g + t) * T1 + c];
+            sz += c2[t] * pz[q * SR * T1 + (g + t) * T1 + c];
+        }
+        sgv[q] = sg;
+        szv[q] = sz;
+    }
+#pragma unroll
+    for (int o = 0; o < KC; ++o) {
+        const int k = k0 + o;
+        const bool on = k < kend;
+        const int kc = on ? k : k0;
+        Window<W> wg, wz;
+#pragma unroll
+        for (int t = 0; t <= 2 * W; ++t) {
+            wg.v[t] = sgv[o + t];
+            wz.v[t] = szv[o + t];
+        }
+        const double* rm = tm + kc * (2 * W + 1);
+        const double py = wg.dot(rm);
+        const double pw = wz.dot(rm);
+        bstore(make_rsrc(ypr + P3 * kc, (on && need_g) ? 8u * (uint32_t)P3 : 0u), oo, py);
+        bstore(make_rsrc(wv + P3 * kc, (on && need_z) ? 8u * (uint32_t)P3 : 0u), oo, pw);
+    }
+}
+
+template <int P, int KC>
+constexpr int pres_all_lds_doubles() {
+    constexpr int W = P - 1, SW = T1 + 2 * W, SR = T2 + 2 * W, NP = KC + 2 * W;
+    return NP * (2 * SR * SW + 2 * SR * T1);
+}
+
 // ---- velocity component C --------------------------------------------------------------
 template <int P, int C>
 __device__ void vel_component(const OpArgs& a, const Fields& out, const Fields& src, double alpha,
@@ -1002,6 +1161,27 @@ hipError_t vel_all_attr() {
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)(sizeof(double) * vel_all_lds_doubles<P, KC>()));
 }
+template <int P, int KC>
+void launch_pres_all(dim3 grid, hipStream_t st, const OpArgs& a, double* yp, long long syp) {
+    constexpr size_t shm = sizeof(double) * pres_all_lds_doubles<P, KC>();
+    hipLaunchKernelGGL((k_pres_all<P, KC>), grid, dim3(NT), shm, st, a, yp, syp);
+}
+template <int P, int KC>
+hipError_t pres_all_attr() {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pres_all<P, KC>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(sizeof(double) * pres_all_lds_doubles<P, KC>()));
+}
+// the all-planes pressure kernels: degrees 2, 3 x chunks 2, 4 (null: stream)
+PresLaunch pres_all_launch(int P, int kc) {
+    switch (P * 16 + kc) {
+        case 2 * 16 + 2: return launch_pres_all<2, 2>;
+        case 2 * 16 + 4: return launch_pres_all<2, 4>;
+        case 3 * 16 + 2: return launch_pres_all<3, 2>;
+        case 3 * 16 + 4: return launch_pres_all<3, 4>;
+        default: return nullptr;
+    }
+}
 // the all-planes velocity kernels: degrees 2..4 x chunks 2, 4, 8 (8: degree <= 3)
 VelLaunch vel_all_launch(int P, int kc) {
     switch (P * 16 + kc) {
@@ -1024,7 +1204,9 @@ bool op_staged_ok(int degree, int kchunk) { return vel_all_launch(degree, kchunk
 hipError_t ops_init_attributes() {
     const hipError_t es[] = {vel_all_attr<2, 2>(), vel_all_attr<2, 4>(), vel_all_attr<2, 8>(),
                              vel_all_attr<3, 2>(), vel_all_attr<3, 4>(), vel_all_attr<3, 8>(),
-                             vel_all_attr<4, 2>(), vel_all_attr<4, 4>()};
+                             vel_all_attr<4, 2>(), vel_all_attr<4, 4>(),
+                             pres_all_attr<2, 2>(), pres_all_attr<2, 4>(),
+                             pres_all_attr<3, 2>(), pres_all_attr<3, 4>()};
     for (hipError_t e : es)
         if (e != hipSuccess) return e;
     return hipSuccess;
@@ -1097,13 +1279,15 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     if (!src) beta = 0.0;
     double* yp = out.f[3];
     const long long syp = out.stride[3];
+    const PresLaunch pall = (sh.staged && (mode == OP_K || mode == OP_A))
+                                ? pres_all_launch(P, a.kchunk) : nullptr;
     auto pres = [&](int lo, int hi) {
         a.kbase = lo;
         a.klim = hi;
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
         dim3 grid(a.nblocks);
-        pres_launch[P](grid, c->stream, a, yp, syp);
+        (pall ? pall : pres_launch[P])(grid, c->stream, a, yp, syp);
     };
     const VelLaunch vall = (sh.staged && (mode == OP_K || mode == OP_A))
                                ? vel_all_launch(P, a.kchunk) : nullptr;

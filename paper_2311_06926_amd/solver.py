@@ -34,7 +34,7 @@ class Solver:
 
     def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
                  precision="fp64", krylov="minres", restart=50, maxit=1000, order=2,
-                 iters=1, max_rhs=1, check_every=6, use_graph=False, autotune=True,
+                 iters=1, max_rhs=1, poll_lag=1, use_graph=False, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
                  device=None):
@@ -54,7 +54,7 @@ class Solver:
         o.order = order
         o.iters = iters
         o.max_rhs = max_rhs
-        o.check_every = check_every
+        o.poll_lag = poll_lag
         o.use_graph = int(use_graph)
         o.autotune = int(bool(autotune))
         o.op_kchunk = op_kchunk

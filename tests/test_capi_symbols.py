@@ -42,7 +42,7 @@ def test_binding_signatures_cover_the_header():
     assert opts.autotune == 1 and opts.op_kchunk == 0 and opts.op_order == -1 and opts.fd_plan == -1
     assert opts.op_slabs == 0 and opts.schur_level == 0
     assert opts.schur_pcg_iters == 20 and opts.schur_pcg_tol == 1e-2 and opts.op_fused == -1
-    assert opts.op_staged == -1 and opts.use_graph == 0
+    assert opts.op_staged == -1 and opts.use_graph == 0 and opts.poll_lag == 1
     assert lib.hp_status_string(-6) == b"not converged within maxit"
 
 
@@ -66,7 +66,8 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
                        ("op_slabs", -1), ("schur_level", -1), ("schur_level", 7),
                        ("schur_variant", 0), ("schur_variant", 4), ("schur_pcg_iters", 0),
                        ("schur_pcg_tol", -1.0), ("op_fused", -2), ("op_fused", 2),
-                       ("op_staged", -2), ("op_staged", 2), ("use_graph", -1), ("use_graph", 2)):
+                       ("op_staged", -2), ("op_staged", 2), ("use_graph", -1), ("use_graph", 2),
+                       ("poll_lag", 0), ("poll_lag", 4)):
         opts = _lib.hp_opts()
         lib.hp_default_opts(ctypes.byref(opts))
         setattr(opts, field, bad)
