@@ -247,6 +247,9 @@ def main():
                     help="--only solve/apply_K/apply_P0: force the operator i3-chunk (no autotuning)")
     ap.add_argument("--op-order", type=int, default=-1,
                     help="--only solve/apply_K/apply_P0: force the velocity workgroup order")
+    ap.add_argument("--op-staged", type=int, default=-1,
+                    help="--only solve/apply_K/apply_P0: force the all-planes operator kernels "
+                         "(1) or the streaming ones (0); -1: tuned")
     ap.add_argument("--fd-plan", type=int, default=-1,
                     help="--only solve/apply_P0: force the fast-diagonalisation plan (-1: tuned)")
     ap.add_argument("--no-sweep", action="store_true")
@@ -302,7 +305,8 @@ def main():
         sol = Solver(E, p, 1.0, precision=args.prec,
                      krylov="minres" if args.prec == "fp64" else "fgmres",
                      autotune=not forced, op_kchunk=args.op_kchunk, op_order=args.op_order,
-                     op_slabs=1 if forced else 0, fd_plan=args.fd_plan)
+                     op_slabs=1 if forced else 0, fd_plan=args.fd_plan,
+                     op_staged=args.op_staged)
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
         fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
@@ -314,7 +318,8 @@ def main():
     log(f"[bench] setup E={E} p={p} q={q} k={k} N={N}")
     forced = args.op_kchunk > 0
     sol = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, fd_plan=args.fd_plan,
-                 op_kchunk=args.op_kchunk, op_order=args.op_order, op_slabs=1 if forced else 0)
+                 op_kchunk=args.op_kchunk, op_order=args.op_order, op_slabs=1 if forced else 0,
+                 op_staged=args.op_staged)
     stream = sol.stream
     b = sol.build_rhs([1.0])
     x, info = sol.solve(b, 1e-8)

@@ -1174,27 +1174,23 @@ hipError_t pres_all_attr() {
 }
 // the all-planes pressure kernels: degrees 2, 3 x chunks 2, 4 (null: stream)
 PresLaunch pres_all_launch(int P, int kc) {
-    switch (P * 16 + kc) {
-        case 2 * 16 + 2: return launch_pres_all<2, 2>;
-        case 2 * 16 + 4: return launch_pres_all<2, 4>;
-        case 3 * 16 + 2: return launch_pres_all<3, 2>;
-        case 3 * 16 + 4: return launch_pres_all<3, 4>;
-        default: return nullptr;
-    }
+    if (P == 2 && kc == 2) return launch_pres_all<2, 2>;
+    if (P == 2 && kc == 4) return launch_pres_all<2, 4>;
+    if (P == 3 && kc == 2) return launch_pres_all<3, 2>;
+    if (P == 3 && kc == 4) return launch_pres_all<3, 4>;
+    return nullptr;
 }
 // the all-planes velocity kernels: degrees 2..4 x chunks 2, 4, 8 (8: degree <= 3)
 VelLaunch vel_all_launch(int P, int kc) {
-    switch (P * 16 + kc) {
-        case 2 * 16 + 2: return launch_vel_all<2, 2>;
-        case 2 * 16 + 4: return launch_vel_all<2, 4>;
-        case 2 * 16 + 8: return launch_vel_all<2, 8>;
-        case 3 * 16 + 2: return launch_vel_all<3, 2>;
-        case 3 * 16 + 4: return launch_vel_all<3, 4>;
-        case 3 * 16 + 8: return launch_vel_all<3, 8>;
-        case 4 * 16 + 2: return launch_vel_all<4, 2>;
-        case 4 * 16 + 4: return launch_vel_all<4, 4>;
-        default: return nullptr;
-    }
+    if (P == 2 && kc == 2) return launch_vel_all<2, 2>;
+    if (P == 2 && kc == 4) return launch_vel_all<2, 4>;
+    if (P == 2 && kc == 8) return launch_vel_all<2, 8>;
+    if (P == 3 && kc == 2) return launch_vel_all<3, 2>;
+    if (P == 3 && kc == 4) return launch_vel_all<3, 4>;
+    if (P == 3 && kc == 8) return launch_vel_all<3, 8>;
+    if (P == 4 && kc == 2) return launch_vel_all<4, 2>;
+    if (P == 4 && kc == 4) return launch_vel_all<4, 4>;
+    return nullptr;
 }
 
 }  // namespace

@@ -207,7 +207,7 @@ def test_batched_solve_full_size(dev):
     sol.close()
 
 
-@pytest.mark.parametrize("E,p", [(8, 3), (15, 3), (5, 2), (4, 4)])
+@pytest.mark.parametrize("E,p", [(8, 3), (15, 3), (5, 2), (4, 4), (20, 3), (19, 2)])
 def test_operator_shapes_agree_bitwise(dev, E, p):
     from paper_2311_06926_amd.solver import Solver
     say(f"[shapes] operators E={E} p={p}")
@@ -225,15 +225,20 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
     nM = E + p - 1
     shapes = [(kc, order, slabs, 0) for kc in sorted({1, 2, 5, nM}) for order in (0, 1)
               for slabs in (1, 3)]
-    # the all-planes velocity kernel (K and A; chunks 2, 4, 8, degree <= 4, 8 only to 3)
-    shapes += [(kc, order, slabs, 1) for kc in (2, 4, 8) if p <= 4 and (kc < 8 or p <= 3)
+    # the all-planes kernels (K and A; chunks 2, 4, 8, degree <= 4, 8 only to 3); other
+    # chunks requested with op_staged=1 must fall back to the streaming kernels
+    def has_staged(kc):
+        return kc in (2, 4, 8) and p <= 4 and (kc < 8 or p <= 3)
+
+    shapes += [(kc, order, slabs, 1) for kc in (2, 3, 4, 5, 8, 18, 20, 36, 52)
                for order in (0, 1) for slabs in (1, 3)]
     for kc, order, slabs, staged in shapes:
         s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=order,
                    op_slabs=slabs, op_staged=staged)
         t = s.tuning(1)
-        assert t["op_kchunk"] == min(kc, nM) and t["op_order"] == order
-        assert t["op_slabs"] == slabs and t["op_staged"] == (staged if kc <= nM else 0)
+        kk = min(kc, nM)
+        assert t["op_kchunk"] == kk and t["op_order"] == order and t["op_slabs"] == slabs
+        assert t["op_staged"] == (1 if staged and has_staged(kk) else 0), (kc, t)
         for a, b in zip(run(s), ref):
             assert torch.equal(a, b), (kc, order, slabs, staged)
         s.close()
