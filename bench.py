@@ -366,15 +366,16 @@ def main():
 
     # ---- the same solve with each iteration replayed as a captured HIP graph
     # against direct launches (the default; identical results)
-    modes = {}
+    launch_modes = {}
     if not args.no_sweep:
         for g in (True, False):
             s2 = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, use_graph=g)
             b2 = s2.build_rhs([1.0])
             _, inf2, t2 = timed_solve(s2, b2, 5)
-            modes["graph" if g else "direct"] = {"iterations": inf2.iterations, "ms": 1e3 * t2}
+            launch_modes["graph" if g else "direct"] = {"iterations": inf2.iterations,
+                                                        "ms": 1e3 * t2}
             s2.close()
-        log(f"[bench] launch modes: {modes}")
+        log(f"[bench] launch modes: {launch_modes}")
 
     # ---- sweep q x k
     sweep = {}
@@ -567,7 +568,7 @@ def main():
         "operators": ops,
         "roofline": roof,
         "cpu_baseline": cpu,
-        "launch_modes": modes,
+        "launch_modes": launch_modes,
         "sweep": sweep,
         "spectra": spectra,
         "schur_options": schur_opts,
