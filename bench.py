@@ -481,14 +481,20 @@ def main():
         _, i1, t1s = timed_solve(s1, b1, 3)
         s64 = Solver(Eb, pb, 1.0, krylov="fgmres", precision="fp64", order=2, iters=1, max_rhs=R)
         _, ib64, tb64 = timed_solve(s64, bb, 2)
+        # the same batch with every Arnoldi step replayed as a captured graph
+        sg = Solver(Eb, pb, 1.0, krylov="fgmres", precision="fp32", order=2, iters=1, max_rhs=R,
+                    use_graph=True)
+        _, ibg, tbg = timed_solve(sg, bb, 2)
         batched = {"rhs": R, "N": sb.N, "ms": 1e3 * tb, "iterations": ib.iterations,
                    "true_relres": ib.true_relres, "dofs": R * sb.N / tb,
                    "single_rhs_ms": 1e3 * t1s, "speedup_vs_sequential": R * t1s / tb,
-                   "fp64_batched_ms": 1e3 * tb64, "speedup_vs_fp64_batched": tb64 / tb}
+                   "fp64_batched_ms": 1e3 * tb64, "speedup_vs_fp64_batched": tb64 / tb,
+                   "graph_ms": 1e3 * tbg, "graph_iterations": ibg.iterations}
         log(f"[bench] batched: {batched}")
         sb.close()
         s1.close()
         s64.close()
+        sg.close()
         # ---- apply_K on an HBM-sized mesh
         Eh = args.hbm_E
         sh = Solver(Eh, p, 1.0)
