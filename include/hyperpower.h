@@ -120,10 +120,11 @@ typedef struct hp_opts {
                               sqrt(r.P^{-1}r) has dropped by this factor (default 1e-2) */
     int op_fused;       /* operator K and A: -1 = tuned/model (default), 0 = the pressure
                            and velocity kernels, 1 = one single-pass kernel (degree <= 4) */
-    int op_staged;      /* operator K and A velocity kernel: -1 = tuned/model (default),
-                           0 = streams its i3-planes, 1 = loads all planes of its chunk at
-                           once (degree <= 4, op_kchunk 2, 4 or 8 (8: degree <= 3));
-                           same results bit for bit */
+    int op_staged;      /* operator kernels: -1 = tuned/model (default), 0 = stream their
+                           i3-planes, 1 = load all planes of a chunk at once where such a
+                           kernel exists (velocity, modes K and A: degree <= 4 and op_kchunk
+                           2, 4 or 8, 8 only to degree 3; pressure chain: degree <= 3 and
+                           op_kchunk 2 or 4); same results bit for bit */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */

@@ -60,10 +60,12 @@ struct Extra {
     MinresScalars* hmsc[2] = {nullptr, nullptr};  // pinned host mirrors
     MinresScalars* dmsc[2] = {nullptr, nullptr};  // their device addresses
     double* mpart = nullptr;   // 2 x DOT partials per rhs
-    // partials of the velocity part of the MINRES (z_new . v_new), written by
-    // the last fast-diagonalisation launch of P_V (3 nM per rhs); zeroed
-    // once, the slots of planes a field lacks stay zero
+    // partials of the MINRES (z_new . v_new), written by the last
+    // fast-diagonalisation launch of the V block (mfg) and of the Q block
+    // (mfq), fd_dot_count per rhs each; zeroed once, slots no workgroup
+    // reaches stay zero
     double* mfg = nullptr;
+    double* mfq = nullptr;
     hipEvent_t mev[4] = {nullptr, nullptr, nullptr, nullptr};  // ring of iteration ends
     hipStream_t cap = nullptr;  // non-blocking stream used only for graph capture
     // cached iteration graphs (one per buffer-rotation phase)
@@ -267,8 +269,8 @@ Fields hq_slot(hp_ctx* c, int level, int slot) {
 // with the sum evaluated in Horner form, s_1 = x, s_{i+1} = x + (I - S X) s_i,
 // so that y = X_{k-1} s_q (one fused update per term instead of two).
 hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
-                     int prec) {
-    if (level == 0) return launch_P0(c, x, y, false, true, false, prec, nrhs);
+                     int prec, const FdDot* dot = nullptr) {
+    if (level == 0) return launch_P0(c, x, y, false, true, false, prec, nrhs, dot);
     Fields sa = hq_slot(c, level, 0), sb = hq_slot(c, level, 1), t = hq_slot(c, level, 2);
     const int lv = l_of(c, level);
     const bool pcg = c->opts.schur_variant == HP_SCHUR_PCG;  // fixed S_pcg (eq. Pcq2 form)
@@ -286,30 +288,37 @@ hipError_t apply_PQ1(hp_ctx* c, int q, int level, const Fields& x, const Fields&
             e = pcg ? apply_Spcg(c, q, t, t, nrhs, prec) : apply_Stilde(c, q, lv, t, t, nrhs, prec);
         }
         if (e != hipSuccess) return e;
+        if (level == 1 && i == q - 1) {
+            // the last s_q = x + s_{q-1} - t is formed where the final
+            // P_{Q,0}^{-1} reads it (the same arithmetic, one launch fewer)
+            const FdComb comb{*s, t, 1.0, 1.0, -1.0};
+            return launch_P0(c, x, y, false, true, false, prec, nrhs, dot, &comb);
+        }
         const Fields* sn = (s == &sa) ? &sb : &sa;
         e = pres_axpbypcz(c, 1.0, x, 1.0, *s, -1.0, t, *sn, nrhs);  // s_{i+1} = x + s_i - t
         if (e != hipSuccess) return e;
         s = sn;
     }
-    return apply_PQ1(c, q, level - 1, *s, y, nrhs, prec);
+    return apply_PQ1(c, q, level - 1, *s, y, nrhs, prec, dot);
 }
 
 // y = P_{Q,level}^{-1} x for eq. Pcq2 with the fixed S~_l, l = opts.schur_level
 // (option (1) of Sec. 4.1 for l = 0, option (2) for l > 0): q^level
 // Richardson steps.
 hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields& y, int nrhs,
-                     int prec) {
-    hipError_t e = launch_P0(c, x, y, false, true, false, prec, nrhs);
-    if (e != hipSuccess) return e;
+                     int prec, const FdDot* dot = nullptr) {
     long long steps = 1;
     for (int i = 0; i < level; ++i) steps *= q;
+    hipError_t e = launch_P0(c, x, y, false, true, false, prec, nrhs, steps == 1 ? dot : nullptr);
+    if (e != hipSuccess) return e;
     Fields t = hq_slot(c, 0, 0);
     for (long long j = 1; j < steps; ++j) {
         e = apply_Stilde(c, q, c->opts.schur_level, y, t, nrhs, prec);  // t = S~_l y
         if (e != hipSuccess) return e;
         e = fields_axpby(c, x, t, 1.0, -1.0, false, true, nrhs);    // t = x - t
         if (e != hipSuccess) return e;
-        e = launch_P0(c, t, y, false, true, true, prec, nrhs);       // y += P_Q0^{-1} t
+        e = launch_P0(c, t, y, false, true, true, prec, nrhs,       // y += P_Q0^{-1} t
+                      j + 1 == steps ? dot : nullptr);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -320,9 +329,8 @@ hipError_t apply_PQ2(hp_ctx* c, int q, int level, const Fields& x, const Fields&
 // workspace and residual slot (fork/join through events, which also holds
 // under stream capture) while the V block runs on the context stream.
 // Optional dot product of the result with `with` (a full vector), as
-// partials: the velocity part from the V block's last launch (3 nM per rhs,
-// into vpart), the pressure part by a dot kernel behind the Q block (into
-// qpart, vec_dot_partial_count() per rhs).
+// partials written by the last launch of each block: the velocity part into
+// vpart, the pressure part into qpart (fd_dot_count(c, true / false) per rhs).
 struct PkDot {
     const double* with;
     double* vpart;
@@ -333,15 +341,12 @@ struct PkDot {
 hipError_t pk_q_block(hp_ctx* c, int q, int k, const double* x, double* y, int nrhs,
                       const PkDot* pd) {
     const int prec = c->opts.precision;
-    hipError_t e;
+    const FdDot qdot = pd ? FdDot{pd->with, pd->qpart} : FdDot{};
     if (c->opts.schur_variant == HP_SCHUR_PCQ2)
-        e = apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-    else
-        e = apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec);
-    const long long oq = c->off[3];
-    if (e == hipSuccess && pd)
-        e = vec_dot_partials(c->stream, c->nQ, c->N, y + oq, pd->with + oq, nrhs, pd->qpart);
-    return e;
+        return apply_PQ2(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec,
+                         pd ? &qdot : nullptr);
+    return apply_PQ1(c, q, k, pres_of_full(c, x), pres_of_full(c, y), nrhs, prec,
+                     pd ? &qdot : nullptr);
 }
 
 // The V block of P_k (and the velocity part of the dot) on c->stream.
@@ -479,7 +484,7 @@ hipError_t minres_a(hp_ctx* c, const MinresBufs& b, int nrhs, int cur) {
 }
 PkDot minres_pk_dot(hp_ctx* c, const MinresBufs& b) {
     Extra* ex = extra_of(c);
-    return PkDot{b.vn, ex->mfg, ex->mpart + vec_partial_doubles(1, c->opts.max_rhs)};
+    return PkDot{b.vn, ex->mfg, ex->mfq};
 }
 hipError_t minres_q(hp_ctx* c, const MinresBufs& b, int nrhs) {
     const PkDot pd = minres_pk_dot(c, b);
@@ -496,8 +501,8 @@ hipError_t minres_w_step(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
     const int R = c->opts.max_rhs;
     const PkDot pd = minres_pk_dot(c, b);
     return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, ex->msc + cur * R,
-                    ex->msc + (cur ^ 1) * R, Partials{pd.vpart, 3LL * c->nM},
-                    Partials{pd.qpart, vec_dot_partial_count()}, tol, mirror);
+                    ex->msc + (cur ^ 1) * R, Partials{pd.vpart, fd_dot_count(c, true)},
+                    Partials{pd.qpart, fd_dot_count(c, false)}, tol, mirror);
 }
 
 hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
@@ -1365,8 +1370,10 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[0]), ex->hmsc[0], 0) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[1]), ex->hmsc[1], 0) != hipSuccess ||
         alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
-        alloc_device(&ex->mfg, (size_t)3 * c->nM * R) != HP_OK ||
-        hipMemset(ex->mfg, 0, sizeof(double) * 3 * c->nM * R) != hipSuccess ||
+        alloc_device(&ex->mfg, (size_t)fd_dot_count(c, true) * R) != HP_OK ||
+        alloc_device(&ex->mfq, (size_t)fd_dot_count(c, false) * R) != HP_OK ||
+        hipMemset(ex->mfg, 0, sizeof(double) * fd_dot_count(c, true) * R) != hipSuccess ||
+        hipMemset(ex->mfq, 0, sizeof(double) * fd_dot_count(c, false) * R) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[2], hipEventDisableTiming) != hipSuccess ||
@@ -1610,6 +1617,7 @@ void hp_destroy(hp_ctx* c) {
     if (ex->hmsc[1]) (void)hipHostFree(ex->hmsc[1]);
     if (ex->mpart) (void)hipFree(ex->mpart);
     if (ex->mfg) (void)hipFree(ex->mfg);
+    if (ex->mfq) (void)hipFree(ex->mfq);
     if (ex->cgv) (void)hipFree(ex->cgv);
     if (ex->cgcoef) (void)hipFree(ex->cgcoef);
     if (ex->cgpart) (void)hipFree(ex->cgpart);

@@ -111,7 +111,31 @@ struct XYArgs {
     double* dpart;
     long long dp_stride;
     int dp_planes;
+    // FP64 input only: for a field with inb[f] set, the input is
+    // ca in + cb inb + cc inc (the same layout as in, rhs strides sinb, sinc)
+    const double* inb[4];
+    const double* inc[4];
+    long long sinb[4], sinc[4];
+    double ca, cb, cc;
 };
+
+// Element e of plane k (right-hand side r) of the forward input of field f,
+// x pointing at that plane of in[f]: x[e], or the combination
+// ca in + cb inb + cc inc, formed in the operation order of the vector
+// kernel k_axpbypcz so that it equals reading a materialised result.
+template <typename TI>
+__device__ __forceinline__ TI xy_input(const XYArgs& a, int f, const TI* x, int r, long long kofs,
+                                       long long e) {
+    if constexpr (std::is_same<TI, double>::value) {
+        if (a.inb[f]) {
+            double v = a.ca * x[e];
+            if (a.cb != 0.0) v += a.cb * a.inb[f][(long long)r * a.sinb[f] + kofs + e];
+            if (a.cc != 0.0) v += a.cc * a.inc[f][(long long)r * a.sinc[f] + kofs + e];
+            return v;
+        }
+    }
+    return x[e];
+}
 
 // The final write-out of plane k of field f from the column-major plane S
 // (leading dimension ld): y = S, or y += S.  With a dot the workgroup also
@@ -191,13 +215,13 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
     const int nb1 = N1 >> 4, nb2 = N2 >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] +
-                  (long long)k * n1 * n2;
+    const long long kofs = (long long)k * n1 * n2;
+    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
     // load plane (zero padded)
     for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_THREADS) {
         int col = idx / N1, row = idx - col * N1;
         T v = 0;
-        if (row < n1 && col < n2) v = (T)x[row + (long long)col * n1];
+        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
         S[col * ld + row] = v;
     }
     __syncthreads();
@@ -252,6 +276,8 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
     xy_store<T, TO, FD_THREADS>(a, S, ld, f, r, k, n1, n2);
 }
 
+constexpr int ZROWS = 64;      // (i1,i2)-rows per z workgroup: 16 per wave
+
 struct ZArgs {
     const void* in[4];
     void* out[4];
@@ -260,9 +286,58 @@ struct ZArgs {
     int fields_lo, fields_hi;
     int accumulate;   // bit f set: field f is added to its output
     double two_nu;
+    // FP64 output, launches of one field only: partial sums of (stored
+    // output) . dw per workgroup to dpart[r * dp_stride + blockIdx.x]
+    const double* dw;  // same layout and rhs stride as the output
+    double* dpart;
+    long long dp_stride;
 };
 
-constexpr int ZROWS = 64;      // (i1,i2)-rows per z workgroup: 16 per wave
+// The final write-out of z rows [r0, r0 + ZROWS) of field f from the
+// row-major buffer Out (leading dimension ld): y = Out or y += Out; with a
+// dot also the workgroup's fixed-order sum of (stored value) x dw, whose
+// scratch reuses S once every read of the LDS buffers is done.
+template <typename T, typename TO, int NTH>
+__device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int ld, int f, int r,
+                                        long long r0, long long plane, int n3) {
+    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
+    if constexpr (std::is_same<TO, double>::value) {
+        if (a.dpart) {
+            const double* w = a.dw + (long long)r * a.sout[f];
+            double s = 0.0;
+            for (int idx = threadIdx.x; idx < ZROWS * n3; idx += NTH) {
+                int kk = idx / ZROWS, row = idx - kk * ZROWS;
+                if (r0 + row >= plane) continue;
+                long long o = r0 + row + (long long)kk * plane;
+                double v = (double)Out[row * ld + kk];
+                if ((a.accumulate >> f) & 1) v += y[o];
+                y[o] = v;
+                s += v * w[o];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            __syncthreads();
+            double* red = reinterpret_cast<double*>(S);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int wv = 0; wv < NTH / 64; ++wv) t += red[wv];
+                a.dpart[(long long)r * a.dp_stride + blockIdx.x] = t;
+            }
+            return;
+        }
+    }
+    for (int idx = threadIdx.x; idx < ZROWS * n3; idx += NTH) {
+        int kk = idx / ZROWS, row = idx - kk * ZROWS;
+        if (r0 + row >= plane) continue;
+        TO v = (TO)Out[row * ld + kk];
+        long long o = r0 + row + (long long)kk * plane;
+        if ((a.accumulate >> f) & 1) y[o] += v;
+        else y[o] = v;
+    }
+}
+
 
 template <typename T, typename TI, typename TO, bool STAGE>
 __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
@@ -354,15 +429,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
                 for (int i = 0; i < 4; ++i) Sw[M::row(lk, i) * ld + b * 16 + lr] = acc[b][i];
     }
     __syncthreads();
-    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
-    for (int idx = threadIdx.x; idx < ZROWS * n3; idx += FD_THREADS) {
-        int kk = idx / ZROWS, row = idx - kk * ZROWS;
-        if (r0 + row >= plane) continue;
-        TO v = (TO)S[row * ld + kk];
-        long long o = r0 + row + (long long)kk * plane;
-        if ((a.accumulate >> f) & 1) y[o] += v;
-        else y[o] = v;
-    }
+    z_store<T, TO, FD_THREADS>(a, S, S, ld, f, r, r0, plane, n3);
 }
 
 // ---- tile-per-wave variants ----------------------------------------------------------
@@ -537,12 +604,12 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nw = FD_WIDE / 64;
     const int lr = lane & 15, lk = lane >> 4;
-    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] +
-                  (long long)k * n1 * n2;
+    const long long kofs = (long long)k * n1 * n2;
+    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
     for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_WIDE) {
         int col = idx / N1, row = idx - col * N1;
         T v = 0;
-        if (row < n1 && col < n2) v = (T)x[row + (long long)col * n1];
+        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
         S[col * ld + row] = v;
     }
     // L (rows contiguous) for step 1 and R^T (rows of R^T = columns of R) for step 2
@@ -738,15 +805,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
         __syncthreads();
         Out = S;
     }
-    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
-    for (int idx = threadIdx.x; idx < ZROWS * n3; idx += FD_WIDE) {
-        int kk = idx / ZROWS, row = idx - kk * ZROWS;
-        if (r0 + row >= plane) continue;
-        TO v = (TO)Out[row * ld + kk];
-        long long o = r0 + row + (long long)kk * plane;
-        if ((a.accumulate >> f) & 1) y[o] += v;
-        else y[o] = v;
-    }
+    z_store<T, TO, FD_WIDE>(a, Out, S, ld, f, r, r0, plane, n3);
 }
 
 // LDS plan for a direction of padded size np: wide (two buffers) or in place,
@@ -804,7 +863,7 @@ bool fd_plan_fits(int np, int code) {
 
 template <typename T, bool SPLIT = false>
 hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Fields& out, bool vel,
-                  bool pres, bool accumulate, int nrhs, const FdDot* dot) {
+                  bool pres, bool accumulate, int nrhs, const FdDot* dot, const FdComb* comb) {
     // scratch for the two intermediate tensors (precision T), per rhs N values each
     const long long N = c->N;
     T* tmp1 = reinterpret_cast<T*>(c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs);
@@ -826,6 +885,17 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     xa.fields_hi = hi;
     xa.inverse = 0;
     xa.accumulate = 0;
+    if (comb) {
+        for (int f = lo; f < hi; ++f) {
+            xa.inb[f] = comb->b.f[f];
+            xa.inc[f] = comb->c.f[f];
+            xa.sinb[f] = comb->b.stride[f];
+            xa.sinc[f] = comb->c.stride[f];
+        }
+        xa.ca = comb->ca;
+        xa.cb = comb->cb;
+        xa.cc = comb->cc;
+    }
     const FDPlan pl = fd_plan<T>(NMp, fd_plan_in_use(c, std::is_same<T, double>::value ? 0 : (SPLIT ? 2 : 1)));
     const dim3 bxy(pl.wide ? FD_WIDE : FD_THREADS);
     auto launch_xy = [&](const XYArgs& xa_, bool to_double, int nfields) {
@@ -911,6 +981,11 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
             ZArgs zp = za;
             zp.fields_lo = 3;
             zp.fields_hi = 4;
+            if (dot && !vel) {
+                zp.dw = dot->with + c->off[3];
+                zp.dpart = dot->part;
+                zp.dp_stride = fd_dot_count(c, false);
+            }
             launch_z(zp, true, 1);
         }
     }
@@ -927,6 +1002,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         xi.inverse = 1;
         xi.accumulate = accumulate ? 1 : 0;
         if (dot) {
+            // xy partials: 3 nM per rhs, see fd_dot_count
             for (int f = 0; f < 3; ++f) xi.dw[f] = dot->with + c->off[f];
             xi.dpart = dot->part;
             xi.dp_stride = 3LL * nM;
@@ -1003,14 +1079,20 @@ int fd_plan_in_use(const hp_ctx* c, int precision) {
     return c->fd_tuned[precision];
 }
 
+long long fd_dot_count(const hp_ctx* c, bool vel) {
+    const long long nM = c->nM;
+    return vel ? 3 * nM : (nM * nM + ZROWS - 1) / ZROWS;
+}
+
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
-                     bool accumulate, int precision, int nrhs, const FdDot* dot) {
-    if (dot && (precision != HP_PREC_FP64 || !vel)) return hipErrorInvalidValue;
+                     bool accumulate, int precision, int nrhs, const FdDot* dot,
+                     const FdComb* comb) {
+    if (dot && (precision != HP_PREC_FP64 || (vel && pres))) return hipErrorInvalidValue;
     if (precision == HP_PREC_FP64)
-        return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs, dot);
+        return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs, dot, comb);
     if (precision == HP_PREC_BF16X3)
-        return run_P0<float, true>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr);
-    return run_P0<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr);
+        return run_P0<float, true>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr, comb);
+    return run_P0<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, nullptr, comb);
 }
 
 }  // namespace hp

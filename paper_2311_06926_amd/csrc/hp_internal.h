@@ -131,16 +131,25 @@ long long ops_ws_stride(const hp_ctx* c);
 hipError_t fd_init_attributes();
 // y = P_0^{-1} x restricted to the selected blocks (velocity and/or pressure);
 // accumulate: y += result instead of y = result.
-// dot (FP64 velocity blocks only, may be null): the last launch also writes
-// partial sums of (final output) . dot->with, one per (velocity field,
-// i3-plane), to dot->part[r * 3 * nM + f * nM + k] (planes a field lacks are
-// never written: kept zero by the caller).
+// dot (FP64, the velocity blocks or the pressure block alone; may be null):
+// the last launch also writes partial sums of (final output) . dot->with to
+// dot->part[r * fd_dot_count(c, vel) + i] -- velocity: one per (field,
+// i3-plane), i = f nM + k (planes a field lacks are never written: kept zero
+// by the caller); pressure: one per workgroup of its mode-3 launch.
+// comb (FP64, may be null): the input is ca in + cb comb->b + cc comb->c,
+// formed where the first launch reads it (as k_axpbypcz would).
 struct FdDot {
     const double* with;  // full vector, same layout and rhs stride as the output's
     double* part;
 };
+struct FdComb {
+    Fields b, c;
+    double ca, cb, cc;
+};
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,
-                     bool accumulate, int precision, int nrhs, const FdDot* dot = nullptr);
+                     bool accumulate, int precision, int nrhs, const FdDot* dot = nullptr,
+                     const FdComb* comb = nullptr);
+long long fd_dot_count(const hp_ctx* c, bool vel);
 // fast-diagonalisation plans: bit 0 = one MFMA tile per wave (wide kernels),
 // bit 1 = stage the 1D matrices in LDS.  Whether plan `plan` fits the LDS for
 // `precision`, and the plan launch_P0 uses (forced, option, tuned, default).

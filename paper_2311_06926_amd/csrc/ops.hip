@@ -294,13 +294,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     }
 }
 
-// ---- pressure chain, all planes of a chunk at once (K and A) -----------------------------
+// ---- pressure chain, all planes of a chunk at once --------------------------------------
 // The counterpart of k_vel_all for k_pres: the loads of all kc + 2w planes
 // (and the u3 plane before them) are issued at once, g and z are formed into
 // LDS, directions 1 and 2 are one pass each over all planes and direction 3
 // reads the thread's column from registers.  Same operation sequence per
-// output as k_pres (bitwise-identical results).  KC = kchunk (2 or 4),
-// degrees 2 and 3.
+// output as k_pres (bitwise-identical results), every mode k_pres serves.
+// KC = kchunk (2 or 4), degrees 2 and 3.
 template <int P, int KC>
 __global__ __launch_bounds__(NT) void k_pres_all(OpArgs a, double* yp, long long syp) {
     constexpr int W = P - 1;
@@ -1275,8 +1275,7 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     if (!src) beta = 0.0;
     double* yp = out.f[3];
     const long long syp = out.stride[3];
-    const PresLaunch pall = (sh.staged && (mode == OP_K || mode == OP_A))
-                                ? pres_all_launch(P, a.kchunk) : nullptr;
+    const PresLaunch pall = sh.staged ? pres_all_launch(P, a.kchunk) : nullptr;
     auto pres = [&](int lo, int hi) {
         a.kbase = lo;
         a.klim = hi;
