@@ -384,6 +384,26 @@ def test_graph_replay_equals_eager_and_is_deterministic(dev, krylov):
     se.close()
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_minres_poll_lag_leaves_solution_unchanged(dev, graph):
+    """The host reads the convergence flags poll_lag iterations behind the
+    device, so up to poll_lag iterations run past convergence: they must
+    leave the solution and the reported iteration count unchanged."""
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] MINRES poll_lag 1..3 graph={graph}")
+    E, p = 6, 3
+    out = []
+    for lag in (1, 2, 3):
+        s = Solver(E, p, 1.0, iters=1, poll_lag=lag, use_graph=graph, max_rhs=2)
+        b = s.build_rhs([1.0, 0.7])
+        x, info = s.solve(b, 1e-8)
+        out.append((x, info.iterations, list(info.iters_per_rhs[:2])))
+        s.close()
+    for x, its, per in out[1:]:
+        assert its == out[0][1] and per == out[0][2]
+        assert torch.equal(x, out[0][0])
+
+
 @pytest.mark.parametrize("krylov", ["minres", "fgmres"])
 def test_batched_solve_matches_single(dev, krylov):
     from paper_2311_06926_amd.solver import Solver
