@@ -97,20 +97,36 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // partial[(r*npair + q)*DOT_BLOCKS + b] = sum over block b's chunk of x_q . y
-// (x_q = X + q*xstride, one y per rhs)
+// (x_q = X + q*xstride, one y per rhs).  A workgroup takes DOT_QB pairs of
+// one chunk, so y is read once per DOT_QB pairs; each pair's sum runs in the
+// same order as with one pair per workgroup.
+constexpr int DOT_QB = 8;
+static_assert(DOT_BLOCKS <= VT, "one partial per thread in the block sums of the partials");
 __global__ void k_dot_partial(long long n, long long ld, const double* X, long long xstride,
                               int npair, const double* Y, double* partial) {
     __shared__ double sh[VT / 64];
-    const int r = blockIdx.z, q = blockIdx.y;
-    const double* x = X + (long long)q * xstride + (long long)r * ld;
+    const int r = blockIdx.z, q0 = blockIdx.y * DOT_QB;
+    const int nq = min(DOT_QB, npair - q0);
+    const double* x = X + (long long)q0 * xstride + (long long)r * ld;
     const double* y = Y + (long long)r * ld;
     const long long chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
     const long long lo = (long long)blockIdx.x * chunk;
     const long long hi = min(n, lo + chunk);
-    double s = 0.0;
-    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) s += x[i] * y[i];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) partial[((long long)r * npair + q) * DOT_BLOCKS + blockIdx.x] = s;
+    double s[DOT_QB];
+#pragma unroll
+    for (int qq = 0; qq < DOT_QB; ++qq) s[qq] = 0.0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double yv = y[i];
+#pragma unroll
+        for (int qq = 0; qq < DOT_QB; ++qq)
+            if (qq < nq) s[qq] += x[qq * xstride + i] * yv;
+    }
+#pragma unroll
+    for (int qq = 0; qq < DOT_QB; ++qq) {
+        if (qq >= nq) break;  // uniform over the workgroup
+        const double t = block_sum(s[qq], sh);
+        if (threadIdx.x == 0) partial[((long long)r * npair + q0 + qq) * DOT_BLOCKS + blockIdx.x] = t;
+    }
 }
 
 __global__ void k_dot_final(const double* partial, int count, double* out) {
@@ -217,7 +233,7 @@ hipError_t vec_lincomb(hipStream_t s, long long n, long long ld, int nrhs, int n
 hipError_t vec_multidot_async(hipStream_t s, long long n, long long ld, const double* X,
                               long long xstride, int npair, const double* Y, int nrhs,
                               double* partial, double* dout) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, npair, nrhs), dim3(VT), 0, s, n, ld, X,
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, (npair + DOT_QB - 1) / DOT_QB, nrhs), dim3(VT), 0, s, n, ld, X,
                        xstride, npair, Y, partial);
     hipLaunchKernelGGL(k_dot_final, dim3(npair * nrhs), dim3(VT), 0, s, partial, DOT_BLOCKS, dout);
     return hipGetLastError();
@@ -558,18 +574,20 @@ __global__ void k_fg_begin(FgScalars* sc, const double* part_ww, double* g, doub
     vscale[r] = s.active ? 1.0 / beta : 0.0;
 }
 
-// Gram-Schmidt pass: h_i = <V_i, w> for i <= j (sum of partials); H[:, j] (+)= h
+// Gram-Schmidt pass: h_i = <V_i, w> for i <= j; H[:, j] (+)= h.  One
+// workgroup per (i, rhs) sums that pair's partials as a block reduction (a
+// fixed order: one partial per thread, then the wave and workgroup trees).
 __global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hcoef, int j, int pass,
-                       int m, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    const FgScalars& s = sc[r];
+                       int m) {
+    __shared__ double sh[VT / 64];
+    const int i = blockIdx.x, r = blockIdx.y;
+    const long long base = ((long long)r * (j + 1) + i) * DOT_BLOCKS;
+    const double h = block_sum(threadIdx.x < DOT_BLOCKS ? part[base + threadIdx.x] : 0.0, sh);
+    if (threadIdx.x != 0) return;
+    const bool active = sc[r].active;
     double* Hr = H + (long long)r * (m + 1) * m;
-    for (int i = 0; i <= j; ++i) {
-        const double h = sum_partials(part, r * (j + 1) + i);
-        if (s.active) Hr[i * m + j] = (pass == 0 ? 0.0 : Hr[i * m + j]) + h;
-        hcoef[(long long)r * (m + 1) + i] = s.active ? h : 0.0;
-    }
+    if (active) Hr[i * m + j] = (pass == 0 ? 0.0 : Hr[i * m + j]) + h;
+    hcoef[(long long)r * (m + 1) + i] = active ? h : 0.0;
 }
 
 // h_{j+1,j} = ||w||, previous rotations on column j, new rotation, residual estimate
@@ -663,7 +681,7 @@ hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g,
 }
 hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
                 int pass, int m, int nrhs) {
-    hipLaunchKernelGGL(k_fg_h, dim3(1), rhs_block(nrhs), 0, s, sc, part, H, hcoef, j, pass, m, nrhs);
+    hipLaunchKernelGGL(k_fg_h, dim3(j + 1, nrhs), dim3(VT), 0, s, sc, part, H, hcoef, j, pass, m);
     return hipGetLastError();
 }
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
@@ -685,7 +703,7 @@ hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol
 hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
                                  long long xstride, int npair, const double* Y, int nrhs,
                                  double* partial) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, npair, nrhs), dim3(VT), 0, s, n, ld, X,
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, (npair + DOT_QB - 1) / DOT_QB, nrhs), dim3(VT), 0, s, n, ld, X,
                        xstride, npair, Y, partial);
     return hipGetLastError();
 }
