@@ -458,11 +458,17 @@ struct Vec4T<float> {
     typedef float V __attribute__((ext_vector_type(4)));
 };
 
+// K (the contraction length) is a multiple of 4: the full 16-wide chunks
+// as above, then the remaining 4, 8 or 12 values with step s taking
+// k = K16 + 4 s + lk (any assignment of k to (step, lane group) that both
+// operands share gives the same sum), so that no MFMA step multiplies only
+// zero padding.
 template <typename T, bool GA>
 __device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* G, int ldg, const T* H, int h_k,
                                                          int h_i, int K, int lr, int lk) {
     using M = Mfma<T>;
     using V4 = typename Vec4T<T>::V;
+    const int K16 = K & ~15;
     const T* gp = G + lr * ldg + 4 * lk;
     const T* hp = H + lr * h_i + 4 * lk * h_k;
     V4 g[2];
@@ -470,14 +476,23 @@ __device__ __forceinline__ typename Mfma<T>::V tile_gemm(const T* G, int ldg, co
     typename M::V acc = {0, 0, 0, 0};
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        if (16 * c >= K) break;
-        if (16 * (c + 1) < K) g[(c + 1) & 1] = *reinterpret_cast<const V4*>(gp + 16 * (c + 1));
+        if (16 * c >= K16) break;
+        if (16 * (c + 1) < K16) g[(c + 1) & 1] = *reinterpret_cast<const V4*>(gp + 16 * (c + 1));
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const T h = hp[(16 * c + s) * h_k];
             const T gv = g[c & 1][s];
             acc = GA ? M::mma(gv, h, acc) : M::mma(h, gv, acc);
         }
+    }
+    const T* gt = G + lr * ldg + K16 + lk;
+    const T* ht = H + lr * h_i + (K16 + lk) * h_k;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        if (K16 + 4 * s >= K) break;
+        const T h = ht[4 * s * h_k];
+        const T gv = gt[4 * s];
+        acc = GA ? M::mma(gv, h, acc) : M::mma(h, gv, acc);
     }
     return acc;
 }
@@ -502,10 +517,11 @@ __device__ __forceinline__ void tile_gemm_2x2(const T* G0, const T* G1, int ldg,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = typename M::V{0, 0, 0, 0};
+    const int K16 = K & ~15;  // K: a multiple of 4, the tail as in tile_gemm
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-        if (16 * c >= K) break;
-        if (16 * (c + 1) < K) {
+        if (16 * c >= K16) break;
+        if (16 * (c + 1) < K16) {
             ga[(c + 1) & 1] = *reinterpret_cast<const V4*>(gp0 + 16 * (c + 1));
             gb[(c + 1) & 1] = g1 ? *reinterpret_cast<const V4*>(gp1 + 16 * (c + 1)) : ga[(c + 1) & 1];
         }
@@ -519,6 +535,22 @@ __device__ __forceinline__ void tile_gemm_2x2(const T* G0, const T* G1, int ldg,
             acc[1][0] = GA ? M::mma(a1, x0, acc[1][0]) : M::mma(x0, a1, acc[1][0]);
             acc[1][1] = GA ? M::mma(a1, x1, acc[1][1]) : M::mma(x1, a1, acc[1][1]);
         }
+    }
+    const T* gt0 = G0 + lr * ldg + K16 + lk;
+    const T* gt1 = G1 + lr * ldg + K16 + lk;
+    const T* ht0 = H0 + lr * h_i + (K16 + lk) * h_k;
+    const T* ht1 = H1 + lr * h_i + (K16 + lk) * h_k;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        if (K16 + 4 * s >= K) break;
+        const T x0 = ht0[4 * s * h_k];
+        const T x1 = h1 ? ht1[4 * s * h_k] : x0;
+        const T a0 = gt0[4 * s];
+        const T a1 = g1 ? gt1[4 * s] : a0;
+        acc[0][0] = GA ? M::mma(a0, x0, acc[0][0]) : M::mma(x0, a0, acc[0][0]);
+        acc[0][1] = GA ? M::mma(a0, x1, acc[0][1]) : M::mma(x1, a0, acc[0][1]);
+        acc[1][0] = GA ? M::mma(a1, x0, acc[1][0]) : M::mma(x0, a1, acc[1][0]);
+        acc[1][1] = GA ? M::mma(a1, x1, acc[1][1]) : M::mma(x1, a1, acc[1][1]);
     }
 }
 
@@ -571,11 +603,13 @@ __device__ __forceinline__ f4 tile_gemm_bf16x3(const float* G, int ldg, const fl
 // dispatch of a 16x16 tile product: native MFMA of T, or split BF16 (T = float)
 template <typename T, bool SPLIT, bool GA>
 __device__ __forceinline__ typename Mfma<T>::V tile_mm(const T* G, int ldg, const T* H, int h_k,
-                                                       int h_i, int K, int lr, int lk) {
+                                                       int h_i, int n, int lr, int lk) {
+    // n: the contraction's true length; the operands are zero from n to the
+    // next multiple of 16
     if constexpr (SPLIT) {
-        return tile_gemm_bf16x3<GA>(G, ldg, H, h_k, h_i, K, lr, lk);
+        return tile_gemm_bf16x3<GA>(G, ldg, H, h_k, h_i, (n + 15) & ~15, lr, lk);
     } else {
-        return tile_gemm<T, GA>(G, ldg, H, h_k, h_i, K, lr, lk);
+        return tile_gemm<T, GA>(G, ldg, H, h_k, h_i, (n + 3) & ~3, lr, lk);
     }
 }
 
@@ -637,8 +671,8 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
             const bool g1 = 2 * RB + 1 < nb1, h1 = 2 * CB + 1 < nb2;
             if (mine)
                 tile_gemm_2x2<T, true>(L + 2 * RB * 16 * ldL, L + (2 * RB + 1) * 16 * ldL, ldL,
-                                       S + 2 * CB * 16 * ld, S + (2 * CB + 1) * 16 * ld, 1, ld, N1,
-                                       lr, lk, g1, h1, bacc);
+                                       S + 2 * CB * 16 * ld, S + (2 * CB + 1) * 16 * ld, 1, ld,
+                                       (n1 + 3) & ~3, lr, lk, g1, h1, bacc);
             __syncthreads();
             if (mine)
 #pragma unroll
@@ -659,8 +693,8 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
             const bool gc1 = 2 * CB2 + 1 < nb2, hr1 = 2 * RB2 + 1 < nb1;
             if (mine2)
                 tile_gemm_2x2<T, false>(Rt + 2 * CB2 * 16 * ldR, Rt + (2 * CB2 + 1) * 16 * ldR, ldR,
-                                        S + 2 * RB2 * 16, S + (2 * RB2 + 1) * 16, ld, 1, N2, lr, lk,
-                                        gc1, hr1, bacc);
+                                        S + 2 * RB2 * 16, S + (2 * RB2 + 1) * 16, ld, 1,
+                                        (n2 + 3) & ~3, lr, lk, gc1, hr1, bacc);
             __syncthreads();
             if (mine2)
 #pragma unroll
@@ -686,7 +720,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
         const int tt = wave + m * nw;
         if (tt < ntile) {
             const int rb = tt % nb1, cb = tt / nb1;
-            acc[m] = tile_mm<T, SPLIT, true>(L + rb * 16 * ldL, ldL, S + cb * 16 * ld, 1, ld, N1,
+            acc[m] = tile_mm<T, SPLIT, true>(L + rb * 16 * ldL, ldL, S + cb * 16 * ld, 1, ld, n1,
                                              lr, lk);
         }
     }
@@ -707,7 +741,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
         const int tt = wave + m * nw;
         if (tt < ntile) {
             const int rb = tt % nb1, cb = tt / nb1;
-            acc[m] = tile_mm<T, SPLIT, false>(Rt + cb * 16 * ldR, ldR, S + rb * 16, ld, 1, N2, lr,
+            acc[m] = tile_mm<T, SPLIT, false>(Rt + cb * 16 * ldR, ldR, S + rb * 16, ld, 1, n2, lr,
                                               lk);
         }
     }
@@ -774,7 +808,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const double* l3 = (f == 2) ? t.lamK : t.lamT;
     for (int tt = wave; tt < ntile; tt += nw) {
         const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-        auto acc = tile_mm<T, SPLIT, false>(U3t + cb * 16 * ldU, ldU, S + rb * 16 * ld, 1, ld, N3, lr, lk);
+        auto acc = tile_mm<T, SPLIT, false>(U3t + cb * 16 * ldU, ldU, S + rb * 16 * ld, 1, ld, n3, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = rb * 16 + M::row(lk, i);
@@ -798,7 +832,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     if (!pres) {
         for (int tt = wave; tt < ntile; tt += nw) {
             const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
-            auto acc = tile_mm<T, SPLIT, false>(U3 + cb * 16 * ldU, ldU, Y + rb * 16 * ld, 1, ld, N3, lr, lk);
+            auto acc = tile_mm<T, SPLIT, false>(U3 + cb * 16 * ldU, ldU, Y + rb * 16 * ld, 1, ld, n3, lr, lk);
 #pragma unroll
             for (int i = 0; i < 4; ++i) S[(rb * 16 + M::row(lk, i)) * ld + cb * 16 + lr] = acc[i];
         }
