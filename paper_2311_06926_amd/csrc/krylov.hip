@@ -591,7 +591,7 @@ __global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hco
 }
 
 // h_{j+1,j} = ||w||, previous rotations on column j, new rotation, residual estimate
-__device__ void fg_rot_one(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
+__device__ void fg_rot_one(FgScalars* sc, double ww, double* H, double* cs, double* sn,
                            double* g, double* vscale, double tol, int j, int m, int r) {
     FgScalars& s = sc[r];
     if (!s.active) {
@@ -602,7 +602,7 @@ __device__ void fg_rot_one(FgScalars* sc, const double* part_ww, double* H, doub
     double* cr = cs + (long long)r * m;
     double* sr = sn + (long long)r * m;
     double* gr = g + (long long)r * (m + 1);
-    const double hn = sqrt(sum_partials(part_ww, r));
+    const double hn = sqrt(ww);
     Hr[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
         const double t = cr[i] * Hr[i * m + j] + sr[i] * Hr[(i + 1) * m + j];
@@ -629,13 +629,18 @@ __device__ void fg_rot_one(FgScalars* sc, const double* part_ww, double* H, doub
     vscale[r] = s.active ? 1.0 / hn : 0.0;
 }
 
-// mirror: host-mapped copy of the scalars (may be null), refreshed after the step
+// mirror: host-mapped copy of the scalars (may be null), refreshed after the step.
+// One workgroup per rhs: ||w||^2 from its partials as a block reduction, then
+// the rotations in thread 0.
 __global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
-                         double* g, double* vscale, double tol, int j, int m, int nrhs,
+                         double* g, double* vscale, double tol, int j, int m,
                          FgScalars* mirror) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    fg_rot_one(sc, part_ww, H, cs, sn, g, vscale, tol, j, m, r);
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double ww = block_sum(
+        threadIdx.x < DOT_BLOCKS ? part_ww[(long long)r * DOT_BLOCKS + threadIdx.x] : 0.0, sh);
+    if (threadIdx.x != 0) return;
+    fg_rot_one(sc, ww, H, cs, sn, g, vscale, tol, j, m, r);
     if (mirror) mirror[r] = sc[r];
 }
 
@@ -687,8 +692,8 @@ hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, dou
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
                   double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs,
                   FgScalars* mirror) {
-    hipLaunchKernelGGL(k_fg_rot, dim3(1), rhs_block(nrhs), 0, s, sc, part, H, cs, sn, g, vscale, tol,
-                       j, m, nrhs, mirror);
+    hipLaunchKernelGGL(k_fg_rot, dim3(nrhs), dim3(VT), 0, s, sc, part, H, cs, sn, g, vscale, tol,
+                       j, m, mirror);
     return hipGetLastError();
 }
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
