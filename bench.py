@@ -16,6 +16,10 @@ The JSON line also carries
   spectra     Lanczos spectra of P_0 (GPU), the predicted condition numbers and
               MINRES bound per k (Corollary cor:Skform), and the (q, k) they
               choose a priori against the sweep's fastest
+  quadrature_forward  the quadrature-based forward operator of Sec. 5.3
+              (apply_K_quad) against apply_K, and the solve with it as the
+              Krylov loop's forward problem for k = 0, 1, 2 (times normalised
+              by k = 0, the normalisation of Table 1)
   mixed       64^3, degree 3 FGMRES: FP64 vs FP32 vs split-BF16 preconditioner
   batched     48^3, degree 2: 32 right-hand sides in one FGMRES vs one at a time
   hbm         apply_K on an HBM-sized mesh (working set > Infinity Cache)
@@ -24,7 +28,7 @@ The JSON line also carries
   cpu_baseline  the FP64 oracle timed on this host (bounded sample)
 
     python bench.py [--steps K] [--warmup W] [--order q] [--iters k]
-    python bench.py --only {solve,apply_K,apply_P0,copy} ...   (profiling runs)
+    python bench.py --only {solve,apply_K,apply_K_quad,apply_P0,copy} ...   (profiling runs)
     python bench.py --only table1     (Table 1: 8^3..64^3, degrees 2..8, k = 0..4)
 """
 import argparse
@@ -247,7 +251,7 @@ def main():
     ap.add_argument("--iters", type=int, default=1)
     ap.add_argument("--schur", default="Pcq1")
     ap.add_argument("--only", default=None,
-                    choices=["solve", "apply_K", "apply_P0", "copy", "table1"])
+                    choices=["solve", "apply_K", "apply_K_quad", "apply_P0", "copy", "table1"])
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
                     help="preconditioner precision for --only apply_P0")
@@ -308,7 +312,7 @@ def main():
                 log(f"[bench] table1 {Et}^3 p={pt}: {its} ms {[round(m, 2) for m in ms]}")
         print(json.dumps({"table1": rows}), flush=True)
         return
-    if args.only in ("apply_K", "apply_P0"):
+    if args.only in ("apply_K", "apply_K_quad", "apply_P0"):
         forced = args.op_kchunk > 0
         sol = Solver(E, p, 1.0, precision=args.prec,
                      krylov="minres" if args.prec == "fp64" else "fgmres",
@@ -317,7 +321,9 @@ def main():
                      op_staged=args.op_staged)
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
-        fn = sol.apply_K if args.only == "apply_K" else sol.apply_P0
+        fn = {"apply_K": sol.apply_K, "apply_K_quad": sol.apply_K_quad,
+              "apply_P0": sol.apply_P0}[args.only]
+        fn(xr, yr)
         t = timed_loop(lambda: fn(xr, yr), args.reps, sol.stream)
         log(f"[bench] {args.only} E={E} p={p} N={sol.N}: {t * 1e6:.2f} us per call "
             f"({args.reps} timed calls after 1 warm-up; tuning {sol.tuning(1)})")
@@ -396,6 +402,29 @@ def main():
                                      "true_relres": inf2.true_relres}
             log(f"[bench] sweep q={qq} k={kk}: {sweep[f'q{qq}_k{kk}']}")
             s2.close()
+
+    # ---- the quadrature-based forward operator (Sec. 5.3): its time against
+    # apply_K, and solves with it as the forward problem (the paper's T_f)
+    quad = {}
+    if not args.no_sweep:
+        sol.apply_K_quad(xr, yk)
+        t_Q = timed_loop(lambda: sol.apply_K_quad(xr, yk), 20, stream)
+        quad = {"apply_K_quad_us": t_Q * 1e6, "apply_K_quad_dofs": N / t_Q,
+                "apply_K_us": t_K * 1e6, "quad_over_kron": t_Q / t_K,
+                "points": (E * (p + 1) + 2) ** 3,
+                f"Tp_over_Tf_q{q}_k{k}": t_Pk / t_Q, "solves": {}}
+        base = {}
+        for kk in (0, 1, 2):
+            for fw in ("quadrature", "kronecker"):
+                s2 = Solver(E, p, 1.0, order=2, iters=kk, schur=args.schur, forward=fw)
+                b2 = s2.build_rhs([1.0])
+                _, inf2, t2 = timed_solve(s2, b2, 3)
+                base.setdefault(fw, t2)
+                quad["solves"][f"{fw}_q2_k{kk}"] = {
+                    "iterations": inf2.iterations, "ms": 1e3 * t2,
+                    "T_sol_normalised": t2 / base[fw], "true_relres": inf2.true_relres}
+                s2.close()
+        log(f"[bench] quadrature forward: {quad}")
 
     # ---- Schur options of Sec. 4.1 at this mesh (FGMRES, q = 2, k = 1, 2):
     # (1) eq. Pcq2 with P_{V,0}, (2) eq. Pcq2 with a fixed P_{V,2}, (3)/(4)
@@ -586,6 +615,7 @@ def main():
         "sweep": sweep,
         "spectra": spectra,
         "schur_options": schur_opts,
+        "quadrature_forward": quad,
         "mixed": mixed,
         "batched": batched,
         "hbm": hbm,

@@ -125,6 +125,10 @@ typedef struct hp_opts {
                            kernel exists (velocity, modes K and A: degree <= 4 and op_kchunk
                            2, 4 or 8, 8 only to degree 3; pressure chain: degree <= 3 and
                            op_kchunk 2 or 4); same results bit for bit */
+    int forward;        /* forward problem y = K x inside hp_solve: 0 = the Kronecker-
+                           factored operator kernels (default), 1 = the quadrature-based
+                           operator of hp_apply_K_quad (the same matrix up to rounding);
+                           the reported true residual always uses hp_apply_K */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -184,6 +188,18 @@ hp_status hp_sizes(const hp_ctx* ctx, int64_t dims[4][3], int64_t offsets[5]);
 
 /* y = K x for nrhs vectors (eq. systemmatrix): y_u = A u + B p, y_p = B' u. */
 hp_status hp_apply_K(hp_ctx* ctx, const double* x, double* y, int nrhs);
+
+/* y = K x by the quadrature-based, matrix-free route of Sec. 5.3: the
+ * velocity gradients and the pressure are evaluated at the p+1 Gauss-Legendre
+ * points per element and direction by global sum factorisation, the flux of
+ * the weak form (Sec. 3.1; symmetric Nitsche face terms of Sec. 3.3 at the
+ * face Gauss points) is formed at every point and integrated back.  Exact
+ * quadrature: the same matrix as hp_apply_K, up to rounding.  x and y are
+ * device arrays of nrhs vectors (stride N, layout of hp_apply_K), y must not
+ * alias x.  The first call allocates the point tables and a scratch of
+ * 7 (E(p+1)+2) n_M^2 + 10 (E(p+1)+2)^2 n_M + 13 (E(p+1)+2)^3 doubles
+ * (one right-hand side at a time); HP_ENOMEM if that fails. */
+hp_status hp_apply_K_quad(hp_ctx* ctx, const double* x, double* y, int nrhs);
 
 /* y = A u (velocity only, stride n_V; Sec. 3.3). */
 hp_status hp_apply_A(hp_ctx* ctx, const double* u, double* y, int nrhs);

@@ -52,6 +52,7 @@ class hp_opts(ctypes.Structure):
         ("schur_pcg_tol", ctypes.c_double),
         ("op_fused", ctypes.c_int),
         ("op_staged", ctypes.c_int),
+        ("forward", ctypes.c_int),
     ]
 
 
@@ -91,6 +92,7 @@ SIGNATURES = {
     "hp_set_nu": (I, [P, D]),
     "hp_sizes": (I, [P, ctypes.POINTER(ctypes.c_int64 * 12), ctypes.POINTER(ctypes.c_int64 * 5)]),
     "hp_apply_K": (I, [P, P, P, I]),
+    "hp_apply_K_quad": (I, [P, P, P, I]),
     "hp_apply_A": (I, [P, P, P, I]),
     "hp_apply_B": (I, [P, P, P, I]),
     "hp_apply_Bt": (I, [P, P, P, I]),

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhyperpower.so")
 ARCH = os.environ.get("HP_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["setup1d.cpp", "capi.cpp", "ops.hip", "fd.hip", "krylov.hip"]
+SOURCES = ["setup1d.cpp", "capi.cpp", "ops.hip", "fd.hip", "krylov.hip", "quad.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -86,6 +86,8 @@ struct Extra {
     double* fhc = nullptr;     // R x 129 Gram-Schmidt coefficients
     double* fvs = nullptr;     // R
     double* fpart = nullptr;   // partials for up to 129 pairs x R
+    // quadrature-based forward operator (tables and scratch made on first use)
+    QuadOp quad;
     bool f_valid = false;
     std::vector<hipGraphExec_t> f_exec;
     int f_q = 0, f_k = 0, f_nrhs = 0, f_var = 0, f_sched = 0, f_prec = 0, f_m = 0;
@@ -109,6 +111,18 @@ Fields full_fields(hp_ctx* c, const double* base) {
         f.stride[b] = c->N;
     }
     return f;
+}
+
+// The forward problem y = K x of the Krylov loops: the Kronecker-factored
+// operator kernels, or (forward = 1) the quadrature-based operator.
+hipError_t launch_forward(hp_ctx* c, const double* x, double* y, int nrhs) {
+    if (c->opts.forward == 1) {
+        QuadOp* q = &extra_of(c)->quad;
+        hipError_t e = quad_setup(c, q);
+        if (e != hipSuccess) return e;
+        return launch_quad_K(c, q, full_fields(c, x), full_fields(c, y), nrhs);
+    }
+    return launch_operator(c, OP_K, full_fields(c, x), full_fields(c, y), 1.0, 0.0, nullptr, nrhs);
 }
 
 Fields vel_fields(hp_ctx* c, const double* base, long long stride) {
@@ -476,8 +490,7 @@ hipError_t minres_a(hp_ctx* c, const MinresBufs& b, int nrhs, int cur) {
     MinresScalars* s_cur = ex->msc + cur * c->opts.max_rhs;
     double* p0 = ex->mpart;
     hipError_t e;
-    if ((e = launch_operator(c, OP_K, full_fields(c, b.z), full_fields(c, b.Kz), 1.0, 0.0, nullptr,
-                             nrhs)) != hipSuccess) return e;
+    if ((e = launch_forward(c, b.z, b.Kz, nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
     return minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur,
                     Partials{p0, vec_dot_partial_count()});
@@ -669,8 +682,7 @@ hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol, FgSca
     double* Zj = Zb + (long long)j * V;
     hipError_t e;
     if ((e = apply_Pk(c, c->opts.order, c->opts.iters, Vj, Zj, nrhs)) != hipSuccess) return e;
-    if ((e = launch_operator(c, OP_K, full_fields(c, Zj), full_fields(c, w), 1.0, 0.0, nullptr,
-                             nrhs)) != hipSuccess) return e;
+    if ((e = launch_forward(c, Zj, w, nrhs)) != hipSuccess) return e;
     for (int pass = 0; pass < 2; ++pass) {
         if ((e = vec_multidot_partials(c->stream, N, N, Vb, V, j + 1, w, nrhs, ex->fpart)) != hipSuccess)
             return e;
@@ -766,7 +778,7 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     int total = 0;
     while (!done && total < c->opts.maxit) {
         // cycle start: w = b - K x, V0 = w / ||w||
-        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs));
+        HIPCHK(launch_forward(c, x, w, nrhs));
         HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
         HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
         HIPCHK(fg_begin(c->stream, ex->fsc, ex->fpart, ex->fg, ex->fvs, m, nrhs));
@@ -794,7 +806,7 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         HIPCHK(fg_solve(c->stream, ex->fsc, ex->fH, ex->fg, ex->fy, m, jl, nrhs));
         HIPCHK(vec_add_combo(c->stream, N, N, Zb, V, jl, ex->fy, m, nrhs, x));
         // true residual
-        HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, w), 1.0, 0.0, nullptr, nrhs));
+        HIPCHK(launch_forward(c, x, w, nrhs));
         HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
         HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
         HIPCHK(fg_check(c->stream, ex->fsc, ex->fpart, tol, nrhs));
@@ -1185,6 +1197,7 @@ void hp_default_opts(hp_opts* o) {
     o->schur_level = 0;
     o->op_fused = -1;
     o->op_staged = -1;
+    o->forward = 0;
     o->schur_pcg_iters = 20;
     o->schur_pcg_tol = 1e-2;
 }
@@ -1218,7 +1231,8 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
-        o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3)
+        o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3 ||
+        o.forward < 0 || o.forward > 1)
         return HP_EINVAL;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
@@ -1406,6 +1420,13 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hp_destroy(c);
         return HP_ENOMEM;
     }
+    if (c->opts.forward == 1) {
+        const hipError_t qe = quad_setup(c, &ex->quad);
+        if (qe != hipSuccess) {
+            hp_destroy(c);
+            return qe == hipErrorOutOfMemory ? HP_ENOMEM : HP_EHIP;
+        }
+    }
     if (hipDeviceSynchronize() != hipSuccess) { hp_destroy(c); return HP_EHIP; }
     if (c->opts.autotune) {
         const hp_status ts = autotune(c);
@@ -1458,6 +1479,16 @@ hp_status hp_sizes(const hp_ctx* c, int64_t dims[4][3], int64_t offsets[5]) {
 hp_status hp_apply_K(hp_ctx* c, const double* x, double* y, int nrhs) {
     if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y) return HP_EINVAL;
     HIPCHK(launch_operator(c, OP_K, full_fields(c, x), full_fields(c, y), 1.0, 0.0, nullptr, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_K_quad(hp_ctx* c, const double* x, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !x || !y || x == y) return HP_EINVAL;
+    QuadOp* q = &extra_of(c)->quad;
+    const hipError_t e = quad_setup(c, q);
+    if (e == hipErrorOutOfMemory) return HP_ENOMEM;
+    HIPCHK(e);
+    HIPCHK(launch_quad_K(c, q, full_fields(c, x), full_fields(c, y), nrhs));
     return HP_OK;
 }
 
@@ -1600,6 +1631,7 @@ void hp_destroy(hp_ctx* c) {
     if (ex->hv) (void)hipFree(ex->hv);
     if (ex->ws2) (void)hipFree(ex->ws2);
     if (ex->side) (void)hipStreamDestroy(ex->side);
+    quad_free(&ex->quad);
     if (ex->fork_ev) (void)hipEventDestroy(ex->fork_ev);
     if (ex->join_ev) (void)hipEventDestroy(ex->join_ev);
     if (ex->hq) (void)hipFree(ex->hq);

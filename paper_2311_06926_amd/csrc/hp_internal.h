@@ -61,6 +61,29 @@ struct OpTuned {
     OpShape shape;
 };
 
+// Banded table of the quadrature-based operator: row r holds
+// A[r][start[r] .. start[r] + w) of a rows x cols matrix.
+struct QBand {
+    const int* start;
+    const double* val;
+    int rows, cols, w;
+};
+
+// Device state of the quadrature-based forward operator (quad.hip): basis
+// tables at the points of one direction ([0] degree p-1, [1] interior degree
+// p; V values, D derivatives, VT/DT their transposes), the point weights and
+// the scratch of one right-hand side.
+struct QuadOp {
+    bool ready = false;
+    int nq = 0;
+    double* tables = nullptr;
+    int* index = nullptr;
+    double* scratch = nullptr;
+    size_t scratch_doubles = 0;
+    QBand V[2]{}, D[2]{}, VT[2]{}, DT[2]{};
+    const double* wq = nullptr;
+};
+
 }  // namespace hp
 
 struct hp_ctx {
@@ -117,6 +140,15 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
                            double alpha, double beta, const Fields* src, int nrhs);
 
 hipError_t ops_init_attributes();
+
+// ---- quadrature-based forward operator (quad.hip) ---------------------------
+// Builds the point tables and allocates the scratch (once per context).
+hipError_t quad_setup(hp_ctx* c, QuadOp* q);
+void quad_free(QuadOp* q);
+// out = K in by global sum factorisation at the Gauss points (the same
+// matrix as OP_K of launch_operator, up to rounding); out must not alias in.
+hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fields& out,
+                         int nrhs);
 // the shape launch_operator uses for nrhs right-hand sides (forced, user
 // option, tuned, else the cost model) and the cost model alone
 OpShape op_shape(const hp_ctx* c, int nrhs);

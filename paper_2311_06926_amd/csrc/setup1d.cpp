@@ -353,6 +353,44 @@ Tables1D build_tables(int E, int p, double c_pen) {
     return T;
 }
 
+QuadTables1D build_quad_tables(const Tables1D& T) {
+    const int E = T.E, p = T.p, nN = T.nN, nM = T.nM, n = T.n;
+    QuadTables1D Q;
+    Q.nq = E * (p + 1) + 2;
+    const int nq = Q.nq;
+    Q.NV.assign((size_t)nq * nN, 0.0);
+    Q.ND.assign((size_t)nq * nN, 0.0);
+    Q.MV.assign((size_t)nq * nM, 0.0);
+    Q.MD.assign((size_t)nq * nM, 0.0);
+    Q.w.assign(nq, 1.0);
+    std::vector<double> gx, gw, Nv, dNv, Mv, dMv;
+    gauss_legendre(p + 1, gx, gw);
+    auto fill = [&](int r, double x) {
+        eval_all(T.tp, p, x, Nv, dNv);
+        eval_all(T.tm, p - 1, x, Mv, dMv);
+        for (int i = 0; i < nN; ++i) {  // interior functions: full indices 1 .. n-2
+            Q.NV[(size_t)r * nN + i] = Nv[i + 1];
+            Q.ND[(size_t)r * nN + i] = dNv[i + 1];
+        }
+        for (int i = 0; i < nM; ++i) {
+            Q.MV[(size_t)r * nM + i] = Mv[i] * T.mscale[i];
+            Q.MD[(size_t)r * nM + i] = dMv[i] * T.mscale[i];
+        }
+    };
+    (void)n;
+    fill(0, 0.0);
+    for (int e = 0; e < E; ++e) {
+        double a = (double)e / E, b = (double)(e + 1) / E;
+        for (int g = 0; g <= p; ++g) {
+            const int r = 1 + e * (p + 1) + g;
+            fill(r, 0.5 * (b - a) * gx[g] + 0.5 * (a + b));
+            Q.w[r] = 0.5 * (b - a) * gw[g];
+        }
+    }
+    fill(nq - 1, 1.0);
+    return Q;
+}
+
 // Load vector of the separable mode sin(pi k x) against the interior degree-p
 // functions (fam = 0) or all M-splines (fam = 1), by Gauss quadrature with
 // p + 8 points per element.

@@ -25,6 +25,19 @@ void generalized_eig(const std::vector<double>& K, const std::vector<double>& M,
                      std::vector<double>& lam, std::vector<double>& U);
 void inverse_spd(const std::vector<double>& M, int n, std::vector<double>& Minv);
 Tables1D build_tables(int E, int p, double c_pen);
+
+// Basis values at the points of the quadrature-based operator (Sec. 5.3:
+// Gauss-Legendre with p+1 points per element, plus the two end points where
+// the Nitsche face terms of Sec. 3.3 are evaluated).  Point 0 is x = 0,
+// point 1 + e (p+1) + g is Gauss point g of element e, point nq - 1 is x = 1.
+// Dense row-major nq x n matrices: values and first derivatives of the
+// interior degree-p functions (n = nN) and of the unit-integral degree p-1
+// functions (n = nM); w holds the Gauss weights (1 at the two end points).
+struct QuadTables1D {
+    int nq = 0;
+    std::vector<double> NV, ND, MV, MD, w;
+};
+QuadTables1D build_quad_tables(const Tables1D& T);
 std::vector<double> sine_load(const Tables1D& T, int fam, int k);
 
 }  // namespace hp

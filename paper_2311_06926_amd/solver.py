@@ -29,7 +29,10 @@ class Solver:
     schedule ('literal'|'prev'), precision ('fp64'|'fp32'|'bf16x3'),
     krylov ('minres'|'fgmres'), restart, maxit, order, iters, max_rhs,
     schur_level (eq. Pcq2: the fixed P_{V,l} in B' P_{V,l}^{-1} B; Pcq_pcg: the
-    inner CG preconditioner P_{V,l}), schur_pcg_iters, schur_pcg_tol.
+    inner CG preconditioner P_{V,l}), schur_pcg_iters, schur_pcg_tol,
+    forward ('kronecker'|'quadrature': the forward problem K x of the Krylov
+    loop by the Kronecker-factored kernels or by the quadrature-based
+    operator of Sec. 5.3).
     """
 
     def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
@@ -37,7 +40,7 @@ class Solver:
                  iters=1, max_rhs=1, poll_lag=1, use_graph=False, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
-                 device=None):
+                 forward="kronecker", device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -66,6 +69,7 @@ class Solver:
         o.schur_pcg_tol = schur_pcg_tol
         o.op_fused = op_fused
         o.op_staged = op_staged
+        o.forward = {"kronecker": 0, "quadrature": 1}[forward]
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -115,6 +119,13 @@ class Solver:
         nr = self._nrhs(x, self.N)
         y = self.empty(self.N, nr) if y is None else y
         check(self.lib.hp_apply_K(self.ctx, _ptr(x), _ptr(y), nr), "hp_apply_K")
+        return y
+
+    def apply_K_quad(self, x, y=None):
+        """y = K x by the quadrature-based (matrix-free) operator, Sec. 5.3."""
+        nr = self._nrhs(x, self.N)
+        y = self.empty(self.N, nr) if y is None else y
+        check(self.lib.hp_apply_K_quad(self.ctx, _ptr(x), _ptr(y), nr), "hp_apply_K_quad")
         return y
 
     def apply_A(self, u, y=None):

@@ -75,6 +75,28 @@ def test_apply_K_full_size_sampled(dev, E):
     sol.close()
 
 
+def test_apply_K_quad_full_size(dev):
+    """The quadrature-based operator at 32^3, degree 3 (about 2.2 M points):
+    sampled rows against the oracle, the whole vector against apply_K."""
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, nu = 32, 3, 1.0
+    say(f"[fullsize] apply_K_quad E={E} p={p}")
+    R = KronRows(E, p, nu)
+    sol = Solver(E, p, nu)
+    x = torch.from_numpy(synth.random_vector(R.N, seed=4)).to(dev)
+    yq = sol.apply_K_quad(x).cpu().numpy()
+    yk = sol.apply_K(x).cpu().numpy()
+    idx = samples(R.offsets, 3000, seed=7)
+    ref = R.rows(x.cpu().numpy(), idx)
+    scale = np.abs(yq).max()
+    err = np.abs(yq[idx] - ref).max() / scale
+    gap = np.abs(yq - yk).max() / scale
+    say(f"[fullsize]   {idx.size} samples, max rel err {err:.2e}; vs apply_K {gap:.2e}")
+    assert err < 1e-12 and gap < 1e-12
+    sol.close()
+
+
 def test_P0_full_size_backward_error(dev):
     from oracle.assemble import KronRows
     from paper_2311_06926_amd.solver import Solver

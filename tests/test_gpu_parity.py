@@ -78,6 +78,26 @@ def test_operators(dev, E, p):
     sol.close()
 
 
+@pytest.mark.parametrize("E,p", [(2, 2), (3, 2), (8, 2), (5, 3), (9, 3), (4, 4), (3, 6),
+                                 (2, 8)])
+def test_apply_K_quad_matches_oracle(dev, E, p):
+    """The quadrature-based forward operator (Sec. 5.3: Gauss points, flux of
+    the weak form, Nitsche face terms) against the oracle's K.  The quadrature
+    is exact, so this is the same matrix; two right-hand sides in one call."""
+    from paper_2311_06926_amd.solver import Solver
+    nu = 1.3
+    say(f"[parity] apply_K_quad E={E} p={p} nu={nu}")
+    S = oracle_sys(E, p, nu)
+    sol = Solver(E, p, nu, max_rhs=2)
+    x = np.concatenate([synth.random_vector(S.N, seed=E * 10 + p),
+                        synth.random_vector(S.N, seed=E * 10 + p + 1)])
+    y = sol.apply_K_quad(to_gpu(x, dev)).cpu().numpy()
+    for r in range(2):
+        seg = slice(r * S.N, (r + 1) * S.N)
+        assert rel_err(y[seg], S.K @ x[seg]) < 1e-12
+    sol.close()
+
+
 @pytest.mark.parametrize("E,p", CASES)
 def test_base_preconditioner(dev, E, p):
     """P_0 against sparse LU.  Both are backward stable, so each velocity
@@ -241,6 +261,30 @@ def test_minres_iteration_limit_matches_oracle_iterates(dev, m, graph):
     assert info.iterations == m and info.converged == 0
     xs = x.cpu().numpy()
     assert np.abs(xs[:S.nV] - ref.x[:S.nV]).max() <= 1e-10 * np.abs(ref.x[:S.nV]).max()
+    sol.close()
+
+
+@pytest.mark.parametrize("krylov,graph", [("minres", 0), ("minres", 1), ("fgmres", 0)])
+def test_solve_with_quadrature_forward(dev, krylov, graph):
+    """The solve with the quadrature-based forward operator in the Krylov loop:
+    iteration count within +-1 of the oracle's MINRES, and the solution of the
+    same system (its true residual is taken with the Kronecker operator)."""
+    from oracle.cases import cavity
+    from oracle.direct import mean_zero_pressure
+    from oracle.krylov import minres
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[parity] quadrature forward {krylov} graph={graph}")
+    S, b = cavity(6, 3)
+    ref = minres(lambda v: S.K @ v, HyperPower(S, 2, 1).apply, b, tol=1e-8)
+    sol = Solver(6, 3, 1.0, iters=1, krylov=krylov, use_graph=graph, forward="quadrature")
+    x, info = sol.solve(sol.build_rhs([1.0]), tol=1e-8)
+    assert info.converged == 1 and info.true_relres < 1e-7
+    if krylov == "minres":
+        assert abs(info.iterations - ref.iters) <= 1
+    xg = mean_zero_pressure(x.cpu().numpy(), S.nV)
+    xr = mean_zero_pressure(ref.x, S.nV)
+    assert np.linalg.norm(xg[:S.nV] - xr[:S.nV]) <= 1e-6 * np.linalg.norm(xr[:S.nV])
     sol.close()
 
 
