@@ -29,7 +29,8 @@ The JSON line also carries
 
     python bench.py [--steps K] [--warmup W] [--order q] [--iters k]
     python bench.py --only {solve,apply_K,apply_K_quad,apply_P0,copy} ...   (profiling runs)
-    python bench.py --only table1     (Table 1: 8^3..64^3, degrees 2..8, k = 0..4)
+    python bench.py --only table1 [--forward quadrature]
+                                      (Table 1: 8^3..64^3, degrees 2..8, k = 0..4)
 """
 import argparse
 import hashlib
@@ -264,6 +265,8 @@ def main():
                          "(1) or the streaming ones (0); -1: tuned")
     ap.add_argument("--fd-plan", type=int, default=-1,
                     help="--only solve/apply_P0: force the fast-diagonalisation plan (-1: tuned)")
+    ap.add_argument("--forward", default="kronecker", choices=["kronecker", "quadrature"],
+                    help="forward problem of the solve and table1 legs (quadrature: Sec. 5.3)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip mixed/batched/hbm legs")
     ap.add_argument("--no-cpu", action="store_true")
@@ -301,7 +304,7 @@ def main():
             for pt in (2, 4, 6, 8):
                 its, ms = [], []
                 for kk in range(5):
-                    s2 = Solver(Et, pt, 1.0, order=2, iters=kk)
+                    s2 = Solver(Et, pt, 1.0, order=2, iters=kk, forward=args.forward)
                     b2 = s2.build_rhs([1.0])
                     _, inf2, t2 = timed_solve(s2, b2, 3)
                     its.append(inf2.iterations)
@@ -310,7 +313,7 @@ def main():
                 rows.append({"E": Et, "p": pt, "iterations": its, "ms": ms,
                              "T_sol": [m / ms[0] for m in ms]})
                 log(f"[bench] table1 {Et}^3 p={pt}: {its} ms {[round(m, 2) for m in ms]}")
-        print(json.dumps({"table1": rows}), flush=True)
+        print(json.dumps({"table1": rows, "forward": args.forward}), flush=True)
         return
     if args.only in ("apply_K", "apply_K_quad", "apply_P0"):
         forced = args.op_kchunk > 0
@@ -333,7 +336,7 @@ def main():
     forced = args.op_kchunk > 0
     sol = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, fd_plan=args.fd_plan,
                  op_kchunk=args.op_kchunk, op_order=args.op_order, op_slabs=1 if forced else 0,
-                 op_staged=args.op_staged)
+                 op_staged=args.op_staged, forward=args.forward)
     stream = sol.stream
     b = sol.build_rhs([1.0])
     x, info = sol.solve(b, 1e-8)
