@@ -116,3 +116,91 @@ def test_kron_rows_match_the_assembled_matrix(E, p):
     xq = x[o[3]:]
     yq = R.mass_q_entries(xq, np.arange(xq.size))
     assert np.allclose(yq, S.Mq @ xq, rtol=0, atol=1e-13 * np.abs(yq).max())
+
+
+def _quadrature_flux_apply(E, p, nu, x):
+    """K x by the pointwise flux form the quadrature-based GPU operator uses:
+    gradients and pressure at the points [0, the E(p+1) Gauss points, 1] of
+    each direction; volume flux nu (G + G^T) + P I and div u; on a face
+    normal to d (outward sign s) and tangential c != d only
+    nu (2 alpha u_c v_c - s d_d u_c v_c - s u_c d_d v_c); edges carry
+    nothing.  Written with numpy contractions (slow, small meshes)."""
+    from oracle.assemble import block_offsets, default_c_pen, field_shapes
+    from oracle.splines import SplinePair, gauss_points
+    sp = SplinePair(E, p)
+    xg, wg = gauss_points(E, p)
+    pts = np.concatenate([[0.0], xg, [1.0]])
+    w1 = np.concatenate([[1.0], wg, [1.0]])
+    nq = pts.size
+    NV, ND = sp.N(pts)
+    MV, MD = sp.M(pts)
+    tab = {"N": (NV[1:-1].T, ND[1:-1].T), "M": (MV.T, MD.T)}
+    alpha = default_c_pen(p) * E
+    sh, off = field_shapes(E, p), block_offsets(E, p)
+    f = [x[off[b]:off[b + 1]].reshape(sh[b][::-1]) for b in range(4)]   # [i3, i2, i1]
+
+    def mode(A, X, m):       # contract direction m (axis 2 - m)
+        ax = 2 - m
+        return np.moveaxis(np.tensordot(A, X, axes=([1], [ax])), 0, ax)
+
+    def typ(c, d):
+        return "N" if c == d else "M"
+
+    U, G = [], []
+    for c in range(3):
+        V1, D1 = tab[typ(c, 0)]
+        V2, D2 = tab[typ(c, 1)]
+        V3, D3 = tab[typ(c, 2)]
+        a, b = mode(V1, f[c], 0), mode(D1, f[c], 0)
+        U.append(mode(V3, mode(V2, a, 1), 2))
+        G.append([mode(V3, mode(V2, b, 1), 2), mode(V3, mode(D2, a, 1), 2),
+                  mode(D3, mode(V2, a, 1), 2)])
+    Mv = tab["M"][0]
+    P = mode(Mv, mode(Mv, mode(Mv, f[3], 0), 1), 2)
+    W = w1[:, None, None] * w1[None, :, None] * w1[None, None, :]
+    end = np.zeros(nq, bool)
+    end[0] = end[-1] = True
+    e2, e1, e0 = np.meshgrid(end, end, end, indexing="ij")
+    ne = e0.astype(int) + e1 + e2
+    vol = ne == 0
+    Fq = np.where(vol, W * (G[0][0] + G[1][1] + G[2][2]), 0.0)
+    F = [[np.zeros_like(W)] + [np.where(vol, W * nu * (G[c][d] + G[d][c])
+                                        + (W * P if c == d else 0.0), 0.0) for d in range(3)]
+         for c in range(3)]
+    sgn = np.ones(nq)
+    sgn[0] = -1.0
+    for d, (ed, ax) in enumerate([(e0, 2), (e1, 1), (e2, 0)]):
+        face = (ne == 1) & ed
+        shp = [1, 1, 1]
+        shp[ax] = nq
+        s = sgn.reshape(shp)
+        for c in range(3):
+            if c != d:
+                F[c][0] = F[c][0] + np.where(face, W * nu * (2 * alpha * U[c] - s * G[c][d]), 0.0)
+                F[c][1 + d] = F[c][1 + d] + np.where(face, -W * nu * s * U[c], 0.0)
+    out = []
+    for c in range(3):
+        V1, D1 = tab[typ(c, 0)]
+        V2, D2 = tab[typ(c, 1)]
+        V3, D3 = tab[typ(c, 2)]
+        aa = mode(V3.T, F[c][0], 2) + mode(D3.T, F[c][3], 2)
+        a = mode(V2.T, aa, 1) + mode(D2.T, mode(V3.T, F[c][2], 2), 1)
+        b = mode(V2.T, mode(V3.T, F[c][1], 2), 1)
+        out.append((mode(V1.T, a, 0) + mode(D1.T, b, 0)).ravel())
+    out.append(mode(Mv.T, mode(Mv.T, mode(Mv.T, Fq, 2), 1), 0).ravel())
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("E,p,nu", [(2, 2, 1.0), (3, 2, 1.3), (3, 3, 0.7), (2, 5, 1.0)])
+def test_quadrature_flux_form_equals_K(E, p, nu):
+    """The reading behind the quadrature-based forward operator (Sec. 5.3):
+    the symmetric-gradient volume flux plus the face terms that keep only
+    the normal derivative of the tangential components (the normal component
+    and its tangential derivatives vanish on the face) reproduce K exactly
+    (Gauss with p+1 points is exact for these integrands).  Dropping the
+    consistency term or the edge rule breaks the match."""
+    S = KronSystem(E, p, nu)
+    x = np.random.default_rng(E * 10 + p).standard_normal(S.N)
+    y = _quadrature_flux_apply(E, p, nu, x)
+    ref = S.K @ x
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
