@@ -22,7 +22,8 @@
 // One application per right-hand side is six launches:
 //   mode 1 then mode 2 evaluation (banded basis tables, k_qpass),
 //   mode 3 evaluation fused with the pointwise flux (k_qflux),
-//   and the transposed contractions mode 3, 2, 1 (k_qpass).
+//   and the transposed contractions mode 3 (k_qpass3t, four output rows
+//   per thread), mode 2 and mode 1 (k_qpass).
 // Every launch is HBM bound; the flux fields at the 13 (E(p+1)+2)^3 points
 // dominate the traffic (13 written, 13 read).
 #include <algorithm>
@@ -60,8 +61,10 @@ __device__ inline double band_dot(const QBand& m, int r, const double* __restric
     return s;
 }
 
+// Modes 1 and 2 (MODE = 0, 1); mode 3 has its own kernels below.
 template <int MODE>
 __global__ __launch_bounds__(QT) void k_qpass(QJobs J) {
+    static_assert(MODE == 0 || MODE == 1, "k_qpass contracts direction 1 or 2");
     const QJob& jb = J.j[blockIdx.y];
     const long long o = (long long)blockIdx.x * QT + threadIdx.x;
     if (o >= jb.nout) return;
@@ -73,20 +76,60 @@ __global__ __launch_bounds__(QT) void k_qpass(QJobs J) {
         r = (int)(o % R);
         base = (o / R) * d0;
         st = 1;
-    } else if (MODE == 1) {
+    } else {
         const long long i0 = o % d0, t = o / d0;
         r = (int)(t % R);
         base = i0 + (t / R) * d0 * d1;
         st = d0;
-    } else {
-        const long long pl = d0 * d1;
-        r = (int)(o / pl);
-        base = o % pl;
-        st = pl;
     }
     double s = band_dot(jb.ma, r, jb.a, base, st);
     if (jb.b) s += band_dot(jb.mb, r, jb.b, base, st);
     jb.out[o] = s;
+}
+
+// Transposed mode-3 contraction with QJB consecutive output rows per thread:
+// rows r0 .. r0+QJB-1 of the band read overlapping windows of one line, so
+// the union of the windows is loaded once.  Each row still sums its terms in
+// window order (a and b separately, then added), as band_dot does.
+constexpr int QJB = 4;
+__global__ __launch_bounds__(QT) void k_qpass3t(QJobs J) {
+    const QJob& jb = J.j[blockIdx.y];
+    const long long pl = (long long)jb.d0 * jb.d1;
+    const int R = jb.ma.rows;
+    const long long o = (long long)blockIdx.x * QT + threadIdx.x;
+    const int nrb = (R + QJB - 1) / QJB;
+    if (o >= pl * nrb) return;
+    const long long base = o % pl;
+    const int r0 = (int)(o / pl) * QJB;
+    const int nr = min(QJB, R - r0);
+    double acc[QJB], accb[QJB];
+#pragma unroll
+    for (int k = 0; k < QJB; ++k) acc[k] = accb[k] = 0.0;
+    auto run = [&](const QBand& m, const double* __restrict__ x, double* out) {
+        int st[QJB];
+#pragma unroll
+        for (int k = 0; k < QJB; ++k) st[k] = m.start[r0 + (k < nr ? k : nr - 1)];
+        int lo = st[0], hi = st[0];
+#pragma unroll
+        for (int k = 0; k < QJB; ++k) {
+            lo = min(lo, st[k]);
+            hi = max(hi, st[k] + m.w);
+        }
+        for (int q = lo; q < hi; ++q) {
+            const double xv = x[base + (long long)q * pl];
+#pragma unroll
+            for (int k = 0; k < QJB; ++k) {
+                const int t = q - st[k];
+                if (k < nr && t >= 0 && t < m.w)
+                    out[k] += m.val[(long long)(r0 + k) * m.w + t] * xv;
+            }
+        }
+    };
+    run(jb.ma, jb.a, acc);
+    if (jb.b) run(jb.mb, jb.b, accb);
+#pragma unroll
+    for (int k = 0; k < QJB; ++k)
+        if (k < nr) jb.out[base + (long long)(r0 + k) * pl] = jb.b ? acc[k] + accb[k] : acc[k];
 }
 
 struct QFluxArgs {
@@ -385,7 +428,13 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
                 ++n;
             }
         }
-        if ((e = run_pass<2>(st, J, n)) != hipSuccess) return e;
+        {
+            int rmax = 0;
+            for (int i = 0; i < n; ++i) rmax = std::max(rmax, J.j[i].ma.rows);
+            const long long nt = (long long)nq * nq * ((rmax + QJB - 1) / QJB);
+            hipLaunchKernelGGL(k_qpass3t, dim3(blocks_for(nt), n), dim3(QT), 0, st, J);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         // transposed mode 2: a_c <- V^T (V1V2) + D^T (V1D2), b_c <- V^T (D1V2); pressure
         J = QJobs{};
         n = 0;
