@@ -288,6 +288,27 @@ def test_solve_with_quadrature_forward(dev, krylov, graph):
     sol.close()
 
 
+def test_batched_fgmres_with_quadrature_forward(dev):
+    """Two lid speeds in one FGMRES solve with the quadrature-based forward
+    operator: each right-hand side matches its own single solve with the
+    Kronecker operator (the same system), and the lid data scale linearly."""
+    from paper_2311_06926_amd.solver import Solver
+    say("[parity] batched FGMRES, quadrature forward")
+    sq = Solver(5, 3, 1.0, iters=1, krylov="fgmres", max_rhs=2, forward="quadrature")
+    xq, iq = sq.solve(sq.build_rhs([1.0, 2.5]), tol=1e-10)
+    sk = Solver(5, 3, 1.0, iters=1, krylov="fgmres")
+    xk, ik = sk.solve(sk.build_rhs([1.0]), tol=1e-10)
+    assert iq.converged == 1 and ik.converged == 1
+    N, nV = sq.N, sq.nV
+    xq = xq.cpu().numpy()
+    xk = xk.cpu().numpy()
+    u0, u1, uk = xq[:nV], xq[N:N + nV], xk[:nV]
+    assert np.linalg.norm(u0 - uk) <= 1e-6 * np.linalg.norm(uk)
+    assert np.linalg.norm(u1 - 2.5 * uk) <= 1e-6 * np.linalg.norm(2.5 * uk)
+    sq.close()
+    sk.close()
+
+
 def test_fgmres_matches_oracle(dev):
     from oracle.cases import cavity
     from oracle.krylov import fgmres
@@ -405,6 +426,10 @@ def test_invalid_arguments(dev):
         sol.apply_K(x, x)                      # aliasing
     with pytest.raises(HPError):
         sol.apply_K(torch.zeros(2 * sol.N, dtype=torch.float64, device=dev))  # nrhs > max_rhs
+    with pytest.raises(HPError):
+        sol.apply_K_quad(x, x)                 # aliasing
+    with pytest.raises(HPError):
+        sol.apply_K_quad(torch.zeros(2 * sol.N, dtype=torch.float64, device=dev))
     with pytest.raises(HPError):
         Solver(3, 2, 1.0, precision="fp32").solve(x)    # MINRES needs FP64
     sol.close()
