@@ -66,7 +66,11 @@ template <int MODE>
 __global__ __launch_bounds__(QT) void k_qpass(QJobs J) {
     static_assert(MODE == 0 || MODE == 1, "k_qpass contracts direction 1 or 2");
     const QJob& jb = J.j[blockIdx.y];
-    const long long o = (long long)blockIdx.x * QT + threadIdx.x;
+    // the grid is a multiple of 8 workgroups; XCD x (workgroups x, x+8, ...)
+    // walks the x-th eighth of the output in order, so the input rows that
+    // neighbouring outputs share are reused from that XCD's L2
+    const long long L = (blockIdx.x % 8) * (gridDim.x / 8) + blockIdx.x / 8;
+    const long long o = L * QT + threadIdx.x;
     if (o >= jb.nout) return;
     const long long d0 = jb.d0, d1 = jb.d1;
     const int R = jb.ma.rows;
@@ -92,15 +96,23 @@ __global__ __launch_bounds__(QT) void k_qpass(QJobs J) {
 // the union of the windows is loaded once.  Each row still sums its terms in
 // window order (a and b separately, then added), as band_dot does.
 constexpr int QJB = 4;
+
+// Workgroup order of the mode-3 kernels: the tiles of one (i1, i2) plane are
+// padded to a multiple of 8, so that a tile lands on the same XCD (workgroups
+// are dealt round-robin to the 8 XCDs) at every i3 level and the planes that
+// neighbouring levels share stay in that XCD's L2.
+__host__ __device__ inline long long xcd_tiles(long long pl) { return (((pl + QT - 1) / QT) + 7) & ~7LL; }
+
 __global__ __launch_bounds__(QT) void k_qpass3t(QJobs J) {
     const QJob& jb = J.j[blockIdx.y];
     const long long pl = (long long)jb.d0 * jb.d1;
     const int R = jb.ma.rows;
-    const long long o = (long long)blockIdx.x * QT + threadIdx.x;
     const int nrb = (R + QJB - 1) / QJB;
-    if (o >= pl * nrb) return;
-    const long long base = o % pl;
-    const int r0 = (int)(o / pl) * QJB;
+    const long long ntp = xcd_tiles(pl);
+    const long long base = (blockIdx.x % ntp) * QT + threadIdx.x;
+    const int rb = (int)(blockIdx.x / ntp);
+    if (base >= pl || rb >= nrb) return;
+    const int r0 = rb * QJB;
     const int nr = min(QJB, R - r0);
     double acc[QJB], accb[QJB];
 #pragma unroll
@@ -143,10 +155,12 @@ struct QFluxArgs {
 
 __global__ __launch_bounds__(QT) void k_qflux(QFluxArgs A) {
     const long long nq = A.nq, pl = nq * nq;
-    const long long o = (long long)blockIdx.x * QT + threadIdx.x;
-    if (o >= pl * nq) return;
-    const int i0 = (int)(o % nq), i1 = (int)((o / nq) % nq), i2 = (int)(o / pl);
-    const long long base = o % pl;
+    const long long ntp = xcd_tiles(pl);
+    const long long base = (blockIdx.x % ntp) * QT + threadIdx.x;
+    const int i2 = (int)(blockIdx.x / ntp);
+    if (base >= pl || i2 >= A.nq) return;
+    const long long o = base + (long long)i2 * pl;
+    const int i0 = (int)(base % nq), i1 = (int)(base / nq);
     double U[3], G[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -254,7 +268,8 @@ hipError_t run_pass(hipStream_t s, const QJobs& J, int njob) {
     long long m = 0;
     for (int i = 0; i < njob; ++i) m = std::max(m, J.j[i].nout);
     if (m == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_qpass<MODE>, dim3(blocks_for(m), njob), dim3(QT), 0, s, J);
+    const unsigned nb = (blocks_for(m) + 7) & ~7u;  // a multiple of 8 (see k_qpass)
+    hipLaunchKernelGGL(k_qpass<MODE>, dim3(nb, njob), dim3(QT), 0, s, J);
     return hipGetLastError();
 }
 
@@ -397,7 +412,8 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
         A.nq = nq;
         A.nu = c->nu;
         A.alpha = c->tab.alpha;
-        hipLaunchKernelGGL(k_qflux, dim3(blocks_for(s3)), dim3(QT), 0, st, A);
+        hipLaunchKernelGGL(k_qflux, dim3((unsigned)(xcd_tiles((long long)nq * nq) * nq)), dim3(QT), 0,
+                           st, A);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // transposed mode 3: (V1V2) <- V^T F_v + D^T F_3, (V1D2) <- V^T F_2,
         // (D1V2) <- V^T F_1; pressure <- V^T F_q
@@ -431,8 +447,9 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
         {
             int rmax = 0;
             for (int i = 0; i < n; ++i) rmax = std::max(rmax, J.j[i].ma.rows);
-            const long long nt = (long long)nq * nq * ((rmax + QJB - 1) / QJB);
-            hipLaunchKernelGGL(k_qpass3t, dim3(blocks_for(nt), n), dim3(QT), 0, st, J);
+            const unsigned nb =
+                (unsigned)(xcd_tiles((long long)nq * nq) * ((rmax + QJB - 1) / QJB));
+            hipLaunchKernelGGL(k_qpass3t, dim3(nb, n), dim3(QT), 0, st, J);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         // transposed mode 2: a_c <- V^T (V1V2) + D^T (V1D2), b_c <- V^T (D1V2); pressure
