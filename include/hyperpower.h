@@ -197,7 +197,7 @@ hp_status hp_apply_K(hp_ctx* ctx, const double* x, double* y, int nrhs);
  * quadrature: the same matrix as hp_apply_K, up to rounding.  x and y are
  * device arrays of nrhs vectors (stride N, layout of hp_apply_K), y must not
  * alias x.  The first call allocates the point tables and a scratch of
- * 7 (E(p+1)+2) n_M^2 + 10 (E(p+1)+2)^2 n_M + 13 (E(p+1)+2)^3 doubles
+ * 7 (E(p+1)+2) n_M^2 + 10 (E(p+1)+2)^2 n_M + 10 (E(p+1)+2)^3 doubles
  * (one right-hand side at a time); HP_ENOMEM if that fails. */
 hp_status hp_apply_K_quad(hp_ctx* ctx, const double* x, double* y, int nrhs);
 

@@ -24,8 +24,8 @@
 //   mode 3 evaluation fused with the pointwise flux (k_qflux),
 //   and the transposed contractions mode 3 (k_qpass3t, four output rows
 //   per thread), mode 2 and mode 1 (k_qpass).
-// Every launch is HBM bound; the flux fields at the 13 (E(p+1)+2)^3 points
-// dominate the traffic (13 written, 13 read).
+// Every launch is HBM bound; the 10 flux fields at the (E(p+1)+2)^3 points
+// dominate the traffic (written once, read once).
 #include <algorithm>
 #include <stdexcept>
 
@@ -144,9 +144,21 @@ __global__ __launch_bounds__(QT) void k_qpass3t(QJobs J) {
         if (k < nr) jb.out[base + (long long)(r0 + k) * pl] = jb.b ? acc[k] + accb[k] : acc[k];
 }
 
+// Flux fields at the points (10): F_v of components 1..3 (0..2), the
+// diagonal S_11, S_22, S_33 (3..5), S_12, S_13, S_23 (6..8) and F_q (9).
+// S_cd serves as the coefficient of d_d v_c and of d_c v_d: equal at volume
+// points; on a face normal to c only d_c v_d is nonzero (u_c is normal
+// there), and S_cd is then read for component c only through its own
+// direction-c value table, whose end-point rows vanish (interior functions),
+// so one field carries both.
+constexpr int QNF = 10;
+__host__ __device__ constexpr int qsym(int c, int d) {
+    return c == d ? 3 + c : (c + d == 1 ? 6 : (c + d == 2 ? 7 : 8));
+}
+
 struct QFluxArgs {
     const double* in[10];  // component c: (V1 V2), (V1 D2), (D1 V2) at 3c..3c+2; pressure 9
-    double* out[13];       // component c: F_v, F_1, F_2, F_3 at 4c..4c+3; pressure 12
+    double* out[QNF];
     QBand V[2], D[2];      // direction-3 tables: [0] degree p-1, [1] interior degree p
     const double* wq;
     int nq;
@@ -176,20 +188,18 @@ __global__ __launch_bounds__(QT) void k_qflux(QFluxArgs A) {
                e2 = i2 == 0 || i2 == last;
     const int ne = (int)e0 + (int)e1 + (int)e2;
     const double w = A.wq[i0] * A.wq[i1] * A.wq[i2];
-    double F[3][4];
-    double Fq = 0.0;
+    double F[QNF];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) F[c][k] = 0.0;
+    for (int k = 0; k < QNF; ++k) F[k] = 0.0;
     if (ne == 0) {
         const double wn = w * A.nu;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
+        for (int c = 0; c < 3; ++c) {
+            F[3 + c] = wn * (G[c][c] + G[c][c]) + w * P;
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-                F[c][1 + d] = wn * (G[c][d] + G[d][c]) + (c == d ? w * P : 0.0);
-        Fq = w * (G[0][0] + G[1][1] + G[2][2]);
+            for (int d = c + 1; d < 3; ++d) F[qsym(c, d)] = wn * (G[c][d] + G[d][c]);
+        }
+        F[9] = w * (G[0][0] + G[1][1] + G[2][2]);
     } else if (ne == 1) {
         // face normal to direction d (register arrays are only indexed by
         // unrolled constants)
@@ -203,16 +213,13 @@ __global__ __launch_bounds__(QT) void k_qflux(QFluxArgs A) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (c == d) continue;
-                F[c][0] = wn * (2.0 * A.alpha * U[c] - s * G[c][d]);
-                F[c][1 + d] = -wn * s * U[c];
+                F[c] = wn * (2.0 * A.alpha * U[c] - s * G[c][d]);
+                F[qsym(c, d)] = -wn * s * U[c];
             }
         }
     }
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) A.out[4 * c + k][o] = F[c][k];
-    A.out[12][o] = Fq;
+    for (int k = 0; k < QNF; ++k) A.out[k][o] = F[k];
 }
 
 // Band form of a dense row-major rows x cols matrix: one common width w,
@@ -301,7 +308,7 @@ hipError_t quad_setup(hp_ctx* c, QuadOp* q) {
     q->nq = nq;
     const long long s1 = (long long)nq * nM * nM, s2 = (long long)nq * nq * nM,
                     s3 = (long long)nq * nq * nq;
-    q->scratch_doubles = (size_t)(7 * s1 + 10 * s2 + 13 * s3);
+    q->scratch_doubles = (size_t)(7 * s1 + 10 * s2 + QNF * s3);
     hipError_t e;
     if ((e = hipMalloc(&q->tables, sizeof(double) * nd)) != hipSuccess) return e;
     if ((e = hipMalloc(&q->index, sizeof(int) * ni)) != hipSuccess) return e;
@@ -350,7 +357,7 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
                     s3 = (long long)nq * nq * nq;
     double* S1 = q->scratch;          // 7 fields after mode 1 (and after transposed mode 2)
     double* S2 = S1 + 7 * s1;         // 10 fields after mode 2 (and after transposed mode 3)
-    double* FL = S2 + 10 * s2;        // 13 flux fields at the points
+    double* FL = S2 + 10 * s2;        // QNF flux fields at the points
     hipStream_t st = c->stream;
     hipError_t e;
     // table type of component c along direction d: interior degree p in its own direction
@@ -403,7 +410,7 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
         // mode 3 evaluation and the flux at every point
         QFluxArgs A{};
         for (int k = 0; k < 10; ++k) A.in[k] = S2 + (long long)k * s2;
-        for (int k = 0; k < 13; ++k) A.out[k] = FL + (long long)k * s3;
+        for (int k = 0; k < QNF; ++k) A.out[k] = FL + (long long)k * s3;
         for (int t = 0; t < 2; ++t) {
             A.V[t] = q->V[t];
             A.D[t] = q->D[t];
@@ -415,8 +422,10 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
         hipLaunchKernelGGL(k_qflux, dim3((unsigned)(xcd_tiles((long long)nq * nq) * nq)), dim3(QT), 0,
                            st, A);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // transposed mode 3: (V1V2) <- V^T F_v + D^T F_3, (V1D2) <- V^T F_2,
-        // (D1V2) <- V^T F_1; pressure <- V^T F_q
+        // transposed mode 3: (V1V2) <- V^T F_v + D^T S_c3, (V1D2) <- V^T S_c2,
+        // (D1V2) <- V^T S_c1; pressure <- V^T F_q.  Component 2's (D1V2) is
+        // V^T S_12 with the degree p-1 table, as component 1's (V1D2): one job
+        // (slot 1) serves both.
         J = QJobs{};
         n = 0;
         for (int comp = 0; comp < 4; ++comp) {
@@ -424,6 +433,7 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
             const int t = comp < 3 ? T(comp, 2) : 0;
             const int nj = comp < 3 ? 3 : 1;
             for (int k = 0; k < nj; ++k) {
+                if (comp == 1 && k == 2) continue;
                 QJob& j = J.j[n];
                 j.d0 = nq;
                 j.d1 = nq;
@@ -433,13 +443,13 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
                 j.b = nullptr;
                 j.ma = q->VT[t];
                 if (comp == 3) {
-                    j.a = FL + 12 * s3;
+                    j.a = FL + 9 * s3;
                 } else if (k == 0) {
-                    j.a = FL + (long long)(4 * comp) * s3;
-                    j.b = FL + (long long)(4 * comp + 3) * s3;
+                    j.a = FL + (long long)comp * s3;
+                    j.b = FL + (long long)qsym(comp, 2) * s3;
                     j.mb = q->DT[t];
                 } else {
-                    j.a = FL + (long long)(4 * comp + (k == 1 ? 2 : 1)) * s3;
+                    j.a = FL + (long long)qsym(comp, k == 1 ? 1 : 0) * s3;
                 }
                 ++n;
             }
@@ -475,7 +485,7 @@ hipError_t launch_quad_K(hp_ctx* c, const QuadOp* q, const Fields& in, const Fie
                     j.b = S2 + (long long)(3 * comp + 1) * s2;
                     j.mb = q->DT[t];
                 } else {
-                    j.a = S2 + (long long)(3 * comp + 2) * s2;
+                    j.a = S2 + (long long)(comp == 1 ? 1 : 3 * comp + 2) * s2;
                 }
                 ++n;
             }
