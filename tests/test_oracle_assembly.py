@@ -118,13 +118,16 @@ def test_kron_rows_match_the_assembled_matrix(E, p):
     assert np.allclose(yq, S.Mq @ xq, rtol=0, atol=1e-13 * np.abs(yq).max())
 
 
-def _quadrature_flux_apply(E, p, nu, x):
+def _quadrature_flux_apply(E, p, nu, x, shared=False):
     """K x by the pointwise flux form the quadrature-based GPU operator uses:
     gradients and pressure at the points [0, the E(p+1) Gauss points, 1] of
     each direction; volume flux nu (G + G^T) + P I and div u; on a face
     normal to d (outward sign s) and tangential c != d only
     nu (2 alpha u_c v_c - s d_d u_c v_c - s u_c d_d v_c); edges carry
-    nothing.  Written with numpy contractions (slow, small meshes)."""
+    nothing.  Written with numpy contractions (slow, small meshes).
+    shared=True stores the off-diagonal fluxes as one field per pair
+    (c, d), S_cd = the coefficient of d_d v_c where c is tangential to the
+    face, else of d_c v_d, and reads it for both."""
     from oracle.assemble import block_offsets, default_c_pen, field_shapes
     from oracle.splines import SplinePair, gauss_points
     sp = SplinePair(E, p)
@@ -178,6 +181,15 @@ def _quadrature_flux_apply(E, p, nu, x):
             if c != d:
                 F[c][0] = F[c][0] + np.where(face, W * nu * (2 * alpha * U[c] - s * G[c][d]), 0.0)
                 F[c][1 + d] = F[c][1 + d] + np.where(face, -W * nu * s * U[c], 0.0)
+    if shared:
+        for c in range(3):
+            for d in range(c + 1, 3):
+                S = F[c][1 + d] + F[d][1 + c]      # never both nonzero off the volume
+                vol_ok = np.allclose(np.where(vol, F[c][1 + d] - F[d][1 + c], 0.0), 0.0)
+                assert vol_ok
+                S = np.where(vol, F[c][1 + d], S)
+                F[c][1 + d] = S
+                F[d][1 + c] = S
     out = []
     for c in range(3):
         V1, D1 = tab[typ(c, 0)]
@@ -198,9 +210,13 @@ def test_quadrature_flux_form_equals_K(E, p, nu):
     the normal derivative of the tangential components (the normal component
     and its tangential derivatives vanish on the face) reproduce K exactly
     (Gauss with p+1 points is exact for these integrands).  Dropping the
-    consistency term or the edge rule breaks the match."""
+    consistency term or the edge rule breaks the match.  The same holds with
+    one field per off-diagonal pair (the storage of the GPU kernel): on a
+    face normal to c the value meant for component d is read by component c
+    only through its own direction-c value table, which vanishes there."""
     S = KronSystem(E, p, nu)
     x = np.random.default_rng(E * 10 + p).standard_normal(S.N)
-    y = _quadrature_flux_apply(E, p, nu, x)
     ref = S.K @ x
-    assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
+    for shared in (False, True):
+        y = _quadrature_flux_apply(E, p, nu, x, shared=shared)
+        assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
