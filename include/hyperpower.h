@@ -129,6 +129,29 @@ typedef struct hp_opts {
                            factored operator kernels (default), 1 = the quadrature-based
                            operator of hp_apply_K_quad (the same matrix up to rounding);
                            the reported true residual always uses hp_apply_K */
+    int use_x0;         /* hp_solve: 0 = start from x_0 = 0 (default, Sec. 5), 1 = start
+                           from the x passed in (warm start / resume); the stopping test
+                           stays relative to b (see hp_solve) */
+    int spectrum_gate;  /* hp_setup: 0 = off (default); n > 0 = run n Lanczos steps on each
+                           block of P_0 (P_{V,0}^{-1} A and P_{Q,0}^{-1} B' P_{V,0}^{-1} B,
+                           as hp_spectrum) and refuse the context with HP_ENOTSPD when an
+                           estimated eigenvalue lies outside (0, 2), where the hyper-power
+                           sequence diverges and P_k (k >= 1) loses definiteness (Sec. 2,
+                           Lemma Sk_posdef, Remark rmk:convergence_Pk) */
+    double p0_scale;    /* damping factor w of the base preconditioner: every
+                           application of P_0^{-1} (both blocks, also inside P_k and
+                           hp_spectrum) is w P_0^{-1}; 0 or 1 (default) = the plain P_0 of
+                           Sec. 4.  The hyper-power sequence needs sigma(w P_0^{-1} A~) in
+                           (0, 2) (Lemma Sk_posdef): a w that pushes the largest eigenvalue
+                           past 2 makes P_k indefinite, which spectrum_gate and MINRES
+                           report as HP_ENOTSPD */
+    double breakdown_tol; /* Krylov breakdown threshold (default 0: exact breakdown only).
+                           MINRES stops with HP_EBREAKDOWN when the rotated diagonal entry
+                           a of the tridiagonal Lanczos matrix has |a| <= breakdown_tol *
+                           (|delta| + gamma + gamma_next), its column's entries; FGMRES when
+                           the rotated pivot of Hessenberg column j is <= breakdown_tol times
+                           that column's 2-norm.  A value >= 1 forces the breakdown path at
+                           the first iteration (used to test the error path) */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -169,7 +192,8 @@ hp_status hp_get_tuning(const hp_ctx* ctx, int nrhs, hp_tuning* out);
  * workspace.  elements >= 1, 2 <= degree <= 8, nu > 0.  Returns HP_ENOTSPD
  * when the Nitsche penalty opts.c_pen is too small for the degree and mesh
  * (the augmented T^ of Sec. 3.3 is then indefinite, e.g. degree 8 with
- * fewer than 6 elements at the default 12.5).  opts may be NULL
+ * fewer than 6 elements at the default 12.5), or, with opts.spectrum_gate,
+ * when P_0 leaves the convergence interval (0, 2).  opts may be NULL
  * (defaults).  stream: a hipStream_t or NULL.  *out receives the context.
  * Fast diagonalisation holds a whole direction in MFMA tiles, so P_0,
  * P_k and the solve need E + degree - 1 <= 128; above that the context
@@ -248,21 +272,36 @@ hp_status hp_spectrum(hp_ctx* ctx, int block, int order, int iters, int s_level,
                       const double* start, double* alpha, double* beta, int* done,
                       double* lmin, double* lmax);
 
-/* Solve K x = b to relative tolerance tol with x_0 = 0 (Sec. 5: MINRES to
- * 1e-8), preconditioned by P_k (opts.order, opts.iters).  MINRES monitors
- * ||r||_{P^{-1}} / ||b||_{P^{-1}}, FGMRES ||r||_2 / ||b||_2.  info may be
- * NULL.  Returns HP_ENOCONV (x = last iterate) if maxit is reached. */
+/* Solve K x = b to relative tolerance tol (Sec. 5: MINRES to 1e-8),
+ * preconditioned by P_k (opts.order, opts.iters), from x_0 = 0, or from the
+ * x passed in when opts.use_x0 = 1 (x is then read first; MINRES and FGMRES
+ * run on the residual b - K x_0 and update x in place).  The stopping test
+ * is relative to b in both cases: MINRES monitors the preconditioned norm
+ * ||r_j||_{P^{-1}} / ||b||_{P^{-1}} (the norm its recurrence carries; a warm
+ * start costs one extra P_k application for ||b||_{P^{-1}}), FGMRES the
+ * 2-norm ||r_j||_2 / ||b||_2, confirmed with the true residual at the end of
+ * each restart cycle.  info->true_relres is always the FP64 2-norm
+ * ||b - K x||_2 / ||b||_2 of the returned x; for MINRES it can differ from
+ * the monitored value by up to the condition number of P_k (converged = 1
+ * refers to the monitored norm).  info may be NULL.  Returns HP_ENOCONV
+ * (x = last iterate) if maxit is reached, HP_ENAN if b, x_0 or an iterate is
+ * not finite, HP_ENOTSPD if MINRES meets r' P_k^{-1} r < 0, HP_EBREAKDOWN
+ * (see opts.breakdown_tol; x = the last iterate). */
 hp_status hp_solve(hp_ctx* ctx, const double* b, double* x, int nrhs, double tol,
                    hp_solve_info* info);
 
 /* Right-hand side of the lid-driven cavity (Sec. 5, Fig. liddrivencavity)
- * with a separable body force: for each rhs r, lid speed lid[r] on x3 = 1
- * (Nitsche data, Sec. 3.1), and for each velocity component c and mode m
- * b_c += amp[(r*3 + c)*nmodes + m] * prod_d sin(pi k_d x_d) with
- * k_d = waves[((r*3 + c)*nmodes + m)*3 + d].  Host arrays lid, amp, waves
- * (amp/waves may be NULL when nmodes == 0); device output b (N x nrhs). */
+ * with a body force, b = [F_lid + F_modes + M_V beta; 0] (the linear form
+ * l(v) of Sec. 3.1 plus the Nitsche lid data): for each rhs r, lid speed
+ * lid[r] on x3 = 1, and for each velocity component c and mode m
+ * F_c += amp[(r*3 + c)*nmodes + m] * prod_d sin(pi k_d x_d) with
+ * k_d = waves[((r*3 + c)*nmodes + m)*3 + d] integrated against the basis,
+ * and, when beta is not NULL, the body force whose coefficients in V_h are
+ * beta (device, n_V per rhs, stride n_V), which contributes M_V beta.
+ * Host arrays lid, amp, waves (lid may be NULL: no lid; amp/waves may be
+ * NULL when nmodes == 0); device output b (N x nrhs, must not overlap beta). */
 hp_status hp_build_rhs(hp_ctx* ctx, const double* lid, int nmodes, const double* amp,
-                       const int* waves, double* b, int nrhs);
+                       const int* waves, const double* beta, double* b, int nrhs);
 
 /* y = M_V u, the velocity mass matrix (block diagonal L2 Gram matrix of
  * V_h), stride n_V; used by the loss gradient of the differentiable solve. */

@@ -53,6 +53,10 @@ class hp_opts(ctypes.Structure):
         ("op_fused", ctypes.c_int),
         ("op_staged", ctypes.c_int),
         ("forward", ctypes.c_int),
+        ("use_x0", ctypes.c_int),
+        ("spectrum_gate", ctypes.c_int),
+        ("p0_scale", ctypes.c_double),
+        ("breakdown_tol", ctypes.c_double),
     ]
 
 
@@ -99,7 +103,7 @@ SIGNATURES = {
     "hp_apply_P0": (I, [P, P, P, I]),
     "hp_apply_hyperpower": (I, [P, I, I, P, P, I]),
     "hp_solve": (I, [P, P, P, I, D, ctypes.POINTER(hp_solve_info)]),
-    "hp_build_rhs": (I, [P, P, I, P, P, P, I]),
+    "hp_build_rhs": (I, [P, P, I, P, P, P, P, I]),
     "hp_apply_MV": (I, [P, P, P, I]),
     "hp_grad": (I, [P, P, P, P, P, P, I]),
     "hp_get_tuning": (I, [P, I, ctypes.POINTER(hp_tuning)]),

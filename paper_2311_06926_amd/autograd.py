@@ -23,8 +23,7 @@ class HyperPowerSolve(torch.autograd.Function):
     def forward(ctx, beta, nu, solver, lid=1.0, tol=1e-10):
         nu_f = float(nu)
         solver.set_nu(nu_f)
-        b = solver.build_rhs([lid])
-        b[:solver.nV] += solver.apply_MV(beta.detach().contiguous())
+        b = solver.build_rhs([lid], beta=beta.detach().contiguous())
         x, info = solver.solve(b, tol)
         ctx.save_for_backward(x)
         ctx.solver, ctx.lid, ctx.tol, ctx.nu = solver, lid, tol, nu_f

@@ -175,6 +175,9 @@ hipError_t pres_axpbypcz(hp_ctx* c, double a, const Fields& x, double b, const F
 
 // ---- hyper-power preconditioner (Secs. 2, 4.1) ------------------------------------
 
+// The factor of P_{Q,0}^{-1} = 2 nu w M_q^{-1} (w: the damping factor p0_scale).
+double q0_factor(const hp_ctx* c) { return 2.0 * c->nu * c->opts.p0_scale; }
+
 // y = P_{V,level}^{-1} x: q^level Richardson steps y <- y + P_{V,0}^{-1}(x - A y)
 // from y = 0, which equals the hyper-power recursion of eq. Pcv (its Neumann
 // form, eq. neumann).  x, y: velocity views; must not alias each other.
@@ -206,7 +209,7 @@ hipError_t apply_Stilde(hp_ctx* c, int q, int l, const Fields& t, const Fields& 
     const long long nV = c->nV;
     Fields b1 = vel_fields(c, ex->hv + nV * c->opts.max_rhs, nV);       // slot 1
     Fields b2 = vel_fields(c, ex->hv + 2 * nV * c->opts.max_rhs, nV);   // slot 2
-    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, b1, 2.0 * c->nu, 0.0, nullptr, nrhs)
+    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, b1, q0_factor(c), 0.0, nullptr, nrhs)
                             : launch_operator(c, OP_B, t, b1, 1.0, 0.0, nullptr, nrhs);
     if (e != hipSuccess) return e;
     e = apply_PV(c, q, l, b1, b2, nrhs, prec);
@@ -236,7 +239,7 @@ hipError_t apply_Spcg(hp_ctx* c, int q, const Fields& t, const Fields& out, int 
     double* cr = cx + 2 * R;
     double* cp = cr + 2 * R;
     auto F = [&](double* b) { return vel_fields(c, b, nV); };
-    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, F(bv), 2.0 * c->nu, 0.0, nullptr, nrhs)
+    hipError_t e = after_q0 ? launch_operator(c, OP_DT, t, F(bv), q0_factor(c), 0.0, nullptr, nrhs)
                             : launch_operator(c, OP_B, t, F(bv), 1.0, 0.0, nullptr, nrhs);
     if (e != hipSuccess) return e;
     const long long n = nV * nrhs;  // velocity vectors are contiguous per rhs
@@ -515,7 +518,8 @@ hipError_t minres_w_step(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
     const PkDot pd = minres_pk_dot(c, b);
     return minres_w(c->stream, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, ex->msc + cur * R,
                     ex->msc + (cur ^ 1) * R, Partials{pd.vpart, fd_dot_count(c, true)},
-                    Partials{pd.qpart, fd_dot_count(c, false)}, tol, mirror);
+                    Partials{pd.qpart, fd_dot_count(c, false)}, tol, c->opts.breakdown_tol,
+                    mirror);
 }
 
 hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
@@ -599,16 +603,28 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     const bool graphs = c->opts.use_graph != 0;
     if (graphs && build_graphs(c, nrhs, tol) != HP_OK) return HP_EHIP;
     MinresBufs b0 = minres_bufs(c, 0, nrhs);
-    HIPCHK(vec_zero(c->stream, V, b0.x));
+    const bool warm = c->opts.use_x0 != 0;
+    double* ref_part = ex->mpart + vec_partial_doubles(1, c->opts.max_rhs);
+    if (warm) {
+        // start residual v = b - K x_0 (x is updated in place from x_0), and
+        // ||b||_{P^{-1}} for the stopping test (z = P_k^{-1} b)
+        HIPCHK(vec_copy(c->stream, V, x, b0.x));
+        HIPCHK(launch_forward(c, b0.x, b0.v, nrhs));
+        HIPCHK(vec_axpby(c->stream, V, 1.0, b, -1.0, b0.v));
+        HIPCHK(apply_Pk(c, c->opts.order, c->opts.iters, b, b0.z, nrhs));
+        HIPCHK(vec_dot_partials(c->stream, N, N, b0.z, b, nrhs, ref_part));
+    } else {
+        HIPCHK(vec_zero(c->stream, V, b0.x));
+        HIPCHK(vec_copy(c->stream, V, b, b0.v));
+    }
     HIPCHK(vec_zero(c->stream, V, b0.vo));
     HIPCHK(vec_zero(c->stream, V, b0.wo));
     HIPCHK(vec_zero(c->stream, V, b0.w));
-    HIPCHK(vec_copy(c->stream, V, b, b0.v));
     HIPCHK(apply_Pk(c, c->opts.order, c->opts.iters, b0.v, b0.z, nrhs));
     HIPCHK(vec_dot_partials(c->stream, N, N, b0.z, b0.v, nrhs, ex->mpart));
     // iteration it reads the state msc[it & 1]: the first reads msc[1]
     MinresScalars* s1 = ex->msc + c->opts.max_rhs;
-    HIPCHK(minres_init(c->stream, s1, ex->mpart, nrhs));
+    HIPCHK(minres_init(c->stream, s1, ex->mpart, warm ? ref_part : nullptr, tol, nrhs));
     const size_t sbytes = sizeof(MinresScalars) * nrhs;
     auto all_done = [&](const MinresScalars* h) {
         for (int r = 0; r < nrhs; ++r)
@@ -692,8 +708,8 @@ hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol, FgSca
             return e;
     }
     if ((e = vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart)) != hipSuccess) return e;
-    if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol, j,
-                    m, nrhs, mirror)) != hipSuccess)
+    if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol,
+                    c->opts.breakdown_tol, j, m, nrhs, mirror)) != hipSuccess)
         return e;
     const double* xs[1] = {w};
     return vec_lincomb(c->stream, N, N, nrhs, 1, xs, ex->fvs, Vb + (long long)(j + 1) * V);
@@ -766,7 +782,8 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     const size_t sbytes = sizeof(FgScalars) * nrhs;
     HIPCHK(vec_dot_partials(c->stream, N, N, b, b, nrhs, ex->fpart));
     HIPCHK(fg_init(c->stream, ex->fsc, ex->fpart, nrhs));
-    HIPCHK(vec_zero(c->stream, Vn, x));
+    // x_0 = 0, or the x passed in (warm start): every cycle starts from b - K x
+    if (!c->opts.use_x0) HIPCHK(vec_zero(c->stream, Vn, x));
     auto all = [&](const FgScalars* h, bool active) {
         for (int r = 0; r < nrhs; ++r)
             if (active ? h[r].active : !h[r].done) return false;
@@ -836,7 +853,7 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
 
 // ---- right-hand side -------------------------------------------------------------------
 hp_status build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp, const int* waves,
-                    double* b, int nrhs) {
+                    const double* beta, double* b, int nrhs) {
     const Tables1D& T = c->tab;
     const int nN = c->nN, nM = c->nM;
     // per (rhs, component): factors s1, s2, s3 (each nt terms) assembled on the host
@@ -889,6 +906,13 @@ hp_status build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp,
                 hipSuccess) { st = HP_EHIP; break; }
             if (hipStreamSynchronize(c->stream) != hipSuccess) { st = HP_EHIP; break; }
         }
+    }
+    // body force with coefficients beta in V_h: b_u += M_V beta
+    if (st == HP_OK && beta) {
+        const Fields bu = vel_of_full(c, b);
+        if (launch_operator(c, OP_MV, vel_fields(c, beta, c->nV), bu, 1.0, 1.0, &bu, nrhs) !=
+            hipSuccess)
+            st = HP_EHIP;
     }
     (void)hipStreamSynchronize(c->stream);
     (void)hipFree(ds);
@@ -1169,6 +1193,31 @@ hp_status spectrum(hp_ctx* c, int block, int q, int k, int sl, int steps, const 
     return HP_OK;
 }
 
+// The setup gate (hp_opts.spectrum_gate): `steps` Lanczos steps on each block
+// of P_0 -- sigma(P_{V,0}^{-1} A) and sigma(P_{Q,0}^{-1} B' P_{V,0}^{-1} B) --
+// from a fixed start vector; HP_ENOTSPD when an estimate leaves (0, 2), the
+// interval in which the hyper-power sequence converges and keeps P_k
+// positive definite (Sec. 2, Lemma Sk_posdef, Remark rmk:convergence_Pk).
+hp_status spectrum_gate(hp_ctx* c, int steps) {
+    for (int block = HP_SPEC_VELOCITY; block <= HP_SPEC_SCHUR; ++block) {
+        const long long n = block == HP_SPEC_VELOCITY ? c->nV : c->nQ;
+        std::vector<double> h((size_t)n);
+        for (long long i = 0; i < n; ++i) h[(size_t)i] = std::sin(0.754877666 * (double)(i + 1)) + 0.1;
+        DevBuf start;
+        if (alloc_device(&start.p, (size_t)n) != HP_OK) return HP_ENOMEM;
+        HIPCHK(hipMemcpyAsync(start.p, h.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::vector<double> al, be;
+        const hp_status st =
+            spectrum(c, block, 2, 0, 0, (int)std::min<long long>(steps, n), start.p, al, be);
+        if (st != HP_OK) return st;
+        std::vector<double> off(be.begin(), be.begin() + (al.size() - 1));
+        const double lmin = tridiag_eig(al, off, 1), lmax = tridiag_eig(al, off, (int)al.size());
+        if (!(lmin > 0.0) || !(lmax < 2.0)) return HP_ENOTSPD;
+    }
+    return HP_OK;
+}
 
 }  // namespace
 
@@ -1200,6 +1249,10 @@ void hp_default_opts(hp_opts* o) {
     o->forward = 0;
     o->schur_pcg_iters = 20;
     o->schur_pcg_tol = 1e-2;
+    o->use_x0 = 0;
+    o->spectrum_gate = 0;
+    o->p0_scale = 1.0;
+    o->breakdown_tol = 0.0;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -1232,8 +1285,10 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
         o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3 ||
-        o.forward < 0 || o.forward > 1)
+        o.forward < 0 || o.forward > 1 || o.use_x0 < 0 || o.use_x0 > 1 || o.spectrum_gate < 0 ||
+        !(o.p0_scale >= 0.0) || !std::isfinite(o.p0_scale) || !(o.breakdown_tol >= 0.0))
         return HP_EINVAL;
+    if (o.p0_scale == 0.0) o.p0_scale = 1.0;
     const int nM = elements + degree - 1;
     if (nM > 4096) return HP_EINVAL;
     if (ops_init_attributes() != hipSuccess || fd_init_attributes() != hipSuccess) return HP_EHIP;
@@ -1435,6 +1490,13 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
             return ts;
         }
     }
+    if (c->opts.spectrum_gate > 0 && c->fd_ok) {
+        const hp_status gs = spectrum_gate(c, c->opts.spectrum_gate);
+        if (gs != HP_OK) {
+            hp_destroy(c);
+            return gs;
+        }
+    }
     *out = c;
     return HP_OK;
 }
@@ -1590,10 +1652,13 @@ hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
 }
 
 hp_status hp_build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp,
-                       const int* waves, double* b, int nrhs) {
+                       const int* waves, const double* beta, double* b, int nrhs) {
     if (check_rhs(c, nrhs) != HP_OK || !b || nmodes < 0 || (nmodes > 0 && (!amp || !waves)))
         return HP_EINVAL;
-    return build_rhs(c, lid, nmodes, amp, waves, b, nrhs);
+    // beta (n_V per rhs) must not overlap b (N per rhs)
+    if (beta && beta < b + c->N * (long long)nrhs && b < beta + c->nV * (long long)nrhs)
+        return HP_EINVAL;
+    return build_rhs(c, lid, nmodes, amp, waves, beta, b, nrhs);
 }
 
 hp_status hp_grad(hp_ctx* c, const double* x, const double* lambda, const double* lid,
@@ -1604,7 +1669,7 @@ hp_status hp_grad(hp_ctx* c, const double* x, const double* lambda, const double
                            0.0, nullptr, nrhs));
     // dL/dnu = lambda_u . (F_lid - A u) / nu ; F_lid into t (full), A u into its velocity part
     double* t = c->ws + ops_ws_stride(c) * (long long)c->opts.max_rhs;  // N * nrhs scratch
-    hp_status s = build_rhs(c, lid, 0, nullptr, nullptr, t, nrhs);
+    hp_status s = build_rhs(c, lid, 0, nullptr, nullptr, nullptr, t, nrhs);
     if (s != HP_OK) return s;
     const Fields tv = vel_of_full(c, t);
     HIPCHK(launch_operator(c, OP_A, vel_of_full(c, x), tv, -1.0, 1.0, &tv, nrhs));

@@ -286,6 +286,7 @@ struct ZArgs {
     int fields_lo, fields_hi;
     int accumulate;   // bit f set: field f is added to its output
     double two_nu;
+    double omega;     // damping factor of P_0^{-1} (1: the plain base preconditioner)
     // FP64 output, launches of one field only: partial sums of (stored
     // output) . dw per workgroup to dpart[r * dp_stride + blockIdx.x]
     const double* dw;  // same layout and rhs stride as the output
@@ -395,7 +396,8 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
             if (b < nb3)
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    Sw[M::row(lk, i) * ld + b * 16 + lr] = (T)(a.two_nu * (double)acc[b][i]);
+                    Sw[M::row(lk, i) * ld + b * 16 + lr] =
+                        (T)(a.omega * a.two_nu * (double)acc[b][i]);
     } else {
         // scale by 1 / (2 nu (l1 + l2 + l3)) and transform back: Z = Y U3^T
         const double* l1 = (f == 0) ? t.lamK : t.lamT;
@@ -412,7 +414,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
                     double sc = 0.0;
                     if (rr < plane && col < n3) {
                         const int i1 = (int)(rr % n1), i2 = (int)(rr / n1);
-                        sc = 1.0 / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
+                        sc = a.omega / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
                     }
                     Sw[row * ld + col] = (T)(sc * (double)acc[b][i]);
                 }
@@ -815,13 +817,13 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
             const int col = cb * 16 + lr;
             double sc;
             if (pres) {
-                sc = a.two_nu;
+                sc = a.omega * a.two_nu;
             } else {
                 sc = 0.0;
                 const long long rr = r0 + row;
                 if (rr < plane && col < n3) {
                     const int i1 = (int)(rr % n1), i2 = (int)(rr / n1);
-                    sc = 1.0 / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
+                    sc = a.omega / (a.two_nu * (l1[i1] + l2[i2] + l3[col]));
                 }
             }
             Y[row * ld + col] = (T)(sc * (double)acc[i]);
@@ -993,6 +995,7 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         za.sout[f] = N;
     }
     za.two_nu = 2.0 * c->nu;
+    za.omega = c->opts.p0_scale;
     // the pressure's mode-3 step writes the final output; the velocity's
     // feeds the inverse xy step.  In FP64 both output types agree, so the
     // four fields share one launch.

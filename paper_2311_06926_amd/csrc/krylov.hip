@@ -296,27 +296,32 @@ __device__ double sum_partials(const double* part, int q) {
 }
 
 // after z = P^{-1} b:  gamma = sqrt(z.v), beta0 = eta = gamma, c = 1, s = 0
-__global__ void k_minres_init(MinresScalars* sc, const double* part_zv, int nrhs) {
+// part_ref (may be null): partials of b . P^{-1} b when the start residual
+// is not b (warm start); the monitored residual is then relative to
+// ||b||_{P^{-1}} instead of ||r_0||_{P^{-1}}.
+__global__ void k_minres_init(MinresScalars* sc, const double* part_zv, const double* part_ref,
+                              double tol, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     MinresScalars& m = sc[r];
     const double zv = sum_partials(part_zv, r);
+    const double ref = part_ref ? sum_partials(part_ref, r) : zv;
     m = MinresScalars{};
     m.status = 0;
-    if (!(zv >= 0.0) || !isfinite(zv)) {
-        m.status = zv < 0.0 ? -4 : -7;
+    if (!(zv >= 0.0) || !isfinite(zv) || !(ref >= 0.0) || !isfinite(ref)) {
+        m.status = (zv < 0.0 || ref < 0.0) ? -4 : -7;
         m.done = 1;
         return;
     }
     m.gamma = sqrt(zv);
     m.gamma_old = 1.0;
-    m.beta0 = m.gamma;
+    m.beta0 = ref > 0.0 ? sqrt(ref) : m.gamma;
     m.eta = m.gamma;
     m.c0 = m.c1 = 1.0;
     m.s0 = m.s1 = 0.0;
-    m.rel = 1.0;
-    m.done = (m.gamma == 0.0);
-    if (m.done) m.rel = 0.0;
+    m.rel = m.beta0 > 0.0 ? m.gamma / m.beta0 : 0.0;
+    m.done = (m.gamma == 0.0) || (part_ref && m.rel <= tol);
+    if (m.gamma == 0.0) m.rel = 0.0;
 }
 
 // after Kz = K z:  delta = (Kz.z)/gamma^2; coefficients of v_new = Kz/gamma - (delta/gamma) v - (gamma/gamma_old) v_old
@@ -334,7 +339,8 @@ __device__ void minres_a_core(MinresScalars& m, double kz, double* cv) {
 
 // after z_new = P^{-1} v_new: gamma_new, the Givens rotation, coefficients of
 // w_new = (z/gamma - a3 w_old - a2 w)/a1 and x += c_new eta w_new, then shift.
-__device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* cx, double tol) {
+__device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* cx, double tol,
+                              double bd_tol) {
     cx[0] = 1.0;
     if (m.done) {
         cw[0] = cw[1] = cw[2] = 0.0;
@@ -357,7 +363,9 @@ __device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* c
     const double a1 = hypot(a0, gn);
     const double a2 = m.s1 * m.delta + m.c0 * m.c1 * g;
     const double a3 = m.s0 * g;
-    if (a1 == 0.0) {
+    // breakdown: the rotated diagonal entry vanishes against its column
+    // (delta, gamma, gamma_next) of the Lanczos matrix (bd_tol = 0: exactly)
+    if (a1 <= bd_tol * (fabs(m.delta) + g + gn)) {
         m.status = -5;
         m.done = 1;
         cw[0] = cw[1] = cw[2] = 0.0;
@@ -469,14 +477,14 @@ __global__ void k_minres_v(long long n, long long ld, const double* kz, const do
 __global__ void k_minres_w(long long n, long long ld, const double* z, const double* wo,
                            const double* w, double* wn, double* x, const MinresScalars* sc_in,
                            MinresScalars* sc_out, Partials pa, Partials pb, double tol,
-                           MinresScalars* mirror) {
+                           double bd_tol, MinresScalars* mirror) {
     __shared__ double sh[VT / 64];
     __shared__ double cw[3], cx[2];
     const int r = blockIdx.y;
     const double d = sum_block_partials(pa, pb, r, sh);
     if (threadIdx.x == 0) {
         MinresScalars m = sc_in[r];
-        minres_b_core(m, d, cw, cx, tol);
+        minres_b_core(m, d, cw, cx, tol, bd_tol);
         if (blockIdx.x == 0) {
             sc_out[r] = m;
             if (mirror) mirror[r] = m;
@@ -496,8 +504,10 @@ __global__ void k_minres_w(long long n, long long ld, const double* z, const dou
 
 }  // namespace
 
-hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs) {
-    hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
+hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
+                       const double* part_ref, double tol, int nrhs) {
+    hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part,
+                       part_ref, tol, nrhs);
     return hipGetLastError();
 }
 hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
@@ -510,9 +520,9 @@ hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const do
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
                     const double* wo, const double* w, double* wn, double* x,
                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
-                    double tol, MinresScalars* mirror) {
+                    double tol, double bd_tol, MinresScalars* mirror) {
     hipLaunchKernelGGL(k_minres_w, dim3(grid_for(n), nrhs), dim3(VT), 0,
-                       s, n, ld, z, wo, w, wn, x, sc_in, sc_out, a, b, tol, mirror);
+                       s, n, ld, z, wo, w, wn, x, sc_in, sc_out, a, b, tol, bd_tol, mirror);
     return hipGetLastError();
 }
 long long vec_dot_partial_count() { return DOT_BLOCKS; }
@@ -557,6 +567,10 @@ __global__ void k_fg_init(FgScalars* sc, const double* part_bb, int nrhs) {
     s.bnorm = sqrt(sum_partials(part_bb, r));
     s.done = (s.bnorm == 0.0);
     s.rel = s.done ? 0.0 : 1.0;
+    if (!isfinite(s.bnorm)) {
+        s.status = -7;
+        s.done = 1;
+    }
 }
 
 // cycle start: w = b - K x;  beta = ||w||, g = beta e1, vscale = 1/beta
@@ -569,6 +583,10 @@ __global__ void k_fg_begin(FgScalars* sc, const double* part_ww, double* g, doub
     double* gr = g + (long long)r * (m + 1);
     for (int i = 0; i <= m; ++i) gr[i] = 0.0;
     s.jr = 0;
+    if (!s.done && !isfinite(beta)) {  // b - K x_0 not finite
+        s.status = -7;
+        s.done = 1;
+    }
     s.active = !s.done && beta > 0.0;
     gr[0] = s.active ? beta : 0.0;
     vscale[r] = s.active ? 1.0 / beta : 0.0;
@@ -592,7 +610,8 @@ __global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hco
 
 // h_{j+1,j} = ||w||, previous rotations on column j, new rotation, residual estimate
 __device__ void fg_rot_one(FgScalars* sc, double ww, double* H, double* cs, double* sn,
-                           double* g, double* vscale, double tol, int j, int m, int r) {
+                           double* g, double* vscale, double tol, double bd_tol, int j, int m,
+                           int r) {
     FgScalars& s = sc[r];
     if (!s.active) {
         vscale[r] = 0.0;
@@ -604,15 +623,27 @@ __device__ void fg_rot_one(FgScalars* sc, double ww, double* H, double* cs, doub
     double* gr = g + (long long)r * (m + 1);
     const double hn = sqrt(ww);
     Hr[(j + 1) * m + j] = hn;
+    double col2 = ww;  // squared 2-norm of column j (the rotations keep it)
+    for (int i = 0; i <= j; ++i) col2 += Hr[i * m + j] * Hr[i * m + j];
     for (int i = 0; i < j; ++i) {
         const double t = cr[i] * Hr[i * m + j] + sr[i] * Hr[(i + 1) * m + j];
         Hr[(i + 1) * m + j] = -sr[i] * Hr[i * m + j] + cr[i] * Hr[(i + 1) * m + j];
         Hr[i * m + j] = t;
     }
     const double d = hypot(Hr[j * m + j], Hr[(j + 1) * m + j]);
-    if (d == 0.0) {
+    if (!isfinite(col2) || !isfinite(d)) {
+        s.status = -7;
+        s.active = 0;
+        s.done = 1;
+        vscale[r] = 0.0;
+        return;
+    }
+    // breakdown: the rotated pivot vanishes against its column (bd_tol = 0:
+    // exactly zero, a singular least-squares problem)
+    if (d <= bd_tol * sqrt(col2)) {
         s.status = -5;
         s.active = 0;
+        s.done = 1;
         vscale[r] = 0.0;
         return;
     }
@@ -633,14 +664,14 @@ __device__ void fg_rot_one(FgScalars* sc, double ww, double* H, double* cs, doub
 // One workgroup per rhs: ||w||^2 from its partials as a block reduction, then
 // the rotations in thread 0.
 __global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
-                         double* g, double* vscale, double tol, int j, int m,
+                         double* g, double* vscale, double tol, double bd_tol, int j, int m,
                          FgScalars* mirror) {
     __shared__ double sh[VT / 64];
     const int r = blockIdx.x;
     const double ww = block_sum(
         threadIdx.x < DOT_BLOCKS ? part_ww[(long long)r * DOT_BLOCKS + threadIdx.x] : 0.0, sh);
     if (threadIdx.x != 0) return;
-    fg_rot_one(sc, ww, H, cs, sn, g, vscale, tol, j, m, r);
+    fg_rot_one(sc, ww, H, cs, sn, g, vscale, tol, bd_tol, j, m, r);
     if (mirror) mirror[r] = sc[r];
 }
 
@@ -668,6 +699,10 @@ __global__ void k_fg_check(FgScalars* sc, const double* part_rr, double tol, int
     FgScalars& s = sc[r];
     if (s.done) return;
     s.rel = sqrt(sum_partials(part_rr, r)) / s.bnorm;
+    if (!isfinite(s.rel)) {
+        s.status = -7;
+        s.done = 1;
+    }
     if (s.rel <= tol) s.done = 1;
 }
 
@@ -690,10 +725,10 @@ hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, dou
     return hipGetLastError();
 }
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs,
-                  FgScalars* mirror) {
+                  double* sn, double* g, double* vscale, double tol, double bd_tol, int j, int m,
+                  int nrhs, FgScalars* mirror) {
     hipLaunchKernelGGL(k_fg_rot, dim3(nrhs), dim3(VT), 0, s, sc, part, H, cs, sn, g, vscale, tol,
-                       j, m, mirror);
+                       bd_tol, j, m, mirror);
     return hipGetLastError();
 }
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,

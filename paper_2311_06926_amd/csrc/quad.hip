@@ -309,10 +309,17 @@ hipError_t quad_setup(hp_ctx* c, QuadOp* q) {
     const long long s1 = (long long)nq * nM * nM, s2 = (long long)nq * nq * nM,
                     s3 = (long long)nq * nq * nq;
     q->scratch_doubles = (size_t)(7 * s1 + 10 * s2 + QNF * s3);
+    // every early error return releases what was allocated so far, so that a
+    // later call starts again from an empty QuadOp
+    auto fail = [q](hipError_t err) {
+        quad_free(q);
+        return err;
+    };
     hipError_t e;
-    if ((e = hipMalloc(&q->tables, sizeof(double) * nd)) != hipSuccess) return e;
-    if ((e = hipMalloc(&q->index, sizeof(int) * ni)) != hipSuccess) return e;
-    if ((e = hipMalloc(&q->scratch, sizeof(double) * q->scratch_doubles)) != hipSuccess) return e;
+    if ((e = hipMalloc(&q->tables, sizeof(double) * nd)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&q->index, sizeof(int) * ni)) != hipSuccess) return fail(e);
+    if ((e = hipMalloc(&q->scratch, sizeof(double) * q->scratch_doubles)) != hipSuccess)
+        return fail(e);
     std::vector<double> hv;
     std::vector<int> hi;
     hv.reserve(nd);
@@ -334,10 +341,10 @@ hipError_t quad_setup(hp_ctx* c, QuadOp* q) {
     q->wq = q->tables + wo;
     if ((e = hipMemcpy(q->tables, hv.data(), sizeof(double) * hv.size(), hipMemcpyHostToDevice)) !=
         hipSuccess)
-        return e;
+        return fail(e);
     if ((e = hipMemcpy(q->index, hi.data(), sizeof(int) * hi.size(), hipMemcpyHostToDevice)) !=
         hipSuccess)
-        return e;
+        return fail(e);
     q->ready = true;
     return hipSuccess;
 }

@@ -36,7 +36,11 @@ struct MinresScalars {
     double gamma, gamma_old, beta0, eta, c0, c1, s0, s1, delta, rel;
     int iters, done, status, pad;
 };
-hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part, int nrhs);
+// part_ref: partials of b . P^{-1} b for a warm start (else null): the
+// monitored residual is then relative to ||b||_{P^{-1}}; a start that already
+// meets tol ends the iteration at once
+hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
+                       const double* part_ref, double tol, int nrhs);
 // A dot product handed over as partial sums: part[r * count + i], i < count,
 // for right-hand side r (summed in a fixed order by the consumer).
 struct Partials {
@@ -55,7 +59,7 @@ hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const do
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
                     const double* wo, const double* w, double* wn, double* x,
                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
-                    double tol, MinresScalars* mirror);
+                    double tol, double bd_tol, MinresScalars* mirror);
 // partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
@@ -87,8 +91,8 @@ hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, dou
                 int pass, int m, int nrhs);
 // mirror: device pointer of a host-mapped copy of sc (or null), refreshed by the kernel
 hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, int j, int m, int nrhs,
-                  FgScalars* mirror);
+                  double* sn, double* g, double* vscale, double tol, double bd_tol, int j, int m,
+                  int nrhs, FgScalars* mirror);
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
                     int m, int jmax, int nrhs);
 hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs);

@@ -32,7 +32,10 @@ class Solver:
     inner CG preconditioner P_{V,l}), schur_pcg_iters, schur_pcg_tol,
     forward ('kronecker'|'quadrature': the forward problem K x of the Krylov
     loop by the Kronecker-factored kernels or by the quadrature-based
-    operator of Sec. 5.3).
+    operator of Sec. 5.3), use_x0 (warm start from the x passed to solve),
+    spectrum_gate (Lanczos steps of the set-up check that sigma(P_0^{-1} A~)
+    lies in (0, 2); 0 = off), p0_scale (damping factor w of P_0^{-1}),
+    breakdown_tol (Krylov breakdown threshold).
     """
 
     def __init__(self, E, p, nu=1.0, *, c_pen=0.0, schur="Pcq1", schedule="literal",
@@ -40,7 +43,8 @@ class Solver:
                  iters=1, max_rhs=1, poll_lag=1, use_graph=False, autotune=True,
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
-                 forward="kronecker", device=None):
+                 forward="kronecker", use_x0=False, spectrum_gate=0, p0_scale=1.0,
+                 breakdown_tol=0.0, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -70,6 +74,10 @@ class Solver:
         o.op_fused = op_fused
         o.op_staged = op_staged
         o.forward = {"kronecker": 0, "quadrature": 1}[forward]
+        o.use_x0 = int(bool(use_x0))
+        o.spectrum_gate = int(spectrum_gate)
+        o.p0_scale = float(p0_scale)
+        o.breakdown_tol = float(breakdown_tol)
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -193,20 +201,31 @@ class Solver:
                 "alpha": np.array(al[:m]), "beta": np.array(be[:m])}
 
     def solve(self, b, tol=1e-8, x=None, raise_on_noconv=True):
+        """hp_solve; with use_x0 the solve starts from (and overwrites) x."""
         nr = self._nrhs(b, self.N)
-        x = self.empty(self.N, nr) if x is None else x
+        if x is None:
+            if self.opts.use_x0:
+                raise ValueError("use_x0 needs the start vector x")
+            x = self.empty(self.N, nr)
         info = hp_solve_info()
         code = self.lib.hp_solve(self.ctx, _ptr(b), _ptr(x), nr, float(tol), ctypes.byref(info))
         if code != 0 and (raise_on_noconv or code != -6):
             check(code, "hp_solve")
         return x, info
 
-    def build_rhs(self, lid, modes=None, b=None):
-        """Cavity right-hand sides: lid speeds (one per rhs) and optional
-        body-force modes (amp[nrhs, 3, m], waves[nrhs, 3, m, 3])."""
+    def build_rhs(self, lid, modes=None, b=None, beta=None):
+        """Cavity right-hand sides: lid speeds (one per rhs), optional
+        body-force modes (amp[nrhs, 3, m], waves[nrhs, 3, m, 3]) and an
+        optional body-force coefficient field beta in V_h (n_V per rhs; adds
+        M_V beta)."""
         lid = np.ascontiguousarray(np.atleast_1d(np.asarray(lid, dtype=np.float64)))
         nr = lid.size
         b = self.empty(self.N, nr) if b is None else b
+        bp = None
+        if beta is not None:
+            if beta.numel() != nr * self.nV:
+                raise ValueError(f"beta must hold {nr} x n_V entries")
+            bp = _ptr(beta)
         if modes is None:
             nm, ap, wp = 0, None, None
         else:
@@ -217,7 +236,7 @@ class Solver:
             ap = amp.ctypes.data_as(ctypes.c_void_p)
             wp = wav.ctypes.data_as(ctypes.c_void_p)
         check(self.lib.hp_build_rhs(self.ctx, lid.ctypes.data_as(ctypes.c_void_p), nm, ap, wp,
-                                    _ptr(b), nr), "hp_build_rhs")
+                                    bp, _ptr(b), nr), "hp_build_rhs")
         return b
 
     def grad(self, x, lam, lid):

@@ -4,8 +4,8 @@ lid-driven cavity with P^_k (order 2, eq. Pcq1), k = 0..4.
 * 8^3, degrees 6 and 8: the GPU counts equal the oracle's MINRES within +-1
   (the oracle is slow at these degrees, so k = 0, 1 for degree 6 and k = 1
   for degree 8).
-* 8^3 and 16^3, degrees 2, 4, 6, 8: the GPU counts against the printed ones
-  within +-3.  The penalty constant (never printed) and the paper's
+* 8^3, 16^3, 32^3 and 64^3, degrees 2, 4, 6, 8 (every row of the table):
+  the GPU counts against the printed ones within +-3.  The penalty constant (never printed) and the paper's
   quadrature-based forward operator are readings, so the printed counts are
   a soft target; the counts measured here are listed in the test output.
 """
@@ -46,7 +46,11 @@ def gpu_counts(E, p, ks):
     for k in ks:
         sol = Solver(E, p, 1.0, iters=k, autotune=False)
         _, info = sol.solve(sol.build_rhs([1.0]), 1e-8)
-        assert info.converged and info.true_relres < 1e-6
+        say(f"[table1]   {E}^3 degree {p} k={k}: {info.iterations} iterations, true relres "
+            f"{info.true_relres:.2e}")
+        # MINRES monitors ||r||_{P^{-1}}; the 2-norm of the true residual is
+        # reported and stays within a small factor of the tolerance
+        assert info.converged and info.true_relres < 1e-7
         out.append(info.iterations)
         sol.close()
     return out
@@ -66,7 +70,7 @@ def test_high_degree_counts_match_oracle(dev, p, ks):
         assert abs(g - ref.iters) <= 1
 
 
-@pytest.mark.parametrize("E", [8, 16])
+@pytest.mark.parametrize("E", [8, 16, 32, 64])
 @pytest.mark.parametrize("p", [2, 4, 6, 8])
 def test_counts_against_table1(dev, E, p):
     paper = table1()[(E, p)]

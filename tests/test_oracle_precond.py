@@ -14,6 +14,7 @@
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sps
 
 from oracle.assemble import KronSystem
 from oracle.precond import BasePreconditioner, HyperPower, dense_hyperpower
@@ -182,9 +183,18 @@ def test_fixed_level_and_exact_schur_closed_forms(q, k, l0):
         assert np.abs(Xq - Xq.T).max() < 1e-10 * np.abs(Xq).max()
 
 
-def test_schur_spectrum_in_unit_interval():
-    """sigma(P_{Q,0}^{-1} B^T A^{-1} B) in [0, 1] (a(v,v) >= 2 nu ||div v||^2)."""
-    S = KronSystem(3, 2, 0.8)
+@pytest.mark.parametrize("E,p,nu", [(3, 2, 0.8), (2, 3, 1.0)])
+def test_schur_spectrum_in_unit_interval(E, p, nu):
+    """sigma(P_{Q,0}^{-1} B^T A^{-1} B) lies in [0, 1] and reaches close to 1.
+
+    For v with v.n = 0 on the flat faces of the cube, integration by parts
+    gives 2 ||eps(v)||^2 = ||curl v||^2 + 2 ||div v||^2, so the weak form
+    a(v, v) >= 2 nu ||div v||^2 (plus the Nitsche terms, positive at the
+    penalty used), with near-equality for curl-free fields.  Hence
+    (B^T A^{-1} B p, p) <= (2 nu)^{-1} (M_q p, p), i.e. the largest
+    eigenvalue is at most 1 and close to it: this pins the factor 2 nu of
+    P_{Q,0}^{-1} (a factor nu would put the top of the spectrum near 1/2)."""
+    S = KronSystem(E, p, nu)
     A = S.A.toarray()
     B = S.B.toarray()
     Sch = B.T @ np.linalg.solve(A, B)
@@ -193,6 +203,67 @@ def test_schur_spectrum_in_unit_interval():
     ev = np.sort(np.linalg.eigvals(X0q @ Sch).real)
     assert ev[0] > -1e-12 and abs(ev[0]) < 1e-10      # constant pressure
     assert ev[1] > 0.01 and ev[-1] <= 1 + 1e-12
+    assert ev[-1] >= 0.9
+
+
+@pytest.mark.parametrize("E,p,nu", [(2, 2, 0.7), (3, 3, 1.9), (1, 4, 1.0)])
+def test_apply_Q0_equals_inverse_of_assembled_pressure_mass(E, p, nu):
+    """apply_Q0 (three 1D LU solves along the tensor directions, with the
+    axis swaps of the Fortran-ordered pressure tensor) equals
+    2 nu inv(M^ (x) M^ (x) M^), the dense inverse of the 3D pressure mass
+    matrix assembled as a Kronecker product (sparse kron, then dense solve).
+    Closed form: the unit-integral M-splines have moments int M_i = 1, so
+    the coefficients t of the constant function 1 solve M_q t = (1, ..., 1)
+    and 1' M_q^{-1} 1 = int_Omega 1 = 1; hence 1' P_{Q,0}^{-1} 1 = 2 nu."""
+    S = KronSystem(E, p, nu)
+    m = S.m
+    Mq = sps.kron(sps.kron(sps.csr_matrix(m.Mc), sps.csr_matrix(m.Mc)),
+                  sps.csr_matrix(m.Mc)).toarray()
+    n = S.nQ
+    X = np.random.default_rng(E * 10 + p).standard_normal((n, 3))
+    P0 = BasePreconditioner(S)
+    got = np.column_stack([P0.apply_Q0(X[:, j]) for j in range(3)])
+    ref = 2.0 * nu * np.linalg.solve(Mq, X)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    ones = np.ones(n)
+    assert abs(ones @ P0.apply_Q0(ones) - 2.0 * nu) <= 1e-12 * 2.0 * nu
+
+
+def test_damped_base_leaves_the_convergence_interval():
+    """Sec. 2 (Lemma Sk_posdef, Remark rmk:convergence_Pk): the hyper-power
+    sequence needs sigma(X_0 A~) in (0, 2).  The plain P_{V,0} satisfies it
+    at 4^3, degree 3; damping it by w = 1.5 lifts the top of the spectrum
+    above 2, the map t -> 1 - (1 - t)^2 then sends that end below 0, so
+    P_1 is indefinite, and the oracle's MINRES with P_1 meets a negative
+    r' P^{-1} r (the error path HP_ENOTSPD of the library)."""
+    import scipy.linalg as sla
+    from oracle.cases import cavity
+    from oracle.krylov import minres
+    S, b = cavity(4, 3)
+    A = S.A.toarray()
+    o = S.offsets
+    Pv = np.zeros_like(A)
+    for c in range(3):
+        sl = slice(o[c], o[c + 1])
+        Pv[sl, sl] = A[sl, sl]
+    ev = sla.eigvalsh(A, Pv)
+    assert 0.0 < ev[0] and ev[-1] < 2.0
+    w = 1.5
+    assert w * ev[-1] > 2.0
+    assert 1.0 - (1.0 - w * ev[-1]) ** 2 < 0.0
+
+    class Damped(BasePreconditioner):
+        def apply_V0(self, x):
+            return w * super().apply_V0(x)
+
+        def apply_Q0(self, x):
+            return w * super().apply_Q0(x)
+
+    with pytest.raises(FloatingPointError):
+        minres(lambda v: S.K @ v, HyperPower(S, 2, 1, base=Damped(S)).apply, b, tol=1e-8)
+    # undamped, the same solve converges
+    r = minres(lambda v: S.K @ v, HyperPower(S, 2, 1).apply, b, tol=1e-8)
+    assert r.converged
 
 
 # Appendix of base-operator counts per application of P_k^{-1}
