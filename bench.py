@@ -25,7 +25,10 @@ The JSON line also carries
   hbm         apply_K on an HBM-sized mesh (working set > Infinity Cache)
   roofline    the kernel group that dominates the step (fast diagonalisation,
               FP64 MFMA), timed live with HIP events on the solver's stream
-  cpu_baseline  the FP64 oracle timed on this host (bounded sample)
+  cpu_baseline  the FP64 oracle timed on this host at the benchmark mesh
+              (one full solve, P_{V,0} by the oracle's einsum fast diagonalisation)
+  sec51_operator_study  P_{V,0}, P^_{V,1}, P^_{V,2} and A at 256^3 (Sec. 5.1):
+              measured c_A / c_P and the cost-model ratios of eq. hyperpower_scaling
 
     python bench.py [--steps K] [--warmup W] [--order q] [--iters k]
     python bench.py --only {solve,apply_K,apply_K_quad,apply_P0,copy} ...   (profiling runs)
@@ -58,6 +61,18 @@ def sizes(E, p):
     nV = 3 * nN * nM * nM
     nQ = nM ** 3
     return nN, nM, nV, nQ, nV + nQ
+
+
+def pk_counts(q, k):
+    """Q-block base applications inside one P_k (eq. Pcq1, literal schedule):
+    (P_{Q,0}, B/B' pairs, P_{V,0}, A) by the recursion T(k) = q T(k-1) +
+    (q-1) [pair + P_{V,l(k)}], l(1) = 0, l(k) = k (Appendix B)."""
+    pq, pb, pv, pa = 1, 0, 0, 0
+    for kk in range(1, k + 1):
+        lv = 0 if kk == 1 else kk
+        pq, pb, pv, pa = (q * pq, q * pb + (q - 1), q * pv + (q - 1) * q ** lv,
+                          q * pa + (q - 1) * (q ** lv - 1))
+    return pq, pb, pv, pa
 
 
 def p0_flops(E, p):
@@ -195,50 +210,87 @@ def pmc_traffic(profile, src_files):
         return None
 
 
-def cpu_baseline(p, q, k, E_full):
-    """The oracle (numpy/scipy, FP64, BLAS pinned to one thread) on this host:
-    one full MINRES solve of the same problem at a reduced mesh whose sparse
-    LU and solve fit a ~30 s budget, plus its CSR apply_K at the full mesh."""
+def cpu_baseline(p, q, k, E_full, gpu_iterations):
+    """The oracle (numpy/scipy, FP64, BLAS pinned to one thread) on this host
+    at the benchmark mesh: one full MINRES solve of the same problem with the
+    oracle's P_k, its P_{V,0} by the oracle's einsum fast-diagonalisation
+    tier (the sparse-LU form takes minutes to factor at 32^3).  Above about
+    half a million unknowns only a fixed number of iterations is timed and
+    scaled to the GPU's iteration count (said in `sample`)."""
     from threadpoolctl import threadpool_info, threadpool_limits
-    from oracle.assemble import KronSystem
     from oracle.cases import cavity
     from oracle.krylov import minres
-    from oracle.precond import HyperPower
-    Es = 12
+    from oracle.precond import FastDiagBase, HyperPower
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        S, b = cavity(Es, p)
-        H = HyperPower(S, q, k)
+        S, b = cavity(E_full, p)
+        H = HyperPower(S, q, k, base=FastDiagBase(S))
         t1 = time.perf_counter()
-        r = minres(lambda v: S.K @ v, H.apply, b, tol=1e-8)
+        full = S.N <= 500_000
+        r = minres(lambda v: S.K @ v, H.apply, b, tol=1e-8 if full else 0.0,
+                   maxit=1000 if full else 4)
         t2 = time.perf_counter()
-        Sf = KronSystem(E_full, p, 1.0)
-        x = np.random.default_rng(0).standard_normal(Sf.N)
+        x = np.random.default_rng(0).standard_normal(S.N)
         t3 = time.perf_counter()
         for _ in range(3):
-            Sf.K @ x
+            S.K @ x
         t4 = time.perf_counter()
-    # the same solve with the BLAS thread pools unrestricted (the sparse LU
-    # and sparse products stay single-threaded)
+    t_iter = (t2 - t1) / max(r.iters, 1)
+    t_solve = (t2 - t1) if full else t_iter * gpu_iterations
+    # a few iterations with the BLAS pools unrestricted (the sparse products
+    # and einsum contractions stay single-threaded)
     t5 = time.perf_counter()
-    r2 = minres(lambda v: S.K @ v, H.apply, b, tol=1e-8)
+    minres(lambda v: S.K @ v, H.apply, b, tol=0.0, maxit=3)
     t6 = time.perf_counter()
     nthreads = max((pool.get("num_threads", 1) for pool in threadpool_info()), default=1)
+    what = (f"one full oracle MINRES solve at {E_full}^3 elements, degree {p}, q={q}, k={k} "
+            f"(N={S.N}, {r.iters} iterations, {t2 - t1:.1f} s)" if full else
+            f"4 oracle MINRES iterations at {E_full}^3 elements, degree {p}, q={q}, k={k} "
+            f"(N={S.N}, {t_iter:.2f} s each), scaled to the GPU's {gpu_iterations} iterations")
     return {
-        "value": S.N / (t2 - t1),
+        "value": S.N / t_solve,
         "unit": "DOF/s (solved to 1e-8)",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one full oracle MINRES solve at {Es}^3 elements, degree {p}, q={q}, k={k} "
-                   f"(N={S.N}, {r.iters} iterations, {t2 - t1:.2f} s; its sparse-LU set-up "
-                   f"{t1 - t0:.2f} s excluded like the GPU set-up); the oracle's sparse LU at "
-                   f"{E_full}^3 alone takes minutes, so the full-size solve is not sampled"),
-        "oracle_iterations": r.iters,
-        "apply_K_dofs_full_mesh": Sf.N / ((t4 - t3) / 3),
+        "sample": (what + "; P_{V,0} by the oracle's einsum fast-diagonalisation tier, P_k "
+                   "by its literal recursion, K as scipy CSR; assembly "
+                   f"({t1 - t0:.1f} s) excluded like the GPU set-up"),
+        "oracle_iterations": r.iters if full else None,
+        "seconds_per_iteration": t_iter,
+        "apply_K_dofs": S.N / ((t4 - t3) / 3),
         "host_cpus": os.cpu_count(),
-        "all_threads": {"value": S.N / (t6 - t5), "blas_threads": nthreads,
-                        "iterations": r2.iters},
+        "all_threads": {"seconds_per_iteration": (t6 - t5) / 3, "blas_threads": nthreads},
     }
+
+
+def sec51_leg(E, p, hbm_peak, fp64_peak):
+    """The operator study of Sec. 5.1 (eq. hyperpower_scaling) at E^3: the
+    velocity block P_{V,k}^{-1} for k = 0, 1, 2 (q = 2) and the operator A,
+    the measured c_A / c_P, and the cost-model ratios C_k / C_0 =
+    2^k + (2^k - 1) c_A / c_P it implies against the measured ones (the
+    paper's 384^3 one-thread CPU run: 4.47 and 11.44, model 4.5 and 11.5)."""
+    import torch
+    from paper_2311_06926_amd import synth
+    from paper_2311_06926_amd.solver import Solver
+    s = Solver(E, p, 1.0)
+    u = torch.from_numpy(synth.random_vector(s.nV, 8)).to("cuda")
+    y = s.empty(s.nV)
+    t = {}
+    for kk in (0, 1, 2):
+        t[kk] = timed_loop(lambda: s.apply_PV(2, kk, u, y), 5, s.stream)
+    tA = timed_loop(lambda: s.apply_A(u, y), 10, s.stream)
+    nN, nM, nV, nQ, N = sizes(E, p)
+    fl_v = 4.0 * nV * (nN + 2 * nM)
+    ratio = tA / t[0]
+    out = {"E": E, "p": p, "n_V": nV, "PV0_ms": 1e3 * t[0], "PV1_ms": 1e3 * t[1],
+           "PV2_ms": 1e3 * t[2], "A_ms": 1e3 * tA, "cA_over_cP": ratio,
+           "C1_over_C0_measured": t[1] / t[0], "C1_over_C0_model": 2 + ratio,
+           "C2_over_C0_measured": t[2] / t[0], "C2_over_C0_model": 4 + 3 * ratio,
+           "PV0_TFLOPs": fl_v / t[0] / 1e12, "PV0_mfma_frac": fl_v / t[0] / 1e12 / fp64_peak,
+           "A_algorithmic_GBps": 16.0 * nV / tA / 1e9,
+           "A_hbm_frac": 16.0 * nV / tA / 1e9 / hbm_peak, "tuning": s.tuning(1)}
+    s.close()
+    return out
 
 
 def main():
@@ -272,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--hbm-E", type=int, default=192)
     ap.add_argument("--diff-E", type=int, default=96)
+    ap.add_argument("--sec51-E", type=int, default=256,
+                    help="mesh of the Sec. 5.1 operator study (P_{V,k} for k = 0, 1, 2)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the solver runs on a single MI355X "
@@ -372,6 +426,34 @@ def main():
     # ---- roofline: fast diagonalisation dominates the step's GPU time
     flops = p0_flops(E, p)
     achieved = flops / t_P0 / 1e12
+    # each operator against its own roof at this mesh (the working set, about
+    # 40 MB, sits in the 256 MB Infinity Cache, so the HBM figures are
+    # effective rates), and P_k weighted: the time its base operators would
+    # take at their roofs (Appendix B counts) over its measured time
+    nN_, nM_, nV_, nQ_, N_ = sizes(E, p)
+    fl_pv0 = 4.0 * nV_ * (nN_ + 2 * nM_)
+    fl_pq0 = 6.0 * nQ_ * nM_
+    t_roof = lambda fl=0.0, by=0.0: max(fl / (FP64_PEAK_TFLOPS * 1e12), by / (HBM_PEAK_GBS * 1e9))
+    nv_pv0, nv_a = q ** k, q ** k - 1
+    if k == 0:
+        nq_pq0, nq_b, nq_pv0, nq_a = 1, 0, 0, 0
+    else:
+        nq_pq0, nq_b, nq_pv0, nq_a = pk_counts(q, k)
+    ideal = ((nv_pv0 + nq_pv0) * t_roof(fl=fl_pv0) + (nv_a + nq_a) * t_roof(by=16.0 * nV_)
+             + nq_pq0 * t_roof(fl=fl_pq0) + nq_b * t_roof(by=16.0 * (nV_ + nQ_)))
+    per_op = {
+        "apply_K": {"bound": "hbm", "unit": "GB/s", "achieved": 16.0 * N / t_K / 1e9,
+                    "peak": HBM_PEAK_GBS, "frac": 16.0 * N / t_K / 1e9 / HBM_PEAK_GBS,
+                    "note": "effective: 16 B/DOF algorithmic, working set in the Infinity Cache"},
+        "apply_P0": {"bound": "mfma", "unit": "TFLOP/s", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "frac": achieved / FP64_PEAK_TFLOPS},
+        f"apply_hyperpower_q{q}_k{k}": {
+            "bound": "weighted", "ideal_us": ideal * 1e6, "measured_us": t_Pk * 1e6,
+            "frac": ideal / t_Pk,
+            "note": ("sum over its base applications (Appendix B counts) of each at its roof "
+                     "(P_0 blocks at FP64 MFMA peak, A and the B pairs at 16 B/DOF over HBM), "
+                     "over the measured time")},
+    }
     roof = {
         "kernel": ("apply_P0: k_fd_xy_w (modes 1,2) + k_fd_z_w (mode 3 + scaling) + k_fd_xy_w "
                    "(inverse), FP64 16x16x4 MFMA"),
@@ -379,6 +461,7 @@ def main():
         "frac": achieved / FP64_PEAK_TFLOPS,
         "traffic": pmc_traffic(f"apply_P0_E{E}p{p}_pmc.txt", ["fd.hip"]),
         "algorithmic_flops_per_launch": flops, "avg_launch_us": t_P0 * 1e6,
+        "per_operator": per_op,
     }
 
     # ---- the same solve with each iteration replayed as a captured HIP graph
@@ -588,10 +671,30 @@ def main():
         diff = differentiable_leg(args.diff_E, 3)
         log(f"[bench] differentiable: {diff}")
 
+    sec51 = []
+    if not args.no_extra:
+        # ---- the operator study of Sec. 5.1 at 256^3 (beyond the in-LDS
+        # tiles: P_0 as mode-product GEMMs)
+        for ps in (2, 3):
+            sec51.append(sec51_leg(args.sec51_E, ps, HBM_PEAK_GBS, FP64_PEAK_TFLOPS))
+            log(f"[bench] sec 5.1: {sec51[-1]}")
+        roof["per_operator"]["apply_P0_E%d" % args.sec51_E] = {
+            r["p"]: {"bound": "mfma", "unit": "TFLOP/s", "achieved": r["PV0_TFLOPs"],
+                     "peak": FP64_PEAK_TFLOPS, "frac": r["PV0_mfma_frac"]} for r in sec51}
+        if hbm:
+            best = max(hbm["sweep"], key=lambda r: r["hbm_frac"])
+            roof["per_operator"]["apply_K_hbm_sweep_best"] = {
+                "bound": "hbm", "unit": "GB/s", "achieved": best["algorithmic_GBps"],
+                "peak": HBM_PEAK_GBS, "frac": best["hbm_frac"], "E": best["E"], "p": best["p"]}
+        if large:
+            roof["per_operator"][f"apply_P0_E{large['E']}"] = {
+                "bound": "mfma", "unit": "TFLOP/s", "achieved": large["apply_P0_TFLOPs"],
+                "peak": FP64_PEAK_TFLOPS, "frac": large["apply_P0_mfma_frac"]}
+
     cpu = None
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(p, q, k, E)
+        cpu = cpu_baseline(p, q, k, E, info.iterations)
         log(f"[bench] cpu: {cpu}")
 
     out = {
@@ -624,6 +727,7 @@ def main():
         "hbm": hbm,
         "large_mesh": large,
         "differentiable": diff,
+        "sec51_operator_study": sec51,
     }
     print(json.dumps(out), flush=True)
     sol.close()

@@ -104,10 +104,13 @@ typedef struct hp_opts {
     int op_kchunk;      /* operator kernels: i3-planes per workgroup, 0 = tuned/model */
     int op_order;       /* operator kernels: velocity workgroup order, -1 = tuned/model,
                            0 = tiles fastest, 1 = components fastest */
-    int fd_plan;        /* P_0 kernels: -1 = tuned/default, else bit 0 = 16-wave
+    int fd_plan;        /* P_0 kernels: -1 = tuned/default; 0..7 = the in-LDS kernels
+                           (a whole direction, <= 128, in MFMA tiles): bit 0 = 16-wave
                            kernels, bit 1 = 1D matrices staged in LDS (if they fit),
                            bit 2 = 2x2 blocks of MFMA tiles per wave (16-wave plans,
-                           FP64/FP32) */
+                           FP64/FP32); 8 = every mode product as a batched GEMM over
+                           HBM (FP64/FP32; the plan used whenever E + degree - 1 > 128,
+                           where split BF16 falls back to FP32 products) */
     int op_slabs;       /* operator: i3-slabs run one after the other (pressure chain
                            then velocity per slab), 0 = tuned/model */
     int schur_level;    /* eq. Pcq2 only: the fixed P_{V,l} inside B' P_{V,l}^{-1} B,
@@ -195,10 +198,9 @@ hp_status hp_get_tuning(const hp_ctx* ctx, int nrhs, hp_tuning* out);
  * fewer than 6 elements at the default 12.5), or, with opts.spectrum_gate,
  * when P_0 leaves the convergence interval (0, 2).  opts may be NULL
  * (defaults).  stream: a hipStream_t or NULL.  *out receives the context.
- * Fast diagonalisation holds a whole direction in MFMA tiles, so P_0,
- * P_k and the solve need E + degree - 1 <= 128; above that the context
- * serves the operators (hp_apply_K/A/B/Bt/MV) only and the preconditioner
- * and solve calls return HP_EINVAL. */
+ * Fast diagonalisation holds a whole direction in MFMA tiles while
+ * E + degree - 1 <= 128 and runs its mode products as batched GEMMs beyond
+ * (opts.fd_plan = 8), so every call serves any mesh that fits in memory. */
 hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts,
                    void* stream, hp_ctx** out);
 
@@ -244,6 +246,13 @@ hp_status hp_apply_P0(hp_ctx* ctx, const double* x, double* y, int nrhs);
  * opts.schur_variant and opts.l_schedule).  order >= 2, 0 <= iters <= 6. */
 hp_status hp_apply_hyperpower(hp_ctx* ctx, int order, int iters, const double* x,
                               double* y, int nrhs);
+
+/* y = P_{V,k}^{-1} u, the velocity block of P_k alone (eq. Pcv; its Neumann
+ * form, eq. neumann: q^k applications of P_{V,0}^{-1} and q^k - 1 of A), the
+ * operator timed in the paper's Sec. 5.1 cost study (eq. hyperpower_scaling).
+ * u, y: velocity vectors (stride n_V), device, must not overlap.
+ * order >= 2, 0 <= iters <= 6; opts.precision applies. */
+hp_status hp_apply_PV(hp_ctx* ctx, int order, int iters, const double* u, double* y, int nrhs);
 
 /* Blocks whose preconditioned spectrum hp_spectrum estimates. */
 enum { HP_SPEC_VELOCITY = 0, HP_SPEC_SCHUR = 1 };

@@ -26,6 +26,9 @@ TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
   (option (2)).
 * Q block with the exact Schur complement: eq. ``Pcq_exact``,
   S = B^T A^{-1} B with A^{-1} applied by sparse LU (``variant='Pcq_exact'``).
+* ``FastDiagBase``: the same P_0 with the velocity blocks by fast
+  diagonalisation (App. A.4, numpy einsum), the CPU timing tier at meshes
+  where the sparse LU is too slow to factor; pinned against the LU form.
 * Q block with an inner iterative solve (options (3) and (4) of Sec. 4.1):
   the sequence of eq. ``Pcq2`` on S_pcg = B^T PCG(A, P_{V,l}) B, where
   PCG(A, P) b is the preconditioned conjugate gradient iterate for A y = b
@@ -89,6 +92,55 @@ class BasePreconditioner:
     def Bt(self, u):
         self.counts["Bt"] += 1
         return self.s.B.T @ u
+
+
+class FastDiagBase(BasePreconditioner):
+    """P_0^{-1} with each velocity block applied by fast diagonalisation
+    (App. A.4), written with numpy: the block A_cc is the generalised
+    Kronecker sum of (K_int, M_int) in direction c and (T^, M^) in the two
+    others (Sec. 3.3), so with the generalised eigenpairs U^T M U = I,
+    U^T K U = diag(lambda) of each pencil (scipy ``eigh``),
+
+        A_cc^{-1} = (U3 (x) U2 (x) U1) diag(1 / (2 nu (l1 + l2 + l3))) (U3 (x) U2 (x) U1)^T.
+
+    The three mode products each way are plain ``einsum`` contractions.  This
+    is the CPU reference tier used to time the oracle at meshes where the
+    sparse LU of ``BasePreconditioner`` takes minutes to factor; it is pinned
+    against that LU form and against the dense inverse.  P_{Q,0} is the
+    parent's (three 1D LU solves)."""
+
+    def __init__(self, sysm):
+        self.s = sysm
+        self.off = sysm.offsets
+        m = sysm.m
+        self.Mc_lu = sla.lu_factor(m.Mc)
+        self.nM = m.nM
+        self.counts = {"PV0": 0, "PQ0": 0, "A": 0, "B": 0, "Bt": 0}
+        lK, UK = sla.eigh(m.K_int, m.M_int)
+        lT, UT = sla.eigh(m.Tc, m.Mc)
+        # (l, U) per direction 1, 2, 3 for each component c: K in direction c
+        self.fams = []
+        for c in range(3):
+            self.fams.append([(lK, UK) if d == c else (lT, UT) for d in range(3)])
+
+    def apply_V0(self, x):
+        """P_{V,0}^{-1} x by fast diagonalisation of each diagonal block."""
+        self.counts["PV0"] += 1
+        y = np.empty_like(x)
+        nu = self.s.nu
+        for c in range(3):
+            (l1, U1), (l2, U2), (l3, U3) = self.fams[c]
+            sl = slice(self.off[c], self.off[c + 1])
+            X = x[sl].reshape(len(l3), len(l2), len(l1))        # [i3, i2, i1]
+            X = np.einsum("ia,kji->kja", U1, X)                  # U1^T along direction 1
+            X = np.einsum("jb,kja->kba", U2, X)                  # U2^T along direction 2
+            X = np.einsum("kc,kba->cba", U3, X)                  # U3^T along direction 3
+            X = X / (2.0 * nu * (l3[:, None, None] + l2[None, :, None] + l1[None, None, :]))
+            X = np.einsum("kc,cba->kba", U3, X)                  # back: U3
+            X = np.einsum("jb,kba->kja", U2, X)
+            X = np.einsum("ia,kja->kji", U1, X)
+            y[sl] = X.reshape(-1)
+        return y
 
 
 def hyperpower_apply(X_prev, Aop, q, x):

@@ -102,6 +102,7 @@ SIGNATURES = {
     "hp_apply_Bt": (I, [P, P, P, I]),
     "hp_apply_P0": (I, [P, P, P, I]),
     "hp_apply_hyperpower": (I, [P, I, I, P, P, I]),
+    "hp_apply_PV": (I, [P, I, I, P, P, I]),
     "hp_solve": (I, [P, P, P, I, D, ctypes.POINTER(hp_solve_info)]),
     "hp_build_rhs": (I, [P, P, I, P, P, P, P, I]),
     "hp_apply_MV": (I, [P, P, P, I]),

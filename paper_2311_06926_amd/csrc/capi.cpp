@@ -1024,9 +1024,9 @@ hp_status autotune(hp_ctx* c) {
     }
     // P_0: every plan that fits, per precision (velocity and pressure blocks)
     for (int prec = 0; prec < 3 && st == HP_OK && c->fd_ok && c->opts.fd_plan < 0; ++prec) {
-        double us[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        double us[FD_PLAN_GEMM + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
         for (int pass = 0; pass < TUNE_PASSES && st == HP_OK; ++pass)
-            for (int plan = 0; plan <= 7 && st == HP_OK; ++plan) {
+            for (int plan = 0; plan <= FD_PLAN_GEMM && st == HP_OK; ++plan) {
                 if (!fd_plan_valid(c, prec, plan)) continue;
                 c->fd_force = plan;
                 const double t = time_launches(c, e0, e1, TUNE_REPS, [&]() {
@@ -1037,7 +1037,7 @@ hp_status autotune(hp_ctx* c) {
             }
         double best = -1.0;
         int best_plan = -1;
-        for (int plan = 0; plan <= 7; ++plan)
+        for (int plan = 0; plan <= FD_PLAN_GEMM; ++plan)
             if (us[plan] >= 0.0 && (best < 0.0 || us[plan] < best)) {
                 best = us[plan];
                 best_plan = plan;
@@ -1280,7 +1280,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen >= 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
-        o.fd_plan < -1 || o.fd_plan > 7 || o.op_slabs < 0 || o.schur_level < 0 ||
+        o.fd_plan < -1 || o.fd_plan > FD_PLAN_GEMM || o.op_slabs < 0 || o.schur_level < 0 ||
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
@@ -1333,7 +1333,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     const int NNp = pad16(nN), NMp = pad16(nM);
     size_t nb = (size_t)3 * nN * (2 * wN + 1) + (size_t)2 * nM * (2 * wM + 1);
     // (+32: the dense tables start on a 256-byte boundary, for vector loads)
-    size_t nfd = NMp <= 128 ? (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM + 32 : 0;
+    size_t nfd = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp + nN + nM + 32;
     if (alloc_device(&c->d_tables, nb + nfd) != HP_OK) { delete ce; return HP_ENOMEM; }
     double* tp = c->d_tables;
     c->band.ptr[BK_N] = tp; upload_band(c->tab.K_int, nN, wN, tp); tp += (size_t)nN * (2 * wN + 1);
@@ -1367,8 +1367,10 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         tp += v.size();
         return r;
     };
-    c->fd_ok = NMp <= 128;  // fast-diagonalisation tiles hold <= 128 per direction
-    if (c->fd_ok) {
+    // fast diagonalisation at any size: in-LDS kernels up to 128 per direction,
+    // mode-product GEMMs beyond
+    c->fd_ok = true;
+    {
     tp += (32 - (size_t)(tp - c->d_tables) % 32) % 32;  // 256-byte alignment of the dense tables
     c->fd64.UK = up64(padded<double>(c->tab.UK, nN, NNp, false));
     c->fd64.UKt = up64(padded<double>(c->tab.UK, nN, NNp, true));
@@ -1380,7 +1382,6 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->fd64.nN = nN; c->fd64.nM = nM; c->fd64.NNp = NNp; c->fd64.NMp = NMp;
     // FP32 copies of the dense FD tables
     size_t n32 = (size_t)2 * NNp * NNp + (size_t)3 * NMp * NMp;
-    if (!c->fd_ok) n32 = 1;
     if (hipMalloc(reinterpret_cast<void**>(&c->d_tables32), n32 * sizeof(float)) != hipSuccess) {
         hp_destroy(c);
         return HP_ENOMEM;
@@ -1595,6 +1596,15 @@ hp_status hp_apply_hyperpower(hp_ctx* c, int order, int iters, const double* x, 
         iters > KMAX || !c->fd_ok)
         return HP_EINVAL;
     HIPCHK(apply_Pk(c, order, iters, x, y, nrhs));
+    return HP_OK;
+}
+
+hp_status hp_apply_PV(hp_ctx* c, int order, int iters, const double* u, double* y, int nrhs) {
+    if (check_rhs(c, nrhs) != HP_OK || !u || !y || order < 2 || iters < 0 || iters > KMAX ||
+        !c->fd_ok || (u < y + c->nV * (long long)nrhs && y < u + c->nV * (long long)nrhs))
+        return HP_EINVAL;
+    HIPCHK(apply_PV(c, order, iters, vel_fields(c, u, c->nV), vel_fields(c, y, c->nV), nrhs,
+                    c->opts.precision));
     return HP_OK;
 }
 

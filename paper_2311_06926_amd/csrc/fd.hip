@@ -17,6 +17,7 @@
 #include <type_traits>
 
 #include "hp_internal.h"
+#include "vec.h"
 
 namespace hp {
 
@@ -1050,6 +1051,325 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     return hipGetLastError();
 }
 
+// ---- mode products as batched GEMMs (directions of any length) ----------------------
+// The in-LDS kernels above hold a whole direction (<= 128) in MFMA tiles.  For
+// longer directions -- and as the selectable plan FD_GEMM at any size -- each
+// mode product of fast diagonalisation runs as a (batched) GEMM over HBM:
+//     C(i, j) = sum_k A(i, k) B(k, j),  B(k, j) = B[k ldb + j] (a dense 1D table)
+// with strided A and C; batch b adds (b % nb1) s1 + (b / nb1) s2 to A and C.
+// Mode 1 is taken transposed (i over the (i2, i3) lines, j over i1') so that
+// B is always a row-major 1D table and the tensor is the A operand:
+//   mode 1: A(i, k) = X[k + i n1]            (k contiguous), C(i, j) = Y[j + i n1]
+//   mode 2: A(i, k) = X[i + k n1], per i3    (i contiguous), C(i, j) = Y[i + j n1]
+//   mode 3: A(i, k) = X[i + k n1 n2]         (i contiguous), C(i, j) = Y[i + j n1 n2]
+// with B = U (forward) or U^T (inverse), M^^{-1} for the pressure.  The
+// eigenvalue scaling (epilogue 2) is fused into the forward mode-3 product.
+// Tile: 64 x 64 outputs per 256-thread workgroup, each wave 2 x 2 MFMA tiles
+// of 16 x 16 (sub-tiles entirely outside the output are skipped, so a ragged
+// direction costs at most 15 padded rows); the contraction runs in chunks of
+// 16 staged k-major in LDS (pitch 80: the 16 lanes of one k row and the next
+// k row fall in disjoint banks), double buffered, the next chunk loaded into
+// registers while the current one is multiplied.  The output tile goes
+// through LDS so that it is stored along C's contiguous direction.
+constexpr int GT = 64;
+constexpr int GK = 16;
+constexpr int GP = 80;
+constexpr int GTHREADS = 256;
+
+struct GemmArgs {
+    const void* A;
+    long long a_i, a_k, a_s1, a_s2;
+    const void* B;
+    int ldb;
+    void* C;
+    long long c_i, c_j, c_s1, c_s2;
+    int M, N, K, nb1, tiles_m;
+    int epi;          // 0: C = acc, 1: C = alpha acc, 2: C = alpha acc / (l1[i1] + l2[i2] + l3[j])
+    int accumulate;   // C += (epilogue value)
+    double alpha;
+    const double* l1;
+    const double* l2;
+    const double* l3;
+    int n1;           // epilogue 2: i = i1 + n1 i2
+};
+
+template <typename T, typename TI, typename TO, bool A_KC, bool C_IC>
+__global__ __launch_bounds__(GTHREADS) void k_mode_gemm(GemmArgs g) {
+    using M = Mfma<T>;
+    using V = typename M::V;
+    constexpr int TILE_T = 2 * 2 * GK * GP;       // As, Bs, double buffered
+    constexpr int CT_T = GT * (GT + 1);           // the output tile [i][j]
+    __shared__ T sm[TILE_T > CT_T ? TILE_T : CT_T];
+    T* As = sm;                                   // [buf][k][i]
+    T* Bs = sm + 2 * GK * GP;                     // [buf][k][j]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tm = blockIdx.x % g.tiles_m, tn = blockIdx.x / g.tiles_m;
+    const int i0 = tm * GT, j0 = tn * GT;
+    const long long bb = blockIdx.y;
+    const long long boffA = (bb % g.nb1) * g.a_s1 + (bb / g.nb1) * g.a_s2;
+    const long long boffC = (bb % g.nb1) * g.c_s1 + (bb / g.nb1) * g.c_s2;
+    const TI* A = reinterpret_cast<const TI*>(g.A) + boffA;
+    const T* B = reinterpret_cast<const T*>(g.B);
+    // staging: four A and four B values per thread per chunk
+    T ra[4], rb[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = tid + GTHREADS * s;
+            int i, k;
+            if (A_KC) { k = e % GK; i = e / GK; }
+            else { i = e % GT; k = e / GT; }
+            const int gi = i0 + i, gk = k0 + k;
+            ra[s] = (gi < g.M && gk < g.K) ? (T)A[gi * g.a_i + gk * g.a_k] : (T)0;
+            const int j = e % GT, kb = e / GT;
+            const int gj = j0 + j, gkb = k0 + kb;
+            rb[s] = (gj < g.N && gkb < g.K) ? B[(long long)gkb * g.ldb + gj] : (T)0;
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int e = tid + GTHREADS * s;
+            int i, k;
+            if (A_KC) { k = e % GK; i = e / GK; }
+            else { i = e % GT; k = e / GT; }
+            As[buf * GK * GP + k * GP + i] = ra[s];
+            Bs[buf * GK * GP + (e / GT) * GP + (e % GT)] = rb[s];
+        }
+    };
+    const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+    bool on[2][2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+            on[ii][jj] = (i0 + wr + 16 * ii < g.M) && (j0 + wc + 16 * jj < g.N);
+    V acc[2][2];
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) acc[ii][jj] = V{0, 0, 0, 0};
+    load(0);
+    for (int k0 = 0, it = 0; k0 < g.K; k0 += GK, ++it) {
+        const int buf = it & 1;
+        store(buf);
+        __syncthreads();
+        if (k0 + GK < g.K) load(k0 + GK);
+        const T* as = As + buf * GK * GP;
+        const T* bs = Bs + buf * GK * GP;
+#pragma unroll
+        for (int st = 0; st < GK / 4; ++st) {
+            const int kk = 4 * st + lk;
+            T av[2], bv[2];
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii) av[ii] = as[kk * GP + wr + 16 * ii + lr];
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) bv[jj] = bs[kk * GP + wc + 16 * jj + lr];
+#pragma unroll
+            for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+                    if (on[ii][jj]) acc[ii][jj] = M::mma(av[ii], bv[jj], acc[ii][jj]);
+        }
+    }
+    __syncthreads();  // every wave is done with As/Bs: the output tile reuses them
+    T* Ct = sm;
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+            if (on[ii][jj])
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    Ct[(wr + 16 * ii + M::row(lk, e)) * (GT + 1) + wc + 16 * jj + lr] = acc[ii][jj][e];
+    __syncthreads();
+    TO* C = reinterpret_cast<TO*>(g.C) + boffC;
+    for (int s = 0; s < GT * GT / GTHREADS; ++s) {
+        const int e = tid + GTHREADS * s;
+        int i, j;
+        if (C_IC) { i = e % GT; j = e / GT; }
+        else { j = e % GT; i = e / GT; }
+        const int gi = i0 + i, gj = j0 + j;
+        if (gi >= g.M || gj >= g.N) continue;
+        double v = (double)Ct[i * (GT + 1) + j];
+        if (g.epi == 1) {
+            v *= g.alpha;
+        } else if (g.epi == 2) {
+            const int i1 = gi % g.n1, i2 = gi / g.n1;
+            v *= g.alpha / (g.l1[i1] + g.l2[i2] + g.l3[gj]);
+        }
+        TO* dst = C + (long long)gi * g.c_i + (long long)gj * g.c_j;
+        if (g.accumulate) *dst += (TO)v;
+        else *dst = (TO)v;
+    }
+}
+
+// Partial sums of y . w for the Krylov dot of launch_P0, in the layout of the
+// in-LDS kernels: velocity, one per (field, i3-plane) at f nM + k; pressure,
+// one per ZROWS-row block of the (i1, i2) plane.  Fixed-order block sums.
+__global__ __launch_bounds__(256) void k_fd_dot_vel(const double* y, const double* w,
+                                                    long long stride, long long plane,
+                                                    double* part, long long dp_stride,
+                                                    int slot0) {
+    __shared__ double red[4];
+    const int k = blockIdx.x, r = blockIdx.y;
+    const double* yr = y + (long long)r * stride + (long long)k * plane;
+    const double* wr = w + (long long)r * stride + (long long)k * plane;
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < plane; i += 256) s += yr[i] * wr[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(long long)r * dp_stride + slot0 + k] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_fd_dot_pres(const double* y, const double* w,
+                                                     long long stride, long long plane, int n3,
+                                                     double* part, long long dp_stride) {
+    __shared__ double red[4];
+    const int r = blockIdx.y;
+    const long long r0 = (long long)blockIdx.x * ZROWS;
+    const double* yr = y + (long long)r * stride;
+    const double* wr = w + (long long)r * stride;
+    double s = 0.0;
+    for (long long idx = threadIdx.x; idx < (long long)ZROWS * n3; idx += 256) {
+        const long long kk = idx / ZROWS, row = idx - kk * ZROWS;
+        if (r0 + row >= plane) continue;
+        const long long o = r0 + row + kk * plane;
+        s += yr[o] * wr[o];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(long long)r * dp_stride + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+template <typename T, typename TI, typename TO, bool A_KC, bool C_IC>
+hipError_t gemm_launch(hipStream_t st, GemmArgs g, int nbatch) {
+    g.tiles_m = (g.M + GT - 1) / GT;
+    const int tiles_n = (g.N + GT - 1) / GT;
+    if (g.M <= 0 || g.N <= 0 || nbatch <= 0) return hipSuccess;
+    if (nbatch > 65535) return hipErrorInvalidConfiguration;  // grid y limit
+    hipLaunchKernelGGL((k_mode_gemm<T, TI, TO, A_KC, C_IC>), dim3(g.tiles_m * tiles_n, nbatch),
+                       dim3(GTHREADS), 0, st, g);
+    return hipGetLastError();
+}
+
+// P_0^{-1} by mode-product GEMMs (velocity: six products per component, the
+// eigenvalue scaling fused into the forward mode-3 product; pressure: three
+// products with M^^{-1}, the factor 2 nu w in the last).  Intermediates of
+// precision T ping-pong between the two fast-diagonalisation scratch
+// buffers; the combination input (comb) is formed first in the operator
+// workspace, the dot partials are summed from the final output.
+template <typename T>
+hipError_t run_P0_gemm(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Fields& out,
+                       bool vel, bool pres, bool accumulate, int nrhs, const FdDot* dot,
+                       const FdComb* comb) {
+    const long long N = c->N, R = c->opts.max_rhs;
+    T* tmp1 = reinterpret_cast<T*>(c->ws + ops_ws_stride(c) * R);
+    T* tmp2 = tmp1 + N * R;
+    const double omega = c->opts.p0_scale, two_nu = 2.0 * c->nu;
+    hipError_t e = hipSuccess;
+    for (int f = vel ? 0 : 3; f < (pres ? 4 : 3) && e == hipSuccess; ++f) {
+        const int n1 = (int)c->dims[f][0], n2 = (int)c->dims[f][1], n3 = (int)c->dims[f][2];
+        const long long n12 = (long long)n1 * n2;
+        const double* x = in.f[f];
+        long long sx = in.stride[f];
+        if (comb && comb->b.f[f]) {
+            // x = ca in + cb b + cc c into the operator workspace (n_Q per rhs >= any field)
+            double* xc = c->ws;
+            e = vec_axpbypcz(c->stream, n12 * n3, nrhs, comb->ca, x, sx, comb->cb, comb->b.f[f],
+                             comb->b.stride[f], comb->cc, comb->c.f[f], comb->c.stride[f], xc,
+                             ops_ws_stride(c));
+            if (e != hipSuccess) break;
+            x = xc;
+            sx = ops_ws_stride(c);
+        }
+        T* Y1 = tmp1 + c->off[f];
+        T* Y2 = tmp2 + c->off[f];
+        const bool isp = (f == 3);
+        // 1D tables per direction: forward B = U, inverse B = U^T (M^^{-1} for p)
+        const T* Uf[3];
+        const T* Ui[3];
+        int ld[3];
+        for (int d = 0; d < 3; ++d) {
+            const bool kdir = (d == f);
+            Uf[d] = isp ? t.Mi : (kdir ? t.UK : t.UT);
+            Ui[d] = isp ? t.Mi : (kdir ? t.UKt : t.UTt);
+            ld[d] = (!isp && kdir) ? t.NNp : t.NMp;
+        }
+        auto mode1 = [&](const void* src, long long ss, const T* U, int ldu, void* dst,
+                         long long sd, bool to_out, int epi, double alpha, bool acc) {
+            GemmArgs g{};
+            g.A = src; g.a_i = n1; g.a_k = 1; g.a_s1 = ss; g.a_s2 = 0;
+            g.B = U; g.ldb = ldu;
+            g.C = dst; g.c_i = n1; g.c_j = 1; g.c_s1 = sd; g.c_s2 = 0;
+            g.M = (int)(n2 * (long long)n3); g.N = n1; g.K = n1; g.nb1 = nrhs;
+            g.epi = epi; g.alpha = alpha; g.accumulate = acc;
+            if (to_out) return gemm_launch<T, T, double, true, false>(c->stream, g, nrhs);
+            return gemm_launch<T, double, T, true, false>(c->stream, g, nrhs);
+        };
+        auto mode2 = [&](const T* src, const T* U, int ldu, T* dst) {
+            GemmArgs g{};
+            g.A = src; g.a_i = 1; g.a_k = n1; g.a_s1 = n12; g.a_s2 = N;
+            g.B = U; g.ldb = ldu;
+            g.C = dst; g.c_i = 1; g.c_j = n1; g.c_s1 = n12; g.c_s2 = N;
+            g.M = n1; g.N = n2; g.K = n2; g.nb1 = n3;
+            return gemm_launch<T, T, T, false, true>(c->stream, g, n3 * nrhs);
+        };
+        auto mode3 = [&](const T* src, const T* U, int ldu, void* dst, long long sd, bool to_out,
+                         int epi, double alpha, bool acc) {
+            GemmArgs g{};
+            g.A = src; g.a_i = 1; g.a_k = n12; g.a_s1 = N; g.a_s2 = 0;
+            g.B = U; g.ldb = ldu;
+            g.C = dst; g.c_i = 1; g.c_j = n12; g.c_s1 = sd; g.c_s2 = 0;
+            g.M = (int)n12; g.N = n3; g.K = n3; g.nb1 = nrhs;
+            g.epi = epi; g.alpha = alpha; g.accumulate = acc;
+            g.n1 = n1;
+            g.l1 = (f == 0) ? t.lamK : t.lamT;
+            g.l2 = (f == 1) ? t.lamK : t.lamT;
+            g.l3 = (f == 2) ? t.lamK : t.lamT;
+            if (to_out) return gemm_launch<T, T, double, false, true>(c->stream, g, nrhs);
+            return gemm_launch<T, T, T, false, true>(c->stream, g, nrhs);
+        };
+        if (isp) {
+            if ((e = mode1(x, sx, Uf[0], ld[0], Y1, N, false, 0, 1.0, false)) != hipSuccess) break;
+            if ((e = mode2(Y1, Uf[1], ld[1], Y2)) != hipSuccess) break;
+            e = mode3(Y2, Uf[2], ld[2], out.f[3], out.stride[3], true, 1, omega * two_nu,
+                      accumulate);
+        } else {
+            if ((e = mode1(x, sx, Uf[0], ld[0], Y1, N, false, 0, 1.0, false)) != hipSuccess) break;
+            if ((e = mode2(Y1, Uf[1], ld[1], Y2)) != hipSuccess) break;
+            if ((e = mode3(Y2, Uf[2], ld[2], Y1, N, false, 2, omega / two_nu, false)) != hipSuccess)
+                break;
+            if ((e = mode3(Y1, Ui[2], ld[2], Y2, N, false, 0, 1.0, false)) != hipSuccess) break;
+            if ((e = mode2(Y2, Ui[1], ld[1], Y1)) != hipSuccess) break;
+            e = mode1(Y1, N, Ui[0], ld[0], out.f[f], out.stride[f], true, 0, 1.0, accumulate);
+        }
+    }
+    if (e != hipSuccess || !dot) return e;
+    const int nM = c->nM;
+    if (vel && !pres) {
+        for (int f = 0; f < 3; ++f) {
+            const long long plane = c->dims[f][0] * c->dims[f][1];
+            hipLaunchKernelGGL(k_fd_dot_vel, dim3((unsigned)c->dims[f][2], nrhs), dim3(256), 0,
+                               c->stream, out.f[f], dot->with + c->off[f], out.stride[f], plane,
+                               dot->part, 3LL * nM, f * nM);
+        }
+    } else if (pres && !vel) {
+        const long long plane = (long long)nM * nM;
+        hipLaunchKernelGGL(k_fd_dot_pres, dim3((unsigned)((plane + ZROWS - 1) / ZROWS), nrhs),
+                           dim3(256), 0, c->stream, out.f[3], dot->with + c->off[3], out.stride[3],
+                           plane, nM, dot->part, fd_dot_count(c, false));
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t set_fd_attrs() {
     const int bytes = 160 * 1024;
@@ -1104,8 +1424,14 @@ hipError_t fd_init_attributes() {
     return hipSuccess;
 }
 
+// directions longer than the in-LDS kernels hold (8 MFMA tiles of 16)
+static bool fd_needs_gemm(const hp_ctx* c) { return ((c->nM + 15) & ~15) > 128; }
+
 bool fd_plan_valid(const hp_ctx* c, int precision, int plan) {
     const int NMp = (c->nM + 15) & ~15;
+    // the mode-product GEMMs run in FP64 or FP32 (split BF16 keeps to the in-LDS kernels)
+    if (plan == FD_PLAN_GEMM) return precision != HP_PREC_BF16X3;
+    if (fd_needs_gemm(c)) return false;
     if (precision == HP_PREC_BF16X3 && plan >= 0 && (plan & 4)) return false;  // not blocked
     return precision == HP_PREC_FP64 ? fd_plan_fits<double>(NMp, plan) : fd_plan_fits<float>(NMp, plan);
 }
@@ -1113,6 +1439,7 @@ bool fd_plan_valid(const hp_ctx* c, int precision, int plan) {
 int fd_plan_in_use(const hp_ctx* c, int precision) {
     if (c->fd_force >= 0) return c->fd_force;
     if (c->opts.fd_plan >= 0 && fd_plan_valid(c, precision, c->opts.fd_plan)) return c->opts.fd_plan;
+    if (fd_needs_gemm(c)) return FD_PLAN_GEMM;
     return c->fd_tuned[precision];
 }
 
@@ -1125,6 +1452,12 @@ hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, b
                      bool accumulate, int precision, int nrhs, const FdDot* dot,
                      const FdComb* comb) {
     if (dot && (precision != HP_PREC_FP64 || (vel && pres))) return hipErrorInvalidValue;
+    if (fd_plan_in_use(c, precision) == FD_PLAN_GEMM || fd_needs_gemm(c)) {
+        // long directions with split BF16 fall back to FP32 products
+        if (precision == HP_PREC_FP64)
+            return run_P0_gemm<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs, dot, comb);
+        return run_P0_gemm<float>(c, c->fd32, in, out, vel, pres, accumulate, nrhs, dot, comb);
+    }
     if (precision == HP_PREC_FP64)
         return run_P0<double>(c, c->fd64, in, out, vel, pres, accumulate, nrhs, dot, comb);
     if (precision == HP_PREC_BF16X3)

@@ -102,7 +102,7 @@ struct hp_ctx {
     hp::BandTables band{};
     hp::FDTables<double> fd64{};
     hp::FDTables<float> fd32{};
-    bool fd_ok = false;  // fast-diagonalisation tables present (<= 128 per direction)
+    bool fd_ok = false;  // fast-diagonalisation tables present
     // workspace (per right-hand side sizes scale with max_rhs)
     double* ws = nullptr;
     size_t ws_doubles = 0;
@@ -183,8 +183,11 @@ hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, b
                      const FdComb* comb = nullptr);
 long long fd_dot_count(const hp_ctx* c, bool vel);
 // fast-diagonalisation plans: bit 0 = one MFMA tile per wave (wide kernels),
-// bit 1 = stage the 1D matrices in LDS.  Whether plan `plan` fits the LDS for
+// bit 1 = stage the 1D matrices in LDS, bit 2 = 2x2 tile blocks per wave;
+// FD_PLAN_GEMM = the mode products as batched GEMMs over HBM (any direction
+// length; the only plan for directions longer than 128).  Whether plan `plan` fits the LDS for
 // `precision`, and the plan launch_P0 uses (forced, option, tuned, default).
+constexpr int FD_PLAN_GEMM = 8;
 bool fd_plan_valid(const hp_ctx* c, int precision, int plan);
 int fd_plan_in_use(const hp_ctx* c, int precision);
 

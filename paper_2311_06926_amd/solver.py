@@ -173,6 +173,13 @@ class Solver:
               "hp_apply_hyperpower")
         return y
 
+    def apply_PV(self, order, iters, u, y=None):
+        """y = P_{V,k}^{-1} u, the velocity block of P_k alone (eq. Pcv)."""
+        nr = self._nrhs(u, self.nV)
+        y = self.empty(self.nV, nr) if y is None else y
+        check(self.lib.hp_apply_PV(self.ctx, order, iters, _ptr(u), _ptr(y), nr), "hp_apply_PV")
+        return y
+
     def spectrum(self, block="velocity", order=2, iters=0, s_level=0, steps=60, start=None,
                  seed=0):
         """Lanczos estimate of the extreme eigenvalues of P_{V,k}^{-1} A

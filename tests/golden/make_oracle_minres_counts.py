@@ -54,7 +54,7 @@ def main():
         H = HyperPower(S, q, k, base=base)
         r = minres(lambda v: S.K @ v, H.apply, b, tol=1e-8)
         vals = " ".join(repr(float(v)) for v in r.x[idx])
-        out.append(f"{q} {k} {r.iters} {r.true_relres!r} {float(r.history[-1])!r} {vals}")
+        out.append(f"{q} {k} {r.iters} {float(r.true_relres)!r} {float(r.history[-1])!r} {vals}")
         print(f"# q={q} k={k}: {r.iters} iterations, true relres {r.true_relres:.3e} "
               f"({time.time() - t:.0f} s)", file=sys.stderr, flush=True)
     print("\n".join(out))

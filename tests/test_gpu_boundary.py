@@ -245,3 +245,28 @@ def test_breakdown_threshold(dev, krylov):
     assert e.value.code == HP_EBREAKDOWN
     for s in (ref, tiny, forced):
         s.close()
+
+
+@pytest.mark.parametrize("q,k", [(2, 0), (2, 2), (3, 1)])
+def test_velocity_block_alone_matches_oracle(dev, q, k):
+    """hp_apply_PV (eq. Pcv, the operator of the Sec. 5.1 cost study) against
+    the oracle's literal recursion, and equal bit for bit to the velocity
+    part of hp_apply_hyperpower (the same launch sequence)."""
+    from oracle.assemble import KronSystem
+    from oracle.precond import HyperPower
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 7, 3
+    say(f"[boundary] P_V,k alone q={q} k={k}")
+    S = KronSystem(E, p, 1.0)
+    sol = Solver(E, p, 1.0, max_rhs=2)
+    x = synth.random_vector(S.N, seed=171)
+    u = np.ascontiguousarray(x[:S.nV])
+    yv = sol.apply_PV(q, k, to_gpu(u, dev)).cpu().numpy()
+    ref = HyperPower(S, q, k).apply_V(k, u)
+    assert rel_err(yv, ref) < 1e-12
+    yfull = sol.apply_hyperpower(q, k, to_gpu(x, dev)).cpu().numpy()
+    assert np.array_equal(yv, yfull[:S.nV])
+    ub = np.concatenate([u, 0.5 * u])
+    yb = sol.apply_PV(q, k, to_gpu(ub, dev)).cpu().numpy()
+    assert np.array_equal(yb[:S.nV], yv)
+    sol.close()

@@ -14,8 +14,8 @@
   the oracle's rows of the factors in absolute value), at most 1e-14.
 * The MINRES sweep of the headline mesh (32^3, degree 3, q in {2, 3},
   k in {0..3}, eq. Pcq1): iteration counts within +-1 of the oracle's and
-  the solution on sampled velocity entries (tests/golden/, written by a
-  script that calls only the oracle).
+  the solution on sampled velocity entries within 1e-10 (tests/golden/,
+  written by a script that calls only the oracle).
 * P_1 at 32^3 through its definition with the separately checked operators.
 * The solve at 32^3 (q = 2, k = 1, MINRES): the oracle's lid right-hand side
   in, and on sampled rows |b - K x|_i <= ||b - K x||_2 <= tol ||b||_2.
@@ -206,7 +206,7 @@ def test_headline_sweep_matches_oracle(dev, q, k):
     """The benchmark's sweep at 32^3, degree 3 (MINRES to 1e-8, eq. Pcq1,
     literal schedule): iteration count within +-1 of the oracle's, the true
     residual below the tolerance, and the solution on the oracle's sampled
-    velocity entries within 1e-6 of the oracle's (relative to their max)."""
+    velocity entries within 1e-10 of the oracle's (relative to their max)."""
     from oracle.assemble import KronRows
     from paper_2311_06926_amd.solver import Solver
     E, p, tol = 32, 3, 1e-8
@@ -225,7 +225,60 @@ def test_headline_sweep_matches_oracle(dev, q, k):
     vel = idx < sol.nV
     gap = np.abs(x[idx][vel] - xs_ref[vel]).max() / np.abs(xs_ref[vel]).max()
     say(f"[fullsize]   sampled velocity gap {gap:.2e}")
-    assert gap <= 1e-6
+    # the same recurrences in the same order: the iterates agree to rounding
+    # (measured 1e-14 .. 3e-14)
+    assert gap <= 1e-10
+    sol.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_P0_above_the_tile_cap(dev, prec):
+    """130^3 elements, degree 2 (nM = 131: beyond the 128 a direction of the
+    in-LDS kernels holds), so P_0 runs as mode-product GEMMs: sampled
+    backward errors <= 1e-14 in FP64, and the FP32 products within 1e-5."""
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, nu = 130, 2, 0.9
+    say(f"[fullsize] P0 above the tile cap E={E} p={p} {prec}")
+    R = KronRows(E, p, nu)
+    s64 = Solver(E, p, nu, autotune=False)
+    assert s64.tuning(1)["fd_plan"][0] == 8
+    x = synth.random_vector(R.N, seed=130)
+    xg = torch.from_numpy(x).to(dev)
+    y = s64.apply_P0(xg)
+    if prec == "fp64":
+        eta = p0_backward_errors(R, x, y.cpu().numpy(), nu, 200, seed=130)
+        say(f"[fullsize]   backward errors {['%.1e' % e for e in eta]}")
+        assert max(eta) <= 1e-14
+    else:
+        s32 = Solver(E, p, nu, autotune=False, precision="fp32", krylov="fgmres")
+        y32 = s32.apply_P0(xg)
+        gap = float((y32 - y).abs().max() / y.abs().max())
+        say(f"[fullsize]   FP32 vs FP64 {gap:.2e}")
+        assert gap < 1e-5
+        s32.close()
+    s64.close()
+
+
+def test_solve_above_the_tile_cap(dev):
+    """MINRES with P_1 at 130^3 elements, degree 2 (N = 8.9 M): converged to
+    1e-8 with the true residual below the tolerance, and on sampled rows
+    |b - K x|_i <= tol ||b||_2 with the oracle's rows of K."""
+    from oracle.assemble import KronRows
+    from paper_2311_06926_amd.solver import Solver
+    E, p, tol = 130, 2, 1e-8
+    say(f"[fullsize] solve above the tile cap E={E} p={p}")
+    R = KronRows(E, p, 1.0)
+    b = R.lid_rhs(1.0)
+    sol = Solver(E, p, 1.0, iters=1)
+    xg, info = sol.solve(torch.from_numpy(b).to(dev), tol)
+    say(f"[fullsize]   {info.iterations} iterations, true relres {info.true_relres:.2e}, "
+        f"{info.seconds * 1e3:.1f} ms")
+    assert info.converged and info.true_relres <= 1.01 * tol
+    x = xg.cpu().numpy()
+    idx = samples(R.offsets, 600, seed=131)
+    r = b[idx] - R.rows(x, idx)
+    assert np.abs(r).max() <= 1.01 * tol * np.linalg.norm(b)
     sol.close()
 
 
@@ -410,7 +463,9 @@ def test_fd_plans_agree(dev, E, p):
     (three, an odd count, so the 2x2-tile plan has a partial block) the
     second row and column tiles of every plan run.  Plans of the same
     kernel family (16-wave: odd codes; 4-wave: even codes) give the same
-    result bit for bit in each precision."""
+    result bit for bit in each precision; plan 8 (the mode products as
+    batched GEMMs over HBM, the path for directions longer than 128) is
+    checked the same way."""
     from oracle.assemble import KronRows
     from paper_2311_06926_amd.solver import Solver
     say(f"[shapes] P0 plans E={E} p={p}")
@@ -420,7 +475,7 @@ def test_fd_plans_agree(dev, E, p):
     x = torch.from_numpy(xh).to(dev)
     seen = set()
     first = {}
-    for plan in range(8):
+    for plan in range(9):
         s = Solver(E, p, nu, autotune=False, fd_plan=plan)
         used = s.tuning(1)["fd_plan"][0]
         if used != plan:          # the plan does not fit in LDS at this size
@@ -438,7 +493,7 @@ def test_fd_plans_agree(dev, E, p):
         y32 = y32g.cpu().numpy()
         assert np.abs(y32 - y).max() / np.abs(y).max() < 1e-5, plan
         s32.close()
-        fam = plan & 1
+        fam = 2 if plan == 8 else plan & 1
         if fam in first:
             assert torch.equal(yg, first[fam][0]), plan
             assert torch.equal(y32g, first[fam][1]), plan

@@ -191,10 +191,12 @@ def test_hyperpower(dev, E, p, q, k, variant):
     y = sol.apply_hyperpower(q, k, to_gpu(x, dev)).cpu().numpy()
     gap = rel_err(y, H.apply(x))
     eta = pv_backward_error(S, H.P0, q, k, x[:S.nV], y[:S.nV])
-    bound = pk_forward_bound(S, q, k)
-    say(f"[parity]   forward gap {gap:.2e} (bound {bound:.1e}), V backward {eta:.2e}")
-    assert gap < bound
-    assert eta <= 1e-14 * q ** k
+    say(f"[parity]   forward gap {gap:.2e} (kappa bound {pk_forward_bound(S, q, k):.1e}), "
+        f"V backward {eta:.2e}")
+    # degrees 2 and 3: the blocks' condition numbers (<= 2e4) leave the
+    # kappa bound far above 1e-12; the measured gaps are a few 1e-15
+    assert gap < 1e-12
+    assert eta <= 1e-15
     sol.close()
 
 
@@ -214,7 +216,7 @@ def test_hyperpower_high_degree(dev, E, p):
     say(f"[parity]   forward gap {gap:.2e} (bound {bound:.1e}, kappa "
         f"{block_kappa(S):.1e}), V backward {eta:.2e}")
     assert gap < bound
-    assert eta <= 1e-14 * 4
+    assert eta <= 1e-15
     sol.close()
 
 
@@ -239,7 +241,7 @@ def test_hyperpower_prev_schedule(dev):
     y = sol.apply_hyperpower(2, 3, to_gpu(x, dev)).cpu().numpy()
     gap = rel_err(y, H.apply(x))
     say(f"[parity]   forward gap {gap:.2e}")
-    assert gap < pk_forward_bound(S, 2, 3)
+    assert gap < 1e-12
     sol.close()
 
 
@@ -410,9 +412,7 @@ def test_inner_pcg_schur_variant(dev, level, k, m):
         xr = x[r * S.N:(r + 1) * S.N]
         gap = rel_err(y[r * S.N:(r + 1) * S.N], H.apply(xr))
         say(f"[parity]   rhs {r}: forward gap {gap:.2e}")
-        # PCG's step coefficients are ratios of inner products; each step
-        # applies P_{V,l} (q^l applications of P_{V,0}) twice
-        assert gap < pk_forward_bound(S, 2, k + level + 1) * (m + 1), r
+        assert gap < 1e-12, r
     y1 = sol.apply_hyperpower(2, k, to_gpu(x[:S.N], dev)).cpu().numpy()
     assert np.array_equal(y1, y[:S.N])
     sol.close()

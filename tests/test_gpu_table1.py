@@ -49,8 +49,8 @@ def gpu_counts(E, p, ks):
         say(f"[table1]   {E}^3 degree {p} k={k}: {info.iterations} iterations, true relres "
             f"{info.true_relres:.2e}")
         # MINRES monitors ||r||_{P^{-1}}; the 2-norm of the true residual is
-        # reported and stays within a small factor of the tolerance
-        assert info.converged and info.true_relres < 1e-7
+        # reported and is below the tolerance as well for every row
+        assert info.converged and info.true_relres <= 1.01e-8
         out.append(info.iterations)
         sol.close()
     return out

@@ -70,6 +70,26 @@ def test_fast_diagonalization_equals_dense_inverse(E, p):
         assert np.abs(Pinv @ blk - np.eye(blk.shape[0])).max() < 1e-10
 
 
+@pytest.mark.parametrize("E,p,nu", [(2, 2, 0.7), (3, 3, 1.3), (2, 5, 1.0)])
+def test_fast_diagonalisation_tier_equals_lu_and_dense_inverse(E, p, nu):
+    """The oracle's einsum fast-diagonalisation tier (App. A.4) equals the
+    sparse-LU P_{V,0} and the dense inverse of each diagonal block of A."""
+    from oracle.precond import FastDiagBase
+    S = KronSystem(E, p, nu)
+    x = np.random.default_rng(E + p).standard_normal(S.N)
+    lu = BasePreconditioner(S)
+    fd = FastDiagBase(S)
+    yv = fd.apply_V0(x[:S.nV])
+    assert np.abs(yv - lu.apply_V0(x[:S.nV])).max() <= 1e-11 * np.abs(yv).max()
+    o = S.offsets
+    A, _ = _dense_ops(S)
+    for c in range(3):
+        blk = A[o[c]:o[c + 1], o[c]:o[c + 1]]
+        ref = np.linalg.solve(blk, x[o[c]:o[c + 1]])
+        assert np.abs(yv[o[c]:o[c + 1]] - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.array_equal(fd.apply_Q0(x[S.nV:]), lu.apply_Q0(x[S.nV:]))
+
+
 def test_trace_of_preconditioned_A():
     S = KronSystem(3, 2, 1.0)
     A, Dv = _dense_ops(S)
