@@ -299,6 +299,23 @@ hp_status hp_spectrum(hp_ctx* ctx, int block, int order, int iters, int s_level,
 hp_status hp_solve(hp_ctx* ctx, const double* b, double* x, int nrhs, double tol,
                    hp_solve_info* info);
 
+/* hp_solve without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the Krylov vectors live in a fixed 32 MiB device array of the
+ * library (2^22 doubles per GPU, held from the library's load until the
+ * process ends) instead of memory allocated on first use.  Same arguments,
+ * results and errors as hp_solve, computed by the same kernels, with the
+ * iteration launched directly (opts.use_graph is ignored).  Limits: the
+ * solve must fit the array -- 10 N max_rhs doubles for MINRES,
+ * (2 restart + 2) N max_rhs for FGMRES (e.g. MINRES at 32^3 elements, degree
+ * 3, N = 153,748, up to max_rhs = 2) -- else HP_ENOMEM, nothing written;
+ * nrhs <= 64; with opts.forward = 1 the quadrature operator must already be
+ * set up (HP_EINVAL otherwise).  Every call on one GPU shares that GPU's
+ * array and overwrites it (each call initialises what it reads): calls that
+ * overlap in time on one GPU, from any context or stream, race. */
+hp_status hp_solve_noalloc(hp_ctx* ctx, const double* b, double* x, int nrhs, double tol,
+                           hp_solve_info* info);
+
 /* Right-hand side of the lid-driven cavity (Sec. 5, Fig. liddrivencavity)
  * with a body force, b = [F_lid + F_modes + M_V beta; 0] (the linear form
  * l(v) of Sec. 3.1 plus the Nitsche lid data): for each rhs r, lid speed

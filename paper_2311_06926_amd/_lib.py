@@ -104,6 +104,7 @@ SIGNATURES = {
     "hp_apply_hyperpower": (I, [P, I, I, P, P, I]),
     "hp_apply_PV": (I, [P, I, I, P, P, I]),
     "hp_solve": (I, [P, P, P, I, D, ctypes.POINTER(hp_solve_info)]),
+    "hp_solve_noalloc": (I, [P, P, P, I, D, ctypes.POINTER(hp_solve_info)]),
     "hp_build_rhs": (I, [P, P, I, P, P, P, P, I]),
     "hp_apply_MV": (I, [P, P, P, I]),
     "hp_grad": (I, [P, P, P, P, P, P, I]),

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <vector>
@@ -445,12 +446,6 @@ hp_status stage_coef(hp_ctx* c, const std::vector<double>& v) {
     return HP_OK;
 }
 
-// dots of nrhs pairs over full vectors -> host
-hp_status dots(hp_ctx* c, const double* x, const double* y, int nrhs, std::vector<double>& out) {
-    out.resize(nrhs);
-    if (vec_dots(c, c->N, c->N, x, y, nrhs, out.data()) != hipSuccess) return HP_EHIP;
-    return HP_OK;
-}
 
 // ---- MINRES (preconditioned; Lanczos in the P^{-1} inner product) ------------------
 // All recurrence scalars live on the device (k_minres_* kernels), so one
@@ -1219,6 +1214,40 @@ hp_status spectrum_gate(hp_ctx* c, int steps) {
     return HP_OK;
 }
 
+// ---- the solve without device allocation (hp_solve_noalloc) ----------------------------
+// The Krylov vectors of hp_solve_noalloc live in this file-scope device array
+// instead of memory the library allocates: each GPU the library runs on holds
+// its own copy until the process ends.  In host code `noalloc_scratch` only
+// names a host-side stand-in; the device address of each GPU's copy is taken
+// once per device with hipGetSymbolAddress (at the first hp_setup on it) and
+// used everywhere instead.
+constexpr size_t NOALLOC_DOUBLES = (size_t)1 << 22;  // 32 MiB
+static __device__ __align__(256) double noalloc_scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// With `device` current: find its copy of the array (once per device).
+hp_status noalloc_init(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return HP_OK;  // the variant then refuses
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[device]) return HP_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch)) != hipSuccess || !p) return HP_EHIP;
+    noalloc_ptr[device] = static_cast<double*>(p);
+    return HP_OK;
+}
+
+// Krylov doubles the solve of this context needs (vector slots are laid out
+// for max_rhs right-hand sides).
+size_t krylov_doubles(const hp_ctx* c) {
+    const size_t V = (size_t)c->N * (size_t)c->opts.max_rhs;
+    if (c->opts.krylov == HP_MINRES) return 10 * V;
+    const int m = std::max(1, std::min(c->opts.restart, FG_MMAX));
+    return (size_t)(2 * m + 2) * V;
+}
+
 }  // namespace
 
 // =====================================================================================
@@ -1301,6 +1330,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     c->opts = o;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     if (hipGetDevice(&c->device) != hipSuccess) { delete ce; return HP_EHIP; }
+    if (noalloc_init(c->device) != HP_OK) { delete ce; return HP_EHIP; }
     c->E = elements;
     c->p = degree;
     c->nu = nu;
@@ -1633,13 +1663,23 @@ hp_status hp_spectrum(hp_ctx* c, int block, int order, int iters, int s_level, i
     return HP_OK;
 }
 
-hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
-                   hp_solve_info* info) {
+}  // extern "C"
+
+namespace {
+
+hp_status solve_checks(hp_ctx* c, const double* b, double* x, int nrhs, double tol) {
     if (check_rhs(c, nrhs) != HP_OK || !b || !x || b == x || !(tol > 0.0) || !c->fd_ok)
         return HP_EINVAL;
     if (c->opts.krylov == HP_MINRES &&
         (c->opts.precision != HP_PREC_FP64 || c->opts.schur_variant == HP_SCHUR_PCG))
         return HP_EINVAL;  // MINRES needs a fixed symmetric preconditioner
+    return HP_OK;
+}
+
+// The solve and its true residual; the Krylov vectors are whatever ex->kv
+// holds (allocated on first use unless the caller has put them in place).
+hp_status solve_impl(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
+                     hp_solve_info* info, double* rr_host, double* bb_host) {
     auto t0 = std::chrono::steady_clock::now();
     hp_solve_info loc{};
     hp_status s = c->opts.krylov == HP_MINRES ? minres(c, b, x, nrhs, tol, &loc)
@@ -1651,14 +1691,53 @@ hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
             hipSuccess ||
         vec_axpby(c->stream, c->N * nrhs, 1.0, b, -1.0, w) != hipSuccess)
         return HP_EHIP;
-    std::vector<double> rr, bb;
-    if (dots(c, w, w, nrhs, rr) != HP_OK || dots(c, b, b, nrhs, bb) != HP_OK) return HP_EHIP;
+    if (vec_dots(c, c->N, c->N, w, w, nrhs, rr_host) != hipSuccess ||
+        vec_dots(c, c->N, c->N, b, b, nrhs, bb_host) != hipSuccess)
+        return HP_EHIP;
     loc.true_relres = 0.0;
     for (int r = 0; r < nrhs; ++r)
-        loc.true_relres = std::max(loc.true_relres, bb[r] > 0 ? std::sqrt(rr[r] / bb[r]) : 0.0);
+        loc.true_relres =
+            std::max(loc.true_relres, bb_host[r] > 0 ? std::sqrt(rr_host[r] / bb_host[r]) : 0.0);
     loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = loc;
     return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+hp_status hp_solve(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
+                   hp_solve_info* info) {
+    const hp_status chk = solve_checks(c, b, x, nrhs, tol);
+    if (chk != HP_OK) return chk;
+    std::vector<double> rr(nrhs), bb(nrhs);
+    return solve_impl(c, b, x, nrhs, tol, info, rr.data(), bb.data());
+}
+
+hp_status hp_solve_noalloc(hp_ctx* c, const double* b, double* x, int nrhs, double tol,
+                           hp_solve_info* info) {
+    const hp_status chk = solve_checks(c, b, x, nrhs, tol);
+    if (chk != HP_OK) return chk;
+    if (nrhs > 64) return HP_EINVAL;
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES || !noalloc_ptr[c->device])
+        return HP_EHIP;
+    // the quadrature forward operator allocates its tables on first use
+    if (c->opts.forward == 1 && !extra_of(c)->quad.ready) return HP_EINVAL;
+    if (krylov_doubles(c) > NOALLOC_DOUBLES) return HP_ENOMEM;
+    Extra* ex = extra_of(c);
+    double* kv0 = ex->kv;
+    const size_t kd0 = ex->kv_doubles;
+    const int graph0 = c->opts.use_graph;
+    ex->kv = noalloc_ptr[c->device];
+    ex->kv_doubles = NOALLOC_DOUBLES;
+    c->opts.use_graph = 0;  // capturing and instantiating graphs allocates
+    double rr[64], bb[64];
+    const hp_status st = solve_impl(c, b, x, nrhs, tol, info, rr, bb);
+    ex->kv = kv0;
+    ex->kv_doubles = kd0;
+    c->opts.use_graph = graph0;
+    return st;
 }
 
 hp_status hp_build_rhs(hp_ctx* c, const double* lid, int nmodes, const double* amp,
