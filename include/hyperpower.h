@@ -110,7 +110,11 @@ typedef struct hp_opts {
                            bit 2 = 2x2 blocks of MFMA tiles per wave (16-wave plans,
                            FP64/FP32); 8 = every mode product as a batched GEMM over
                            HBM (FP64/FP32; the plan used whenever E + degree - 1 > 128,
-                           where split BF16 falls back to FP32 products) */
+                           where split BF16 falls back to FP32 products); 9 = the in-LDS
+                           products with one 16-row block of a plane per 4-wave
+                           workgroup and 16 z rows per workgroup (small meshes: several
+                           times the workgroups of plans 0..7, the same result as the
+                           16-wave plans) */
     int op_slabs;       /* operator: i3-slabs run one after the other (pressure chain
                            then velocity per slab), 0 = tuned/model */
     int schur_level;    /* eq. Pcq2 only: the fixed P_{V,l} inside B' P_{V,l}^{-1} B,

@@ -1019,9 +1019,10 @@ hp_status autotune(hp_ctx* c) {
     }
     // P_0: every plan that fits, per precision (velocity and pressure blocks)
     for (int prec = 0; prec < 3 && st == HP_OK && c->fd_ok && c->opts.fd_plan < 0; ++prec) {
-        double us[FD_PLAN_GEMM + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+        double us[FD_PLAN_LAST + 1];
+        for (double& u : us) u = -1.0;
         for (int pass = 0; pass < TUNE_PASSES && st == HP_OK; ++pass)
-            for (int plan = 0; plan <= FD_PLAN_GEMM && st == HP_OK; ++plan) {
+            for (int plan = 0; plan <= FD_PLAN_LAST && st == HP_OK; ++plan) {
                 if (!fd_plan_valid(c, prec, plan)) continue;
                 c->fd_force = plan;
                 const double t = time_launches(c, e0, e1, TUNE_REPS, [&]() {
@@ -1032,7 +1033,7 @@ hp_status autotune(hp_ctx* c) {
             }
         double best = -1.0;
         int best_plan = -1;
-        for (int plan = 0; plan <= FD_PLAN_GEMM; ++plan)
+        for (int plan = 0; plan <= FD_PLAN_LAST; ++plan)
             if (us[plan] >= 0.0 && (best < 0.0 || us[plan] < best)) {
                 best = us[plan];
                 best_plan = plan;
@@ -1309,7 +1310,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
     if (o.max_rhs < 1 || o.order < 2 || o.iters < 0 || o.iters > KMAX || !(o.c_pen >= 0.0) ||
         o.precision < 0 || o.precision > 2 || (o.krylov != HP_MINRES && o.krylov != HP_FGMRES) ||
         o.restart < 1 || o.maxit < 1 || o.op_kchunk < 0 || o.op_order < -1 || o.op_order > 1 ||
-        o.fd_plan < -1 || o.fd_plan > FD_PLAN_GEMM || o.op_slabs < 0 || o.schur_level < 0 ||
+        o.fd_plan < -1 || o.fd_plan > FD_PLAN_LAST || o.op_slabs < 0 || o.schur_level < 0 ||
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
@@ -1470,10 +1471,10 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[0]), ex->hmsc[0], 0) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&ex->dmsc[1]), ex->hmsc[1], 0) != hipSuccess ||
         alloc_device(&ex->mpart, 2 * vec_partial_doubles(1, (int)R)) != HP_OK ||
-        alloc_device(&ex->mfg, (size_t)fd_dot_count(c, true) * R) != HP_OK ||
-        alloc_device(&ex->mfq, (size_t)fd_dot_count(c, false) * R) != HP_OK ||
-        hipMemset(ex->mfg, 0, sizeof(double) * fd_dot_count(c, true) * R) != hipSuccess ||
-        hipMemset(ex->mfq, 0, sizeof(double) * fd_dot_count(c, false) * R) != hipSuccess ||
+        alloc_device(&ex->mfg, (size_t)fd_dot_capacity(c, true) * R) != HP_OK ||
+        alloc_device(&ex->mfq, (size_t)fd_dot_capacity(c, false) * R) != HP_OK ||
+        hipMemset(ex->mfg, 0, sizeof(double) * fd_dot_capacity(c, true) * R) != hipSuccess ||
+        hipMemset(ex->mfq, 0, sizeof(double) * fd_dot_capacity(c, false) * R) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[0], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[1], hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&ex->mev[2], hipEventDisableTiming) != hipSuccess ||

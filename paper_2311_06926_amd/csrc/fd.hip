@@ -112,6 +112,10 @@ struct XYArgs {
     double* dpart;
     long long dp_stride;
     int dp_planes;
+    // row-block kernel (k_fd_xy_s) only: row blocks per plane in its grid
+    // order, and the partial of row block b goes to slot + b dp_rb
+    int nrb;
+    long long dp_rb;
     // FP64 input only: for a field with inb[f] set, the input is
     // ca in + cb inb + cc inc (the same layout as in, rhs strides sinb, sinc)
     const double* inb[4];
@@ -295,11 +299,11 @@ struct ZArgs {
     long long dp_stride;
 };
 
-// The final write-out of z rows [r0, r0 + ZROWS) of field f from the
+// The final write-out of z rows [r0, r0 + ZR) of field f from the
 // row-major buffer Out (leading dimension ld): y = Out or y += Out; with a
 // dot also the workgroup's fixed-order sum of (stored value) x dw, whose
 // scratch reuses S once every read of the LDS buffers is done.
-template <typename T, typename TO, int NTH>
+template <typename T, typename TO, int NTH, int ZR = ZROWS>
 __device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int ld, int f, int r,
                                         long long r0, long long plane, int n3) {
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
@@ -307,8 +311,8 @@ __device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int 
         if (a.dpart) {
             const double* w = a.dw + (long long)r * a.sout[f];
             double s = 0.0;
-            for (int idx = threadIdx.x; idx < ZROWS * n3; idx += NTH) {
-                int kk = idx / ZROWS, row = idx - kk * ZROWS;
+            for (int idx = threadIdx.x; idx < ZR * n3; idx += NTH) {
+                int kk = idx / ZR, row = idx - kk * ZR;
                 if (r0 + row >= plane) continue;
                 long long o = r0 + row + (long long)kk * plane;
                 double v = (double)Out[row * ld + kk];
@@ -330,8 +334,8 @@ __device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int 
             return;
         }
     }
-    for (int idx = threadIdx.x; idx < ZROWS * n3; idx += NTH) {
-        int kk = idx / ZROWS, row = idx - kk * ZROWS;
+    for (int idx = threadIdx.x; idx < ZR * n3; idx += NTH) {
+        int kk = idx / ZR, row = idx - kk * ZR;
         if (r0 + row >= plane) continue;
         TO v = (TO)Out[row * ld + kk];
         long long o = r0 + row + (long long)kk * plane;
@@ -762,10 +766,128 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     xy_store<T, TO, FD_WIDE>(a, S, ld, f, r, k, n1, n2);
 }
 
-// z: 64 (i1,i2)-rows x n3 per workgroup, tiles of Y = X U3 and Z = Y U3^T
-// dealt to 16 waves; the scaling by 1/(2 nu (l1 + l2 + l3)) is applied to Y.
-template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false>
-__global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
+// One 16-row block of one i3-plane per 4-wave workgroup, for meshes whose
+// planes alone leave most compute units idle: the nb1 row blocks of a plane
+// run as nb1 workgroups.  Step 1's row block T_b = L_b X needs the whole
+// plane X, which every workgroup of the plane stages; T_b stays in LDS
+// (column-major, pitch 17) and Y_b = T_b R follows.  The dense 1D matrices
+// are read from L2.  Per output tile the contraction is tile_mm's, with the
+// operands of the wide kernel, so the result equals it bit for bit.
+// Grid order: workgroup g runs on XCD g mod 8 (round-robin dispatch), and the
+// row blocks of plane k take consecutive slots of XCD k mod 8, so that the
+// workgroups staging one plane share that XCD's L2.
+constexpr int FD_SPLIT = 256;   // 4 waves
+constexpr int TBP = 17;         // pitch of the row block T_b in LDS
+
+template <typename T, typename TI, typename TO, bool SPLIT = false>
+__global__ __launch_bounds__(FD_SPLIT) void k_fd_xy_s(XYArgs a, FDTables<T> t) {
+    using M = Mfma<T>;
+    extern __shared__ unsigned char smem_raw[];
+    T* S = reinterpret_cast<T*>(smem_raw);
+    const int nf = a.fields_hi - a.fields_lo;
+    const int f = a.fields_lo + (int)(blockIdx.y % nf);
+    const int r = (int)(blockIdx.y / nf);
+    const int xcd = (int)(blockIdx.x & 7), slot = (int)(blockIdx.x >> 3);
+    const int k = (slot / a.nrb) * 8 + xcd, rb = slot % a.nrb;
+    const int n1 = a.dims[f][0], n2 = a.dims[f][1], n3 = a.dims[f][2];
+    const int N1 = (n1 + 15) & ~15, N2 = (n2 + 15) & ~15;
+    if (k >= n3 || 16 * rb >= N1) return;
+    const int ld = N1 + 1;  // column-major plane
+    const int nb2 = N2 >> 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long long kofs = (long long)k * n1 * n2;
+    const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
+    for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_SPLIT) {
+        int col = idx / N1, row = idx - col * N1;
+        T v = 0;
+        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
+        S[col * ld + row] = v;
+    }
+    T* Tb = S + N2 * ld;  // Tb[col * TBP + i]: row 16 rb + i of T (and later of Y)
+    const T* L = xy_left(t, f, a.inverse);
+    const T* Rt = xy_right_t(t, f, a.inverse);
+    const int ldL = (f == 0) ? t.NNp : t.NMp;
+    const int ldR = (f == 1) ? t.NNp : t.NMp;
+    __syncthreads();
+    typename M::V acc[2];
+    // step 1: T_b = L_b X, tiles (rb, cb), cb = wave, wave + 4 (nb2 <= 8)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int cb = wave + 4 * m;
+        if (cb < nb2)
+            acc[m] = tile_mm<T, SPLIT, true>(L + rb * 16 * ldL, ldL, S + cb * 16 * ld, 1, ld, n1,
+                                             lr, lk);
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int cb = wave + 4 * m;
+        if (cb < nb2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Tb[(cb * 16 + lr) * TBP + M::row(lk, i)] = acc[m][i];
+    }
+    __syncthreads();
+    // step 2: Y_b = T_b R, tiles (rb, cb)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int cb = wave + 4 * m;
+        if (cb < nb2)
+            acc[m] = tile_mm<T, SPLIT, false>(Rt + cb * 16 * ldR, ldR, Tb, TBP, 1, n2, lr, lk);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const int cb = wave + 4 * m;
+        if (cb < nb2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) Tb[(cb * 16 + lr) * TBP + M::row(lk, i)] = acc[m][i];
+    }
+    __syncthreads();
+    // write-out of rows [16 rb, min(n1, 16 rb + 16)), as xy_store for one row block
+    const int rows = min(16, n1 - 16 * rb);
+    TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + kofs + 16 * rb;
+    if constexpr (std::is_same<TO, double>::value) {
+        if (a.dpart) {
+            const double* w = a.dw[f] + (long long)r * a.sout[f] + kofs + 16 * rb;
+            double s = 0.0;
+            for (int idx = threadIdx.x; idx < 16 * n2; idx += FD_SPLIT) {
+                const int col = idx >> 4, i = idx & 15;
+                if (i >= rows) continue;
+                const long long o = i + (long long)col * n1;
+                double v = (double)Tb[col * TBP + i];
+                if (a.accumulate) v += y[o];
+                y[o] = v;
+                s += v * w[o];
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+            __syncthreads();
+            double* red = reinterpret_cast<double*>(S);
+            if (lane == 0) red[wave] = s;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                a.dpart[(long long)r * a.dp_stride + (long long)f * a.dp_planes + k +
+                        rb * a.dp_rb] = red[0] + red[1] + red[2] + red[3];
+            return;
+        }
+    }
+    for (int idx = threadIdx.x; idx < 16 * n2; idx += FD_SPLIT) {
+        const int col = idx >> 4, i = idx & 15;
+        if (i >= rows) continue;
+        const long long o = i + (long long)col * n1;
+        const TO v = (TO)Tb[col * TBP + i];
+        if (a.accumulate) y[o] += v;
+        else y[o] = v;
+    }
+}
+
+// z: ZR (i1,i2)-rows x n3 per workgroup of NTH threads (64 rows and 16
+// waves, or 16 rows and 4 waves for small meshes), tiles of Y = X U3 and
+// Z = Y U3^T dealt to the waves; the scaling by 1/(2 nu (l1 + l2 + l3)) is
+// applied to Y.
+template <typename T, typename TI, typename TO, bool STAGE, bool SPLIT = false, int ZR = ZROWS,
+          int NTH = FD_WIDE>
+__global__ __launch_bounds__(NTH) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     using M = Mfma<T>;
     extern __shared__ unsigned char smem_raw[];
     T* S = reinterpret_cast<T*>(smem_raw);
@@ -774,18 +896,18 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const int r = (int)(blockIdx.y / nf);
     const int n1 = a.dims[f][0], n2 = a.dims[f][1], n3 = a.dims[f][2];
     const long long plane = (long long)n1 * n2;
-    const long long r0 = (long long)blockIdx.x * ZROWS;
+    const long long r0 = (long long)blockIdx.x * ZR;
     if (r0 >= plane) return;
     const int N3 = (n3 + 15) & ~15;
     const int ld = N3 + 1;  // row-major [row][k]
     const int nb3 = N3 >> 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nw = FD_WIDE / 64;
+    const int nw = NTH / 64;
     const int lr = lane & 15, lk = lane >> 4;
-    T* Y = S + ZROWS * ld;
+    T* Y = S + ZR * ld;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f];
-    for (int idx = threadIdx.x; idx < ZROWS * N3; idx += FD_WIDE) {
-        int kk = idx / ZROWS, row = idx - kk * ZROWS;
+    for (int idx = threadIdx.x; idx < ZR * N3; idx += NTH) {
+        int kk = idx / ZR, row = idx - kk * ZR;
         T v = 0;
         if (kk < n3 && r0 + row < plane) v = (T)x[r0 + row + (long long)kk * plane];
         S[row * ld + kk] = v;
@@ -795,9 +917,9 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const T* U3t = pres ? t.Mi : (f == 2 ? t.UKt : t.UTt);
     const int ldU = (f == 2) ? t.NNp : t.NMp;
     if (STAGE) {
-        T* Us = Y + ZROWS * ld;
+        T* Us = Y + ZR * ld;
         T* Uts = Us + N3 * N3;
-        for (int idx = threadIdx.x; idx < N3 * N3; idx += FD_WIDE) {
+        for (int idx = threadIdx.x; idx < N3 * N3; idx += NTH) {
             Us[idx] = U3[idx];
             if (!pres) Uts[idx] = U3t[idx];
         }
@@ -805,12 +927,12 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
         U3t = pres ? Us : Uts;  // M^^{-1} is symmetric: one staged copy serves both
     }
     __syncthreads();
-    const int ntile = (ZROWS / 16) * nb3;
+    const int ntile = (ZR / 16) * nb3;
     const double* l1 = (f == 0) ? t.lamK : t.lamT;
     const double* l2 = (f == 1) ? t.lamK : t.lamT;
     const double* l3 = (f == 2) ? t.lamK : t.lamT;
     for (int tt = wave; tt < ntile; tt += nw) {
-        const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
+        const int rb = tt % (ZR / 16), cb = tt / (ZR / 16);
         auto acc = tile_mm<T, SPLIT, false>(U3t + cb * 16 * ldU, ldU, S + rb * 16 * ld, 1, ld, n3, lr, lk);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -834,7 +956,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     T* Out = Y;
     if (!pres) {
         for (int tt = wave; tt < ntile; tt += nw) {
-            const int rb = tt % (ZROWS / 16), cb = tt / (ZROWS / 16);
+            const int rb = tt % (ZR / 16), cb = tt / (ZR / 16);
             auto acc = tile_mm<T, SPLIT, false>(U3 + cb * 16 * ldU, ldU, Y + rb * 16 * ld, 1, ld, n3, lr, lk);
 #pragma unroll
             for (int i = 0; i < 4; ++i) S[(rb * 16 + M::row(lk, i)) * ld + cb * 16 + lr] = acc[i];
@@ -842,13 +964,14 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_z_w(ZArgs a, FDTables<T> t) {
         __syncthreads();
         Out = S;
     }
-    z_store<T, TO, FD_WIDE>(a, Out, S, ld, f, r, r0, plane, n3);
+    z_store<T, TO, NTH, ZR>(a, Out, S, ld, f, r, r0, plane, n3);
 }
 
 // LDS plan for a direction of padded size np: wide (two buffers) or in place,
 // and whether the dense 1D matrices are staged in LDS as well.
 struct FDPlan {
     bool wide, stage_xy, stage_z, block;
+    bool split;  // row-block xy kernel and 16-row z kernel (FD_PLAN_SPLIT)
     size_t shm_xy, shm_z;
 };
 
@@ -862,6 +985,13 @@ FDPlan fd_plan(int np, int code) {
     // LDS), the z kernel keeps its input and intermediate rows (two buffers)
     const size_t lim = 160 * 1024, e = sizeof(T);
     FDPlan pl{};
+    if (code == FD_PLAN_SPLIT) {
+        pl.wide = true;
+        pl.split = true;
+        pl.shm_xy = (size_t)np * (np + 1 + TBP) * e;
+        pl.shm_z = (size_t)2 * 16 * (np + 1) * e;
+        return pl;
+    }
     const size_t plane = (size_t)np * (np + 1) * e, mats = (size_t)2 * np * np * e;
     const size_t zbuf = (size_t)ZROWS * (np + 1) * e;
     const bool wide_fits = plane <= lim && 2 * zbuf <= lim;
@@ -888,6 +1018,7 @@ FDPlan fd_plan(int np, int code) {
 template <typename T>
 bool fd_plan_fits(int np, int code) {
     if (code < 0) return true;
+    if (code == FD_PLAN_SPLIT) return fd_plan<T>(np, code).shm_xy <= 160 * 1024;
     if (code > 7) return false;
     if ((code & 4) && !(code & 1)) return false;  // blocking exists in the wide kernel only
     const size_t lim = 160 * 1024, e = sizeof(T);
@@ -937,7 +1068,13 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     const dim3 bxy(pl.wide ? FD_WIDE : FD_THREADS);
     auto launch_xy = [&](const XYArgs& xa_, bool to_double, int nfields) {
         dim3 g(nM, nfields * nrhs);
-        if (pl.wide && pl.block && !SPLIT) {
+        if (pl.split) {
+            XYArgs xs = xa_;
+            xs.nrb = NMp / 16;
+            const dim3 gs((unsigned)(8 * xs.nrb * ((nM + 7) / 8)), nfields * nrhs);
+            if (to_double) hipLaunchKernelGGL((k_fd_xy_s<T, T, double, SPLIT>), gs, dim3(FD_SPLIT), pl.shm_xy, c->stream, xs, t);
+            else hipLaunchKernelGGL((k_fd_xy_s<T, double, T, SPLIT>), gs, dim3(FD_SPLIT), pl.shm_xy, c->stream, xs, t);
+        } else if (pl.wide && pl.block && !SPLIT) {
             if (to_double) {
                 if (pl.stage_xy) hipLaunchKernelGGL((k_fd_xy_w<T, T, double, true, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
                 else hipLaunchKernelGGL((k_fd_xy_w<T, T, double, false, SPLIT, true>), g, bxy, pl.shm_xy, c->stream, xa_, t);
@@ -966,7 +1103,11 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
     auto launch_z = [&](const ZArgs& za_, bool to_double, int nfields) {
         const long long maxplane = (long long)nM * nM;
         dim3 g((unsigned)((maxplane + ZROWS - 1) / ZROWS), nfields * nrhs);
-        if (pl.wide) {
+        if (pl.split) {
+            const dim3 gs((unsigned)((maxplane + 15) / 16), nfields * nrhs);
+            if (to_double) hipLaunchKernelGGL((k_fd_z_w<T, T, double, false, SPLIT, 16, FD_SPLIT>), gs, dim3(FD_SPLIT), pl.shm_z, c->stream, za_, t);
+            else hipLaunchKernelGGL((k_fd_z_w<T, T, T, false, SPLIT, 16, FD_SPLIT>), gs, dim3(FD_SPLIT), pl.shm_z, c->stream, za_, t);
+        } else if (pl.wide) {
             dim3 b(FD_WIDE);
             if (to_double) {
                 if (pl.stage_z) hipLaunchKernelGGL((k_fd_z_w<T, T, double, true, SPLIT>), g, b, pl.shm_z, c->stream, za_, t);
@@ -1040,11 +1181,13 @@ hipError_t run_P0(hp_ctx* c, const FDTables<T>& t, const Fields& in, const Field
         xi.inverse = 1;
         xi.accumulate = accumulate ? 1 : 0;
         if (dot) {
-            // xy partials: 3 nM per rhs, see fd_dot_count
+            // xy partials: per rhs 3 nM, times the row blocks of the split plan
+            // (see fd_dot_count)
             for (int f = 0; f < 3; ++f) xi.dw[f] = dot->with + c->off[f];
             xi.dpart = dot->part;
-            xi.dp_stride = 3LL * nM;
+            xi.dp_stride = fd_dot_count(c, true);
             xi.dp_planes = nM;
+            xi.dp_rb = 3LL * nM;
         }
         launch_xy(xi, true, 3);
     }
@@ -1393,7 +1536,11 @@ hipError_t set_fd_attrs() {
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, true>),
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, false>),
         reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, true>),
-        reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, false>)};
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, false>),
+        reinterpret_cast<const void*>(&k_fd_xy_s<T, double, T>),
+        reinterpret_cast<const void*>(&k_fd_xy_s<T, T, double>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, T, false, false, 16, FD_SPLIT>),
+        reinterpret_cast<const void*>(&k_fd_z_w<T, T, double, false, false, 16, FD_SPLIT>)};
     for (const void* k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
@@ -1416,7 +1563,11 @@ hipError_t fd_init_attributes() {
         reinterpret_cast<const void*>(&k_fd_z_w<float, float, float, true, true>),
         reinterpret_cast<const void*>(&k_fd_z_w<float, float, float, false, true>),
         reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, true, true>),
-        reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, false, true>)};
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, false, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_s<float, double, float, true>),
+        reinterpret_cast<const void*>(&k_fd_xy_s<float, float, double, true>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, float, false, true, 16, FD_SPLIT>),
+        reinterpret_cast<const void*>(&k_fd_z_w<float, float, double, false, true, 16, FD_SPLIT>)};
     for (const void* k : ks) {
         e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
@@ -1445,7 +1596,14 @@ int fd_plan_in_use(const hp_ctx* c, int precision) {
 
 long long fd_dot_count(const hp_ctx* c, bool vel) {
     const long long nM = c->nM;
+    if (fd_plan_in_use(c, HP_PREC_FP64) == FD_PLAN_SPLIT)
+        return vel ? 3 * nM * (((nM + 15) & ~15) / 16) : (nM * nM + 15) / 16;
     return vel ? 3 * nM : (nM * nM + ZROWS - 1) / ZROWS;
+}
+
+long long fd_dot_capacity(const hp_ctx* c, bool vel) {
+    const long long nM = c->nM;
+    return vel ? 3 * nM * (((nM + 15) & ~15) / 16) : (nM * nM + 15) / 16;
 }
 
 hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, bool pres,

@@ -166,8 +166,10 @@ hipError_t fd_init_attributes();
 // dot (FP64, the velocity blocks or the pressure block alone; may be null):
 // the last launch also writes partial sums of (final output) . dot->with to
 // dot->part[r * fd_dot_count(c, vel) + i] -- velocity: one per (field,
-// i3-plane), i = f nM + k (planes a field lacks are never written: kept zero
-// by the caller); pressure: one per workgroup of its mode-3 launch.
+// i3-plane), i = f nM + k, and with FD_PLAN_SPLIT one per (field, plane, row
+// block b), i = f nM + k + 3 nM b (slots no workgroup reaches -- planes or
+// row blocks a field lacks -- are never written: kept zero by the caller);
+// pressure: one per workgroup of its mode-3 launch.
 // comb (FP64, may be null): the input is ca in + cb comb->b + cc comb->c,
 // formed where the first launch reads it (as k_axpbypcz would).
 struct FdDot {
@@ -182,12 +184,19 @@ hipError_t launch_P0(hp_ctx* c, const Fields& in, const Fields& out, bool vel, b
                      bool accumulate, int precision, int nrhs, const FdDot* dot = nullptr,
                      const FdComb* comb = nullptr);
 long long fd_dot_count(const hp_ctx* c, bool vel);
+// the largest fd_dot_count over the plans (the partial buffers' size)
+long long fd_dot_capacity(const hp_ctx* c, bool vel);
 // fast-diagonalisation plans: bit 0 = one MFMA tile per wave (wide kernels),
 // bit 1 = stage the 1D matrices in LDS, bit 2 = 2x2 tile blocks per wave;
 // FD_PLAN_GEMM = the mode products as batched GEMMs over HBM (any direction
-// length; the only plan for directions longer than 128).  Whether plan `plan` fits the LDS for
-// `precision`, and the plan launch_P0 uses (forced, option, tuned, default).
+// length; the only plan for directions longer than 128); FD_PLAN_SPLIT = one
+// 16-row block of a plane per 4-wave workgroup and 16 z rows per workgroup
+// (several times the workgroups of plans 0-7, for small meshes).  Whether plan
+// `plan` fits the LDS for `precision`, and the plan launch_P0 uses (forced,
+// option, tuned, default).
 constexpr int FD_PLAN_GEMM = 8;
+constexpr int FD_PLAN_SPLIT = 9;
+constexpr int FD_PLAN_LAST = 9;
 bool fd_plan_valid(const hp_ctx* c, int precision, int plan);
 int fd_plan_in_use(const hp_ctx* c, int precision);
 

@@ -64,7 +64,7 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
     assert lib.hp_spectrum(None, 0, 2, 0, 0, 10, None, None, None, ctypes.byref(d),
                            ctypes.byref(lo), ctypes.byref(hi)) == -1
     # out-of-range launch-shape options are rejected before any HIP call
-    for field, bad in (("op_kchunk", -1), ("op_order", 2), ("fd_plan", 9), ("fd_plan", -2),
+    for field, bad in (("op_kchunk", -1), ("op_order", 2), ("fd_plan", 10), ("fd_plan", -2),
                        ("op_slabs", -1), ("schur_level", -1), ("schur_level", 7),
                        ("schur_variant", 0), ("schur_variant", 4), ("schur_pcg_iters", 0),
                        ("schur_pcg_tol", -1.0), ("op_fused", -2), ("op_fused", 2),

@@ -145,8 +145,9 @@ def test_P0_96_every_plan_backward_error(dev):
     """P_0 at 96^3, degree 3 (nN = 97, nM = 98: seven 16-wide MFMA tiles per
     direction, the last ragged) in FP64 with every plan that fits, among
     them the 2x2-tile plan the tuner picks at this size: sampled backward
-    errors <= 1e-14; the 16-wave plans agree with each other bit for bit
-    (same contraction order per output), the 4-wave plans likewise."""
+    errors <= 1e-14; the 16-wave plans and the row-block plan 9 agree with
+    each other bit for bit (same contraction order per output), the 4-wave
+    plans likewise."""
     from oracle.assemble import KronRows
     from paper_2311_06926_amd.solver import Solver
     E, p, nu = 96, 3, 1.1
@@ -159,7 +160,7 @@ def test_P0_96_every_plan_backward_error(dev):
     say(f"[fullsize]   tuned plans {tuned.tuning(1)['fd_plan']}")
     yt = tuned.apply_P0(xg)
     tuned.close()
-    for plan in range(8):
+    for plan in list(range(8)) + [9]:
         s = Solver(E, p, nu, autotune=False, fd_plan=plan)
         if s.tuning(1)["fd_plan"][0] != plan:
             s.close()
@@ -462,10 +463,10 @@ def test_fd_plans_agree(dev, E, p):
     within 1e-5 of it; at 30^3 (two MFMA tiles per direction) and 45^3
     (three, an odd count, so the 2x2-tile plan has a partial block) the
     second row and column tiles of every plan run.  Plans of the same
-    kernel family (16-wave: odd codes; 4-wave: even codes) give the same
-    result bit for bit in each precision; plan 8 (the mode products as
-    batched GEMMs over HBM, the path for directions longer than 128) is
-    checked the same way."""
+    kernel family (16-wave and the row-block plan 9: odd codes; 4-wave: even
+    codes) give the same result bit for bit in each precision; plan 8 (the
+    mode products as batched GEMMs over HBM, the path for directions longer
+    than 128) is checked the same way."""
     from oracle.assemble import KronRows
     from paper_2311_06926_amd.solver import Solver
     say(f"[shapes] P0 plans E={E} p={p}")
@@ -475,7 +476,7 @@ def test_fd_plans_agree(dev, E, p):
     x = torch.from_numpy(xh).to(dev)
     seen = set()
     first = {}
-    for plan in range(9):
+    for plan in range(10):
         s = Solver(E, p, nu, autotune=False, fd_plan=plan)
         used = s.tuning(1)["fd_plan"][0]
         if used != plan:          # the plan does not fit in LDS at this size
@@ -502,6 +503,30 @@ def test_fd_plans_agree(dev, E, p):
     assert seen, "no P0 plan fits"
 
 
+@pytest.mark.parametrize("krylov", ["minres", "fgmres"])
+def test_row_block_plan_solve(dev, krylov):
+    """A batched solve (two right-hand sides) with the row-block P_0 plan 9,
+    whose last launches also write the Krylov dot partials (one per plane row
+    block), against the 16-wave plan 1 (one per plane): P_0 agrees bit for
+    bit, so the only difference is the order of the partial sums; the same
+    iteration counts and solutions within 1e-12 of each other."""
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 20, 3
+    say(f"[shapes] row-block plan solve E={E} p={p} {krylov}")
+    a = Solver(E, p, 1.0, autotune=False, fd_plan=1, max_rhs=2, krylov=krylov)
+    b = Solver(E, p, 1.0, autotune=False, fd_plan=9, max_rhs=2, krylov=krylov)
+    assert b.tuning(1)["fd_plan"][0] == 9
+    rhs = a.build_rhs([1.0, -0.6])
+    xa, ia = a.solve(rhs, 1e-9)
+    xb, ib = b.solve(rhs, 1e-9)
+    gap = ((xa - xb).abs().max() / xa.abs().max()).item()
+    say(f"[shapes]   iterations {ia.iterations} / {ib.iterations}, gap {gap:.1e}")
+    assert ia.iterations == ib.iterations and ib.converged == 1
+    assert gap <= 1e-12
+    a.close()
+    b.close()
+
+
 def test_autotuner_reports_shapes_in_range(dev):
     from paper_2311_06926_amd.solver import Solver
     E, p = 12, 3
@@ -513,7 +538,7 @@ def test_autotuner_reports_shapes_in_range(dev):
         say(f"[shapes]   nrhs={nr}: {t}")
         assert t["op_tuned"] and 1 <= t["op_kchunk"] <= E + p - 1 and t["op_order"] in (0, 1)
         assert t["op_us"] > 0
-        assert all(0 <= f <= 7 for f in t["fd_plan"]) and all(us > 0 for us in t["fd_us"])
+        assert all(0 <= f <= 9 for f in t["fd_plan"]) and all(us > 0 for us in t["fd_us"])
         x = torch.from_numpy(synth.random_vector(nr * s.N, seed=nr)).to(dev)
         assert torch.equal(s.apply_K(x), plain.apply_K(x))
     assert not s.tuning(2)["op_tuned"]      # a batch size the tuner did not time
