@@ -454,9 +454,17 @@ def main():
                      "(P_0 blocks at FP64 MFMA peak, A and the B pairs at 16 B/DOF over HBM), "
                      "over the measured time")},
     }
+    plan = sol.tuning(1)["fd_plan"][0]
+    if plan == 9:
+        kname = ("apply_P0 (plan 9): k_fd_xy_s (16-row blocks, modes 1,2) + k_fd_z_w (16 rows, "
+                 "mode 3 + scaling) + k_fd_xy_s (inverse), FP64 16x16x4 MFMA")
+    elif plan == 8:
+        kname = "apply_P0 (plan 8): k_mode_gemm (six mode products per component), FP64 MFMA"
+    else:
+        kname = (f"apply_P0 (plan {plan}): k_fd_xy_w (modes 1,2) + k_fd_z_w (mode 3 + scaling) "
+                 "+ k_fd_xy_w (inverse), FP64 16x16x4 MFMA")
     roof = {
-        "kernel": ("apply_P0: k_fd_xy_w (modes 1,2) + k_fd_z_w (mode 3 + scaling) + k_fd_xy_w "
-                   "(inverse), FP64 16x16x4 MFMA"),
+        "kernel": kname,
         "bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / FP64_PEAK_TFLOPS,
         "traffic": pmc_traffic(f"apply_P0_E{E}p{p}_pmc.txt", ["fd.hip"]),
