@@ -41,9 +41,6 @@ struct Extra {
     // events and a second operator / fast-diagonalisation workspace
     hipStream_t side = nullptr;
     hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-    // MINRES without graphs: the w/x update of iteration j runs on the side
-    // stream beside K z of iteration j + 1 (wfork_ev: P_k done; w_ev: update done)
-    hipEvent_t wfork_ev = nullptr, w_ev = nullptr;
     double* ws2 = nullptr;
     double* hq = nullptr;  // 3 pressure vectors per level x (KMAX+1) x max_rhs
     // inner PCG of the Schur variant HP_SCHUR_PCG: r, z, p, A p (velocity x
@@ -530,42 +527,6 @@ hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol
     return minres_w_step(c, b, nrhs, tol, mirror, cur);
 }
 
-// The same iteration with the w/x update (minres_w_step) moved to the side
-// stream: it needs only P_k's output, and nothing before the next
-// iteration's v update needs it, so it runs beside the next K z.  The next
-// iteration waits for it (wait_w) just before its v update, which reads the
-// state it writes.  `poll` is recorded on the side stream after the update,
-// so the host reads the flags of this iteration through it.  The launches
-// are those of minres_iteration in the same order per stream: same results.
-hipError_t minres_iteration_overlap(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
-                                    MinresScalars* mirror, int cur, bool wait_w,
-                                    hipEvent_t poll) {
-    Extra* ex = extra_of(c);
-    const long long N = c->N;
-    const int R = c->opts.max_rhs;
-    hipStream_t main = c->stream;
-    MinresScalars* s_cur = ex->msc + cur * R;
-    hipError_t e;
-    if ((e = launch_forward(c, b.z, b.Kz, nrhs)) != hipSuccess) return e;
-    if ((e = vec_dot_partials(main, N, N, b.Kz, b.z, nrhs, ex->mpart)) != hipSuccess) return e;
-    if (wait_w && (e = hipStreamWaitEvent(main, ex->w_ev, 0)) != hipSuccess) return e;
-    if ((e = minres_v(main, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur,
-                      Partials{ex->mpart, vec_dot_partial_count()})) != hipSuccess)
-        return e;
-    const PkDot pd = minres_pk_dot(c, b);
-    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd)) != hipSuccess)
-        return e;
-    if ((e = hipEventRecord(ex->wfork_ev, main)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(ex->side, ex->wfork_ev, 0)) != hipSuccess) return e;
-    if ((e = minres_w(ex->side, N, N, nrhs, b.z, b.wo, b.w, b.wn, b.x, s_cur,
-                      ex->msc + (cur ^ 1) * R, Partials{pd.vpart, fd_dot_count(c, true)},
-                      Partials{pd.qpart, fd_dot_count(c, false)}, tol, c->opts.breakdown_tol,
-                      mirror)) != hipSuccess)
-        return e;
-    if ((e = hipEventRecord(ex->w_ev, ex->side)) != hipSuccess) return e;
-    return hipEventRecord(poll, ex->side);
-}
-
 void drop_graphs(Extra* ex) {
     for (auto& g : ex->g_exec)
         if (g) {
@@ -670,28 +631,23 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     int it = 0;
     const int lag = c->opts.poll_lag;
     bool finished = all_done(ex->hmsc[0]);
-    const bool overlap = !graphs && ex->side;
     while (!finished && it < c->opts.maxit) {
         const int ph = it % 6;
         ++it;
         if (graphs) {
             HIPCHK(hipGraphLaunch(ex->g_exec[ph], c->stream));
-        } else if (overlap) {
-            HIPCHK(minres_iteration_overlap(c, minres_bufs(c, ph, nrhs), nrhs, tol,
-                                            ex->dmsc[it & 1], it & 1, it > 1, ex->mev[it & 3]));
         } else {
             HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1],
                                     it & 1));
         }
         // the flags of iteration it - lag, read once iteration it is enqueued
         // (its mirror slot may already hold a later state: done is monotone)
-        if (!overlap) HIPCHK(hipEventRecord(ex->mev[it & 3], c->stream));
+        HIPCHK(hipEventRecord(ex->mev[it & 3], c->stream));
         if (it > lag) {
             HIPCHK(hipEventSynchronize(ex->mev[(it - lag) & 3]));
             finished = all_done(ex->hmsc[(it - lag) & 1]);
         }
     }
-    if (overlap && it > 0) HIPCHK(hipStreamWaitEvent(c->stream, ex->w_ev, 0));
     HIPCHK(hipStreamSynchronize(c->stream));
     // after `it` iterations the state is msc[(it + 1) & 1]
     const MinresScalars* h = ex->hmsc[it & 1];
@@ -1487,9 +1443,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         if (alloc_device(&ex->ws2, c->ws_doubles) != HP_OK ||
             hipStreamCreateWithFlags(&ex->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ex->fork_ev, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ex->join_ev, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ex->wfork_ev, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&ex->w_ev, hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&ex->join_ev, hipEventDisableTiming) != hipSuccess) {
             hp_destroy(c);
             return HP_ENOMEM;
         }
@@ -1835,8 +1789,6 @@ void hp_destroy(hp_ctx* c) {
     quad_free(&ex->quad);
     if (ex->fork_ev) (void)hipEventDestroy(ex->fork_ev);
     if (ex->join_ev) (void)hipEventDestroy(ex->join_ev);
-    if (ex->wfork_ev) (void)hipEventDestroy(ex->wfork_ev);
-    if (ex->w_ev) (void)hipEventDestroy(ex->w_ev);
     if (ex->hq) (void)hipFree(ex->hq);
     if (ex->kv) (void)hipFree(ex->kv);
     if (ex->dcoef) (void)hipFree(ex->dcoef);
