@@ -159,6 +159,10 @@ typedef struct hp_opts {
                            the rotated pivot of Hessenberg column j is <= breakdown_tol times
                            that column's 2-norm.  A value >= 1 forces the breakdown path at
                            the first iteration (used to test the error path) */
+    int op_dma;         /* streaming velocity kernel (modes K, A, M_V): -1 = default (1),
+                           1 = stage each plane's tile with direct-to-LDS loads into a ring
+                           of three LDS planes (two planes in flight), 0 = stage through
+                           registers (one plane in flight); same results bit for bit */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */

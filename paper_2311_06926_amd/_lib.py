@@ -57,6 +57,7 @@ class hp_opts(ctypes.Structure):
         ("spectrum_gate", ctypes.c_int),
         ("p0_scale", ctypes.c_double),
         ("breakdown_tol", ctypes.c_double),
+        ("op_dma", ctypes.c_int),
     ]
 
 

@@ -1283,6 +1283,7 @@ void hp_default_opts(hp_opts* o) {
     o->spectrum_gate = 0;
     o->p0_scale = 1.0;
     o->breakdown_tol = 0.0;
+    o->op_dma = -1;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -1314,6 +1315,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
+        o.op_dma < -1 || o.op_dma > 1 ||
         o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3 ||
         o.forward < 0 || o.forward > 1 || o.use_x0 < 0 || o.use_x0 > 1 || o.spectrum_gate < 0 ||
         !(o.p0_scale >= 0.0) || !std::isfinite(o.p0_scale) || !(o.breakdown_tol >= 0.0))

@@ -54,6 +54,7 @@ struct OpShape {
     int slabs = 1;  // i3-slabs, each running the pressure then the velocity kernel
     int fused = 0;  // K and A in one single-pass kernel (k_fused)
     int staged = 0;  // K and A velocity: all planes of a chunk at once (k_vel_all)
+    int dma = 1;     // streaming velocity kernel: staging by direct-to-LDS loads (k_vel_dma)
 };
 struct OpTuned {
     int nrhs = 0;

@@ -666,6 +666,227 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, lds);
 }
 
+// ---- velocity component C, planes staged by direct-to-LDS loads -------------------------
+// The streaming velocity kernel above keeps one plane in flight, in
+// registers: its waves wait on memory most of the time, and deeper register
+// prefetch costs more occupancy than it adds.  This variant stages the tile
+// and halo of each plane with buffer loads that write LDS directly
+// (buffer_load_dword ... lds, no registers), into a ring of three LDS
+// slots, so two planes are in flight.  The staged array is the same SR x SW
+// doubles as xs, filled as 2 SR SW dwords by consecutive lanes (lane l of
+// load s of wave w writes dword s NT + 64 w + l; lanes past the array write
+// into the slot's padding, so every load of a plane is issued by every
+// lane and the count per plane is fixed).  Each slot is its own __shared__
+// array so that the compiler's wait for the loads into one slot leaves the
+// later slots' loads in flight; a read of the thread's own element of the
+// slot before the barrier makes the compiler wait for this wave's loads of
+// that plane there, and the barrier (with only an LDS wait, no fence: a
+// fence would wait for every load in flight) then orders every wave's.  The
+// arithmetic per output is vel_component's, so the results agree bit for bit.
+template <int P, int C>
+constexpr int dma_dwords() {
+    constexpr int W1 = (C == 0) ? P : P - 1, W2 = (C == 1) ? P : P - 1;
+    return ((2 * (T2 + 2 * W2) * (T1 + 2 * W1) + NT - 1) / NT) * NT;
+}
+template <int P>
+constexpr int dma_slot_doubles() {
+    constexpr int a = dma_dwords<P, 0>(), b = dma_dwords<P, 1>(), c = dma_dwords<P, 2>();
+    return (a > b ? (a > c ? a : c) : (b > c ? b : c)) / 2;
+}
+typedef __attribute__((address_space(3))) void* lds_vptr;
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int P, int C>
+__device__ void vel_component_dma(const OpArgs& a, const Fields& out, const Fields& src,
+                                  double alpha, double beta, int r, int i0, int j0, int k0,
+                                  double* s0, double* s1, double* s2, double* pab) {
+    constexpr int W1 = (C == 0) ? P : P - 1;
+    constexpr int W2 = (C == 1) ? P : P - 1;
+    constexpr int W3 = (C == 2) ? P : P - 1;
+    constexpr int SW = T1 + 2 * W1, SR = T2 + 2 * W2;
+    constexpr int ND = dma_dwords<P, C>() / NT;  // dword loads per thread and plane
+    const int n1 = a.dims[C][0], n2 = a.dims[C][1], n3 = a.dims[C][2];
+    if (i0 >= n1 || j0 >= n2 || k0 >= n3) return;
+    const int kend = min(min(k0 + a.kchunk, a.klim), n3);
+    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int i = i0 + c, j = j0 + g;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // uniform
+    const bool act = i < n1 && j < n2;
+    const int mode = a.mode;
+    const bool mv = (mode == OP_MV);
+    const int nM = a.nM;
+    const double* wv = a.ws + (long long)r * a.ws_stride;
+    const long long plane = (long long)n1 * n2;
+    const long long wplane = (long long)nM * nM;
+    const uint32_t YB = 8u * (uint32_t)plane, WB = 8u * (uint32_t)wplane;
+    double* y = out.f[C] + (long long)r * out.stride[C];
+    const bool has_src = beta != 0.0;
+    const double* sv = has_src ? src.f[C] + (long long)r * src.stride[C] : y;
+    const uint32_t SB = has_src ? YB : 0u;
+    const uint32_t WBm = mv ? 0u : WB;
+    const uint32_t wo = act ? 8u * (i + nM * j) : OOB;
+    const uint32_t wo1 = act ? wo + (C == 0 ? 8u : C == 1 ? 8u * nM : 0u) : OOB;
+    const uint32_t yo = act ? 8u * (i + n1 * j) : OOB;
+    double* pa = pab;
+    double* pb = pab + SR * T1;
+    const double* t1a = a.bt.ptr[C == 0 ? (mv ? BM_N : BK_N) : BM_C];
+    const double* t1b = a.bt.ptr[C == 0 ? BM_N : BT_C];
+    const double* m2t = a.bt.ptr[C == 1 ? BM_N : BM_C];
+    const double* k2t = a.bt.ptr[C == 1 ? BK_N : BT_C];
+    const double* ta = a.bt.ptr[C == 2 ? (mv ? BM_N : BK_N) : BM_C];
+    const double* tb = a.bt.ptr[C == 2 ? BM_N : BT_C];
+    const double* x = a.u[C] + (long long)r * a.su;
+    // byte offsets of this thread's dwords of the staged plane (OOB outside
+    // the component and in the padding)
+    uint32_t so[ND];
+#pragma unroll
+    for (int s = 0; s < ND; ++s) {
+        const int d = threadIdx.x + s * NT;
+        const int idx = d >> 1;
+        const int rr = idx / SW, cc = idx - rr * SW;
+        const int jj = j0 - W2 + rr, ii = i0 - W1 + cc;
+        const bool ok = idx < SR * SW && jj >= 0 && jj < n2 && ii >= 0 && ii < n1;
+        so[s] = ok ? 8u * (jj * n1 + ii) + 4u * (d & 1) : OOB;
+    }
+    auto fetch_x = [&](int kk, double* slot) {
+        const bool kin = kk >= 0 && kk < n3;
+        const auto rx = make_rsrc(x + plane * (kin ? kk : 0), kin ? YB : 0u);
+        uint32_t* base = reinterpret_cast<uint32_t*>(slot) + 64 * wave;
+#pragma unroll
+        for (int s = 0; s < ND; ++s)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_vptr)(base + s * NT), 4, so[s], 0, 0,
+                                                     0);
+    };
+    auto fetch_out = [&](int k, double& w0, double& w1, double& sd) {
+        const bool kin = k >= 0 && k < n3;
+        const int kc = kin ? k : 0;
+        w0 = bload(make_rsrc(wv + wplane * kc, kin ? WBm : 0u), wo);
+        w1 = bload(make_rsrc(wv + wplane * (C == 2 ? kc + 1 : kc), kin ? WBm : 0u), wo1);
+        sd = bload(make_rsrc(sv + plane * kc, kin ? SB : 0u), yo);
+    };
+    double ca[2 * W1 + 1], cb[2 * W1 + 1], cm[2 * W2 + 1], ck[2 * W2 + 1];
+    load_band_row<W1>(t1a, i, i < n1, ca);
+    load_band_row<W1>(t1b, i, i < n1 && !mv, cb);
+    load_band_row<W2>(m2t, j, j < n2, cm);
+    load_band_row<W2>(k2t, j, j < n2 && !mv, ck);
+    Window<W3> wa, wb;
+    wa.clear();
+    wb.clear();
+    double fw0, fw1, fsd;
+    fetch_x(k0 - W3, s0);
+    fetch_x(k0 - W3 + 1, s1);
+    fetch_out(k0 - 2 * W3, fw0, fw1, fsd);
+    int pk = -1;
+    double pv = 0.0;
+    // one step: wait for plane kk (slot cur), start plane kk + 2 into the
+    // slot plane kk - 1 used, store the pending output, process plane kk
+    auto step = [&](int kk, double* cur, double* nxt) {
+        {
+            const double probe = cur[threadIdx.x];
+            asm volatile("" ::"v"(probe));
+        }
+        lds_barrier();
+        fetch_x(kk + 2, nxt);
+        bstore(make_rsrc(y + plane * (pk >= 0 ? pk : 0), pk >= 0 ? YB : 0u), yo, pv);
+        // direction 1 over rows g, g + T2, ... (unrolled: a loop would make the
+        // compiler wait for every load into LDS at its header)
+#pragma unroll
+        for (int m = 0; m < (SR + T2 - 1) / T2; ++m) {
+            const int rr = g + m * T2;
+            if (rr < SR) {
+                double sa = 0.0, sb = 0.0;
+#pragma unroll
+                for (int t = 0; t <= 2 * W1; ++t) {
+                    const double xv = cur[rr * SW + c + t];
+                    sa += ca[t] * xv;
+                    sb += cb[t] * xv;
+                }
+                pa[rr * T1 + c] = sa;
+                pb[rr * T1 + c] = sb;
+            }
+        }
+        lds_barrier();
+        double am = 0.0, ak = 0.0, bm = 0.0, bk = 0.0;
+#pragma unroll
+        for (int t = 0; t <= 2 * W2; ++t) {
+            const double va = pa[(g + t) * T1 + c], vb = pb[(g + t) * T1 + c];
+            am += cm[t] * va;
+            ak += ck[t] * va;
+            bm += cm[t] * vb;
+            bk += ck[t] * vb;
+        }
+        double ga, gb = 0.0;
+        if (mv) {
+            ga = am;
+        } else if (C == 0) {
+            ga = am + 2.0 * bk;
+            gb = 2.0 * bm;
+        } else if (C == 1) {
+            ga = ak + 2.0 * bm;
+            gb = 2.0 * am;
+        } else {
+            ga = am;
+            gb = 2.0 * (ak + bm);
+        }
+        wa.push(ga);
+        wb.push(gb);
+        const int k = kk - W3;
+        pk = (k >= k0 && k < kend) ? k : -1;
+        if (pk >= 0) {
+            double v;
+            if (mv) v = wa.dot(ta + k * (2 * W3 + 1));
+            else v = a.nu * (wa.dot(ta + k * (2 * W3 + 1)) + wb.dot(tb + k * (2 * W3 + 1))) + (fw0 - fw1);
+            pv = alpha * v + beta * fsd;
+        }
+        fetch_out(k + 1, fw0, fw1, fsd);
+    };
+    for (int kk = k0 - W3; kk < kend + W3; kk += 3) {
+        step(kk, s0, s2);
+        step(kk + 1, s1, s0);
+        step(kk + 2, s2, s1);
+    }
+    if (pk >= 0) bstore(make_rsrc(y + plane * pk, YB), yo, pv);
+    // no load into LDS may outlive the workgroup
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <int P>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>()))) void k_vel_dma(
+    OpArgs a, Fields out, Fields src, double alpha, double beta) {
+    constexpr int SL = dma_slot_doubles<P>();
+    __shared__ double s0[SL], s1[SL], s2[SL], pab[2 * (T2 + 2 * P) * T1];
+    int id = xcd_block(blockIdx.x, a.nblocks);
+    int comp;
+    if (a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
+    const int t1 = id % a.ntile1;
+    id /= a.ntile1;
+    const int t2 = id % a.ntile2;
+    id /= a.ntile2;
+    const int ch = id % a.nchunk;
+    id /= a.nchunk;
+    if (!a.comp_fast) {
+        comp = id % 3;
+        id /= 3;
+    }
+    const int r = id;
+    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    if (a.mode != OP_K && a.mode != OP_A && a.mode != OP_MV) {
+        // the coupling-only modes stage nothing
+        if (comp == 0) vel_component<P, 0>(a, out, src, alpha, beta, r, i0, j0, k0, pab);
+        else if (comp == 1) vel_component<P, 1>(a, out, src, alpha, beta, r, i0, j0, k0, pab);
+        else vel_component<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, pab);
+        return;
+    }
+    if (comp == 0) vel_component_dma<P, 0>(a, out, src, alpha, beta, r, i0, j0, k0, s0, s1, s2, pab);
+    else if (comp == 1) vel_component_dma<P, 1>(a, out, src, alpha, beta, r, i0, j0, k0, s0, s1, s2, pab);
+    else vel_component_dma<P, 2>(a, out, src, alpha, beta, r, i0, j0, k0, s0, s1, s2, pab);
+}
+
 // ---- velocity, all planes of a chunk at once (K and A) ------------------------------------
 // For small meshes, where k_vel's per-plane chain (stage, barrier, band,
 // barrier, band) repeated kc + 2w times sets its duration, this variant
@@ -1125,6 +1346,12 @@ void launch_vel(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, c
 }
 
 template <int P>
+void launch_vel_dma(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
+                    double alpha, double beta) {
+    hipLaunchKernelGGL(k_vel_dma<P>, grid, dim3(NT), 0, st, a, out, s, alpha, beta);
+}
+
+template <int P>
 void launch_fused(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
                   double alpha, double beta) {
     hipLaunchKernelGGL(k_fused<P>, grid, dim3(NT), 0, st, a, out, s, alpha, beta);
@@ -1148,6 +1375,9 @@ const PresLaunch pres_launch[PMAX + 1] = {nullptr,        nullptr,        launch
 const VelLaunch vel_launch[PMAX + 1] = {nullptr,       nullptr,       launch_vel<2>,
                                         launch_vel<3>, launch_vel<4>, launch_vel<5>,
                                         launch_vel<6>, launch_vel<7>, launch_vel<8>};
+const VelLaunch vel_dma_launch[PMAX + 1] = {nullptr,           nullptr,           launch_vel_dma<2>,
+                                            launch_vel_dma<3>, launch_vel_dma<4>, launch_vel_dma<5>,
+                                            launch_vel_dma<6>, launch_vel_dma<7>, launch_vel_dma<8>};
 
 template <int P, int KC>
 void launch_vel_all(dim3 grid, hipStream_t st, const OpArgs& a, const Fields& out, const Fields& s,
@@ -1242,6 +1472,7 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
     if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
     if (c->opts.op_fused >= 0) sh.fused = c->opts.op_fused;
     if (c->opts.op_staged >= 0) sh.staged = c->opts.op_staged;
+    sh.dma = c->opts.op_dma != 0;
     if (c->op_force.kchunk > 0) sh = c->op_force;
     if (c->p > FUSED_PMAX) sh.fused = 0;
     return sh;
@@ -1292,7 +1523,8 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * 3 * nrhs;
         dim3 grid(a.nblocks);
-        (vall ? vall : vel_launch[P])(grid, c->stream, a, out, s, alpha, beta);
+        (vall ? vall : (sh.dma ? vel_dma_launch[P] : vel_launch[P]))(grid, c->stream, a, out, s,
+                                                                     alpha, beta);
     };
     if (sh.fused && (mode == OP_K || mode == OP_A)) {
         a.kbase = 0;

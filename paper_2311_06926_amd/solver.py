@@ -44,7 +44,7 @@ class Solver:
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
                  forward="kronecker", use_x0=False, spectrum_gate=0, p0_scale=1.0,
-                 breakdown_tol=0.0, device=None):
+                 breakdown_tol=0.0, op_dma=-1, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -78,6 +78,7 @@ class Solver:
         o.spectrum_gate = int(spectrum_gate)
         o.p0_scale = float(p0_scale)
         o.breakdown_tol = float(breakdown_tol)
+        o.op_dma = int(op_dma)
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):

@@ -427,6 +427,14 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
         for a, b in zip(run(s), ref):
             assert torch.equal(a, b), (kc, order, slabs, staged)
         s.close()
+    # the streaming velocity kernel with register staging (op_dma = 0) against
+    # the default direct-to-LDS staging
+    for kc in sorted({1, 5, nM}):
+        s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=1, op_slabs=1,
+                   op_staged=0, op_dma=0)
+        for a, b in zip(run(s), ref):
+            assert torch.equal(a, b), (kc, "op_dma=0")
+        s.close()
     base.close()
 
 
