@@ -263,6 +263,46 @@ def cpu_baseline(p, q, k, E_full, gpu_iterations):
     }
 
 
+def cpu_baseline_configs(c1_gpu, c4_gpu):
+    """The oracle on one host core at the two other configurations the
+    measurement names: the 8^3, degree-2 cavity (q = 2, k = 1, MINRES to
+    1e-8, a full solve) and one right-hand side of the 48^3, degree-2 batch
+    (right-hand side 0: 16 seeded Fourier modes per component and its lid
+    speed; q = 2, k = 1; FGMRES(50); three iterations timed and scaled to
+    the GPU's iteration count for that right-hand side).  P_{V,0} by the
+    oracle's einsum fast-diagonalisation tier; assembly excluded."""
+    from threadpoolctl import threadpool_limits
+    from oracle.cases import cavity
+    from oracle.krylov import fgmres, minres
+    from oracle.precond import FastDiagBase, HyperPower
+    from paper_2311_06926_amd import synth
+    out = {}
+    with threadpool_limits(limits=1):
+        S, b = cavity(8, 2)
+        H = HyperPower(S, 2, 1, base=FastDiagBase(S))
+        t0 = time.perf_counter()
+        r = minres(lambda v: S.K @ v, H.apply, b, tol=1e-8)
+        t1 = time.perf_counter()
+        out["C1"] = {"E": 8, "p": 2, "N": S.N, "oracle_iterations": r.iters,
+                     "oracle_ms": 1e3 * (t1 - t0), "oracle_dofs": S.N / (t1 - t0),
+                     "gpu": c1_gpu,
+                     "sample": "one full oracle MINRES solve, q=2, k=1, one core"}
+        modes, U = synth.body_force_modes(0)
+        S, b = cavity(48, 2, U=U, modes=modes)
+        H = HyperPower(S, 2, 1, base=FastDiagBase(S))
+        t0 = time.perf_counter()
+        fgmres(lambda v: S.K @ v, lambda v, j: H.apply(v), b, tol=0.0, restart=50, maxit=3)
+        t1 = time.perf_counter()
+        t_it = (t1 - t0) / 3
+        its = c4_gpu.get("iterations") if c4_gpu else None
+        out["C4_one_rhs"] = {
+            "E": 48, "p": 2, "N": S.N, "oracle_seconds_per_iteration": t_it,
+            "oracle_dofs": S.N / (t_it * its) if its else None, "gpu": c4_gpu,
+            "sample": ("3 oracle FGMRES(50) iterations on right-hand side 0 of the batch, "
+                       "q=2, k=1, one core, scaled to the GPU's iteration count")}
+    return out
+
+
 def sec51_leg(E, p, hbm_peak, fp64_peak):
     """The operator study of Sec. 5.1 (eq. hyperpower_scaling) at E^3: the
     velocity block P_{V,k}^{-1} for k = 0, 1, 2 (q = 2) and the operator A,
@@ -618,7 +658,8 @@ def main():
         _, ibg, tbg = timed_solve(sg, bb, 2)
         batched = {"rhs": R, "N": sb.N, "ms": 1e3 * tb, "iterations": ib.iterations,
                    "true_relres": ib.true_relres, "dofs": R * sb.N / tb,
-                   "single_rhs_ms": 1e3 * t1s, "speedup_vs_sequential": R * t1s / tb,
+                   "single_rhs_ms": 1e3 * t1s, "single_rhs_iterations": i1.iterations,
+                   "speedup_vs_sequential": R * t1s / tb,
                    "fp64_batched_ms": 1e3 * tb64, "speedup_vs_fp64_batched": tb64 / tb,
                    "graph_ms": 1e3 * tbg, "graph_iterations": ibg.iterations}
         log(f"[bench] batched: {batched}")
@@ -703,6 +744,16 @@ def main():
     if not args.no_cpu:
         log("[bench] cpu baseline (oracle) ...")
         cpu = cpu_baseline(p, q, k, E, info.iterations)
+        # the 8^3 degree-2 cavity on the GPU (median of 5 solves) beside the
+        # oracle there and at one right-hand side of the batch
+        s8 = Solver(8, 2, 1.0, order=2, iters=1)
+        b8 = s8.build_rhs([1.0])
+        _, i8, t8 = timed_solve(s8, b8, 5)
+        s8.close()
+        c1_gpu = {"iterations": i8.iterations, "ms": 1e3 * t8, "dofs": s8.N / t8}
+        c4_gpu = ({"iterations": batched["single_rhs_iterations"], "ms": batched["single_rhs_ms"],
+                   "precision": "fp32 P_k, FP64 FGMRES"} if batched else None)
+        cpu["other_configs"] = cpu_baseline_configs(c1_gpu, c4_gpu)
         log(f"[bench] cpu: {cpu}")
 
     out = {
