@@ -438,6 +438,26 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
     base.close()
 
 
+@pytest.mark.parametrize("E,p", [(4, 5), (3, 6), (5, 7), (3, 8)])
+def test_direct_to_lds_velocity_kernel_high_degree(dev, E, p):
+    """Degrees 5-8 (the streaming kernels only): the velocity kernel staging
+    through direct-to-LDS loads (op_dma = 1, the default) against register
+    staging (op_dma = 0), bit for bit, for K, A and M_V at two i3-chunk
+    lengths."""
+    from paper_2311_06926_amd.solver import Solver
+    say(f"[shapes] direct-to-LDS velocity kernel E={E} p={p}")
+    for kc in (1, 3):
+        a = Solver(E, p, 1.1, autotune=False, op_kchunk=kc, op_staged=0, op_dma=1)
+        b = Solver(E, p, 1.1, autotune=False, op_kchunk=kc, op_staged=0, op_dma=0)
+        x = torch.from_numpy(synth.random_vector(a.N, seed=E * p + kc)).to(dev)
+        u = x[:a.nV].contiguous()
+        assert torch.equal(a.apply_K(x), b.apply_K(x)), kc
+        assert torch.equal(a.apply_A(u), b.apply_A(u)), kc
+        assert torch.equal(a.apply_MV(u), b.apply_MV(u)), kc
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("E,p", [(3, 2), (8, 3), (13, 2), (4, 4), (33, 3)])
 def test_single_pass_operator_matches(dev, E, p):
     """The single-pass kernel (op_fused=1: D_c^T M_q z applied as a Kronecker
