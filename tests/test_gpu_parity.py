@@ -181,8 +181,6 @@ def test_base_preconditioner(dev, E, p):
 def test_hyperpower(dev, E, p, q, k, variant):
     from oracle.precond import HyperPower
     from paper_2311_06926_amd.solver import Solver
-    if (E, p) == (13, 2) and q ** k > 4:
-        pytest.skip("large q^k only on the small meshes (oracle time)")
     say(f"[parity] hyperpower E={E} p={p} q={q} k={k} {variant}")
     S = oracle_sys(E, p)
     H = HyperPower(S, q, k, variant=variant)
