@@ -750,21 +750,29 @@ __device__ void vel_component_dma(const OpArgs& a, const Fields& out, const Fiel
         const bool ok = idx < SR * SW && jj >= 0 && jj < n2 && ii >= 0 && ii < n1;
         so[s] = ok ? 8u * (jj * n1 + ii) + 4u * (d & 1) : OOB;
     }
-    auto fetch_x = [&](int kk, double* slot) {
+    // The planes a step touches, as byte addresses advanced by one plane per
+    // step (one 64-bit add each instead of a product per plane); a plane
+    // outside the field gets a zero-size resource, so its address, which may
+    // lie outside the field, is never dereferenced.
+    const uint64_t PY = 8ull * (uint64_t)plane, PW = 8ull * (uint64_t)wplane;
+    auto addr = [](const double* base, long long elems) {
+        return reinterpret_cast<uint64_t>(base) + (uint64_t)(elems * 8);
+    };
+    auto ptr = [](uint64_t a) { return reinterpret_cast<const double*>(a); };
+    auto fetch_x = [&](int kk, uint64_t ax, double* slot) {
         const bool kin = kk >= 0 && kk < n3;
-        const auto rx = make_rsrc(x + plane * (kin ? kk : 0), kin ? YB : 0u);
+        const auto rx = make_rsrc(ptr(ax), kin ? YB : 0u);
         uint32_t* base = reinterpret_cast<uint32_t*>(slot) + 64 * wave;
 #pragma unroll
         for (int s = 0; s < ND; ++s)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_vptr)(base + s * NT), 4, so[s], 0, 0,
                                                      0);
     };
-    auto fetch_out = [&](int k, double& w0, double& w1, double& sd) {
+    auto fetch_out = [&](int k, uint64_t aw, uint64_t as, double& w0, double& w1, double& sd) {
         const bool kin = k >= 0 && k < n3;
-        const int kc = kin ? k : 0;
-        w0 = bload(make_rsrc(wv + wplane * kc, kin ? WBm : 0u), wo);
-        w1 = bload(make_rsrc(wv + wplane * (C == 2 ? kc + 1 : kc), kin ? WBm : 0u), wo1);
-        sd = bload(make_rsrc(sv + plane * kc, kin ? SB : 0u), yo);
+        w0 = bload(make_rsrc(ptr(aw), kin ? WBm : 0u), wo);
+        w1 = bload(make_rsrc(ptr(C == 2 ? aw + PW : aw), kin ? WBm : 0u), wo1);
+        sd = bload(make_rsrc(ptr(as), kin ? SB : 0u), yo);
     };
     double ca[2 * W1 + 1], cb[2 * W1 + 1], cm[2 * W2 + 1], ck[2 * W2 + 1];
     load_band_row<W1>(t1a, i, i < n1, ca);
@@ -775,11 +783,18 @@ __device__ void vel_component_dma(const OpArgs& a, const Fields& out, const Fiel
     wa.clear();
     wb.clear();
     double fw0, fw1, fsd;
-    fetch_x(k0 - W3, s0);
-    fetch_x(k0 - W3 + 1, s1);
-    fetch_out(k0 - 2 * W3, fw0, fw1, fsd);
+    fetch_x(k0 - W3, addr(x, plane * (k0 - W3)), s0);
+    fetch_x(k0 - W3 + 1, addr(x, plane * (k0 - W3 + 1)), s1);
+    fetch_out(k0 - 2 * W3, addr(wv, wplane * (k0 - 2 * W3)), addr(sv, plane * (k0 - 2 * W3)), fw0,
+              fw1, fsd);
     int pk = -1;
     double pv = 0.0;
+    // at the first step kk = k0 - W3: x plane kk + 2, output plane kk - W3 - 1,
+    // coupling and source planes kk - W3 + 1
+    uint64_t ax = addr(x, plane * (k0 - W3 + 2));
+    uint64_t ay = addr(y, plane * (k0 - 2 * W3 - 1));
+    uint64_t aw = addr(wv, wplane * (k0 - 2 * W3 + 1));
+    uint64_t as = addr(sv, plane * (k0 - 2 * W3 + 1));
     // one step: wait for plane kk (slot cur), start plane kk + 2 into the
     // slot plane kk - 1 used, store the pending output, process plane kk
     auto step = [&](int kk, double* cur, double* nxt) {
@@ -788,8 +803,11 @@ __device__ void vel_component_dma(const OpArgs& a, const Fields& out, const Fiel
             asm volatile("" ::"v"(probe));
         }
         lds_barrier();
-        fetch_x(kk + 2, nxt);
-        bstore(make_rsrc(y + plane * (pk >= 0 ? pk : 0), pk >= 0 ? YB : 0u), yo, pv);
+        fetch_x(kk + 2, ax, nxt);
+        ax += PY;
+        // the pending output (plane kk - W3 - 1, if it is one)
+        bstore(make_rsrc(ptr(ay), pk >= 0 ? YB : 0u), yo, pv);
+        ay += PY;
         // direction 1 over rows g, g + T2, ... (unrolled: a loop would make the
         // compiler wait for every load into LDS at its header)
 #pragma unroll
@@ -840,7 +858,9 @@ __device__ void vel_component_dma(const OpArgs& a, const Fields& out, const Fiel
             else v = a.nu * (wa.dot(ta + k * (2 * W3 + 1)) + wb.dot(tb + k * (2 * W3 + 1))) + (fw0 - fw1);
             pv = alpha * v + beta * fsd;
         }
-        fetch_out(k + 1, fw0, fw1, fsd);
+        fetch_out(k + 1, aw, as, fw0, fw1, fsd);
+        aw += PW;
+        as += PY;
     };
     for (int kk = k0 - W3; kk < kend + W3; kk += 3) {
         step(kk, s0, s2);
