@@ -198,15 +198,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
         od[s] = (ok && jj >= 1) ? 8u * (ii + nM * (jj - 1)) : OOB;
         oe[s] = ok ? 8u * (ii + nM * jj) : OOB;
     }
-    // raw values of plane kk (zero outside the mesh)
-    auto fetch = [&](int kk, double (&v)[NS][6]) {
+    // Plane addresses advanced by one plane per step (one 64-bit add each
+    // instead of a product per plane); a plane outside the mesh gets a
+    // zero-size resource, so its address is never dereferenced.
+    auto addr = [](const double* base, long long elems) {
+        return reinterpret_cast<uint64_t>(base) + (uint64_t)(elems * 8);
+    };
+    auto ptr = [](uint64_t a) { return reinterpret_cast<const double*>(a); };
+    const uint64_t Q1 = 8ull * (uint64_t)P1, Q2 = 8ull * (uint64_t)P2, Q3 = 8ull * (uint64_t)P3;
+    // raw values of plane kk (zero outside the mesh) from the plane addresses
+    // a[0..3] of u1, u2, u3 and p at kk
+    auto fetch = [&](int kk, const uint64_t (&ad)[4], double (&v)[NS][6]) {
         const bool kin = kk >= 0 && kk < nM;
         const bool k3in = kk >= 0 && kk < nN;
-        const int kc = kin ? kk : 0, k3 = k3in ? kk : 0;
-        const auto r1 = make_rsrc(u1 + P1 * kc, kin ? B1 : 0u);
-        const auto r2 = make_rsrc(u2 + P2 * kc, kin ? B2 : 0u);
-        const auto r3 = make_rsrc(u3 + P3 * k3, k3in ? B3 : 0u);
-        const auto rp = make_rsrc(pp + P3 * kc, kin ? BP : 0u);
+        const auto r1 = make_rsrc(ptr(ad[0]), kin ? B1 : 0u);
+        const auto r2 = make_rsrc(ptr(ad[1]), kin ? B2 : 0u);
+        const auto r3 = make_rsrc(ptr(ad[2]), k3in ? B3 : 0u);
+        const auto rp = make_rsrc(ptr(ad[3]), kin ? BP : 0u);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             v[s][0] = bload(r1, oa[s]);
@@ -224,17 +232,33 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     Window<W> wg, wz;
     wg.clear();
     wz.clear();
+    auto planes = [&](int kk, uint64_t (&ad)[4]) {
+        ad[0] = addr(u1, P1 * kk);
+        ad[1] = addr(u2, P2 * kk);
+        ad[2] = addr(u3, P3 * kk);
+        ad[3] = addr(pp, P3 * kk);
+    };
     double buf[PF][NS][6], a3prev[NS];
     {
         double t[NS][6];
-        fetch(k0 - W - 1, t);
+        uint64_t ad[4];
+        planes(k0 - W - 1, ad);
+        fetch(k0 - W - 1, ad, t);
 #pragma unroll
         for (int s = 0; s < NS; ++s) a3prev[s] = t[s][4];
     }
 #pragma unroll
-    for (int d = 0; d < PF; ++d) fetch(k0 - W + d, buf[d]);
+    for (int d = 0; d < PF; ++d) {
+        uint64_t ad[4];
+        planes(k0 - W + d, ad);
+        fetch(k0 - W + d, ad, buf[d]);
+    }
     int pk = -1;  // plane of the pending output (none yet)
     double py = 0.0, pw = 0.0;
+    // at the first step kk = k0 - W: input plane kk + PF, pending output kk - W - 1
+    uint64_t an[4];
+    planes(k0 - W + PF, an);
+    uint64_t ayo = addr(ypr, P3 * (k0 - 2 * W - 1)), awo = addr(wv, P3 * (k0 - 2 * W - 1));
     // one step: consume plane kk, store the pending output, refill the
     // registers with plane kk + PF, then process plane kk
     auto step = [&](int kk, double (&b)[NS][6]) {
@@ -250,11 +274,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
         }
         {
             const bool on = pk >= 0;
-            const int kc = on ? pk : 0;
-            bstore(make_rsrc(ypr + P3 * kc, (on && need_g) ? 8u * (uint32_t)P3 : 0u), oo, py);
-            bstore(make_rsrc(wv + P3 * kc, (on && need_z) ? 8u * (uint32_t)P3 : 0u), oo, pw);
+            bstore(make_rsrc(ptr(ayo), (on && need_g) ? 8u * (uint32_t)P3 : 0u), oo, py);
+            bstore(make_rsrc(ptr(awo), (on && need_z) ? 8u * (uint32_t)P3 : 0u), oo, pw);
+            ayo += Q3;
+            awo += Q3;
         }
-        fetch(kk + PF, b);
+        fetch(kk + PF, an, b);
+        an[0] += Q1;
+        an[1] += Q2;
+        an[2] += Q3;
+        an[3] += Q3;
         __syncthreads();
         for (int rr = g; rr < SR; rr += T2) {
             double sg = 0.0, sz = 0.0;
