@@ -64,7 +64,13 @@ typedef enum {
     HP_ENAN = -7
 } hp_status;
 
-/* Precision of the preconditioner (the Krylov method always runs in FP64). */
+/* Precision of the preconditioner's fast-diagonalisation products (the
+ * Krylov method always runs in FP64): FP64; FP32 (FP32 MFMA, FP32 storage of
+ * the intermediates); split BF16 (each FP32 operand as hi + lo BF16 halves,
+ * three BF16 MFMA products accumulated in FP32: about 16 significant bits,
+ * products good to ~1e-5 relative).  Split BF16 runs in the 16-wave and
+ * row-block plans (odd fd_plan codes, no 2x2 blocks); the 4-wave plans and
+ * the mode-product GEMMs take FP32 products for it. */
 enum { HP_PREC_FP64 = 0, HP_PREC_FP32 = 1, HP_PREC_BF16X3 = 2 };
 /* Krylov method. MINRES needs an exactly symmetric preconditioner (FP64). */
 enum { HP_MINRES = 0, HP_FGMRES = 1 };

@@ -564,8 +564,10 @@ __device__ __forceinline__ void tile_gemm_2x2(const T* G0, const T* G1, int ldg,
 // Split-BF16 ("bf16x3") product for FP32 data: each operand is written as
 // hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even), and
 // A B ~= A_hi B_hi + A_hi B_lo + A_lo B_hi, three 16x16x16 BF16 MFMAs per
-// 16-wide k step accumulated in FP32 (the lo*lo term is below FP32
-// rounding of the sum and is dropped).  A lane supplies the four values
+// 16-wide k step accumulated in FP32.  hi + lo keeps 16 significant bits of
+// each operand (relative error up to 2^-17), so a product is good to about
+// 1e-5 relative, not to FP32 rounding; the dropped lo*lo term is of the
+// same order.  A lane supplies the four values
 // k = 16c + 4 lk + j, j < 4, of both operands (the instruction only needs
 // the same k for both); result rows are 4 (l/16) + i as for FP32.  Operand
 // roles and layouts as in tile_gemm.

@@ -522,6 +522,17 @@ def test_fd_plans_agree(dev, E, p):
         y32 = y32g.cpu().numpy()
         assert np.abs(y32 - y).max() / np.abs(y).max() < 1e-5, plan
         s32.close()
+        # split BF16 where the plan takes it (hi + lo BF16 halves keep 16
+        # significant bits per operand, so each product is good to ~2^-16
+        # relative and P_0's six contractions to ~1e-5; the 4-wave plans run
+        # FP32 products for this precision: FP32-level gaps)
+        s16 = Solver(E, p, nu, autotune=False, fd_plan=plan, precision="bf16x3", krylov="fgmres")
+        if s16.tuning(1)["fd_plan"][2] == plan:
+            y16 = s16.apply_P0(x).cpu().numpy()
+            e16 = np.abs(y16 - y).max() / np.abs(y).max()
+            say(f"[shapes]   plan {plan}: split-BF16 gap {e16:.1e}")
+            assert e16 < (2e-4 if plan & 1 else 1e-5), plan
+        s16.close()
         fam = 2 if plan == 8 else plan & 1
         if fam in first:
             assert torch.equal(yg, first[fam][0]), plan
