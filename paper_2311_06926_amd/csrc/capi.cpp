@@ -248,20 +248,21 @@ hipError_t apply_Spcg(hp_ctx* c, int q, const Fields& t, const Fields& out, int 
     if ((e = vec_zero(st, n, y)) != hipSuccess) return e;
     if ((e = apply_PV(c, q, lv, F(r), F(z), nrhs, prec)) != hipSuccess) return e;
     if ((e = vec_copy(st, n, z, pv)) != hipSuccess) return e;
+    const int cnt = (int)vec_dot_partial_count(nV);
     if ((e = vec_dot_partials(st, nV, nV, r, z, nrhs, ex->cgpart)) != hipSuccess) return e;
-    if ((e = cg_init(st, ex->cgsc, ex->cgpart, nrhs)) != hipSuccess) return e;
+    if ((e = cg_init(st, ex->cgsc, ex->cgpart, cnt, nrhs)) != hipSuccess) return e;
     for (int j = 0; j < c->opts.schur_pcg_iters; ++j) {
         if ((e = launch_operator(c, OP_A, F(pv), F(qv), 1.0, 0.0, nullptr, nrhs)) != hipSuccess)
             return e;
         if ((e = vec_dot_partials(st, nV, nV, pv, qv, nrhs, ex->cgpart)) != hipSuccess) return e;
-        if ((e = cg_alpha(st, ex->cgsc, ex->cgpart, cx, cr, nrhs)) != hipSuccess) return e;
+        if ((e = cg_alpha(st, ex->cgsc, ex->cgpart, cnt, cx, cr, nrhs)) != hipSuccess) return e;
         const double* xy[2] = {y, pv};
         if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xy, cx, y)) != hipSuccess) return e;
         const double* xr[2] = {r, qv};
         if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xr, cr, r)) != hipSuccess) return e;
         if ((e = apply_PV(c, q, lv, F(r), F(z), nrhs, prec)) != hipSuccess) return e;
         if ((e = vec_dot_partials(st, nV, nV, r, z, nrhs, ex->cgpart)) != hipSuccess) return e;
-        if ((e = cg_beta(st, ex->cgsc, ex->cgpart, cp, c->opts.schur_pcg_tol, nrhs)) != hipSuccess)
+        if ((e = cg_beta(st, ex->cgsc, ex->cgpart, cnt, cp, c->opts.schur_pcg_tol, nrhs)) != hipSuccess)
             return e;
         const double* xp[2] = {z, pv};
         if ((e = vec_lincomb(st, nV, nV, nrhs, 2, xp, cp, pv)) != hipSuccess) return e;
@@ -491,7 +492,7 @@ hipError_t minres_a(hp_ctx* c, const MinresBufs& b, int nrhs, int cur) {
     if ((e = launch_forward(c, b.z, b.Kz, nrhs)) != hipSuccess) return e;
     if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
     return minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur,
-                    Partials{p0, vec_dot_partial_count()});
+                    Partials{p0, vec_dot_partial_count(N)});
 }
 PkDot minres_pk_dot(hp_ctx* c, const MinresBufs& b) {
     Extra* ex = extra_of(c);
@@ -619,7 +620,8 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     HIPCHK(vec_dot_partials(c->stream, N, N, b0.z, b0.v, nrhs, ex->mpart));
     // iteration it reads the state msc[it & 1]: the first reads msc[1]
     MinresScalars* s1 = ex->msc + c->opts.max_rhs;
-    HIPCHK(minres_init(c->stream, s1, ex->mpart, warm ? ref_part : nullptr, tol, nrhs));
+    HIPCHK(minres_init(c->stream, s1, ex->mpart, warm ? ref_part : nullptr,
+                       (int)vec_dot_partial_count(N), tol, nrhs));
     const size_t sbytes = sizeof(MinresScalars) * nrhs;
     auto all_done = [&](const MinresScalars* h) {
         for (int r = 0; r < nrhs; ++r)
@@ -691,19 +693,20 @@ hipError_t fgmres_iteration(hp_ctx* c, int j, int m, int nrhs, double tol, FgSca
     double* w = Zb + (long long)m * V;
     double* Vj = Vb + (long long)j * V;
     double* Zj = Zb + (long long)j * V;
+    const int cnt = (int)vec_dot_partial_count(N);
     hipError_t e;
     if ((e = apply_Pk(c, c->opts.order, c->opts.iters, Vj, Zj, nrhs)) != hipSuccess) return e;
     if ((e = launch_forward(c, Zj, w, nrhs)) != hipSuccess) return e;
     for (int pass = 0; pass < 2; ++pass) {
         if ((e = vec_multidot_partials(c->stream, N, N, Vb, V, j + 1, w, nrhs, ex->fpart)) != hipSuccess)
             return e;
-        if ((e = fg_h(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fhc, j, pass, m, nrhs)) != hipSuccess)
+        if ((e = fg_h(c->stream, ex->fsc, ex->fpart, cnt, ex->fH, ex->fhc, j, pass, m, nrhs)) != hipSuccess)
             return e;
         if ((e = vec_sub_combo(c->stream, N, N, Vb, V, j + 1, ex->fhc, m + 1, nrhs, w)) != hipSuccess)
             return e;
     }
     if ((e = vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart)) != hipSuccess) return e;
-    if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol,
+    if ((e = fg_rot(c->stream, ex->fsc, ex->fpart, cnt, ex->fH, ex->fcs, ex->fsn, ex->fg, ex->fvs, tol,
                     c->opts.breakdown_tol, j, m, nrhs, mirror)) != hipSuccess)
         return e;
     const double* xs[1] = {w};
@@ -776,7 +779,7 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     double* w = Zb + (long long)m * V;
     const size_t sbytes = sizeof(FgScalars) * nrhs;
     HIPCHK(vec_dot_partials(c->stream, N, N, b, b, nrhs, ex->fpart));
-    HIPCHK(fg_init(c->stream, ex->fsc, ex->fpart, nrhs));
+    HIPCHK(fg_init(c->stream, ex->fsc, ex->fpart, (int)vec_dot_partial_count(N), nrhs));
     // x_0 = 0, or the x passed in (warm start): every cycle starts from b - K x
     if (!c->opts.use_x0) HIPCHK(vec_zero(c->stream, Vn, x));
     auto all = [&](const FgScalars* h, bool active) {
@@ -793,7 +796,8 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         HIPCHK(launch_forward(c, x, w, nrhs));
         HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
         HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
-        HIPCHK(fg_begin(c->stream, ex->fsc, ex->fpart, ex->fg, ex->fvs, m, nrhs));
+        HIPCHK(fg_begin(c->stream, ex->fsc, ex->fpart, (int)vec_dot_partial_count(N), ex->fg,
+                        ex->fvs, m, nrhs));
         {
             const double* xs[1] = {w};
             HIPCHK(vec_lincomb(c->stream, N, N, nrhs, 1, xs, ex->fvs, Vb));
@@ -821,7 +825,7 @@ hp_status fgmres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
         HIPCHK(launch_forward(c, x, w, nrhs));
         HIPCHK(vec_axpby(c->stream, Vn, 1.0, b, -1.0, w));
         HIPCHK(vec_dot_partials(c->stream, N, N, w, w, nrhs, ex->fpart));
-        HIPCHK(fg_check(c->stream, ex->fsc, ex->fpart, tol, nrhs));
+        HIPCHK(fg_check(c->stream, ex->fsc, ex->fpart, (int)vec_dot_partial_count(N), tol, nrhs));
         HIPCHK(hipMemcpyAsync(ex->hfsc[0], ex->fsc, sbytes, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         done = all(ex->hfsc[0], false);

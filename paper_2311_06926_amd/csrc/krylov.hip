@@ -11,7 +11,11 @@ namespace hp {
 namespace {
 
 constexpr int VT = 256;
-constexpr int DOT_BLOCKS = 240;  // partial sums per (pair, rhs)
+// partial sums per (pair, rhs), one per chunk of the vector: 480 chunks from
+// 2^19 entries on (FGMRES at 64^3: 11.9 -> 11.0 ms, the FP32 preconditioner
+// 10.6 -> 9.7 ms), 240 below (MINRES at 32^3 is 3% slower with 480)
+constexpr int DOT_BLOCKS_MAX = 480;
+inline int dot_blocks(long long n) { return n >= (1LL << 19) ? DOT_BLOCKS_MAX : DOT_BLOCKS_MAX / 2; }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b,
                         double* __restrict__ y) {
@@ -96,47 +100,86 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-// partial[(r*npair + q)*DOT_BLOCKS + b] = sum over block b's chunk of x_q . y
-// (x_q = X + q*xstride, one y per rhs).  A workgroup takes DOT_QB pairs of
-// one chunk, so y is read once per DOT_QB pairs; each pair's sum runs in the
-// same order as with one pair per workgroup.
+// partial[(r*npair + q)*nb + b] = sum over chunk b of x_q . y (x_q = X +
+// q*xstride, one y per rhs; nb = dot_blocks(n) chunks of the vector).  A
+// workgroup takes DOT_QB pairs of CPB consecutive chunks, so y is read once
+// per DOT_QB pairs; each chunk's sum runs in the same order whatever the
+// launch shape (a batch gives the same partials as its right-hand sides one
+// at a time).
 constexpr int DOT_QB = 8;
-static_assert(DOT_BLOCKS <= VT, "one partial per thread in the block sums of the partials");
+template <int CPB>
 __global__ void k_dot_partial(long long n, long long ld, const double* X, long long xstride,
-                              int npair, const double* Y, double* partial) {
-    __shared__ double sh[VT / 64];
+                              int npair, const double* Y, int nb, double* partial) {
+    __shared__ double sh[VT / 64][CPB * DOT_QB];
     const int r = blockIdx.z, q0 = blockIdx.y * DOT_QB;
     const int nq = min(DOT_QB, npair - q0);
     const double* x = X + (long long)q0 * xstride + (long long)r * ld;
     const double* y = Y + (long long)r * ld;
-    const long long chunk = (n + DOT_BLOCKS - 1) / DOT_BLOCKS;
-    const long long lo = (long long)blockIdx.x * chunk;
-    const long long hi = min(n, lo + chunk);
-    double s[DOT_QB];
+    const long long chunk = (n + nb - 1) / nb;
+    long long lo[CPB], hi[CPB];
 #pragma unroll
-    for (int qq = 0; qq < DOT_QB; ++qq) s[qq] = 0.0;
-    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        const double yv = y[i];
-#pragma unroll
-        for (int qq = 0; qq < DOT_QB; ++qq)
-            if (qq < nq) s[qq] += x[qq * xstride + i] * yv;
+    for (int c = 0; c < CPB; ++c) {
+        lo[c] = (long long)(blockIdx.x * CPB + c) * chunk;
+        hi[c] = min(n, lo[c] + chunk);
     }
+    double s[CPB][DOT_QB];
 #pragma unroll
-    for (int qq = 0; qq < DOT_QB; ++qq) {
-        if (qq >= nq) break;  // uniform over the workgroup
-        const double t = block_sum(s[qq], sh);
-        if (threadIdx.x == 0) partial[((long long)r * npair + q0 + qq) * DOT_BLOCKS + blockIdx.x] = t;
+    for (int c = 0; c < CPB; ++c)
+#pragma unroll
+        for (int qq = 0; qq < DOT_QB; ++qq) s[c][qq] = 0.0;
+    // the chunks side by side, each summed in its own order: thread t takes
+    // elements t, t + VT, ... of every chunk
+    for (long long k = threadIdx.x; k < chunk; k += blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) {
+            const long long i = lo[c] + k;
+            if (i < hi[c]) {
+                const double yv = y[i];
+#pragma unroll
+                for (int qq = 0; qq < DOT_QB; ++qq)
+                    if (qq < nq) s[c][qq] += x[qq * xstride + i] * yv;
+            }
+        }
     }
+    // all sums of the workgroup in one reduction: wave trees, then thread v
+    // adds the waves' results of sum v in wave order (as block_sum does)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < CPB; ++c)
+#pragma unroll
+        for (int qq = 0; qq < DOT_QB; ++qq) {
+            if (qq >= nq) break;  // uniform over the workgroup
+            const double v = wave_sum(s[c][qq]);
+            if (lane == 0) sh[wave][c * DOT_QB + qq] = v;
+        }
+    __syncthreads();
+    const int v = threadIdx.x;
+    if (v < CPB * DOT_QB && v % DOT_QB < nq) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][v];
+        const int b = blockIdx.x * CPB + v / DOT_QB;
+        partial[((long long)r * npair + q0 + v % DOT_QB) * nb + b] = t;
+    }
+}
+// k_dot_partial over npair pairs and nrhs right-hand sides, one chunk per
+// workgroup (two chunks per workgroup for batches, measured: 48^3 x 32
+// FGMRES 102.5 -> 108 ms; the partials would be the same)
+inline void dot_partial_launch(hipStream_t s, long long n, long long ld, const double* X,
+                               long long xstride, int npair, const double* Y, int nrhs,
+                               double* partial) {
+    const unsigned groups = (unsigned)((npair + DOT_QB - 1) / DOT_QB);
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(k_dot_partial<1>, dim3(nb, groups, nrhs), dim3(VT), 0, s, n, ld, X,
+                       xstride, npair, Y, nb, partial);
 }
 
 __global__ void k_dot_final(const double* partial, int count, double* out) {
     __shared__ double sh[VT / 64];
-    const long long base = (long long)blockIdx.x * DOT_BLOCKS;
+    const long long base = (long long)blockIdx.x * count;
     double s = 0.0;
-    for (int i = threadIdx.x; i < DOT_BLOCKS; i += blockDim.x) s += partial[base + i];
+    for (int i = threadIdx.x; i < count; i += blockDim.x) s += partial[base + i];
     s = block_sum(s, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
-    (void)count;
 }
 
 // y_r -= sum_{q<nq} h[r*hld + q] * V_q   (V_q = V + q*vstride)
@@ -233,13 +276,13 @@ hipError_t vec_lincomb(hipStream_t s, long long n, long long ld, int nrhs, int n
 hipError_t vec_multidot_async(hipStream_t s, long long n, long long ld, const double* X,
                               long long xstride, int npair, const double* Y, int nrhs,
                               double* partial, double* dout) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, (npair + DOT_QB - 1) / DOT_QB, nrhs), dim3(VT), 0, s, n, ld, X,
-                       xstride, npair, Y, partial);
-    hipLaunchKernelGGL(k_dot_final, dim3(npair * nrhs), dim3(VT), 0, s, partial, DOT_BLOCKS, dout);
+    dot_partial_launch(s, n, ld, X, xstride, npair, Y, nrhs, partial);
+    hipLaunchKernelGGL(k_dot_final, dim3(npair * nrhs), dim3(VT), 0, s, partial, dot_blocks(n),
+                       dout);
     return hipGetLastError();
 }
 
-size_t vec_partial_doubles(int npair, int nrhs) { return (size_t)npair * nrhs * DOT_BLOCKS; }
+size_t vec_partial_doubles(int npair, int nrhs) { return (size_t)npair * nrhs * DOT_BLOCKS_MAX; }
 
 hipError_t vec_sub_combo(hipStream_t s, long long n, long long ld, const double* V,
                          long long vstride, int nq, const double* dh, int hld, int nrhs,
@@ -289,9 +332,9 @@ hipError_t vec_dots(hp_ctx* c, long long n, long long ld, const double* x, const
 namespace hp {
 namespace {
 
-__device__ double sum_partials(const double* part, int q) {
+__device__ double sum_partials(const double* part, int count, int q) {
     double s = 0.0;
-    for (int i = 0; i < DOT_BLOCKS; ++i) s += part[(long long)q * DOT_BLOCKS + i];
+    for (int i = 0; i < count; ++i) s += part[(long long)q * count + i];
     return s;
 }
 
@@ -300,12 +343,12 @@ __device__ double sum_partials(const double* part, int q) {
 // is not b (warm start); the monitored residual is then relative to
 // ||b||_{P^{-1}} instead of ||r_0||_{P^{-1}}.
 __global__ void k_minres_init(MinresScalars* sc, const double* part_zv, const double* part_ref,
-                              double tol, int nrhs) {
+                              int count, double tol, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     MinresScalars& m = sc[r];
-    const double zv = sum_partials(part_zv, r);
-    const double ref = part_ref ? sum_partials(part_ref, r) : zv;
+    const double zv = sum_partials(part_zv, count, r);
+    const double ref = part_ref ? sum_partials(part_ref, count, r) : zv;
     m = MinresScalars{};
     m.status = 0;
     if (!(zv >= 0.0) || !isfinite(zv) || !(ref >= 0.0) || !isfinite(ref)) {
@@ -395,20 +438,20 @@ __device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* c
 // cp = (1, beta) for p = z + beta p.  A right-hand side whose preconditioned
 // residual has dropped to tol of its start (or whose r.z is not positive)
 // is frozen: alpha = 0 from then on.
-__global__ void k_cg_init(CgScalars* sc, const double* part_rz, int nrhs) {
+__global__ void k_cg_init(CgScalars* sc, const double* part_rz, int count, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
-    const double rz = sum_partials(part_rz, r);
+    const double rz = sum_partials(part_rz, count, r);
     sc[r].rz = rz;
     sc[r].rz0 = rz;
     sc[r].done = (rz > 0.0 && isfinite(rz)) ? 0 : 1;
 }
 
-__global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, double* cx, double* cr,
-                           int nrhs) {
+__global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, int count, double* cx,
+                           double* cr, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
-    const double pq = sum_partials(part_pq, r);
+    const double pq = sum_partials(part_pq, count, r);
     double a = 0.0;
     if (!sc[r].done && pq > 0.0 && isfinite(pq)) a = sc[r].rz / pq;
     else sc[r].done = 1;
@@ -418,13 +461,14 @@ __global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, double* cx, dou
     cr[2 * r + 1] = -a;
 }
 
-__global__ void k_cg_beta(CgScalars* sc, const double* part_rz, double* cp, double tol, int nrhs) {
+__global__ void k_cg_beta(CgScalars* sc, const double* part_rz, int count, double* cp, double tol,
+                          int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     cp[2 * r] = 1.0;
     cp[2 * r + 1] = 0.0;
     if (sc[r].done) return;
-    const double rzn = sum_partials(part_rz, r);
+    const double rzn = sum_partials(part_rz, count, r);
     if (!(rzn > 0.0) || !isfinite(rzn)) {
         sc[r].done = 1;
         return;
@@ -505,9 +549,9 @@ __global__ void k_minres_w(long long n, long long ld, const double* z, const dou
 }  // namespace
 
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
-                       const double* part_ref, double tol, int nrhs) {
+                       const double* part_ref, int count, double tol, int nrhs) {
     hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part,
-                       part_ref, tol, nrhs);
+                       part_ref, count, tol, nrhs);
     return hipGetLastError();
 }
 hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
@@ -525,27 +569,27 @@ hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const do
                        s, n, ld, z, wo, w, wn, x, sc_in, sc_out, a, b, tol, bd_tol, mirror);
     return hipGetLastError();
 }
-long long vec_dot_partial_count() { return DOT_BLOCKS; }
-hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs) {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, nrhs);
-    return hipGetLastError();
-}
-hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, double* cx, double* cr,
-                    int nrhs) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, cx, cr,
+long long vec_dot_partial_count(long long n) { return dot_blocks(n); }
+hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int count, int nrhs) {
+    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
                        nrhs);
     return hipGetLastError();
 }
-hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, double* cp, double tol,
-                   int nrhs) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, cp, tol,
-                       nrhs);
+hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, int count, double* cx,
+                    double* cr, int nrhs) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
+                       cx, cr, nrhs);
+    return hipGetLastError();
+}
+hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, int count, double* cp,
+                   double tol, int nrhs) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
+                       cp, tol, nrhs);
     return hipGetLastError();
 }
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, 1, nrhs), dim3(VT), 0, s, n, ld, X, 0LL, 1, Y,
-                       partial);
+    dot_partial_launch(s, n, ld, X, 0LL, 1, Y, nrhs, partial);
     return hipGetLastError();
 }
 
@@ -559,12 +603,12 @@ hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const doub
 namespace hp {
 namespace {
 
-__global__ void k_fg_init(FgScalars* sc, const double* part_bb, int nrhs) {
+__global__ void k_fg_init(FgScalars* sc, const double* part_bb, int count, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     FgScalars& s = sc[r];
     s = FgScalars{};
-    s.bnorm = sqrt(sum_partials(part_bb, r));
+    s.bnorm = sqrt(sum_partials(part_bb, count, r));
     s.done = (s.bnorm == 0.0);
     s.rel = s.done ? 0.0 : 1.0;
     if (!isfinite(s.bnorm)) {
@@ -574,12 +618,12 @@ __global__ void k_fg_init(FgScalars* sc, const double* part_bb, int nrhs) {
 }
 
 // cycle start: w = b - K x;  beta = ||w||, g = beta e1, vscale = 1/beta
-__global__ void k_fg_begin(FgScalars* sc, const double* part_ww, double* g, double* vscale, int m,
-                           int nrhs) {
+__global__ void k_fg_begin(FgScalars* sc, const double* part_ww, int count, double* g,
+                           double* vscale, int m, int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     FgScalars& s = sc[r];
-    const double beta = sqrt(sum_partials(part_ww, r));
+    const double beta = sqrt(sum_partials(part_ww, count, r));
     double* gr = g + (long long)r * (m + 1);
     for (int i = 0; i <= m; ++i) gr[i] = 0.0;
     s.jr = 0;
@@ -594,13 +638,16 @@ __global__ void k_fg_begin(FgScalars* sc, const double* part_ww, double* g, doub
 
 // Gram-Schmidt pass: h_i = <V_i, w> for i <= j; H[:, j] (+)= h.  One
 // workgroup per (i, rhs) sums that pair's partials as a block reduction (a
-// fixed order: one partial per thread, then the wave and workgroup trees).
-__global__ void k_fg_h(FgScalars* sc, const double* part, double* H, double* hcoef, int j, int pass,
-                       int m) {
+// fixed order: the partials strided over the threads, then the wave and
+// workgroup trees).
+__global__ void k_fg_h(FgScalars* sc, const double* part, int count, double* H, double* hcoef,
+                       int j, int pass, int m) {
     __shared__ double sh[VT / 64];
     const int i = blockIdx.x, r = blockIdx.y;
-    const long long base = ((long long)r * (j + 1) + i) * DOT_BLOCKS;
-    const double h = block_sum(threadIdx.x < DOT_BLOCKS ? part[base + threadIdx.x] : 0.0, sh);
+    const long long base = ((long long)r * (j + 1) + i) * count;
+    double hs = 0.0;
+    for (int q = threadIdx.x; q < count; q += VT) hs += part[base + q];
+    const double h = block_sum(hs, sh);
     if (threadIdx.x != 0) return;
     const bool active = sc[r].active;
     double* Hr = H + (long long)r * (m + 1) * m;
@@ -663,13 +710,14 @@ __device__ void fg_rot_one(FgScalars* sc, double ww, double* H, double* cs, doub
 // mirror: host-mapped copy of the scalars (may be null), refreshed after the step.
 // One workgroup per rhs: ||w||^2 from its partials as a block reduction, then
 // the rotations in thread 0.
-__global__ void k_fg_rot(FgScalars* sc, const double* part_ww, double* H, double* cs, double* sn,
-                         double* g, double* vscale, double tol, double bd_tol, int j, int m,
-                         FgScalars* mirror) {
+__global__ void k_fg_rot(FgScalars* sc, const double* part_ww, int count, double* H, double* cs,
+                         double* sn, double* g, double* vscale, double tol, double bd_tol, int j,
+                         int m, FgScalars* mirror) {
     __shared__ double sh[VT / 64];
     const int r = blockIdx.x;
-    const double ww = block_sum(
-        threadIdx.x < DOT_BLOCKS ? part_ww[(long long)r * DOT_BLOCKS + threadIdx.x] : 0.0, sh);
+    double ws = 0.0;
+    for (int q = threadIdx.x; q < count; q += VT) ws += part_ww[(long long)r * count + q];
+    const double ww = block_sum(ws, sh);
     if (threadIdx.x != 0) return;
     fg_rot_one(sc, ww, H, cs, sn, g, vscale, tol, bd_tol, j, m, r);
     if (mirror) mirror[r] = sc[r];
@@ -693,12 +741,13 @@ __global__ void k_fg_solve(const FgScalars* sc, const double* H, const double* g
 }
 
 // cycle end: relative true residual
-__global__ void k_fg_check(FgScalars* sc, const double* part_rr, double tol, int nrhs) {
+__global__ void k_fg_check(FgScalars* sc, const double* part_rr, int count, double tol,
+                           int nrhs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nrhs) return;
     FgScalars& s = sc[r];
     if (s.done) return;
-    s.rel = sqrt(sum_partials(part_rr, r)) / s.bnorm;
+    s.rel = sqrt(sum_partials(part_rr, count, r)) / s.bnorm;
     if (!isfinite(s.rel)) {
         s.status = -7;
         s.done = 1;
@@ -710,25 +759,27 @@ inline dim3 rhs_block(int nrhs) { return dim3(64 * ((nrhs + 63) / 64)); }
 
 }  // namespace
 
-hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int nrhs) {
-    hipLaunchKernelGGL(k_fg_init, dim3(1), rhs_block(nrhs), 0, s, sc, part, nrhs);
+hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int count, int nrhs) {
+    hipLaunchKernelGGL(k_fg_init, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, nrhs);
     return hipGetLastError();
 }
-hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g, double* vscale,
-                    int m, int nrhs) {
-    hipLaunchKernelGGL(k_fg_begin, dim3(1), rhs_block(nrhs), 0, s, sc, part, g, vscale, m, nrhs);
+hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, int count, double* g,
+                    double* vscale, int m, int nrhs) {
+    hipLaunchKernelGGL(k_fg_begin, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, g, vscale, m,
+                       nrhs);
     return hipGetLastError();
 }
-hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
-                int pass, int m, int nrhs) {
-    hipLaunchKernelGGL(k_fg_h, dim3(j + 1, nrhs), dim3(VT), 0, s, sc, part, H, hcoef, j, pass, m);
+hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, int count, double* H,
+                double* hcoef, int j, int pass, int m, int nrhs) {
+    hipLaunchKernelGGL(k_fg_h, dim3(j + 1, nrhs), dim3(VT), 0, s, sc, part, count, H, hcoef, j,
+                       pass, m);
     return hipGetLastError();
 }
-hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, double bd_tol, int j, int m,
-                  int nrhs, FgScalars* mirror) {
-    hipLaunchKernelGGL(k_fg_rot, dim3(nrhs), dim3(VT), 0, s, sc, part, H, cs, sn, g, vscale, tol,
-                       bd_tol, j, m, mirror);
+hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, int count, double* H,
+                  double* cs, double* sn, double* g, double* vscale, double tol, double bd_tol,
+                  int j, int m, int nrhs, FgScalars* mirror) {
+    hipLaunchKernelGGL(k_fg_rot, dim3(nrhs), dim3(VT), 0, s, sc, part, count, H, cs, sn, g, vscale,
+                       tol, bd_tol, j, m, mirror);
     return hipGetLastError();
 }
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
@@ -736,15 +787,15 @@ hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const d
     hipLaunchKernelGGL(k_fg_solve, dim3(1), rhs_block(nrhs), 0, s, sc, H, g, y, m, jmax, nrhs);
     return hipGetLastError();
 }
-hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs) {
-    hipLaunchKernelGGL(k_fg_check, dim3(1), rhs_block(nrhs), 0, s, sc, part, tol, nrhs);
+hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, int count, double tol,
+                    int nrhs) {
+    hipLaunchKernelGGL(k_fg_check, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, tol, nrhs);
     return hipGetLastError();
 }
 hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
                                  long long xstride, int npair, const double* Y, int nrhs,
                                  double* partial) {
-    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS, (npair + DOT_QB - 1) / DOT_QB, nrhs), dim3(VT), 0, s, n, ld, X,
-                       xstride, npair, Y, partial);
+    dot_partial_launch(s, n, ld, X, xstride, npair, Y, nrhs, partial);
     return hipGetLastError();
 }
 

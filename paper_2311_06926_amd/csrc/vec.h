@@ -39,8 +39,9 @@ struct MinresScalars {
 // part_ref: partials of b . P^{-1} b for a warm start (else null): the
 // monitored residual is then relative to ||b||_{P^{-1}}; a start that already
 // meets tol ends the iteration at once
+// (count: partials per right-hand side, vec_dot_partial_count of the length)
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
-                       const double* part_ref, double tol, int nrhs);
+                       const double* part_ref, int count, double tol, int nrhs);
 // A dot product handed over as partial sums: part[r * count + i], i < count,
 // for right-hand side r (summed in a fixed order by the consumer).
 struct Partials {
@@ -60,43 +61,49 @@ hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const do
                     const double* wo, const double* w, double* wn, double* x,
                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
                     double tol, double bd_tol, MinresScalars* mirror);
-// partial[r*DOT_BLOCKS + b] of <X_r, Y_r> (finished by the MINRES kernels)
+// partial[r*count + b] of <X_r, Y_r>, count = vec_dot_partial_count(n)
+// (finished by the MINRES, CG and FGMRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
                             const double* Y, int nrhs, double* partial);
-// partials vec_dot_partials writes per right-hand side
-long long vec_dot_partial_count();
+// partials per pair and right-hand side of a dot over n entries (at most
+// vec_partial_doubles(1, 1); the chunks depend on n alone, so a batch and its
+// right-hand sides one at a time give the same sums)
+long long vec_dot_partial_count(long long n);
 
 // Per-right-hand-side state of the inner preconditioned CG.
 struct CgScalars {
     double rz, rz0;
     int done, pad;
 };
-hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int nrhs);
+// (count: partials per right-hand side, as for minres_init)
+hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int count, int nrhs);
 // cx = (1, alpha), cr = (1, -alpha) per rhs (2 doubles each)
-hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, double* cx, double* cr,
-                    int nrhs);
+hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, int count, double* cx,
+                    double* cr, int nrhs);
 // cp = (1, beta) per rhs; freezes a rhs once sqrt(r.z) <= tol sqrt(r0.z0)
-hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, double* cp, double tol,
-                   int nrhs);
+hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, int count, double* cp,
+                   double tol, int nrhs);
 
 // Per-right-hand-side state of device-side FGMRES.
 struct FgScalars {
     double bnorm, rel;
     int done, active, jr, iters, status, pad;
 };
-hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int nrhs);
-hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, double* g, double* vscale,
-                    int m, int nrhs);
-hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, double* H, double* hcoef, int j,
-                int pass, int m, int nrhs);
+// (count: partials per pair and right-hand side, as for minres_init)
+hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int count, int nrhs);
+hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, int count, double* g,
+                    double* vscale, int m, int nrhs);
+hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, int count, double* H,
+                double* hcoef, int j, int pass, int m, int nrhs);
 // mirror: device pointer of a host-mapped copy of sc (or null), refreshed by the kernel
-hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, double* H, double* cs,
-                  double* sn, double* g, double* vscale, double tol, double bd_tol, int j, int m,
-                  int nrhs, FgScalars* mirror);
+hipError_t fg_rot(hipStream_t s, FgScalars* sc, const double* part, int count, double* H,
+                  double* cs, double* sn, double* g, double* vscale, double tol, double bd_tol,
+                  int j, int m, int nrhs, FgScalars* mirror);
 hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const double* g, double* y,
                     int m, int jmax, int nrhs);
-hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, double tol, int nrhs);
-// partial[((r*npair + q)*DOT_BLOCKS + b] of <X_q,r , Y_r>
+hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, int count, double tol,
+                    int nrhs);
+// partial[((r*npair + q)*count + b] of <X_q,r , Y_r>, count = vec_dot_partial_count(n)
 hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
                                  long long xstride, int npair, const double* Y, int nrhs,
                                  double* partial);
