@@ -99,8 +99,11 @@ typedef struct hp_opts {
     int max_rhs;        /* largest batch accepted (workspace size, default 1) */
     int poll_lag;       /* MINRES: the host reads the convergence flags of iteration j
                            once iteration j + poll_lag is enqueued (1..3, default 1), so
-                           that it stays that far ahead of the device; up to poll_lag
-                           iterations then run past convergence and leave x unchanged */
+                           that it stays that far ahead of the device (with direct
+                           launches it waits for the start of iteration j + 1, which
+                           finishes iteration j; with graphs for the end of iteration
+                           j); up to poll_lag iterations then run past convergence and
+                           leave x unchanged */
     int use_graph;      /* solve: 0 = launch the kernels of each iteration directly
                            (default), 1 = replay each iteration (FGMRES: each Arnoldi
                            step) as one captured HIP graph; results are identical bit

@@ -480,31 +480,17 @@ MinresBufs minres_bufs(hp_ctx* c, int phase, int nrhs) {
 
 // One MINRES iteration; it reads the scalar state msc[cur] and writes the
 // next one to msc[cur ^ 1] and to the host mirror `mirror` (device address
-// of pinned host memory).  Its pieces: (a) K z, (Kz . z) and the v update;
-// then P_k as the Q block (q) beside the V block (v), whose launches also
-// leave the partials of (z_new . v_new); (w) the rotation and the w/x update.
-hipError_t minres_a(hp_ctx* c, const MinresBufs& b, int nrhs, int cur) {
-    Extra* ex = extra_of(c);
-    const long long N = c->N;
-    MinresScalars* s_cur = ex->msc + cur * c->opts.max_rhs;
-    double* p0 = ex->mpart;
-    hipError_t e;
-    if ((e = launch_forward(c, b.z, b.Kz, nrhs)) != hipSuccess) return e;
-    if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
-    return minres_v(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, s_cur,
-                    Partials{p0, vec_dot_partial_count(N)});
-}
+// of pinned host memory).  Its pieces: K z and (Kz . z); one update launch
+// that finishes the previous iteration (its rotation and w/x update, from the
+// partials of (z . v) its P_k left; skipped in the first iteration, pb null)
+// and forms v_new; then P_k as the Q block beside the V block, whose launches
+// leave the partials of (z_new . v_new) for the next iteration's update (or
+// for minres_w_step after the last one).  pb: the previous iteration's
+// buffers; polled (may be null): an event recorded after the update launch,
+// which marks the point where the previous iteration's flags are final.
 PkDot minres_pk_dot(hp_ctx* c, const MinresBufs& b) {
     Extra* ex = extra_of(c);
     return PkDot{b.vn, ex->mfg, ex->mfq};
-}
-hipError_t minres_q(hp_ctx* c, const MinresBufs& b, int nrhs) {
-    const PkDot pd = minres_pk_dot(c, b);
-    return pk_q_block(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd);
-}
-hipError_t minres_vb(hp_ctx* c, const MinresBufs& b, int nrhs) {
-    const PkDot pd = minres_pk_dot(c, b);
-    return pk_v_block(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd);
 }
 hipError_t minres_w_step(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
                          MinresScalars* mirror, int cur) {
@@ -518,14 +504,26 @@ hipError_t minres_w_step(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
                     mirror);
 }
 
-hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, int nrhs, double tol,
-                            MinresScalars* mirror, int cur) {
+hipError_t minres_iteration(hp_ctx* c, const MinresBufs& b, const MinresBufs* pb, int nrhs,
+                            double tol, MinresScalars* mirror, int cur, hipEvent_t polled) {
+    Extra* ex = extra_of(c);
+    const long long N = c->N;
+    const int R = c->opts.max_rhs;
+    double* p0 = ex->mpart;
     hipError_t e;
-    if ((e = minres_a(c, b, nrhs, cur)) != hipSuccess) return e;
-    const PkDot pd = minres_pk_dot(c, b);
-    if ((e = apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd)) != hipSuccess)
+    if ((e = launch_forward(c, b.z, b.Kz, nrhs)) != hipSuccess) return e;
+    if ((e = vec_dot_partials(c->stream, N, N, b.Kz, b.z, nrhs, p0)) != hipSuccess) return e;
+    const MinresBufs& q = pb ? *pb : b;  // the w/x vectors are not touched without pb
+    const Partials pa = pb ? Partials{ex->mfg, fd_dot_count(c, true)} : Partials{nullptr, 0};
+    const Partials pq = pb ? Partials{ex->mfq, fd_dot_count(c, false)} : Partials{nullptr, 0};
+    if ((e = minres_wv(c->stream, N, N, nrhs, b.Kz, b.v, b.vo, b.vn, q.z, q.wo, q.w, q.wn, b.x,
+                       ex->msc + cur * R, ex->msc + (cur ^ 1) * R,
+                       Partials{p0, vec_dot_partial_count(N)}, pa, pq, tol,
+                       c->opts.breakdown_tol, mirror)) != hipSuccess)
         return e;
-    return minres_w_step(c, b, nrhs, tol, mirror, cur);
+    if (polled && (e = hipEventRecord(polled, c->stream)) != hipSuccess) return e;
+    const PkDot pd = minres_pk_dot(c, b);
+    return apply_Pk(c, c->opts.order, c->opts.iters, b.vn, b.zn, nrhs, &pd);
 }
 
 void drop_graphs(Extra* ex) {
@@ -566,11 +564,13 @@ hp_status build_graphs(hp_ctx* c, int nrhs, double tol) {
     hp_status st = HP_OK;
     for (int ph = 0; ph < 6 && st == HP_OK; ++ph) {
         // iteration it (phase (it-1) % 6) reads state it & 1 and is polled
-        // through mirror it & 1
+        // through mirror it & 1; the graphs serve iterations 2, 3, ... (the
+        // first has no previous iteration to finish)
         const MinresBufs bb = minres_bufs(c, ph, nrhs);
+        const MinresBufs bp = minres_bufs(c, (ph + 5) % 6, nrhs);
         const int cur = (ph + 1) & 1;
         st = capture_graph(c, &ex->g_exec[ph], [&]() {
-            return minres_iteration(c, bb, nrhs, tol, ex->dmsc[cur], cur);
+            return minres_iteration(c, bb, &bp, nrhs, tol, ex->dmsc[cur], cur, nullptr);
         });
     }
     c->stream = user;
@@ -636,24 +636,38 @@ hp_status minres(hp_ctx* c, const double* b, double* x, int nrhs, double tol, hp
     while (!finished && it < c->opts.maxit) {
         const int ph = it % 6;
         ++it;
-        if (graphs) {
+        if (graphs && it > 1) {
             HIPCHK(hipGraphLaunch(ex->g_exec[ph], c->stream));
+            HIPCHK(hipEventRecord(ex->mev[it & 3], c->stream));
         } else {
-            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), nrhs, tol, ex->dmsc[it & 1],
-                                    it & 1));
+            const MinresBufs bp = minres_bufs(c, (ph + 5) % 6, nrhs);
+            HIPCHK(minres_iteration(c, minres_bufs(c, ph, nrhs), it > 1 ? &bp : nullptr, nrhs,
+                                    tol, ex->dmsc[it & 1], it & 1, ex->mev[it & 3]));
         }
-        // the flags of iteration it - lag, read once iteration it is enqueued
-        // (its mirror slot may already hold a later state: done is monotone)
-        HIPCHK(hipEventRecord(ex->mev[it & 3], c->stream));
-        if (it > lag) {
-            HIPCHK(hipEventSynchronize(ex->mev[(it - lag) & 3]));
-            finished = all_done(ex->hmsc[(it - lag) & 1]);
+        // the flags of iteration it - lag are final once the update launch of
+        // iteration it - lag + 1 has run (its mirror slot may already hold a
+        // later state: done is monotone).  Launched directly, that launch is
+        // marked by its own event, and the host waits for it with the rest of
+        // iteration it - lag + 1 still queued (for lag 1, P_k of iteration it:
+        // measured at 32^3, the device does not wait for the host then, and
+        // one iteration less runs past convergence); a graph is marked at
+        // its end only, so the host waits for iteration it - lag.
+        const int pj = graphs ? it - lag : it - lag + 1;
+        if (pj >= 1) {
+            HIPCHK(hipEventSynchronize(ex->mev[pj & 3]));
+            finished = all_done(ex->hmsc[pj & 1]);
         }
     }
+    // the last iteration's rotation and w/x update (nothing for a state
+    // already done); after it the state is msc[it & 1] (msc[1], from
+    // minres_init, when no iteration ran)
+    if (it > 0)
+        HIPCHK(minres_w_step(c, minres_bufs(c, (it - 1) % 6, nrhs), nrhs, tol, nullptr,
+                             (it + 1) & 1));
     HIPCHK(hipStreamSynchronize(c->stream));
-    // after `it` iterations the state is msc[(it + 1) & 1]
-    const MinresScalars* h = ex->hmsc[it & 1];
-    HIPCHK(hipMemcpy(ex->hmsc[it & 1], ex->msc + ((it + 1) & 1) * c->opts.max_rhs, sbytes,
+    const int fin = it > 0 ? (it & 1) : 1;
+    const MinresScalars* h = ex->hmsc[fin];
+    HIPCHK(hipMemcpy(ex->hmsc[fin], ex->msc + fin * c->opts.max_rhs, sbytes,
                      hipMemcpyDeviceToHost));
     HIPCHK(vec_copy(c->stream, V, b0.x, x));
     hp_status status = HP_OK;

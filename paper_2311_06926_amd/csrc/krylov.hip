@@ -478,17 +478,17 @@ __global__ void k_cg_beta(CgScalars* sc, const double* part_rz, int count, doubl
     if (sqrt(rzn) <= tol * sqrt(sc[r].rz0)) sc[r].done = 1;
 }
 
-// The two MINRES vector updates, each fused with the scalar step that gives
-// its coefficients: every workgroup finishes the dot product from the
+// The MINRES vector updates, fused with the scalar steps that give their
+// coefficients: every workgroup finishes the dot products from the
 // per-block partials (the same fixed-order sum in each) and forms the
 // coefficients itself, so no separate scalar launch is needed.
-//   k_minres_v: delta from (Kz.z); v_new = cv . (Kz, v, v_old); workgroup 0
-//               records delta in the state.
-//   k_minres_w: gamma_new, the Givens rotation and the shift from (z_new.v_new)
-//               applied to a copy of the state; w_new = cw . (z, w_old, w) and
-//               x += cx1 w_new; workgroup 0 writes the new state to sc_out
-//               (a second buffer, so no workgroup reads a half-updated state)
-//               and to the host mirror.
+//   Lanczos step (minres_a_core): delta from (Kz.z); v_new = cv . (Kz, v, v_old).
+//   Rotation step (minres_b_core): gamma_new, the Givens rotation and the
+//               shift from (z_new.v_new); w_new = cw . (z, w_old, w) and
+//               x += cx1 w_new.
+// Each kernel applies its steps to a copy of the state read from sc_in;
+// workgroup 0 writes the new state to sc_out (a second buffer, so no
+// workgroup reads a half-updated state) and to the host mirror.
 // Thread t sums partials t, t + VT, ... of set a, then of set b; the block
 // sum of those is valid in thread 0.  The order depends only on the counts.
 __device__ __forceinline__ double sum_block_partials(Partials a, Partials b, int r, double* sh) {
@@ -497,25 +497,6 @@ __device__ __forceinline__ double sum_block_partials(Partials a, Partials b, int
     if (b.part)
         for (long long i = threadIdx.x; i < b.count; i += VT) s += b.part[r * b.count + i];
     return block_sum(s, sh);
-}
-
-__global__ void k_minres_v(long long n, long long ld, const double* kz, const double* v,
-                           const double* vo, double* vn, MinresScalars* sc, Partials part) {
-    __shared__ double sh[VT / 64];
-    __shared__ double cv[3];
-    const int r = blockIdx.y;
-    const double d = sum_block_partials(part, Partials{nullptr, 0}, r, sh);
-    if (threadIdx.x == 0) {
-        MinresScalars m = sc[r];
-        minres_a_core(m, d, cv);
-        if (blockIdx.x == 0) sc[r].delta = m.delta;
-    }
-    __syncthreads();
-    const double c0 = cv[0], c1 = cv[1], c2 = cv[2];
-    const long long off = (long long)r * ld;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long st = (long long)gridDim.x * blockDim.x;
-    for (; i < n; i += st) vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
 }
 
 __global__ void k_minres_w(long long n, long long ld, const double* z, const double* wo,
@@ -546,6 +527,52 @@ __global__ void k_minres_w(long long n, long long ld, const double* z, const dou
     }
 }
 
+// k_minres_v and the previous iteration's k_minres_w in one launch.  Iteration
+// j's v update and iteration j-1's w/x update both come after the partials
+// they need (j-1's (z.v) from its P_k, j's (Kz.z) from its dot) and before
+// iteration j's P_k, which overwrites j-1's z; so they share a launch:
+// every workgroup applies the rotation of j-1 (when pw is set) and then the
+// Lanczos step of j to its copy of the state, as the two kernels do one
+// after the other, and updates its slice of w_new, x and v_new.
+// Workgroup 0 writes the state to sc_out and to the host mirror.
+__global__ void k_minres_wv(long long n, long long ld, const double* kz, const double* v,
+                            const double* vo, double* vn, const double* z, const double* wo,
+                            const double* w, double* wn, double* x, const MinresScalars* sc_in,
+                            MinresScalars* sc_out, Partials pkz, Partials pa, Partials pb,
+                            double tol, double bd_tol, MinresScalars* mirror) {
+    __shared__ double sh[VT / 64];
+    __shared__ double cv[3], cw[3], cx[2];
+    const int r = blockIdx.y;
+    const bool prev = pa.part != nullptr;
+    const double dzv = prev ? sum_block_partials(pa, pb, r, sh) : 0.0;
+    const double dkz = sum_block_partials(pkz, Partials{nullptr, 0}, r, sh);
+    if (threadIdx.x == 0) {
+        MinresScalars m = sc_in[r];
+        if (prev) minres_b_core(m, dzv, cw, cx, tol, bd_tol);
+        minres_a_core(m, dkz, cv);
+        if (blockIdx.x == 0) {
+            sc_out[r] = m;
+            if (mirror) mirror[r] = m;
+        }
+    }
+    __syncthreads();
+    const double c0 = cv[0], c1 = cv[1], c2 = cv[2];
+    const long long off = (long long)r * ld;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    if (prev) {
+        const double e0 = cw[0], e1 = cw[1], e2 = cw[2], d0 = cx[0], d1 = cx[1];
+        for (; i < n; i += st) {
+            const double t = e0 * z[off + i] + e1 * wo[off + i] + e2 * w[off + i];
+            wn[off + i] = t;
+            x[off + i] = d0 * x[off + i] + d1 * t;
+            vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
+        }
+    } else {
+        for (; i < n; i += st) vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
+    }
+}
+
 }  // namespace
 
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
@@ -554,19 +581,21 @@ hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
                        part_ref, count, tol, nrhs);
     return hipGetLastError();
 }
-hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
-                    const double* v, const double* vo, double* vn, MinresScalars* sc,
-                    Partials part) {
-    hipLaunchKernelGGL(k_minres_v, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n,
-                       ld, kz, v, vo, vn, sc, part);
-    return hipGetLastError();
-}
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
                     const double* wo, const double* w, double* wn, double* x,
                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
                     double tol, double bd_tol, MinresScalars* mirror) {
     hipLaunchKernelGGL(k_minres_w, dim3(grid_for(n), nrhs), dim3(VT), 0,
                        s, n, ld, z, wo, w, wn, x, sc_in, sc_out, a, b, tol, bd_tol, mirror);
+    return hipGetLastError();
+}
+hipError_t minres_wv(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
+                     const double* v, const double* vo, double* vn, const double* z,
+                     const double* wo, const double* w, double* wn, double* x,
+                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials pkz, Partials a,
+                     Partials b, double tol, double bd_tol, MinresScalars* mirror) {
+    hipLaunchKernelGGL(k_minres_wv, dim3(grid_for(n), nrhs), dim3(VT), 0, s, n, ld, kz, v, vo, vn,
+                       z, wo, w, wn, x, sc_in, sc_out, pkz, a, b, tol, bd_tol, mirror);
     return hipGetLastError();
 }
 long long vec_dot_partial_count(long long n) { return dot_blocks(n); }

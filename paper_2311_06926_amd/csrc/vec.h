@@ -48,11 +48,6 @@ struct Partials {
     const double* part;
     long long count;
 };
-// v_new = cv . (Kz, v, v_old) with delta and cv formed from the partials of
-// (Kz.z) in every workgroup; records delta in sc
-hipError_t minres_v(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
-                    const double* v, const double* vo, double* vn, MinresScalars* sc,
-                    Partials part);
 // from the partials of (z_new.v_new) (the sum of two sets, b.part may be
 // null): the rotation of sc_in, w_new = cw . (z, w_old, w), x += cx1 w_new;
 // the new state goes to sc_out (not sc_in) and to mirror (device pointer of a
@@ -61,6 +56,16 @@ hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const do
                     const double* wo, const double* w, double* wn, double* x,
                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials a, Partials b,
                     double tol, double bd_tol, MinresScalars* mirror);
+// the rotation and w/x update of iteration j-1 (as minres_w, when a.part is
+// set; z, wo, w, wn, x its vectors) and the Lanczos step of iteration j in one
+// launch: delta from the partials pkz of (Kz.z), v_new = cv . (Kz, v, v_old);
+// reads the state of sc_in and writes the state after both to sc_out and
+// mirror
+hipError_t minres_wv(hipStream_t s, long long n, long long ld, int nrhs, const double* kz,
+                     const double* v, const double* vo, double* vn, const double* z,
+                     const double* wo, const double* w, double* wn, double* x,
+                     const MinresScalars* sc_in, MinresScalars* sc_out, Partials pkz, Partials a,
+                     Partials b, double tol, double bd_tol, MinresScalars* mirror);
 // partial[r*count + b] of <X_r, Y_r>, count = vec_dot_partial_count(n)
 // (finished by the MINRES, CG and FGMRES kernels)
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
