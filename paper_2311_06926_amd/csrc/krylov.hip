@@ -332,10 +332,14 @@ hipError_t vec_dots(hp_ctx* c, long long n, long long ld, const double* x, const
 namespace hp {
 namespace {
 
-__device__ double sum_partials(const double* part, int count, int q) {
+// The scalar kernels below run one workgroup per right-hand side: the
+// partials of its dot products are summed by the whole workgroup (strided
+// over the threads, then the wave and workgroup trees: a fixed order), and
+// thread 0 then takes the scalar step.  The result is valid in thread 0.
+__device__ double sum_partials(const double* part, int count, int q, double* sh) {
     double s = 0.0;
-    for (int i = 0; i < count; ++i) s += part[(long long)q * count + i];
-    return s;
+    for (int i = threadIdx.x; i < count; i += VT) s += part[(long long)q * count + i];
+    return block_sum(s, sh);
 }
 
 // after z = P^{-1} b:  gamma = sqrt(z.v), beta0 = eta = gamma, c = 1, s = 0
@@ -343,12 +347,13 @@ __device__ double sum_partials(const double* part, int count, int q) {
 // is not b (warm start); the monitored residual is then relative to
 // ||b||_{P^{-1}} instead of ||r_0||_{P^{-1}}.
 __global__ void k_minres_init(MinresScalars* sc, const double* part_zv, const double* part_ref,
-                              int count, double tol, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+                              int count, double tol) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double zv = sum_partials(part_zv, count, r, sh);
+    const double ref = part_ref ? sum_partials(part_ref, count, r, sh) : zv;
+    if (threadIdx.x != 0) return;
     MinresScalars& m = sc[r];
-    const double zv = sum_partials(part_zv, count, r);
-    const double ref = part_ref ? sum_partials(part_ref, count, r) : zv;
     m = MinresScalars{};
     m.status = 0;
     if (!(zv >= 0.0) || !isfinite(zv) || !(ref >= 0.0) || !isfinite(ref)) {
@@ -438,20 +443,22 @@ __device__ void minres_b_core(MinresScalars& m, double zv, double* cw, double* c
 // cp = (1, beta) for p = z + beta p.  A right-hand side whose preconditioned
 // residual has dropped to tol of its start (or whose r.z is not positive)
 // is frozen: alpha = 0 from then on.
-__global__ void k_cg_init(CgScalars* sc, const double* part_rz, int count, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    const double rz = sum_partials(part_rz, count, r);
+__global__ void k_cg_init(CgScalars* sc, const double* part_rz, int count) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double rz = sum_partials(part_rz, count, r, sh);
+    if (threadIdx.x != 0) return;
     sc[r].rz = rz;
     sc[r].rz0 = rz;
     sc[r].done = (rz > 0.0 && isfinite(rz)) ? 0 : 1;
 }
 
 __global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, int count, double* cx,
-                           double* cr, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    const double pq = sum_partials(part_pq, count, r);
+                           double* cr) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double pq = sum_partials(part_pq, count, r, sh);
+    if (threadIdx.x != 0) return;
     double a = 0.0;
     if (!sc[r].done && pq > 0.0 && isfinite(pq)) a = sc[r].rz / pq;
     else sc[r].done = 1;
@@ -461,14 +468,18 @@ __global__ void k_cg_alpha(CgScalars* sc, const double* part_pq, int count, doub
     cr[2 * r + 1] = -a;
 }
 
-__global__ void k_cg_beta(CgScalars* sc, const double* part_rz, int count, double* cp, double tol,
-                          int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    cp[2 * r] = 1.0;
-    cp[2 * r + 1] = 0.0;
-    if (sc[r].done) return;
-    const double rzn = sum_partials(part_rz, count, r);
+__global__ void k_cg_beta(CgScalars* sc, const double* part_rz, int count, double* cp,
+                          double tol) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const bool done = sc[r].done;  // the same in every thread of the workgroup
+    if (threadIdx.x == 0) {
+        cp[2 * r] = 1.0;
+        cp[2 * r + 1] = 0.0;
+    }
+    if (done) return;
+    const double rzn = sum_partials(part_rz, count, r, sh);
+    if (threadIdx.x != 0) return;
     if (!(rzn > 0.0) || !isfinite(rzn)) {
         sc[r].done = 1;
         return;
@@ -540,14 +551,51 @@ __global__ void k_minres_wv(long long n, long long ld, const double* kz, const d
                             const double* w, double* wn, double* x, const MinresScalars* sc_in,
                             MinresScalars* sc_out, Partials pkz, Partials pa, Partials pb,
                             double tol, double bd_tol, MinresScalars* mirror) {
-    __shared__ double sh[VT / 64];
+    __shared__ double sh[2][VT / 64];
     __shared__ double cv[3], cw[3], cx[2];
     const int r = blockIdx.y;
     const bool prev = pa.part != nullptr;
-    const double dzv = prev ? sum_block_partials(pa, pb, r, sh) : 0.0;
-    const double dkz = sum_block_partials(pkz, Partials{nullptr, 0}, r, sh);
+    const long long off = (long long)r * ld;
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long st = (long long)gridDim.x * blockDim.x;
+    // this thread's first element of every vector and the state are loaded
+    // before the partial sums, so that their latencies overlap
+    double e_kz = 0.0, e_v = 0.0, e_vo = 0.0, e_z = 0.0, e_wo = 0.0, e_w = 0.0, e_x = 0.0;
+    if (i0 < n) {
+        e_kz = kz[off + i0];
+        e_v = v[off + i0];
+        e_vo = vo[off + i0];
+        if (prev) {
+            e_z = z[off + i0];
+            e_wo = wo[off + i0];
+            e_w = w[off + i0];
+            e_x = x[off + i0];
+        }
+    }
+    MinresScalars m{};
+    if (threadIdx.x == 0) m = sc_in[r];
+    // both dot products in one reduction, each in the order of
+    // sum_block_partials: this thread's strided partials (set a, then set
+    // b), the wave tree, then the waves in order
+    double szv = 0.0, skz = 0.0;
+    if (prev) {
+        for (long long q = threadIdx.x; q < pa.count; q += VT) szv += pa.part[r * pa.count + q];
+        if (pb.part)
+            for (long long q = threadIdx.x; q < pb.count; q += VT) szv += pb.part[r * pb.count + q];
+    }
+    for (long long q = threadIdx.x; q < pkz.count; q += VT) skz += pkz.part[r * pkz.count + q];
+    szv = wave_sum(szv);
+    skz = wave_sum(skz);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[0][wave] = szv;
+        sh[1][wave] = skz;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        MinresScalars m = sc_in[r];
+        double dzv = 0.0, dkz = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) dzv += sh[0][k];
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) dkz += sh[1][k];
         if (prev) minres_b_core(m, dzv, cw, cx, tol, bd_tol);
         minres_a_core(m, dkz, cv);
         if (blockIdx.x == 0) {
@@ -557,19 +605,24 @@ __global__ void k_minres_wv(long long n, long long ld, const double* kz, const d
     }
     __syncthreads();
     const double c0 = cv[0], c1 = cv[1], c2 = cv[2];
-    const long long off = (long long)r * ld;
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long st = (long long)gridDim.x * blockDim.x;
     if (prev) {
-        const double e0 = cw[0], e1 = cw[1], e2 = cw[2], d0 = cx[0], d1 = cx[1];
-        for (; i < n; i += st) {
-            const double t = e0 * z[off + i] + e1 * wo[off + i] + e2 * w[off + i];
+        const double f0 = cw[0], f1 = cw[1], f2 = cw[2], d0 = cx[0], d1 = cx[1];
+        if (i0 < n) {
+            const double t = f0 * e_z + f1 * e_wo + f2 * e_w;
+            wn[off + i0] = t;
+            x[off + i0] = d0 * e_x + d1 * t;
+            vn[off + i0] = c0 * e_kz + c1 * e_v + c2 * e_vo;
+        }
+        for (long long i = i0 + st; i < n; i += st) {
+            const double t = f0 * z[off + i] + f1 * wo[off + i] + f2 * w[off + i];
             wn[off + i] = t;
             x[off + i] = d0 * x[off + i] + d1 * t;
             vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
         }
     } else {
-        for (; i < n; i += st) vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
+        if (i0 < n) vn[off + i0] = c0 * e_kz + c1 * e_v + c2 * e_vo;
+        for (long long i = i0 + st; i < n; i += st)
+            vn[off + i] = c0 * kz[off + i] + c1 * v[off + i] + c2 * vo[off + i];
     }
 }
 
@@ -577,8 +630,7 @@ __global__ void k_minres_wv(long long n, long long ld, const double* kz, const d
 
 hipError_t minres_init(hipStream_t s, MinresScalars* sc, const double* part,
                        const double* part_ref, int count, double tol, int nrhs) {
-    hipLaunchKernelGGL(k_minres_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part,
-                       part_ref, count, tol, nrhs);
+    hipLaunchKernelGGL(k_minres_init, dim3(nrhs), dim3(VT), 0, s, sc, part, part_ref, count, tol);
     return hipGetLastError();
 }
 hipError_t minres_w(hipStream_t s, long long n, long long ld, int nrhs, const double* z,
@@ -600,20 +652,17 @@ hipError_t minres_wv(hipStream_t s, long long n, long long ld, int nrhs, const d
 }
 long long vec_dot_partial_count(long long n) { return dot_blocks(n); }
 hipError_t cg_init(hipStream_t s, CgScalars* sc, const double* part, int count, int nrhs) {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
-                       nrhs);
+    hipLaunchKernelGGL(k_cg_init, dim3(nrhs), dim3(VT), 0, s, sc, part, count);
     return hipGetLastError();
 }
 hipError_t cg_alpha(hipStream_t s, CgScalars* sc, const double* part, int count, double* cx,
                     double* cr, int nrhs) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
-                       cx, cr, nrhs);
+    hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(VT), 0, s, sc, part, count, cx, cr);
     return hipGetLastError();
 }
 hipError_t cg_beta(hipStream_t s, CgScalars* sc, const double* part, int count, double* cp,
                    double tol, int nrhs) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(64 * ((nrhs + 63) / 64)), 0, s, sc, part, count,
-                       cp, tol, nrhs);
+    hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(VT), 0, s, sc, part, count, cp, tol);
     return hipGetLastError();
 }
 hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const double* X,
@@ -632,12 +681,14 @@ hipError_t vec_dot_partials(hipStream_t s, long long n, long long ld, const doub
 namespace hp {
 namespace {
 
-__global__ void k_fg_init(FgScalars* sc, const double* part_bb, int count, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+__global__ void k_fg_init(FgScalars* sc, const double* part_bb, int count) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double bb = sum_partials(part_bb, count, r, sh);
+    if (threadIdx.x != 0) return;
     FgScalars& s = sc[r];
     s = FgScalars{};
-    s.bnorm = sqrt(sum_partials(part_bb, count, r));
+    s.bnorm = sqrt(bb);
     s.done = (s.bnorm == 0.0);
     s.rel = s.done ? 0.0 : 1.0;
     if (!isfinite(s.bnorm)) {
@@ -648,11 +699,13 @@ __global__ void k_fg_init(FgScalars* sc, const double* part_bb, int count, int n
 
 // cycle start: w = b - K x;  beta = ||w||, g = beta e1, vscale = 1/beta
 __global__ void k_fg_begin(FgScalars* sc, const double* part_ww, int count, double* g,
-                           double* vscale, int m, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+                           double* vscale, int m) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    const double ww = sum_partials(part_ww, count, r, sh);
+    if (threadIdx.x != 0) return;
     FgScalars& s = sc[r];
-    const double beta = sqrt(sum_partials(part_ww, count, r));
+    const double beta = sqrt(ww);
     double* gr = g + (long long)r * (m + 1);
     for (int i = 0; i <= m; ++i) gr[i] = 0.0;
     s.jr = 0;
@@ -770,13 +823,14 @@ __global__ void k_fg_solve(const FgScalars* sc, const double* H, const double* g
 }
 
 // cycle end: relative true residual
-__global__ void k_fg_check(FgScalars* sc, const double* part_rr, int count, double tol,
-                           int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+__global__ void k_fg_check(FgScalars* sc, const double* part_rr, int count, double tol) {
+    __shared__ double sh[VT / 64];
+    const int r = blockIdx.x;
+    if (sc[r].done) return;  // the same in every thread of the workgroup
+    const double rr = sum_partials(part_rr, count, r, sh);
+    if (threadIdx.x != 0) return;
     FgScalars& s = sc[r];
-    if (s.done) return;
-    s.rel = sqrt(sum_partials(part_rr, count, r)) / s.bnorm;
+    s.rel = sqrt(rr) / s.bnorm;
     if (!isfinite(s.rel)) {
         s.status = -7;
         s.done = 1;
@@ -789,13 +843,12 @@ inline dim3 rhs_block(int nrhs) { return dim3(64 * ((nrhs + 63) / 64)); }
 }  // namespace
 
 hipError_t fg_init(hipStream_t s, FgScalars* sc, const double* part, int count, int nrhs) {
-    hipLaunchKernelGGL(k_fg_init, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, nrhs);
+    hipLaunchKernelGGL(k_fg_init, dim3(nrhs), dim3(VT), 0, s, sc, part, count);
     return hipGetLastError();
 }
 hipError_t fg_begin(hipStream_t s, FgScalars* sc, const double* part, int count, double* g,
                     double* vscale, int m, int nrhs) {
-    hipLaunchKernelGGL(k_fg_begin, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, g, vscale, m,
-                       nrhs);
+    hipLaunchKernelGGL(k_fg_begin, dim3(nrhs), dim3(VT), 0, s, sc, part, count, g, vscale, m);
     return hipGetLastError();
 }
 hipError_t fg_h(hipStream_t s, FgScalars* sc, const double* part, int count, double* H,
@@ -818,7 +871,7 @@ hipError_t fg_solve(hipStream_t s, const FgScalars* sc, const double* H, const d
 }
 hipError_t fg_check(hipStream_t s, FgScalars* sc, const double* part, int count, double tol,
                     int nrhs) {
-    hipLaunchKernelGGL(k_fg_check, dim3(1), rhs_block(nrhs), 0, s, sc, part, count, tol, nrhs);
+    hipLaunchKernelGGL(k_fg_check, dim3(nrhs), dim3(VT), 0, s, sc, part, count, tol);
     return hipGetLastError();
 }
 hipError_t vec_multidot_partials(hipStream_t s, long long n, long long ld, const double* X,
