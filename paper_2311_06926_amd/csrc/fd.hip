@@ -124,22 +124,106 @@ struct XYArgs {
     double ca, cb, cc;
 };
 
-// Element e of plane k (right-hand side r) of the forward input of field f,
-// x pointing at that plane of in[f]: x[e], or the combination
-// ca in + cb inb + cc inc, formed in the operation order of the vector
-// kernel k_axpbypcz so that it equals reading a materialised result.
-template <typename TI>
-__device__ __forceinline__ TI xy_input(const XYArgs& a, int f, const TI* x, int r, long long kofs,
-                                       long long e) {
+// Global-to-LDS staging and the write-outs run in batches: a thread issues
+// the loads of FD_BATCH elements before it uses any of them, so that their
+// latencies overlap (a load, its wait and the LDS write per element in turn
+// would add them up).  Indices past the end are clamped for the load and
+// their values dropped, so no load leaves the array.
+constexpr int FD_BATCH = 8;
+
+// Plane k of field f (n1 x n2 at x) into S, column-major with leading
+// dimension ld, zero padded to N1 x N2.  The forward input is x itself or,
+// when inb[f] is set, the combination ca x + cb inb + cc inc (the same
+// layout; terms with a zero coefficient are not read), formed in the
+// operation order of the vector kernel k_axpbypcz so that it equals reading
+// a materialised result.
+template <typename T, typename TI, int NTH>
+__device__ __forceinline__ void xy_stage(const XYArgs& a, int f, const TI* x, int r,
+                                         long long kofs, T* S, int ld, int n1, int n2, int N1,
+                                         int N2) {
+    const int n = n1 * n2;
+    // the combination's three loads are issued before its arithmetic
+    const double* xb = nullptr;
+    const double* xc = nullptr;
     if constexpr (std::is_same<TI, double>::value) {
         if (a.inb[f]) {
-            double v = a.ca * x[e];
-            if (a.cb != 0.0) v += a.cb * a.inb[f][(long long)r * a.sinb[f] + kofs + e];
-            if (a.cc != 0.0) v += a.cc * a.inc[f][(long long)r * a.sinc[f] + kofs + e];
-            return v;
+            if (a.cb != 0.0) xb = a.inb[f] + (long long)r * a.sinb[f] + kofs;
+            if (a.cc != 0.0) xc = a.inc[f] + (long long)r * a.sinc[f] + kofs;
         }
     }
-    return x[e];
+    const bool comb = std::is_same<TI, double>::value && a.inb[f] != nullptr;
+    for (int base = 0; base < n; base += FD_BATCH * NTH) {
+        TI vx[FD_BATCH];
+        double vb[FD_BATCH], vc[FD_BATCH];
+#pragma unroll
+        for (int u = 0; u < FD_BATCH; ++u) vx[u] = x[min(base + u * NTH + (int)threadIdx.x, n - 1)];
+        if (xb)
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u)
+                vb[u] = xb[min(base + u * NTH + (int)threadIdx.x, n - 1)];
+        if (xc)
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u)
+                vc[u] = xc[min(base + u * NTH + (int)threadIdx.x, n - 1)];
+#pragma unroll
+        for (int u = 0; u < FD_BATCH; ++u) {
+            const int idx = base + u * NTH + (int)threadIdx.x;
+            if (idx < n) {
+                T v;
+                if (comb) {
+                    double c = a.ca * (double)vx[u];
+                    if (xb) c += a.cb * vb[u];
+                    if (xc) c += a.cc * vc[u];
+                    v = (T)c;
+                } else {
+                    v = (T)vx[u];
+                }
+                const int col = idx / n1;
+                S[col * ld + (idx - col * n1)] = v;
+            }
+        }
+    }
+    const int pr = N1 - n1;
+    for (int idx = threadIdx.x; idx < pr * N2; idx += NTH) {
+        const int col = idx / pr;
+        S[col * ld + n1 + (idx - col * pr)] = T(0);
+    }
+    for (int idx = threadIdx.x; idx < n1 * (N2 - n2); idx += NTH) {
+        const int c = idx / n1;
+        S[(n2 + c) * ld + (idx - c * n1)] = T(0);
+    }
+}
+
+// Rows [r0, r0 + ZR) of field f (rows of length n3 at stride `plane` in x,
+// none at or past `plane`) into S, row-major with leading dimension ld, zero
+// padded to N3 columns and for the missing rows.
+template <typename T, typename TI, int NTH, int ZR>
+__device__ __forceinline__ void z_stage(const TI* x, long long r0, long long plane, int n3,
+                                        int N3, T* S, int ld) {
+    const int n = ZR * n3;
+    for (int base = 0; base < n; base += FD_BATCH * NTH) {
+        T v[FD_BATCH];
+#pragma unroll
+        for (int u = 0; u < FD_BATCH; ++u) {
+            const int idx = base + u * NTH + (int)threadIdx.x;
+            const int kk = idx / ZR, row = idx - kk * ZR;
+            const bool ok = idx < n && r0 + row < plane;
+            const T e = (T)x[ok ? r0 + row + (long long)kk * plane : r0];
+            v[u] = ok ? e : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < FD_BATCH; ++u) {
+            const int idx = base + u * NTH + (int)threadIdx.x;
+            if (idx < n) {
+                const int kk = idx / ZR, row = idx - kk * ZR;
+                S[row * ld + kk] = v[u];
+            }
+        }
+    }
+    for (int idx = threadIdx.x; idx < ZR * (N3 - n3); idx += NTH) {
+        const int kk = idx / ZR, row = idx - kk * ZR;
+        S[row * ld + n3 + kk] = T(0);
+    }
 }
 
 // The final write-out of plane k of field f from the column-major plane S
@@ -150,16 +234,30 @@ template <typename T, typename TO, int NTH>
 __device__ __forceinline__ void xy_store(const XYArgs& a, T* S, int ld, int f, int r, int k,
                                          int n1, int n2) {
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + (long long)k * n1 * n2;
+    const int n = n1 * n2;
     if constexpr (std::is_same<TO, double>::value) {
         if (a.dpart) {
             const double* w = a.dw[f] + (long long)r * a.sout[f] + (long long)k * n1 * n2;
             double s = 0.0;
-            for (int idx = threadIdx.x; idx < n1 * n2; idx += NTH) {
-                int col = idx / n1, row = idx - col * n1;
-                double v = (double)S[col * ld + row];
-                if (a.accumulate) v += y[idx];
-                y[idx] = v;
-                s += v * w[idx];
+            for (int base = 0; base < n; base += FD_BATCH * NTH) {
+                double yv[FD_BATCH], wv[FD_BATCH];
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int e = min(base + u * NTH + (int)threadIdx.x, n - 1);
+                    yv[u] = a.accumulate ? y[e] : 0.0;
+                    wv[u] = w[e];
+                }
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int idx = base + u * NTH + (int)threadIdx.x;
+                    if (idx < n) {
+                        const int col = idx / n1, row = idx - col * n1;
+                        double v = (double)S[col * ld + row];
+                        if (a.accumulate) v += yv[u];
+                        y[idx] = v;
+                        s += v * wv[u];
+                    }
+                }
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -175,11 +273,25 @@ __device__ __forceinline__ void xy_store(const XYArgs& a, T* S, int ld, int f, i
             return;
         }
     }
-    for (int idx = threadIdx.x; idx < n1 * n2; idx += NTH) {
+    if (a.accumulate) {
+        for (int base = 0; base < n; base += FD_BATCH * NTH) {
+            TO yv[FD_BATCH];
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) yv[u] = y[min(base + u * NTH + (int)threadIdx.x, n - 1)];
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) {
+                const int idx = base + u * NTH + (int)threadIdx.x;
+                if (idx < n) {
+                    const int col = idx / n1, row = idx - col * n1;
+                    y[idx] = yv[u] + (TO)S[col * ld + row];
+                }
+            }
+        }
+        return;
+    }
+    for (int idx = threadIdx.x; idx < n; idx += NTH) {
         int col = idx / n1, row = idx - col * n1;
-        TO v = (TO)S[col * ld + row];
-        if (a.accumulate) y[idx] += v;
-        else y[idx] = v;
+        y[idx] = (TO)S[col * ld + row];
     }
 }
 
@@ -223,12 +335,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_xy(XYArgs a, FDTables<T> t) {
     const long long kofs = (long long)k * n1 * n2;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
     // load plane (zero padded)
-    for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_THREADS) {
-        int col = idx / N1, row = idx - col * N1;
-        T v = 0;
-        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
-        S[col * ld + row] = v;
-    }
+    xy_stage<T, TI, FD_THREADS>(a, f, x, r, kofs, S, ld, n1, n2, N1, N2);
     __syncthreads();
     const T* L = xy_left(t, f, a.inverse);
     const T* R = xy_right(t, f, a.inverse);
@@ -307,18 +414,35 @@ template <typename T, typename TO, int NTH, int ZR = ZROWS>
 __device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int ld, int f, int r,
                                         long long r0, long long plane, int n3) {
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f];
+    const int n = ZR * n3;
+    const bool acc = (a.accumulate >> f) & 1;
     if constexpr (std::is_same<TO, double>::value) {
         if (a.dpart) {
             const double* w = a.dw + (long long)r * a.sout[f];
             double s = 0.0;
-            for (int idx = threadIdx.x; idx < ZR * n3; idx += NTH) {
-                int kk = idx / ZR, row = idx - kk * ZR;
-                if (r0 + row >= plane) continue;
-                long long o = r0 + row + (long long)kk * plane;
-                double v = (double)Out[row * ld + kk];
-                if ((a.accumulate >> f) & 1) v += y[o];
-                y[o] = v;
-                s += v * w[o];
+            for (int base = 0; base < n; base += FD_BATCH * NTH) {
+                double yv[FD_BATCH], wv[FD_BATCH];
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int idx = base + u * NTH + (int)threadIdx.x;
+                    const int kk = idx / ZR, row = idx - kk * ZR;
+                    const long long o =
+                        idx < n && r0 + row < plane ? r0 + row + (long long)kk * plane : r0;
+                    yv[u] = acc ? y[o] : 0.0;
+                    wv[u] = w[o];
+                }
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int idx = base + u * NTH + (int)threadIdx.x;
+                    const int kk = idx / ZR, row = idx - kk * ZR;
+                    if (idx < n && r0 + row < plane) {
+                        const long long o = r0 + row + (long long)kk * plane;
+                        double v = (double)Out[row * ld + kk];
+                        if (acc) v += yv[u];
+                        y[o] = v;
+                        s += v * wv[u];
+                    }
+                }
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -334,13 +458,29 @@ __device__ __forceinline__ void z_store(const ZArgs& a, const T* Out, T* S, int 
             return;
         }
     }
-    for (int idx = threadIdx.x; idx < ZR * n3; idx += NTH) {
+    if (acc) {
+        for (int base = 0; base < n; base += FD_BATCH * NTH) {
+            TO yv[FD_BATCH];
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) {
+                const int idx = base + u * NTH + (int)threadIdx.x;
+                const int kk = idx / ZR, row = idx - kk * ZR;
+                yv[u] = y[idx < n && r0 + row < plane ? r0 + row + (long long)kk * plane : r0];
+            }
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) {
+                const int idx = base + u * NTH + (int)threadIdx.x;
+                const int kk = idx / ZR, row = idx - kk * ZR;
+                if (idx < n && r0 + row < plane)
+                    y[r0 + row + (long long)kk * plane] = yv[u] + (TO)Out[row * ld + kk];
+            }
+        }
+        return;
+    }
+    for (int idx = threadIdx.x; idx < n; idx += NTH) {
         int kk = idx / ZR, row = idx - kk * ZR;
         if (r0 + row >= plane) continue;
-        TO v = (TO)Out[row * ld + kk];
-        long long o = r0 + row + (long long)kk * plane;
-        if ((a.accumulate >> f) & 1) y[o] += v;
-        else y[o] = v;
+        y[r0 + row + (long long)kk * plane] = (TO)Out[row * ld + kk];
     }
 }
 
@@ -364,12 +504,7 @@ __global__ __launch_bounds__(FD_THREADS) void k_fd_z(ZArgs a, FDTables<T> t) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f];
-    for (int idx = threadIdx.x; idx < ZROWS * N3; idx += FD_THREADS) {
-        int kk = idx / ZROWS, row = idx - kk * ZROWS;
-        T v = 0;
-        if (kk < n3 && r0 + row < plane) v = (T)x[r0 + row + (long long)kk * plane];
-        S[row * ld + kk] = v;
-    }
+    z_stage<T, TI, FD_THREADS, ZROWS>(x, r0, plane, n3, N3, S, ld);
     const bool pres = (f == 3);
     const T* U3 = pres ? t.Mi : (f == 2 ? t.UK : t.UT);
     const T* U3t = pres ? t.Mi : (f == 2 ? t.UKt : t.UTt);
@@ -649,12 +784,7 @@ __global__ __launch_bounds__(FD_WIDE) void k_fd_xy_w(XYArgs a, FDTables<T> t) {
     const int lr = lane & 15, lk = lane >> 4;
     const long long kofs = (long long)k * n1 * n2;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
-    for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_WIDE) {
-        int col = idx / N1, row = idx - col * N1;
-        T v = 0;
-        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
-        S[col * ld + row] = v;
-    }
+    xy_stage<T, TI, FD_WIDE>(a, f, x, r, kofs, S, ld, n1, n2, N1, N2);
     // L (rows contiguous) for step 1 and R^T (rows of R^T = columns of R) for step 2
     const T* L = xy_left(t, f, a.inverse);
     const T* Rt = xy_right_t(t, f, a.inverse);
@@ -800,12 +930,7 @@ __global__ __launch_bounds__(FD_SPLIT) void k_fd_xy_s(XYArgs a, FDTables<T> t) {
     const int lr = lane & 15, lk = lane >> 4;
     const long long kofs = (long long)k * n1 * n2;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f] + kofs;
-    for (int idx = threadIdx.x; idx < N1 * N2; idx += FD_SPLIT) {
-        int col = idx / N1, row = idx - col * N1;
-        T v = 0;
-        if (row < n1 && col < n2) v = (T)xy_input(a, f, x, r, kofs, row + (long long)col * n1);
-        S[col * ld + row] = v;
-    }
+    xy_stage<T, TI, FD_SPLIT>(a, f, x, r, kofs, S, ld, n1, n2, N1, N2);
     T* Tb = S + N2 * ld;  // Tb[col * TBP + i]: row 16 rb + i of T (and later of Y)
     const T* L = xy_left(t, f, a.inverse);
     const T* Rt = xy_right_t(t, f, a.inverse);
@@ -846,20 +971,33 @@ __global__ __launch_bounds__(FD_SPLIT) void k_fd_xy_s(XYArgs a, FDTables<T> t) {
     }
     __syncthreads();
     // write-out of rows [16 rb, min(n1, 16 rb + 16)), as xy_store for one row block
-    const int rows = min(16, n1 - 16 * rb);
+    const int rows = min(16, n1 - 16 * rb), n = 16 * n2;
     TO* y = reinterpret_cast<TO*>(a.out[f]) + (long long)r * a.sout[f] + kofs + 16 * rb;
     if constexpr (std::is_same<TO, double>::value) {
         if (a.dpart) {
             const double* w = a.dw[f] + (long long)r * a.sout[f] + kofs + 16 * rb;
             double s = 0.0;
-            for (int idx = threadIdx.x; idx < 16 * n2; idx += FD_SPLIT) {
-                const int col = idx >> 4, i = idx & 15;
-                if (i >= rows) continue;
-                const long long o = i + (long long)col * n1;
-                double v = (double)Tb[col * TBP + i];
-                if (a.accumulate) v += y[o];
-                y[o] = v;
-                s += v * w[o];
+            for (int base = 0; base < n; base += FD_BATCH * FD_SPLIT) {
+                double yv[FD_BATCH], wv[FD_BATCH];
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int idx = base + u * FD_SPLIT + (int)threadIdx.x;
+                    const int col = idx >> 4, i = idx & 15;
+                    const long long o = idx < n && i < rows ? i + (long long)col * n1 : 0;
+                    yv[u] = a.accumulate ? y[o] : 0.0;
+                    wv[u] = w[o];
+                }
+#pragma unroll
+                for (int u = 0; u < FD_BATCH; ++u) {
+                    const int idx = base + u * FD_SPLIT + (int)threadIdx.x;
+                    const int col = idx >> 4, i = idx & 15;
+                    if (idx < n && i < rows) {
+                        double v = (double)Tb[col * TBP + i];
+                        if (a.accumulate) v += yv[u];
+                        y[i + (long long)col * n1] = v;
+                        s += v * wv[u];
+                    }
+                }
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
@@ -873,13 +1011,28 @@ __global__ __launch_bounds__(FD_SPLIT) void k_fd_xy_s(XYArgs a, FDTables<T> t) {
             return;
         }
     }
-    for (int idx = threadIdx.x; idx < 16 * n2; idx += FD_SPLIT) {
+    if (a.accumulate) {
+        for (int base = 0; base < n; base += FD_BATCH * FD_SPLIT) {
+            TO yv[FD_BATCH];
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) {
+                const int idx = base + u * FD_SPLIT + (int)threadIdx.x;
+                const int col = idx >> 4, i = idx & 15;
+                yv[u] = y[idx < n && i < rows ? i + (long long)col * n1 : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < FD_BATCH; ++u) {
+                const int idx = base + u * FD_SPLIT + (int)threadIdx.x;
+                const int col = idx >> 4, i = idx & 15;
+                if (idx < n && i < rows) y[i + (long long)col * n1] = yv[u] + (TO)Tb[col * TBP + i];
+            }
+        }
+        return;
+    }
+    for (int idx = threadIdx.x; idx < n; idx += FD_SPLIT) {
         const int col = idx >> 4, i = idx & 15;
         if (i >= rows) continue;
-        const long long o = i + (long long)col * n1;
-        const TO v = (TO)Tb[col * TBP + i];
-        if (a.accumulate) y[o] += v;
-        else y[o] = v;
+        y[i + (long long)col * n1] = (TO)Tb[col * TBP + i];
     }
 }
 
@@ -908,12 +1061,7 @@ __global__ __launch_bounds__(NTH) void k_fd_z_w(ZArgs a, FDTables<T> t) {
     const int lr = lane & 15, lk = lane >> 4;
     T* Y = S + ZR * ld;
     const TI* x = reinterpret_cast<const TI*>(a.in[f]) + (long long)r * a.sin[f];
-    for (int idx = threadIdx.x; idx < ZR * N3; idx += NTH) {
-        int kk = idx / ZR, row = idx - kk * ZR;
-        T v = 0;
-        if (kk < n3 && r0 + row < plane) v = (T)x[r0 + row + (long long)kk * plane];
-        S[row * ld + kk] = v;
-    }
+    z_stage<T, TI, NTH, ZR>(x, r0, plane, n3, N3, S, ld);
     const bool pres = (f == 3);
     const T* U3 = pres ? t.Mi : (f == 2 ? t.UK : t.UT);
     const T* U3t = pres ? t.Mi : (f == 2 ? t.UKt : t.UTt);
