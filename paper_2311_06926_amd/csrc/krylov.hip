@@ -128,17 +128,29 @@ __global__ void k_dot_partial(long long n, long long ld, const double* X, long l
 #pragma unroll
         for (int qq = 0; qq < DOT_QB; ++qq) s[c][qq] = 0.0;
     // the chunks side by side, each summed in its own order: thread t takes
-    // elements t, t + VT, ... of every chunk
-    for (long long k = threadIdx.x; k < chunk; k += blockDim.x) {
+    // elements t, t + VT, ... of every chunk, DOT_U of them at a time with
+    // all their loads issued before the first product (an index past the
+    // chunk is clamped for the load and its product skipped)
+    constexpr int DOT_U = 4;
+    for (long long k0 = threadIdx.x; k0 < chunk; k0 += DOT_U * VT) {
 #pragma unroll
         for (int c = 0; c < CPB; ++c) {
-            const long long i = lo[c] + k;
-            if (i < hi[c]) {
-                const double yv = y[i];
+            double yv[DOT_U], xv[DOT_U][DOT_QB];
+#pragma unroll
+            for (int u = 0; u < DOT_U; ++u) {
+                const long long i = lo[c] + k0 + u * VT;
+                const long long ic = i < hi[c] ? i : lo[c];
+                yv[u] = y[ic];
 #pragma unroll
                 for (int qq = 0; qq < DOT_QB; ++qq)
-                    if (qq < nq) s[c][qq] += x[qq * xstride + i] * yv;
+                    if (qq < nq) xv[u][qq] = x[qq * xstride + ic];
             }
+#pragma unroll
+            for (int u = 0; u < DOT_U; ++u)
+                if (lo[c] + k0 + u * VT < hi[c])
+#pragma unroll
+                    for (int qq = 0; qq < DOT_QB; ++qq)
+                        if (qq < nq) s[c][qq] += xv[u][qq] * yv[u];
         }
     }
     // all sums of the workgroup in one reduction: wave trees, then thread v
