@@ -100,6 +100,18 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
+// s + p[t] + p[t + VT] + p[t + 2 VT] + ... over the indices below count
+// (t = threadIdx.x, a workgroup of VT threads), in that order; the first two
+// are loaded together so that their latencies overlap.
+__device__ __forceinline__ double strided_sum(const double* p, long long count, double s) {
+    const long long t = threadIdx.x;
+    const double a = p[t < count ? t : 0], b = p[t + VT < count ? t + VT : 0];
+    if (t < count) s += a;
+    if (t + VT < count) s += b;
+    for (long long i = t + 2 * VT; i < count; i += VT) s += p[i];
+    return s;
+}
+
 // partial[(r*npair + q)*nb + b] = sum over chunk b of x_q . y (x_q = X +
 // q*xstride, one y per rhs; nb = dot_blocks(n) chunks of the vector).  A
 // workgroup takes DOT_QB pairs of CPB consecutive chunks, so y is read once
@@ -189,7 +201,7 @@ __global__ void k_dot_final(const double* partial, int count, double* out) {
     __shared__ double sh[VT / 64];
     const long long base = (long long)blockIdx.x * count;
     double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += blockDim.x) s += partial[base + i];
+    s = strided_sum(partial + base, count, s);
     s = block_sum(s, sh);
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
@@ -350,7 +362,7 @@ namespace {
 // thread 0 then takes the scalar step.  The result is valid in thread 0.
 __device__ double sum_partials(const double* part, int count, int q, double* sh) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += VT) s += part[(long long)q * count + i];
+    s = strided_sum(part + (long long)q * count, count, s);
     return block_sum(s, sh);
 }
 
@@ -516,9 +528,8 @@ __global__ void k_cg_beta(CgScalars* sc, const double* part_rz, int count, doubl
 // sum of those is valid in thread 0.  The order depends only on the counts.
 __device__ __forceinline__ double sum_block_partials(Partials a, Partials b, int r, double* sh) {
     double s = 0.0;
-    for (long long i = threadIdx.x; i < a.count; i += VT) s += a.part[r * a.count + i];
-    if (b.part)
-        for (long long i = threadIdx.x; i < b.count; i += VT) s += b.part[r * b.count + i];
+    s = strided_sum(a.part + r * a.count, a.count, s);
+    if (b.part) s = strided_sum(b.part + r * b.count, b.count, s);
     return block_sum(s, sh);
 }
 
@@ -589,13 +600,36 @@ __global__ void k_minres_wv(long long n, long long ld, const double* kz, const d
     // both dot products in one reduction, each in the order of
     // sum_block_partials: this thread's strided partials (set a, then set
     // b), the wave tree, then the waves in order
+    // (the first two strided partials of every set are loaded together
+    // before any is added: a loop per set would wait for each in turn)
+    double fa[2] = {0.0, 0.0}, fb[2] = {0.0, 0.0}, fk[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const long long q = threadIdx.x + u * VT;
+        if (prev) {
+            fa[u] = pa.part[r * pa.count + (q < pa.count ? q : 0)];
+            if (pb.part) fb[u] = pb.part[r * pb.count + (q < pb.count ? q : 0)];
+        }
+        fk[u] = pkz.part[r * pkz.count + (q < pkz.count ? q : 0)];
+    }
     double szv = 0.0, skz = 0.0;
     if (prev) {
-        for (long long q = threadIdx.x; q < pa.count; q += VT) szv += pa.part[r * pa.count + q];
-        if (pb.part)
-            for (long long q = threadIdx.x; q < pb.count; q += VT) szv += pb.part[r * pb.count + q];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (threadIdx.x + u * VT < pa.count) szv += fa[u];
+        for (long long q = threadIdx.x + 2 * VT; q < pa.count; q += VT) szv += pa.part[r * pa.count + q];
+        if (pb.part) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (threadIdx.x + u * VT < pb.count) szv += fb[u];
+            for (long long q = threadIdx.x + 2 * VT; q < pb.count; q += VT)
+                szv += pb.part[r * pb.count + q];
+        }
     }
-    for (long long q = threadIdx.x; q < pkz.count; q += VT) skz += pkz.part[r * pkz.count + q];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (threadIdx.x + u * VT < pkz.count) skz += fk[u];
+    for (long long q = threadIdx.x + 2 * VT; q < pkz.count; q += VT) skz += pkz.part[r * pkz.count + q];
     szv = wave_sum(szv);
     skz = wave_sum(skz);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -740,7 +774,7 @@ __global__ void k_fg_h(FgScalars* sc, const double* part, int count, double* H, 
     const int i = blockIdx.x, r = blockIdx.y;
     const long long base = ((long long)r * (j + 1) + i) * count;
     double hs = 0.0;
-    for (int q = threadIdx.x; q < count; q += VT) hs += part[base + q];
+    hs = strided_sum(part + base, count, hs);
     const double h = block_sum(hs, sh);
     if (threadIdx.x != 0) return;
     const bool active = sc[r].active;
@@ -810,7 +844,7 @@ __global__ void k_fg_rot(FgScalars* sc, const double* part_ww, int count, double
     __shared__ double sh[VT / 64];
     const int r = blockIdx.x;
     double ws = 0.0;
-    for (int q = threadIdx.x; q < count; q += VT) ws += part_ww[(long long)r * count + q];
+    ws = strided_sum(part_ww + (long long)r * count, count, ws);
     const double ww = block_sum(ws, sh);
     if (threadIdx.x != 0) return;
     fg_rot_one(sc, ww, H, cs, sn, g, vscale, tol, bd_tol, j, m, r);
