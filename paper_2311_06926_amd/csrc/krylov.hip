@@ -114,87 +114,73 @@ __device__ __forceinline__ double strided_sum(const double* p, long long count, 
 
 // partial[(r*npair + q)*nb + b] = sum over chunk b of x_q . y (x_q = X +
 // q*xstride, one y per rhs; nb = dot_blocks(n) chunks of the vector).  A
-// workgroup takes DOT_QB pairs of CPB consecutive chunks, so y is read once
-// per DOT_QB pairs; each chunk's sum runs in the same order whatever the
-// launch shape (a batch gives the same partials as its right-hand sides one
-// at a time).
+// workgroup takes DOT_QB pairs of one chunk, so y is read once per DOT_QB
+// pairs; each chunk's sum runs in the same order whatever the number of
+// pairs or right-hand sides (a batch gives the same partials as its
+// right-hand sides one at a time).
 constexpr int DOT_QB = 8;
-template <int CPB>
 __global__ void k_dot_partial(long long n, long long ld, const double* X, long long xstride,
                               int npair, const double* Y, int nb, double* partial) {
-    __shared__ double sh[VT / 64][CPB * DOT_QB];
+    __shared__ double sh[VT / 64][DOT_QB];
     const int r = blockIdx.z, q0 = blockIdx.y * DOT_QB;
     const int nq = min(DOT_QB, npair - q0);
     const double* x = X + (long long)q0 * xstride + (long long)r * ld;
     const double* y = Y + (long long)r * ld;
     const long long chunk = (n + nb - 1) / nb;
-    long long lo[CPB], hi[CPB];
+    const long long lo = (long long)blockIdx.x * chunk;
+    const long long hi = min(n, lo + chunk);
+    double s[DOT_QB];
 #pragma unroll
-    for (int c = 0; c < CPB; ++c) {
-        lo[c] = (long long)(blockIdx.x * CPB + c) * chunk;
-        hi[c] = min(n, lo[c] + chunk);
-    }
-    double s[CPB][DOT_QB];
-#pragma unroll
-    for (int c = 0; c < CPB; ++c)
-#pragma unroll
-        for (int qq = 0; qq < DOT_QB; ++qq) s[c][qq] = 0.0;
-    // the chunks side by side, each summed in its own order: thread t takes
-    // elements t, t + VT, ... of every chunk, DOT_U of them at a time with
-    // all their loads issued before the first product (an index past the
-    // chunk is clamped for the load and its product skipped)
+    for (int qq = 0; qq < DOT_QB; ++qq) s[qq] = 0.0;
+    // thread t takes elements t, t + VT, ... of the chunk, DOT_U of them at
+    // a time with all their loads issued before the first product (an index
+    // past the chunk is clamped for the load and its product skipped)
     constexpr int DOT_U = 4;
     for (long long k0 = threadIdx.x; k0 < chunk; k0 += DOT_U * VT) {
+        double yv[DOT_U], xv[DOT_U][DOT_QB];
 #pragma unroll
-        for (int c = 0; c < CPB; ++c) {
-            double yv[DOT_U], xv[DOT_U][DOT_QB];
+        for (int u = 0; u < DOT_U; ++u) {
+            const long long i = lo + k0 + u * VT;
+            const long long ic = i < hi ? i : lo;
+            yv[u] = y[ic];
 #pragma unroll
-            for (int u = 0; u < DOT_U; ++u) {
-                const long long i = lo[c] + k0 + u * VT;
-                const long long ic = i < hi[c] ? i : lo[c];
-                yv[u] = y[ic];
+            for (int qq = 0; qq < DOT_QB; ++qq)
+                if (qq < nq) xv[u][qq] = x[qq * xstride + ic];
+        }
+#pragma unroll
+        for (int u = 0; u < DOT_U; ++u)
+            if (lo + k0 + u * VT < hi)
 #pragma unroll
                 for (int qq = 0; qq < DOT_QB; ++qq)
-                    if (qq < nq) xv[u][qq] = x[qq * xstride + ic];
-            }
-#pragma unroll
-            for (int u = 0; u < DOT_U; ++u)
-                if (lo[c] + k0 + u * VT < hi[c])
-#pragma unroll
-                    for (int qq = 0; qq < DOT_QB; ++qq)
-                        if (qq < nq) s[c][qq] += xv[u][qq] * yv[u];
-        }
+                    if (qq < nq) s[qq] += xv[u][qq] * yv[u];
     }
     // all sums of the workgroup in one reduction: wave trees, then thread v
     // adds the waves' results of sum v in wave order (as block_sum does)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < CPB; ++c)
-#pragma unroll
-        for (int qq = 0; qq < DOT_QB; ++qq) {
-            if (qq >= nq) break;  // uniform over the workgroup
-            const double v = wave_sum(s[c][qq]);
-            if (lane == 0) sh[wave][c * DOT_QB + qq] = v;
-        }
+    for (int qq = 0; qq < DOT_QB; ++qq) {
+        if (qq >= nq) break;  // uniform over the workgroup
+        const double v = wave_sum(s[qq]);
+        if (lane == 0) sh[wave][qq] = v;
+    }
     __syncthreads();
     const int v = threadIdx.x;
-    if (v < CPB * DOT_QB && v % DOT_QB < nq) {
+    if (v < nq) {
         double t = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w][v];
-        const int b = blockIdx.x * CPB + v / DOT_QB;
-        partial[((long long)r * npair + q0 + v % DOT_QB) * nb + b] = t;
+        partial[((long long)r * npair + q0 + v) * nb + blockIdx.x] = t;
     }
 }
 // k_dot_partial over npair pairs and nrhs right-hand sides, one chunk per
-// workgroup (two chunks per workgroup for batches, measured: 48^3 x 32
-// FGMRES 102.5 -> 108 ms; the partials would be the same)
+// workgroup (two chunks per workgroup for batches, the same partials with
+// half the workgroups, was measured slower: 48^3 x 32 FGMRES 102.5 -> 108 ms)
 inline void dot_partial_launch(hipStream_t s, long long n, long long ld, const double* X,
                                long long xstride, int npair, const double* Y, int nrhs,
                                double* partial) {
     const unsigned groups = (unsigned)((npair + DOT_QB - 1) / DOT_QB);
     const int nb = dot_blocks(n);
-    hipLaunchKernelGGL(k_dot_partial<1>, dim3(nb, groups, nrhs), dim3(VT), 0, s, n, ld, X,
-                       xstride, npair, Y, nb, partial);
+    hipLaunchKernelGGL(k_dot_partial, dim3(nb, groups, nrhs), dim3(VT), 0, s, n, ld, X, xstride,
+                       npair, Y, nb, partial);
 }
 
 __global__ void k_dot_final(const double* partial, int count, double* out) {

@@ -566,6 +566,31 @@ def test_row_block_plan_solve(dev, krylov):
     b.close()
 
 
+@pytest.mark.parametrize("krylov", ["minres", "fgmres"])
+def test_batched_equals_single_above_dot_chunk_switch(dev, krylov):
+    """From 2^19 unknowns on the Krylov dot products use 480 chunks per
+    vector instead of 240 (the count depends on the length alone): a batch
+    of two right-hand sides still reproduces each one's single solve bit for
+    bit, and the MINRES iterations end where the single solves end."""
+    from paper_2311_06926_amd.solver import Solver
+    E, p = 50, 3
+    say(f"[shapes] batched vs single above 2^19 unknowns E={E} p={p} {krylov}")
+    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=2)
+    ss = Solver(E, p, 1.0, iters=1, krylov=krylov)
+    N = sb.N
+    assert N >= 1 << 19
+    rhs = sb.build_rhs([1.0, -0.6])
+    xb, ib = sb.solve(rhs, 1e-8)
+    assert ib.converged == 1
+    for r in range(2):
+        xs, is_ = ss.solve(rhs[r * N:(r + 1) * N].clone(), 1e-8)
+        say(f"[shapes]   rhs {r}: {ib.iters_per_rhs[r]} / {is_.iterations} iterations")
+        assert ib.iters_per_rhs[r] == is_.iterations
+        assert torch.equal(xb[r * N:(r + 1) * N], xs)
+    sb.close()
+    ss.close()
+
+
 def test_autotuner_reports_shapes_in_range(dev):
     from paper_2311_06926_amd.solver import Solver
     E, p = 12, 3
