@@ -547,14 +547,14 @@ __global__ void k_minres_w(long long n, long long ld, const double* z, const dou
     }
 }
 
-// k_minres_v and the previous iteration's k_minres_w in one launch.  Iteration
-// j's v update and iteration j-1's w/x update both come after the partials
-// they need (j-1's (z.v) from its P_k, j's (Kz.z) from its dot) and before
-// iteration j's P_k, which overwrites j-1's z; so they share a launch:
-// every workgroup applies the rotation of j-1 (when pw is set) and then the
-// Lanczos step of j to its copy of the state, as the two kernels do one
-// after the other, and updates its slice of w_new, x and v_new.
-// Workgroup 0 writes the state to sc_out and to the host mirror.
+// Iteration j's v update and iteration j-1's rotation and w/x update (the
+// work of k_minres_w) in one launch.  Both come after the partials they
+// need (j-1's (z.v) from its P_k, j's (Kz.z) from its dot) and before
+// iteration j's P_k, which overwrites j-1's z; so every workgroup applies
+// the rotation of j-1 (when pa.part is set) and then the Lanczos step of j
+// to its copy of the state, in that order, and updates its slice of w_new,
+// x and v_new.  Workgroup 0 writes the state to sc_out and to the host
+// mirror.
 __global__ void k_minres_wv(long long n, long long ld, const double* kz, const double* v,
                             const double* vo, double* vn, const double* z, const double* wo,
                             const double* w, double* wn, double* x, const MinresScalars* sc_in,
