@@ -358,6 +358,9 @@ def main():
     ap.add_argument("--op-dma", type=int, default=-1,
                     help="--only apply_K/solve: the streaming velocity kernel's staging "
                          "(1 direct-to-LDS loads, 0 registers, -1 default)")
+    ap.add_argument("--op-pres-wide", type=int, default=-1,
+                    help="--only apply_K/solve: the streaming pressure kernel's tiles "
+                         "(1 32 x 8, 0 16 x 8, -1 tuned)")
     ap.add_argument("--fd-plan", type=int, default=-1,
                     help="--only solve/apply_P0: force the fast-diagonalisation plan (-1: tuned)")
     ap.add_argument("--forward", default="kronecker", choices=["kronecker", "quadrature"],
@@ -418,7 +421,8 @@ def main():
                      krylov="minres" if args.prec == "fp64" else "fgmres",
                      autotune=not forced, op_kchunk=args.op_kchunk, op_order=args.op_order,
                      op_slabs=1 if forced else 0, fd_plan=args.fd_plan,
-                     op_staged=args.op_staged, op_dma=args.op_dma)
+                     op_staged=args.op_staged, op_dma=args.op_dma,
+                     op_pres_wide=args.op_pres_wide)
         xr = torch.from_numpy(synth.random_vector(sol.N, 3)).to("cuda")
         yr = sol.empty(sol.N)
         fn = {"apply_K": sol.apply_K, "apply_K_quad": sol.apply_K_quad,
@@ -433,7 +437,8 @@ def main():
     forced = args.op_kchunk > 0
     sol = Solver(E, p, 1.0, order=q, iters=k, schur=args.schur, fd_plan=args.fd_plan,
                  op_kchunk=args.op_kchunk, op_order=args.op_order, op_slabs=1 if forced else 0,
-                 op_staged=args.op_staged, op_dma=args.op_dma, forward=args.forward)
+                 op_staged=args.op_staged, op_dma=args.op_dma,
+                 op_pres_wide=args.op_pres_wide, forward=args.forward)
     stream = sol.stream
     b = sol.build_rhs([1.0])
     x, info = sol.solve(b, 1e-8)

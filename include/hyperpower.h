@@ -172,6 +172,9 @@ typedef struct hp_opts {
                            1 = stage each plane's tile with direct-to-LDS loads into a ring
                            of three LDS planes (two planes in flight), 0 = stage through
                            registers (one plane in flight); same results bit for bit */
+    int op_pres_wide;   /* streaming pressure kernel (modes K, A, B, B^T): -1 = tuned/model
+                           (default), 0 = 16 x 8 tiles, 1 = 32 x 8 tiles (less halo per
+                           point, larger workgroups); same results bit for bit */
 } hp_opts;
 
 /* Launch shapes in use (host struct, filled by hp_get_tuning). */
@@ -184,6 +187,7 @@ typedef struct hp_tuning {
     double op_us;       /* tuned apply_K time (microseconds), 0 if not tuned */
     double fd_us[3];    /* tuned apply_P0 time per precision, 0 if not tuned */
     int op_staged;      /* 1 if the operator uses the all-planes velocity kernel */
+    int op_pres_wide;   /* 1 if the streaming pressure kernel runs on 32 x 8 tiles */
 } hp_tuning;
 
 /* Per-solve report (host struct, filled by hp_solve / hp_grad). */

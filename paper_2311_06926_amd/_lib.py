@@ -58,6 +58,7 @@ class hp_opts(ctypes.Structure):
         ("p0_scale", ctypes.c_double),
         ("breakdown_tol", ctypes.c_double),
         ("op_dma", ctypes.c_int),
+        ("op_pres_wide", ctypes.c_int),
     ]
 
 
@@ -71,6 +72,7 @@ class hp_tuning(ctypes.Structure):
         ("op_us", ctypes.c_double),
         ("fd_us", ctypes.c_double * 3),
         ("op_staged", ctypes.c_int),
+        ("op_pres_wide", ctypes.c_int),
     ]
 
 

@@ -1002,15 +1002,23 @@ hp_status autotune(hp_ctx* c) {
             if (kc > c->nM) break;
             for (int order = 0; order <= 1; ++order)
                 for (int slabs = 1; slabs <= 4; slabs *= 2)
-                    for (int staged = 0; staged <= 1; ++staged) {
-                        if (c->opts.op_order >= 0 && order != c->opts.op_order) continue;
-                        if (c->opts.op_slabs > 0 ? slabs != c->opts.op_slabs
-                                                 : (slabs > 1 && c->nM < 64))
-                            continue;
-                        if (c->opts.op_staged >= 0 && staged != c->opts.op_staged) continue;
-                        if (staged && !op_staged_ok(c->p, kc)) continue;
-                        shapes.push_back(OpShape{kc, order, slabs, 0, staged});
-                    }
+                    for (int staged = 0; staged <= 1; ++staged)
+                        for (int pwide = 0; pwide <= 1; ++pwide) {
+                            if (c->opts.op_order >= 0 && order != c->opts.op_order) continue;
+                            if (c->opts.op_slabs > 0 ? slabs != c->opts.op_slabs
+                                                     : (slabs > 1 && c->nM < 64))
+                                continue;
+                            if (c->opts.op_staged >= 0 && staged != c->opts.op_staged) continue;
+                            if (staged && !op_staged_ok(c->p, kc)) continue;
+                            // the 32 x 8 pressure tiles: streaming kernels, 32+ points wide
+                            if (pwide && (staged || c->nM < 32)) continue;
+                            if (c->opts.op_pres_wide >= 0 && pwide != c->opts.op_pres_wide)
+                                continue;
+                            OpShape sh{kc, order, slabs, 0, staged};
+                            sh.pwide = pwide;
+                            sh.dma = c->opts.op_dma != 0;
+                            shapes.push_back(sh);
+                        }
         }
         std::vector<double> us(shapes.size(), -1.0);
         for (int pass = 0; pass < TUNE_PASSES && st == HP_OK; ++pass)
@@ -1302,6 +1310,7 @@ void hp_default_opts(hp_opts* o) {
     o->p0_scale = 1.0;
     o->breakdown_tol = 0.0;
     o->op_dma = -1;
+    o->op_pres_wide = -1;
 }
 
 const char* hp_status_string(hp_status s) {
@@ -1333,7 +1342,7 @@ hp_status hp_setup(int elements, int degree, double nu, const hp_opts* opts, voi
         o.schur_level > KMAX || o.schur_variant < HP_SCHUR_PCQ1 || o.schur_variant > HP_SCHUR_PCG ||
         o.schur_pcg_iters < 1 || o.schur_pcg_iters > 1000 || !(o.schur_pcg_tol >= 0.0) ||
         o.op_fused < -1 || o.op_fused > 1 || o.op_staged < -1 || o.op_staged > 1 ||
-        o.op_dma < -1 || o.op_dma > 1 ||
+        o.op_dma < -1 || o.op_dma > 1 || o.op_pres_wide < -1 || o.op_pres_wide > 1 ||
         o.use_graph < 0 || o.use_graph > 1 || o.poll_lag < 1 || o.poll_lag > 3 ||
         o.forward < 0 || o.forward > 1 || o.use_x0 < 0 || o.use_x0 > 1 || o.spectrum_gate < 0 ||
         !(o.p0_scale >= 0.0) || !std::isfinite(o.p0_scale) || !(o.breakdown_tol >= 0.0))
@@ -1560,6 +1569,7 @@ hp_status hp_get_tuning(const hp_ctx* c, int nrhs, hp_tuning* out) {
     out->op_order = sh.comp_fast;
     out->op_slabs = std::max(1, std::min(sh.slabs, c->nM));
     out->op_staged = sh.staged && !sh.fused && op_staged_ok(c->p, out->op_kchunk) ? 1 : 0;
+    out->op_pres_wide = sh.pwide && !sh.fused && !out->op_staged ? 1 : 0;
     out->op_tuned = 0;
     out->op_us = 0.0;
     for (int e = 0; e < 2; ++e)

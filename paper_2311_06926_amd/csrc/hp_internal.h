@@ -55,6 +55,7 @@ struct OpShape {
     int fused = 0;  // K and A in one single-pass kernel (k_fused)
     int staged = 0;  // K and A velocity: all planes of a chunk at once (k_vel_all)
     int dma = 1;     // streaming velocity kernel: staging by direct-to-LDS loads (k_vel_dma)
+    int pwide = 0;   // streaming pressure kernel on 32 x 8 tiles instead of 16 x 8
 };
 struct OpTuned {
     int nrhs = 0;

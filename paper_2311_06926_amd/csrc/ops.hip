@@ -146,12 +146,13 @@ constexpr int waves_for() {
     return P < 4 ? 4 : (P == 4 ? 3 : 2);
 }
 
-template <int P>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>()))) void k_pres(OpArgs a, double* yp, long long syp) {
+template <int P, int PT1, int PT2>
+__global__ __launch_bounds__(PT1 * PT2) __attribute__((amdgpu_waves_per_eu(waves_for<P>()))) void k_pres(OpArgs a, double* yp, long long syp) {
+    constexpr int PNT = PT1 * PT2;
     constexpr int W = P - 1;
-    constexpr int SW = T1 + 2 * W, SR = T2 + 2 * W;
-    constexpr int NS = (SR * SW + NT - 1) / NT;  // staging slots per thread
-    __shared__ double gs[SR * SW], zs[SR * SW], pg[SR * T1], pz[SR * T1];
+    constexpr int SW = PT1 + 2 * W, SR = PT2 + 2 * W;
+    constexpr int NS = (SR * SW + PNT - 1) / PNT;  // staging slots per thread
+    __shared__ double gs[SR * SW], zs[SR * SW], pg[SR * PT1], pz[SR * PT1];
     const int nM = a.nM, nN = a.nN;
     int id = xcd_block(blockIdx.x, a.nblocks);
     const int t1 = id % a.ntile1;
@@ -160,9 +161,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     id /= a.ntile2;
     const int ch = id % a.nchunk;
     const int r = id / a.nchunk;
-    const int i0 = t1 * T1, j0 = t2 * T2, k0 = a.kbase + ch * a.kchunk;
+    const int i0 = t1 * PT1, j0 = t2 * PT2, k0 = a.kbase + ch * a.kchunk;
     const int kend = min(min(k0 + a.kchunk, a.klim), nM);
-    const int c = threadIdx.x % T1, g = threadIdx.x / T1;
+    const int c = threadIdx.x % PT1, g = threadIdx.x / PT1;
     const int i = i0 + c, j = j0 + g;
     const bool act = i < nM && j < nM;
     const int mode = a.mode;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     uint32_t oa[NS], ob[NS], oc[NS], od[NS], oe[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const int idx = threadIdx.x + s * NT;
+        const int idx = threadIdx.x + s * PNT;
         const int rr = idx / SW, cc = idx - rr * SW;
         const int jj = j0 - W + rr, ii = i0 - W + cc;
         const bool ok = idx < SR * SW && jj >= 0 && jj < nM && ii >= 0 && ii < nM;
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
     auto step = [&](int kk, double (&b)[NS][6]) {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const int idx = threadIdx.x + s * NT;
+            const int idx = threadIdx.x + s * PNT;
             if (idx < SR * SW) {
                 const double gv = (b[s][0] - b[s][1]) + (b[s][2] - b[s][3]) + (b[s][4] - a3prev[s]);
                 gs[idx] = gv;
@@ -285,22 +286,22 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_for<P>
         an[2] += Q3;
         an[3] += Q3;
         __syncthreads();
-        for (int rr = g; rr < SR; rr += T2) {
+        for (int rr = g; rr < SR; rr += PT2) {
             double sg = 0.0, sz = 0.0;
 #pragma unroll
             for (int t = 0; t <= 2 * W; ++t) {
                 sg += c1[t] * gs[rr * SW + c + t];
                 sz += c1[t] * zs[rr * SW + c + t];
             }
-            pg[rr * T1 + c] = sg;
-            pz[rr * T1 + c] = sz;
+            pg[rr * PT1 + c] = sg;
+            pz[rr * PT1 + c] = sz;
         }
         __syncthreads();
         double sg = 0.0, sz = 0.0;
 #pragma unroll
         for (int t = 0; t <= 2 * W; ++t) {
-            sg += c2[t] * pg[(g + t) * T1 + c];
-            sz += c2[t] * pz[(g + t) * T1 + c];
+            sg += c2[t] * pg[(g + t) * PT1 + c];
+            sz += c2[t] * pz[(g + t) * PT1 + c];
         }
         wg.push(sg);
         wz.push(sz);
@@ -1385,7 +1386,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
 template <int P>
 void launch_pres(dim3 grid, hipStream_t st, const OpArgs& a, double* yp, long long syp) {
-    hipLaunchKernelGGL(k_pres<P>, grid, dim3(NT), 0, st, a, yp, syp);
+    hipLaunchKernelGGL((k_pres<P, T1, T2>), grid, dim3(NT), 0, st, a, yp, syp);
+}
+// the pressure chain on 32 x 8 tiles: less halo per point (36 x 12 staged
+// values per 256 outputs against 20 x 12 per 128), larger workgroups
+constexpr int PW1 = 32, PW2 = 8;
+template <int P>
+void launch_pres_wide(dim3 grid, hipStream_t st, const OpArgs& a, double* yp, long long syp) {
+    hipLaunchKernelGGL((k_pres<P, PW1, PW2>), grid, dim3(PW1 * PW2), 0, st, a, yp, syp);
 }
 
 template <int P>
@@ -1421,6 +1429,10 @@ constexpr int PMAX = 8;
 const PresLaunch pres_launch[PMAX + 1] = {nullptr,        nullptr,        launch_pres<2>,
                                           launch_pres<3>, launch_pres<4>, launch_pres<5>,
                                           launch_pres<6>, launch_pres<7>, launch_pres<8>};
+const PresLaunch pres_wide_launch[PMAX + 1] = {
+    nullptr,             nullptr,             launch_pres_wide<2>, launch_pres_wide<3>,
+    launch_pres_wide<4>, launch_pres_wide<5>, launch_pres_wide<6>, launch_pres_wide<7>,
+    launch_pres_wide<8>};
 const VelLaunch vel_launch[PMAX + 1] = {nullptr,       nullptr,       launch_vel<2>,
                                         launch_vel<3>, launch_vel<4>, launch_vel<5>,
                                         launch_vel<6>, launch_vel<7>, launch_vel<8>};
@@ -1521,6 +1533,7 @@ OpShape op_shape(const hp_ctx* c, int nrhs) {
     if (c->opts.op_order >= 0) sh.comp_fast = c->opts.op_order;
     if (c->opts.op_fused >= 0) sh.fused = c->opts.op_fused;
     if (c->opts.op_staged >= 0) sh.staged = c->opts.op_staged;
+    if (c->opts.op_pres_wide >= 0) sh.pwide = c->opts.op_pres_wide;
     sh.dma = c->opts.op_dma != 0;
     if (c->op_force.kchunk > 0) sh = c->op_force;
     if (c->p > FUSED_PMAX) sh.fused = 0;
@@ -1556,13 +1569,21 @@ hipError_t launch_operator(hp_ctx* c, OpMode mode, const Fields& in, const Field
     double* yp = out.f[3];
     const long long syp = out.stride[3];
     const PresLaunch pall = sh.staged ? pres_all_launch(P, a.kchunk) : nullptr;
+    const bool pwide = !pall && sh.pwide;
     auto pres = [&](int lo, int hi) {
         a.kbase = lo;
         a.klim = hi;
         a.nchunk = (hi - lo + a.kchunk - 1) / a.kchunk;
+        if (pwide) {
+            a.ntile1 = (nM + PW1 - 1) / PW1;
+            a.ntile2 = (nM + PW2 - 1) / PW2;
+        }
         a.nblocks = a.ntile1 * a.ntile2 * a.nchunk * nrhs;
         dim3 grid(a.nblocks);
-        (pall ? pall : pres_launch[P])(grid, c->stream, a, yp, syp);
+        (pall ? pall : (pwide ? pres_wide_launch[P] : pres_launch[P]))(grid, c->stream, a, yp,
+                                                                       syp);
+        a.ntile1 = (nM + T1 - 1) / T1;  // the velocity kernels' tiles
+        a.ntile2 = (nM + T2 - 1) / T2;
     };
     const VelLaunch vall = (sh.staged && (mode == OP_K || mode == OP_A))
                                ? vel_all_launch(P, a.kchunk) : nullptr;

@@ -44,7 +44,7 @@ class Solver:
                  op_kchunk=0, op_order=-1, fd_plan=-1, op_slabs=0, schur_level=0,
                  schur_pcg_iters=20, schur_pcg_tol=1e-2, op_fused=-1, op_staged=-1,
                  forward="kronecker", use_x0=False, spectrum_gate=0, p0_scale=1.0,
-                 breakdown_tol=0.0, op_dma=-1, device=None):
+                 breakdown_tol=0.0, op_dma=-1, op_pres_wide=-1, device=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the hyper-power solver runs on a GPU (none visible)")
         self.lib = _lib.load()
@@ -79,6 +79,7 @@ class Solver:
         o.p0_scale = float(p0_scale)
         o.breakdown_tol = float(breakdown_tol)
         o.op_dma = int(op_dma)
+        o.op_pres_wide = int(op_pres_wide)
         self.opts = o
         self.E, self.p, self.nu = E, p, nu
         with torch.cuda.device(self.device):
@@ -105,7 +106,7 @@ class Solver:
         return {"op_kchunk": t.op_kchunk, "op_order": t.op_order, "op_slabs": t.op_slabs,
                 "op_tuned": bool(t.op_tuned),
                 "op_us": t.op_us, "fd_plan": list(t.fd_plan), "fd_us": list(t.fd_us),
-                "op_staged": t.op_staged}
+                "op_staged": t.op_staged, "op_pres_wide": t.op_pres_wide}
 
     # -- memory helpers ------------------------------------------------------
     def empty(self, n, nrhs=1):

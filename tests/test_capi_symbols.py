@@ -45,6 +45,7 @@ def test_binding_signatures_cover_the_header():
     assert opts.op_staged == -1 and opts.use_graph == 0 and opts.poll_lag == 1
     assert opts.forward == 0 and opts.use_x0 == 0 and opts.spectrum_gate == 0
     assert opts.p0_scale == 1.0 and opts.breakdown_tol == 0.0 and opts.op_dma == -1
+    assert opts.op_pres_wide == -1
     assert lib.hp_status_string(-6) == b"not converged within maxit"
 
 
@@ -72,7 +73,8 @@ def test_setup_rejects_bad_arguments_without_touching_the_gpu():
                        ("poll_lag", 0), ("poll_lag", 4), ("forward", -1), ("forward", 2),
                        ("use_x0", 2), ("use_x0", -1), ("spectrum_gate", -1),
                        ("p0_scale", -0.5), ("p0_scale", float("nan")),
-                       ("breakdown_tol", -1.0), ("op_dma", -2), ("op_dma", 2)):
+                       ("breakdown_tol", -1.0), ("op_dma", -2), ("op_dma", 2),
+                       ("op_pres_wide", -2), ("op_pres_wide", 2)):
         opts = _lib.hp_opts()
         lib.hp_default_opts(ctypes.byref(opts))
         setattr(opts, field, bad)

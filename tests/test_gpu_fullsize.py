@@ -435,6 +435,14 @@ def test_operator_shapes_agree_bitwise(dev, E, p):
         for a, b in zip(run(s), ref):
             assert torch.equal(a, b), (kc, "op_dma=0")
         s.close()
+    # the streaming pressure kernel on 32 x 8 tiles against 16 x 8
+    for kc, slabs in ((1, 1), (5, 3), (nM, 1)):
+        s = Solver(E, p, nu, autotune=False, max_rhs=2, op_kchunk=kc, op_order=0,
+                   op_slabs=slabs, op_staged=0, op_pres_wide=1)
+        assert s.tuning(1)["op_pres_wide"] == 1
+        for a, b in zip(run(s), ref):
+            assert torch.equal(a, b), (kc, slabs, "op_pres_wide=1")
+        s.close()
     base.close()
 
 
@@ -571,12 +579,16 @@ def test_batched_equals_single_above_dot_chunk_switch(dev, krylov):
     """From 2^19 unknowns on the Krylov dot products use 480 chunks per
     vector instead of 240 (the count depends on the length alone): a batch
     of two right-hand sides still reproduces each one's single solve bit for
-    bit, and the MINRES iterations end where the single solves end."""
+    bit, and the MINRES iterations end where the single solves end.  The
+    operator shapes are tuned per context (results do not depend on them);
+    the P_0 plan is fixed for both, since the plan sets how the last launches
+    of P_k split the Krylov dot into partials (the row-block plan per row
+    block, the others per plane), i.e. its summation order."""
     from paper_2311_06926_amd.solver import Solver
     E, p = 50, 3
     say(f"[shapes] batched vs single above 2^19 unknowns E={E} p={p} {krylov}")
-    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=2)
-    ss = Solver(E, p, 1.0, iters=1, krylov=krylov)
+    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=2, fd_plan=9)
+    ss = Solver(E, p, 1.0, iters=1, krylov=krylov, fd_plan=9)
     N = sb.N
     assert N >= 1 << 19
     rhs = sb.build_rhs([1.0, -0.6])

@@ -544,8 +544,10 @@ def test_batched_solve_matches_single(dev, krylov):
     from paper_2311_06926_amd.solver import Solver
     say(f"[parity] batched solve nrhs=3 {krylov}")
     E, p, R = 6, 2, 3
-    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=R)
-    ss = Solver(E, p, 1.0, iters=1, krylov=krylov)
+    # the same P_0 plan in both contexts: the plan sets how P_k's last
+    # launches split the Krylov dot into partials (the summation order)
+    sb = Solver(E, p, 1.0, iters=1, krylov=krylov, max_rhs=R, fd_plan=1)
+    ss = Solver(E, p, 1.0, iters=1, krylov=krylov, fd_plan=1)
     lids, amps, wavs = [], [], []
     for r in range(R):
         modes, U = synth.body_force_modes(r, nmodes=16)
